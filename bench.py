@@ -1,0 +1,233 @@
+#!/usr/bin/env python3
+"""Benchmark of the rasterizer hot path on one GPU.
+
+One step = one frame of the whole path: host camera composition (FP64), key
+clear, render (project + cull + 64-bit atomic-min visibility) and resolve
+(depth, attribute planes and the colour channel; Vel2D too where the workload
+has velocities).  Steps walk the workload's camera path.  Inputs are resident
+in device memory before timing starts.
+
+Prints one JSON line.  `value` is points rendered per second over the timed
+steps; `roofline` reports the render kernel (the dominant one) against HBM
+peak using HIP events recorded on the launch stream; `cpu_baseline` times the
+CPU oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Gpoints/s raster; 1080p frame ms raster+BF16 net vs Gaussian splat @PSNR"
+HBM_PEAK_GBPS = 8000.0
+RASTER_SRC = os.path.join(ROOT, "paper_2407_19097_amd", "csrc", "raster.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "render_traffic.json")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def source_hash(path):
+    with open(path, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def make_scene(name, device):
+    from paper_2407_19097_amd import scenes
+    if name == "trajectories":
+        return scenes.trajectories(device=device), "trajectories: 3.5M particles x 100 RK4 steps = 350M points, double gyre, 1920x1080, 120-frame fly-through + overview"
+    if name == "vector_field":
+        return scenes.vector_field(device=device), "vector field: 500x500x200 = 50M jittered points, Rankine vortex, 1920x1080, 60-frame orbit"
+    if name == "unit_cube":
+        sc = scenes.unit_cube()
+        import torch
+        sc.x, sc.y, sc.z = (torch.from_numpy(a).to(device) for a in (sc.x, sc.y, sc.z))
+        sc.attrs = [torch.from_numpy(a).to(device) for a in sc.attrs]
+        return sc, "unit cube: 1M points, 512x512"
+    if name == "terrain":
+        return scenes.terrain(device=device), "terrain: 1B jittered samples of an fBm height field, RGBA u8, 3840x2160"
+    if name == "terrain25":
+        sc = scenes.terrain(device=device)
+        return scenes.subsample(sc, 4), "terrain, every 4th point: 250M points, 3840x2160"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def read_traffic(launch_points, W, H):
+    """HBM bytes per render launch from committed rocprofv3 counter runs, if
+    they were taken on the current kernel source and the same workload."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256_16") != source_hash(RASTER_SRC):
+        return None
+    if rec.get("points") != launch_points or rec.get("W") != W or rec.get("H") != H:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(sc, cam, budget_s=15.0):
+    """The oracle as it stands (single thread) on the first S points of one frame."""
+    from oracle import camera as ocam
+    from oracle import raster as orast
+    n, W, H = sc.n, sc.W, sc.H
+    M, near, far = ocam.clip_matrix(cam, W, H)
+    cal = min(n, 2_000_000)
+    xs = sc.x[:cal].cpu().numpy()
+    ys = sc.y[:cal].cpu().numpy()
+    zs = sc.z[:cal].cpu().numpy()
+    t0 = time.perf_counter()
+    orast.render(xs, ys, zs, M, near, far, W, H)
+    rate = cal / max(time.perf_counter() - t0, 1e-6)
+    S = int(min(n, max(cal, rate * budget_s)))
+    S -= S % 4
+    xs = sc.x[:S].cpu().numpy()
+    ys = sc.y[:S].cpu().numpy()
+    zs = sc.z[:S].cpu().numpy()
+    attrs = []
+    for a in sc.attrs:
+        h = a[:S].cpu().numpy()
+        attrs.append(h.view(np.uint16) if h.dtype == np.int16 else h)
+    t0 = time.perf_counter()
+    keys = orast.render(xs, ys, zs, M, near, far, W, H)
+    orast.resolve(keys, W, H, xs, ys, zs, M, attrs)
+    dt = time.perf_counter() - t0
+    return {"value": S / dt / 1e9, "unit": "Gpoints/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {S} of {n} points, one frame ({W}x{H}), render + resolve (depth, attributes), "
+                      f"single-threaded C oracle, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=121)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="trajectories",
+                    choices=["trajectories", "vector_field", "unit_cube", "terrain", "terrain25"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the rasterizer runs on a single device "
+              "(a multi-GPU run would shard points and min-reduce key buffers; not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2407_19097_amd import narvis, scenes
+
+    dev = "cuda"
+    t0 = time.time()
+    sc, desc = make_scene(args.workload, dev)
+    torch.cuda.synchronize()
+    log(f"scene {sc.name}: {sc.n} points generated in {time.time() - t0:.1f}s")
+    n, W, H = sc.n, sc.W, sc.H
+    cams = sc.cameras
+    mats = [narvis.narvis_camera_matrix(c, W, H) for c in cams]
+
+    g = narvis.GBuffer.allocate(W, H, nattr=len(sc.attrs), depth=True, rgb=sc.lut_attr >= 0,
+                                vel2d=sc.vel_attr >= 0)
+    if sc.lut_attr >= 0:
+        g.lut = torch.from_numpy(scenes.colour_lut()).to(dev)
+        g.lut_attr, g.lut_min = sc.lut_attr, sc.lut_min
+        g.lut_inv_range = float(np.float32(1.0 / (sc.lut_max - sc.lut_min)))
+    g.vel_attr = sc.vel_attr
+    pts = (sc.x, sc.y, sc.z)
+    stream = torch.cuda.current_stream()
+
+    def step(k, ev=None):
+        # host camera composition is part of the step
+        vp, nf, ff = narvis.narvis_camera_matrix(cams[k % len(cams)], W, H)
+        narvis.narvis_raster_clear(g.keys, W, H, stream)
+        if ev is not None:
+            ev[0].record(stream)
+        narvis.narvis_raster_render(pts, n, vp, nf, ff, W, H, g.keys, stream=stream)
+        if ev is not None:
+            ev[1].record(stream)
+        narvis.narvis_raster_resolve(pts, sc.attrs, n, vp, W, H, g, stream=stream)
+
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    log("warmup done")
+
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_host = time.perf_counter()
+    start.record(stream)
+    for k in range(args.steps):
+        step(k, evs[k])
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_host
+    total_ms = start.elapsed_time(stop)
+    render_ms = [a.elapsed_time(b) for a, b in evs]
+    log(f"timed {args.steps} steps: {total_ms:.3f} ms on the stream, {wall * 1e3:.3f} ms wall")
+
+    ms_per_step = total_ms / args.steps
+    value = n * args.steps / (total_ms / 1e3) / 1e9
+    render_avg = float(np.mean(render_ms))
+    alg_bytes = 12.0 * n + 16.0 * W * H
+    achieved = alg_bytes / (render_avg / 1e3) / 1e9
+    traffic = read_traffic(n, W, H)
+
+    # coverage of the first frame, for context
+    step(0)
+    torch.cuda.synchronize()
+    covered = float((g.keys != -1).float().mean().item())
+
+    # device copy bandwidth of a plain copy kernel, for context
+    a = torch.empty(1 << 29, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(5):
+        b.copy_(a)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbps = 5 * 2 * a.numel() * 4 / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del a, b
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Gpoints/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": desc, "points": n, "W": W, "H": H, "frames": len(cams),
+                   "planes": ["keys", "depth"] + [f"attr:{nm}" for nm in sc.attr_names]
+                   + (["rgb"] if sc.lut_attr >= 0 else []) + (["vel2d"] if sc.vel_attr >= 0 else []),
+                   "covered_fraction_frame0": round(covered, 4)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+                     "kernel": "render (k_render_vec)", "avg_launch_ms": round(render_avg, 4),
+                     "algorithmic_bytes_per_launch": alg_bytes},
+        "stream_copy_GBps": round(copy_gbps, 1),
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle sample")
+        out["cpu_baseline"] = cpu_baseline(sc, cams[0])
+        out["cpu_baseline"]["value"] = round(out["cpu_baseline"]["value"], 5)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

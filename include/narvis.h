@@ -1,0 +1,177 @@
+/*
+ * narvis.h -- C ABI of the NARVis hot path on MI355X (gfx950).
+ *
+ * The library renders attributed point clouds the way the multi-attribute
+ * compute rasterizer of NARVis does (Sec. 3.2): a render stage projects
+ * every point, culls it against the view frustum and keeps, per pixel, the
+ * point closest to the camera through a depth test on a custom framebuffer;
+ * a resolve stage then copies the winning point's attributes into G-buffer
+ * planes (no blending of overlapping points).
+ *
+ * Conventions shared by every entry point
+ *  - Every buffer argument is device memory owned by the caller (for example
+ *    a torch tensor); the library never allocates, frees or retains it.
+ *  - Work is enqueued asynchronously on the HIP stream passed as `stream`
+ *    (a hipStream_t, NULL = the default stream).  No call synchronises with
+ *    the host; results are visible once the stream reaches that point.
+ *  - Arguments are validated on the host before anything is enqueued.  On any
+ *    error status nothing has been enqueued and outputs are untouched.
+ *    Launch failures reported by the runtime come back as NARVIS_ERR_DEVICE.
+ *  - Calls are re-entrant for disjoint output buffers.
+ *  - Images are row-major with row 0 at the top; a "plane" is W*H values.
+ */
+#ifndef NARVIS_H
+#define NARVIS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NARVIS_OK = 0,
+    NARVIS_ERR_INVALID_ARG = -1,
+    NARVIS_ERR_OUT_OF_MEMORY = -2,
+    NARVIS_ERR_DEVICE = -3,
+    NARVIS_ERR_UNSUPPORTED = -4,
+    NARVIS_ERR_WORKSPACE = -5
+} narvis_status;
+
+/* Element formats of a per-point attribute stream (Sec. 3.2 names uint8 and
+ * fp32; uint16 and fp16 are accepted as well). */
+typedef enum { NARVIS_U8 = 0, NARVIS_U16 = 1, NARVIS_F16 = 2, NARVIS_F32 = 3 } narvis_dtype;
+
+#define NARVIS_MAX_ATTRS 8
+#define NARVIS_KEY_EMPTY 0xFFFFFFFFFFFFFFFFull
+
+/* Point positions, structure of arrays: x[n], y[n], z[n] float32, device. */
+typedef struct {
+    const float *x;
+    const float *y;
+    const float *z;
+} narvis_points;
+
+/* One attribute stream: element i lives at (char*)data + i*stride_bytes.
+ * stride_bytes >= element size (1, 2, 2, 4 bytes); AoS layouts are described
+ * by a stride larger than the element. */
+typedef struct {
+    const void *data;
+    int32_t dtype;        /* narvis_dtype */
+    int32_t stride_bytes;
+} narvis_attr;
+
+/* Up to 8 attribute streams ("currently tested up to 8", Sec. 3.2). */
+typedef struct {
+    int32_t count;
+    narvis_attr a[NARVIS_MAX_ATTRS];
+} narvis_attrs;
+
+/* Pinhole camera placement.  Vertical field of view in degrees, aspect W/H,
+ * right-handed look-at, OpenGL-style perspective (the paper trains with a 60
+ * degree field of view, near 0.1 and far 2e5, Sec. 3.3). */
+typedef struct {
+    double eye[3];
+    double target[3];
+    double up[3];
+    double fovy_deg;
+    double znear;
+    double zfar;
+} narvis_camera;
+
+/* Output planes of the resolve stage.  `keys` is required; every other plane
+ * pointer may be NULL to skip it.
+ *   keys   uint64[H][W]   per pixel: (fp32 depth bits << 32) | point index of
+ *                         the closest point, NARVIS_KEY_EMPTY if none.
+ *   depth  float[H][W]    depth of the winner (distance along the viewing
+ *                         axis), 0 for an empty pixel.
+ *   attr   float[count][H][W]  attribute c of the winner converted exactly to
+ *                         fp32 (integers by value, fp16 widened; a half NaN
+ *                         becomes the quiet fp32 NaN with the same sign and
+ *                         payload), 0 for an empty pixel.
+ *   rgb    float[3][H][W] transfer-function colour lut[q] of attribute
+ *                         lut_attr, q = floor((s - lut_min) * lut_inv_range * 256)
+ *                         clamped to [0,255] (NaN -> 0); 0 for an empty pixel.
+ *   vel2d  float[4][H][W] Vel2D of Sec. 4.5.3 from attributes vel_attr,
+ *                         vel_attr+1, vel_attr+2 (vx, vy, vz): the derivative
+ *                         of normalised device coordinates along v
+ *                         (v'x, v'y), then theta = atan2(v'y, v'x)/pi and
+ *                         |v'|; 0 for an empty pixel.
+ *   lut    float[256][3] device table for rgb. */
+typedef struct {
+    uint64_t *keys;
+    float *depth;
+    float *attr;
+    float *rgb;
+    float *vel2d;
+    const float *lut;
+    int32_t lut_attr;
+    float lut_min;
+    float lut_inv_range;
+    int32_t vel_attr;
+} narvis_gbuffer;
+
+/* Render-stage strategy.  Every variant produces the same key buffer; they
+ * differ only in how the per-pixel minimum is reached. */
+typedef enum {
+    NARVIS_RENDER_AUTO = 0,    /* library's choice for the device            */
+    NARVIS_RENDER_GLOBAL = 1,  /* atomic min per surviving point, no z-test  */
+    NARVIS_RENDER_EARLYZ = 2   /* read the key first, atomic only if closer  */
+} narvis_render_variant;
+
+typedef struct {
+    int32_t variant;      /* narvis_render_variant                           */
+    int32_t grid_blocks;  /* 0 = automatic, otherwise the number of
+                             workgroups (a grid-stride loop covers all points) */
+} narvis_raster_opts;
+
+/* Human-readable name of a status code (static storage). */
+const char *narvis_status_string(narvis_status s);
+
+/* Compose the clip-space matrix M = P * V of `cam` in FP64 on the host and
+ * round each entry once to fp32 (round to nearest even).  vp_rowmajor[16]
+ * receives M row-major; *near_f / *far_f receive the fp32 cull bounds.
+ * Host only, touches no device.  INVALID_ARG for W or H < 1, eye == target,
+ * up parallel to the viewing direction, fovy outside (0,180) or not
+ * 0 < znear < zfar. */
+narvis_status narvis_camera_matrix(const narvis_camera *cam, int32_t W, int32_t H,
+                                   float vp_rowmajor[16], float *near_f, float *far_f);
+
+/* Fill keys[W*H] with NARVIS_KEY_EMPTY. */
+narvis_status narvis_raster_clear(uint64_t *keys, int32_t W, int32_t H, void *stream);
+
+/* Render stage (Sec. 3.2: transform to screen space, keep the closest point
+ * per pixel by a depth test).  For every point i < n, in fp32 with each
+ * operation rounded in the order written (no fused multiply-add):
+ *   cx = ((M00 x + M01 y) + M02 z) + M03,  cy likewise with row 1,
+ *   w  = ((M30 x + M31 y) + M32 z) + M33   (the depth),
+ *   kept iff near_f <= w <= far_f,
+ *   sx = ((cx / w) * 0.5 + 0.5) * W,  sy = (0.5 - (cy / w) * 0.5) * H,
+ *   kept iff 0 <= sx < W and 0 <= sy < H, pixel = (int)sy * W + (int)sx,
+ *   keys[pixel] = min(keys[pixel], (bits(w) << 32) | i).
+ * Keys are merged into the existing buffer (clear it first for a new frame).
+ * n may be 0; n <= 2^32.  W, H >= 1 and W*H < 2^31.  `opts` may be NULL. */
+narvis_status narvis_raster_render(const narvis_points *pts, uint64_t n, const float vp_rowmajor[16],
+                                   float near_f, float far_f, int32_t W, int32_t H, uint64_t *keys,
+                                   const narvis_raster_opts *opts, void *stream);
+
+/* Resolve stage (Sec. 3.2: transfer the winner's attributes to the
+ * G-buffers): reads gbuf->keys and writes the requested planes (see
+ * narvis_gbuffer).  `pts` and vp_rowmajor are needed only for vel2d (the
+ * winner's clip coordinates are recomputed exactly as in the render stage).
+ * `attrs` may be NULL when no attribute plane is requested. */
+narvis_status narvis_raster_resolve(const narvis_points *pts, const narvis_attrs *attrs, uint64_t n,
+                                    const float vp_rowmajor[16], int32_t W, int32_t H,
+                                    const narvis_gbuffer *gbuf, void *stream);
+
+/* Whole frame: camera matrix, clear, render, resolve. */
+narvis_status narvis_rasterize(const narvis_points *pts, const narvis_attrs *attrs, uint64_t n,
+                               const narvis_camera *cam, int32_t W, int32_t H,
+                               narvis_gbuffer *gbuf, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NARVIS_H */

@@ -1,0 +1,96 @@
+"""ctypes binding of libnarvis.so: structure layouts and symbol signatures.
+
+Argument marshalling only.  The library is loaded from this package's
+directory; if it has not been built the import of any entry point fails with
+an error that says so -- there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnarvis.so")
+
+MAX_ATTRS = 8
+KEY_EMPTY = 0xFFFFFFFFFFFFFFFF
+
+STATUS = {0: "NARVIS_OK", -1: "NARVIS_ERR_INVALID_ARG", -2: "NARVIS_ERR_OUT_OF_MEMORY",
+          -3: "NARVIS_ERR_DEVICE", -4: "NARVIS_ERR_UNSUPPORTED", -5: "NARVIS_ERR_WORKSPACE"}
+
+
+class NarvisError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {STATUS.get(status, status)}")
+
+
+class Points(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p)]
+
+
+class Attr(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("dtype", ctypes.c_int32), ("stride_bytes", ctypes.c_int32)]
+
+
+class Attrs(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("a", Attr * MAX_ATTRS)]
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("eye", ctypes.c_double * 3), ("target", ctypes.c_double * 3), ("up", ctypes.c_double * 3),
+                ("fovy_deg", ctypes.c_double), ("znear", ctypes.c_double), ("zfar", ctypes.c_double)]
+
+
+class GBuffer(ctypes.Structure):
+    _fields_ = [("keys", ctypes.c_void_p), ("depth", ctypes.c_void_p), ("attr", ctypes.c_void_p),
+                ("rgb", ctypes.c_void_p), ("vel2d", ctypes.c_void_p), ("lut", ctypes.c_void_p),
+                ("lut_attr", ctypes.c_int32), ("lut_min", ctypes.c_float), ("lut_inv_range", ctypes.c_float),
+                ("vel_attr", ctypes.c_int32)]
+
+
+class RasterOpts(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("grid_blocks", ctypes.c_int32)]
+
+
+_P = ctypes.c_void_p
+_F16 = ctypes.c_float * 16
+
+# name -> (restype, argtypes); every entry point of include/narvis.h
+SIGNATURES = {
+    "narvis_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "narvis_camera_matrix": (ctypes.c_int, [ctypes.POINTER(Camera), ctypes.c_int32, ctypes.c_int32, _F16,
+                                            ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
+    "narvis_raster_clear": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P]),
+    "narvis_raster_render": (ctypes.c_int, [ctypes.POINTER(Points), ctypes.c_uint64, _F16, ctypes.c_float,
+                                            ctypes.c_float, ctypes.c_int32, ctypes.c_int32, _P,
+                                            ctypes.POINTER(RasterOpts), _P]),
+    "narvis_raster_resolve": (ctypes.c_int, [ctypes.POINTER(Points), ctypes.POINTER(Attrs), ctypes.c_uint64, _F16,
+                                             ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(GBuffer), _P]),
+    "narvis_rasterize": (ctypes.c_int, [ctypes.POINTER(Points), ctypes.POINTER(Attrs), ctypes.c_uint64,
+                                        ctypes.POINTER(Camera), ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.POINTER(GBuffer), _P]),
+}
+
+_lib = None
+
+
+def load():
+    """Load libnarvis.so (built by paper_2407_19097_amd.build) and bind every symbol."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run paper_2407_19097_amd/build.py "
+                              "(the HIP library is the only implementation)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status: int, where: str) -> None:
+    if status != 0:
+        raise NarvisError(status, where)

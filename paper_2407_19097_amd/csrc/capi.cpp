@@ -1,0 +1,193 @@
+// C-ABI glue: argument validation, device facts and stage sequencing.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <mutex>
+#include <vector>
+
+#include "internal.h"
+#include "narvis.h"
+
+namespace narvis {
+
+DeviceInfo device_info()
+{
+    static std::mutex mu;
+    static std::vector<DeviceInfo> cache;
+    static std::vector<bool> have;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    std::lock_guard<std::mutex> lock(mu);
+    if ((int)cache.size() <= dev) {
+        cache.resize(dev + 1);
+        have.resize(dev + 1, false);
+    }
+    if (!have[dev]) {
+        DeviceInfo d{256, 8};
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) d.cus = v;
+        // gfx950 (MI355X) and gfx942 carry 8 XCDs per device in single-partition mode;
+        // with fewer compute units (a partitioned device) fall back to one.
+        d.xcds = d.cus >= 64 ? 8 : 1;
+        cache[dev] = d;
+        have[dev] = true;
+    }
+    return cache[dev];
+}
+
+}  // namespace narvis
+
+using namespace narvis;
+
+namespace {
+
+constexpr int64_t kMaxPixels = (int64_t(1) << 31) - 1;
+constexpr int32_t kMaxSide = 1 << 24;
+constexpr uint64_t kMaxPoints = uint64_t(1) << 32;
+
+bool image_ok(int32_t W, int32_t H)
+{
+    return W >= 1 && H >= 1 && W <= kMaxSide && H <= kMaxSide && (int64_t)W * (int64_t)H <= kMaxPixels;
+}
+
+bool points_ok(const narvis_points *pts, uint64_t n)
+{
+    if (n > kMaxPoints) return false;
+    if (n == 0) return true;
+    return pts && pts->x && pts->y && pts->z;
+}
+
+bool matrix_ok(const float vp[16], float near_f, float far_f)
+{
+    if (!vp) return false;
+    for (int k = 0; k < 16; ++k)
+        if (!std::isfinite(vp[k])) return false;
+    return std::isfinite(near_f) && std::isfinite(far_f) && near_f > 0.0f && near_f <= far_f;
+}
+
+int dtype_size(int32_t dt)
+{
+    switch (dt) {
+    case NARVIS_U8: return 1;
+    case NARVIS_U16: return 2;
+    case NARVIS_F16: return 2;
+    case NARVIS_F32: return 4;
+    default: return 0;
+    }
+}
+
+bool pack_attrs(const narvis_attrs *attrs, uint64_t n, AttrPack &out)
+{
+    out = AttrPack{};
+    if (!attrs) return true;
+    if (attrs->count < 0 || attrs->count > NARVIS_MAX_ATTRS) return false;
+    out.count = attrs->count;
+    for (int c = 0; c < attrs->count; ++c) {
+        const narvis_attr &a = attrs->a[c];
+        const int sz = dtype_size(a.dtype);
+        if (sz == 0 || a.stride_bytes < sz) return false;
+        if (n > 0 && !a.data) return false;
+        // element alignment is required for the typed loads
+        if ((reinterpret_cast<uintptr_t>(a.data) | (uintptr_t)a.stride_bytes) & (uintptr_t)(sz - 1)) return false;
+        out.a[c].p = static_cast<const unsigned char *>(a.data);
+        out.a[c].dtype = a.dtype;
+        out.a[c].stride = a.stride_bytes;
+    }
+    return true;
+}
+
+narvis_status from_hip(hipError_t e) { return e == hipSuccess ? NARVIS_OK : NARVIS_ERR_DEVICE; }
+
+}  // namespace
+
+extern "C" const char *narvis_status_string(narvis_status s)
+{
+    switch (s) {
+    case NARVIS_OK: return "ok";
+    case NARVIS_ERR_INVALID_ARG: return "invalid argument";
+    case NARVIS_ERR_OUT_OF_MEMORY: return "out of memory";
+    case NARVIS_ERR_DEVICE: return "device error";
+    case NARVIS_ERR_UNSUPPORTED: return "unsupported";
+    case NARVIS_ERR_WORKSPACE: return "workspace too small";
+    default: return "unknown status";
+    }
+}
+
+extern "C" narvis_status narvis_raster_clear(uint64_t *keys, int32_t W, int32_t H, void *stream)
+{
+    if (!keys || !image_ok(W, H) || (reinterpret_cast<uintptr_t>(keys) & 7u)) return NARVIS_ERR_INVALID_ARG;
+    return from_hip(launch_clear(keys, (int64_t)W * H, static_cast<hipStream_t>(stream)));
+}
+
+extern "C" narvis_status narvis_raster_render(const narvis_points *pts, uint64_t n, const float vp[16],
+                                              float near_f, float far_f, int32_t W, int32_t H, uint64_t *keys,
+                                              const narvis_raster_opts *opts, void *stream)
+{
+    if (!keys || !image_ok(W, H) || !points_ok(pts, n) || !matrix_ok(vp, near_f, far_f))
+        return NARVIS_ERR_INVALID_ARG;
+    if (reinterpret_cast<uintptr_t>(keys) & 7u) return NARVIS_ERR_INVALID_ARG;
+    int32_t variant = opts ? opts->variant : NARVIS_RENDER_AUTO;
+    int32_t grid = opts ? opts->grid_blocks : 0;
+    if (variant < NARVIS_RENDER_AUTO || variant > NARVIS_RENDER_EARLYZ || grid < 0) return NARVIS_ERR_INVALID_ARG;
+    if (n > 0 && ((reinterpret_cast<uintptr_t>(pts->x) | reinterpret_cast<uintptr_t>(pts->y) |
+                   reinterpret_cast<uintptr_t>(pts->z)) & 3u))
+        return NARVIS_ERR_INVALID_ARG;
+    const Proj P = make_proj(vp, near_f, far_f, W, H);
+    return from_hip(launch_render(n ? pts->x : nullptr, n ? pts->y : nullptr, n ? pts->z : nullptr, n, P, keys,
+                                  variant, grid, static_cast<hipStream_t>(stream)));
+}
+
+extern "C" narvis_status narvis_raster_resolve(const narvis_points *pts, const narvis_attrs *attrs, uint64_t n,
+                                               const float vp[16], int32_t W, int32_t H,
+                                               const narvis_gbuffer *gbuf, void *stream)
+{
+    if (!gbuf || !gbuf->keys || !image_ok(W, H) || (reinterpret_cast<uintptr_t>(gbuf->keys) & 7u))
+        return NARVIS_ERR_INVALID_ARG;
+    AttrPack pack;
+    if (!pack_attrs(attrs, n, pack)) return NARVIS_ERR_INVALID_ARG;
+    if (gbuf->attr && pack.count == 0) return NARVIS_ERR_INVALID_ARG;
+    if (gbuf->rgb && (!gbuf->lut || gbuf->lut_attr < 0 || gbuf->lut_attr >= pack.count)) return NARVIS_ERR_INVALID_ARG;
+    if (gbuf->vel2d) {
+        if (gbuf->vel_attr < 0 || gbuf->vel_attr + 2 >= pack.count) return NARVIS_ERR_INVALID_ARG;
+        if (!points_ok(pts, n) || !vp) return NARVIS_ERR_INVALID_ARG;
+        for (int k = 0; k < 16; ++k)
+            if (!std::isfinite(vp[k])) return NARVIS_ERR_INVALID_ARG;
+    }
+    if (n > kMaxPoints) return NARVIS_ERR_INVALID_ARG;
+    float ident[16] = {1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1};
+    const Proj P = make_proj(vp ? vp : ident, 1.0f, 1.0f, W, H);
+    const bool need_pts = gbuf->vel2d != nullptr && n > 0;
+    return from_hip(launch_resolve(need_pts ? pts->x : nullptr, need_pts ? pts->y : nullptr,
+                                   need_pts ? pts->z : nullptr, n, P, pack, *gbuf,
+                                   static_cast<hipStream_t>(stream)));
+}
+
+extern "C" narvis_status narvis_rasterize(const narvis_points *pts, const narvis_attrs *attrs, uint64_t n,
+                                          const narvis_camera *cam, int32_t W, int32_t H, narvis_gbuffer *gbuf,
+                                          void *stream)
+{
+    float vp[16], near_f = 0.0f, far_f = 0.0f;
+    narvis_status st = narvis_camera_matrix(cam, W, H, vp, &near_f, &far_f);
+    if (st != NARVIS_OK) return st;
+    if (!gbuf || !gbuf->keys || !image_ok(W, H) || !points_ok(pts, n)) return NARVIS_ERR_INVALID_ARG;
+    AttrPack pack;
+    if (!pack_attrs(attrs, n, pack)) return NARVIS_ERR_INVALID_ARG;
+    if (!matrix_ok(vp, near_f, far_f)) return NARVIS_ERR_INVALID_ARG;
+    // validate the resolve arguments before enqueuing anything
+    if (gbuf->attr && pack.count == 0) return NARVIS_ERR_INVALID_ARG;
+    if (gbuf->rgb && (!gbuf->lut || gbuf->lut_attr < 0 || gbuf->lut_attr >= pack.count)) return NARVIS_ERR_INVALID_ARG;
+    if (gbuf->vel2d && (gbuf->vel_attr < 0 || gbuf->vel_attr + 2 >= pack.count)) return NARVIS_ERR_INVALID_ARG;
+    if (n > 0 && ((reinterpret_cast<uintptr_t>(pts->x) | reinterpret_cast<uintptr_t>(pts->y) |
+                   reinterpret_cast<uintptr_t>(pts->z)) & 3u))
+        return NARVIS_ERR_INVALID_ARG;
+    if (reinterpret_cast<uintptr_t>(gbuf->keys) & 7u) return NARVIS_ERR_INVALID_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    st = from_hip(launch_clear(gbuf->keys, (int64_t)W * H, s));
+    if (st != NARVIS_OK) return st;
+    const Proj P = make_proj(vp, near_f, far_f, W, H);
+    st = from_hip(launch_render(n ? pts->x : nullptr, n ? pts->y : nullptr, n ? pts->z : nullptr, n, P,
+                                gbuf->keys, NARVIS_RENDER_AUTO, 0, s));
+    if (st != NARVIS_OK) return st;
+    return from_hip(launch_resolve(n ? pts->x : nullptr, n ? pts->y : nullptr, n ? pts->z : nullptr, n, P, pack,
+                                   *gbuf, s));
+}

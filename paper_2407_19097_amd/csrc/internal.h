@@ -1,0 +1,49 @@
+// Internal interfaces between the C-ABI glue and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "narvis.h"
+
+namespace narvis {
+
+// Projection constants of one frame: the three used rows of M, the cull
+// bounds and the image size (float and integer).
+struct Proj {
+    float m00, m01, m02, m03;
+    float m10, m11, m12, m13;
+    float m30, m31, m32, m33;
+    float near_f, far_f;
+    float Wf, Hf;
+    int32_t W, H;
+};
+
+struct AttrArg {
+    const unsigned char *p;
+    int32_t dtype;
+    int32_t stride;
+};
+
+struct AttrPack {
+    AttrArg a[NARVIS_MAX_ATTRS];
+    int32_t count;
+};
+
+Proj make_proj(const float vp[16], float near_f, float far_f, int32_t W, int32_t H);
+
+// Per-device facts cached on first use.
+struct DeviceInfo {
+    int cus;
+    int xcds;
+};
+DeviceInfo device_info();
+
+hipError_t launch_clear(uint64_t *keys, int64_t npx, hipStream_t s);
+hipError_t launch_render(const float *x, const float *y, const float *z, uint64_t n, const Proj &P,
+                         uint64_t *keys, int32_t variant, int32_t grid_blocks, hipStream_t s);
+hipError_t launch_resolve(const float *x, const float *y, const float *z, uint64_t n, const Proj &P,
+                          const AttrPack &attrs, const narvis_gbuffer &g, hipStream_t s);
+
+}  // namespace narvis

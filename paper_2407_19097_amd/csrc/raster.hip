@@ -1,0 +1,322 @@
+// Multi-attribute point rasterizer for gfx950: clear, render, resolve.
+//
+// Render (Sec. 3.2, "transforms the points from world to screen space and
+// renders point depth to a custom framebuffer ... closest visible points ...
+// via early z-buffer testing"): every thread streams four consecutive points
+// of the SoA x/y/z arrays with 16-byte loads, projects them in fp32 with
+// every operation rounded in the written order (this file is compiled with
+// FMA contraction off), and merges (depth bits << 32 | index) into the
+// per-pixel 64-bit key with an unsigned atomic minimum.  The early-z variant
+// first reads the key and skips the atomic when the point cannot win: the key
+// buffer only ever decreases, so a stale read can only skip a point that
+// would lose anyway.
+//
+// Resolve (Sec. 3.2, "transfers other corresponding point attributes to the
+// final G-buffers"): one thread per pixel gathers the winner's attributes.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+#pragma clang fp contract(off)
+
+namespace narvis {
+
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kBlock = 256;
+constexpr int kQuadsPerThread = 2;
+
+__device__ __forceinline__ bool project(const Proj &P, float x, float y, float z, uint32_t &pix, float &w)
+{
+    float cx = P.m00 * x;
+    cx = cx + P.m01 * y;
+    cx = cx + P.m02 * z;
+    cx = cx + P.m03;
+    float cy = P.m10 * x;
+    cy = cy + P.m11 * y;
+    cy = cy + P.m12 * z;
+    cy = cy + P.m13;
+    float ww = P.m30 * x;
+    ww = ww + P.m31 * y;
+    ww = ww + P.m32 * z;
+    ww = ww + P.m33;
+    if (!(ww >= P.near_f && ww <= P.far_f)) return false;
+    float nx = cx / ww;
+    float ny = cy / ww;
+    float sx = nx * 0.5f;
+    sx = sx + 0.5f;
+    sx = sx * P.Wf;
+    float sy = ny * 0.5f;
+    sy = 0.5f - sy;
+    sy = sy * P.Hf;
+    if (!(sx >= 0.0f && sx < P.Wf && sy >= 0.0f && sy < P.Hf)) return false;
+    pix = (uint32_t)(int32_t)sy * (uint32_t)P.W + (uint32_t)(int32_t)sx;
+    w = ww;
+    return true;
+}
+
+template <int VARIANT>
+__device__ __forceinline__ void merge(unsigned long long *keys, uint32_t pix, float w, uint32_t idx)
+{
+    const unsigned long long key = ((unsigned long long)__float_as_uint(w) << 32) | idx;
+    if (VARIANT == NARVIS_RENDER_EARLYZ) {
+        if (key >= keys[pix]) return;
+    }
+    __hip_atomic_fetch_min(keys + pix, key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Workgroups are handed to the XCDs round-robin.  Renumber them so that XCD k
+// works through one contiguous stretch of the point stream: neighbouring
+// points of a coherent cloud then hit the key lines cached in the same L2.
+__device__ __forceinline__ uint32_t logical_block(uint32_t xcds)
+{
+    const uint32_t b = blockIdx.x;
+    const uint32_t per = gridDim.x / xcds;
+    return (b % xcds) * per + b / xcds;
+}
+
+template <int VARIANT>
+__global__ __launch_bounds__(kBlock) void k_render_vec(const float *__restrict__ X, const float *__restrict__ Y,
+                                                        const float *__restrict__ Z, uint64_t n, Proj P,
+                                                        unsigned long long *__restrict__ keys, uint32_t xcds)
+{
+    const uint64_t nq = n >> 2;
+    const uint64_t lb = logical_block(xcds);
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock * kQuadsPerThread;
+    for (uint64_t base = lb * kBlock * kQuadsPerThread + threadIdx.x; base < nq; base += stride) {
+        f32x4 xs[kQuadsPerThread], ys[kQuadsPerThread], zs[kQuadsPerThread];
+#pragma unroll
+        for (int k = 0; k < kQuadsPerThread; ++k) {
+            const uint64_t q = base + (uint64_t)k * kBlock;
+            if (q < nq) {
+                xs[k] = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(X) + q);
+                ys[k] = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(Y) + q);
+                zs[k] = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(Z) + q);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kQuadsPerThread; ++k) {
+            const uint64_t q = base + (uint64_t)k * kBlock;
+            if (q >= nq) continue;
+            const uint32_t i0 = (uint32_t)(q << 2);
+            const float px[4] = {xs[k].x, xs[k].y, xs[k].z, xs[k].w};
+            const float py[4] = {ys[k].x, ys[k].y, ys[k].z, ys[k].w};
+            const float pz[4] = {zs[k].x, zs[k].y, zs[k].z, zs[k].w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                uint32_t pix;
+                float w;
+                if (project(P, px[j], py[j], pz[j], pix, w)) merge<VARIANT>(keys, pix, w, i0 + (uint32_t)j);
+            }
+        }
+    }
+    // the last n % 4 points
+    if (blockIdx.x == 0 && threadIdx.x < (n & 3)) {
+        const uint64_t i = (nq << 2) + threadIdx.x;
+        uint32_t pix;
+        float w;
+        if (project(P, X[i], Y[i], Z[i], pix, w)) merge<VARIANT>(keys, pix, w, (uint32_t)i);
+    }
+}
+
+template <int VARIANT>
+__global__ __launch_bounds__(kBlock) void k_render_scalar(const float *__restrict__ X, const float *__restrict__ Y,
+                                                           const float *__restrict__ Z, uint64_t n, Proj P,
+                                                           unsigned long long *__restrict__ keys, uint32_t xcds)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t i = (uint64_t)logical_block(xcds) * kBlock + threadIdx.x; i < n; i += stride) {
+        uint32_t pix;
+        float w;
+        if (project(P, X[i], Y[i], Z[i], pix, w)) merge<VARIANT>(keys, pix, w, (uint32_t)i);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_empty(unsigned long long *__restrict__ keys, int64_t npx)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < npx) keys[i] = NARVIS_KEY_EMPTY;
+}
+
+__device__ __forceinline__ float half_to_float(uint32_t h)
+{
+    const uint32_t sign = (h & 0x8000u) << 16;
+    const uint32_t e = (h >> 10) & 0x1Fu;
+    const uint32_t m = h & 0x3FFu;
+    if (e == 0) {
+        // zero or subnormal: m * 2^-24 is exact in fp32
+        const float v = (float)m * 5.9604644775390625e-8f;
+        return __uint_as_float(__float_as_uint(v) | sign);
+    }
+    if (e == 31) return __uint_as_float(sign | 0x7F800000u | (m ? (0x00400000u | (m << 13)) : 0u));
+    return __uint_as_float(sign | ((e + 112u) << 23) | (m << 13));
+}
+
+__device__ __forceinline__ float load_attr(const AttrArg &a, uint32_t i)
+{
+    const unsigned char *p = a.p + (size_t)i * (size_t)a.stride;
+    switch (a.dtype) {
+    case NARVIS_U8: return (float)(*p);
+    case NARVIS_U16: return (float)(*reinterpret_cast<const uint16_t *>(p));
+    case NARVIS_F16: return half_to_float(*reinterpret_cast<const uint16_t *>(p));
+    default: return *reinterpret_cast<const float *>(p);
+    }
+}
+
+struct ResolveArgs {
+    const unsigned long long *keys;
+    const float *X, *Y, *Z;
+    float *depth, *attr, *rgb, *vel;
+    const float *lut;
+    int32_t lut_attr, vel_attr;
+    float lut_min, lut_inv;
+    int64_t npx;
+    uint64_t n;
+};
+
+__global__ __launch_bounds__(kBlock) void k_resolve(ResolveArgs R, AttrPack A, Proj P)
+{
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= R.npx) return;
+    const unsigned long long k = R.keys[p];
+    // an index outside [0, n) can only come from a buffer this frame did not
+    // render; it resolves as empty instead of reading out of bounds
+    const bool empty = (k == NARVIS_KEY_EMPTY) || (uint64_t)(uint32_t)k >= R.n;
+    const uint32_t i = (uint32_t)k;
+    if (R.depth) R.depth[p] = empty ? 0.0f : __uint_as_float((uint32_t)(k >> 32));
+    if (R.attr) {
+        for (int c = 0; c < A.count; ++c) R.attr[c * R.npx + p] = empty ? 0.0f : load_attr(A.a[c], i);
+    }
+    if (R.rgb) {
+        float r = 0.0f, g = 0.0f, b = 0.0f;
+        if (!empty) {
+            float t = load_attr(A.a[R.lut_attr], i) - R.lut_min;
+            t = t * R.lut_inv;
+            t = t * 256.0f;
+            int q;
+            if (!(t > 0.0f)) q = 0;
+            else if (t >= 255.0f) q = 255;
+            else q = (int)t;
+            r = R.lut[q * 3 + 0];
+            g = R.lut[q * 3 + 1];
+            b = R.lut[q * 3 + 2];
+        }
+        R.rgb[p] = r;
+        R.rgb[R.npx + p] = g;
+        R.rgb[2 * R.npx + p] = b;
+    }
+    if (R.vel) {
+        float o0 = 0.0f, o1 = 0.0f, o2 = 0.0f, o3 = 0.0f;
+        if (!empty) {
+            const float x = R.X[i], y = R.Y[i], z = R.Z[i];
+            float cx = P.m00 * x; cx = cx + P.m01 * y; cx = cx + P.m02 * z; cx = cx + P.m03;
+            float cy = P.m10 * x; cy = cy + P.m11 * y; cy = cy + P.m12 * z; cy = cy + P.m13;
+            float w = P.m30 * x; w = w + P.m31 * y; w = w + P.m32 * z; w = w + P.m33;
+            const float vx = load_attr(A.a[R.vel_attr], i);
+            const float vy = load_attr(A.a[R.vel_attr + 1], i);
+            const float vz = load_attr(A.a[R.vel_attr + 2], i);
+            float dcx = P.m00 * vx; dcx = dcx + P.m01 * vy; dcx = dcx + P.m02 * vz;
+            float dcy = P.m10 * vx; dcy = dcy + P.m11 * vy; dcy = dcy + P.m12 * vz;
+            float dw = P.m30 * vx; dw = dw + P.m31 * vy; dw = dw + P.m32 * vz;
+            const float ww = w * w;
+            const float nxv = dcx * w - cx * dw;
+            const float nyv = dcy * w - cy * dw;
+            o0 = nxv / ww;
+            o1 = nyv / ww;
+            float m2 = o0 * o0;
+            m2 = m2 + o1 * o1;
+            o3 = sqrtf(m2);
+            o2 = atan2f(o1, o0) / 3.14159265358979323846f;
+        }
+        R.vel[p] = o0;
+        R.vel[R.npx + p] = o1;
+        R.vel[2 * R.npx + p] = o2;
+        R.vel[3 * R.npx + p] = o3;
+    }
+}
+
+}  // namespace
+
+Proj make_proj(const float vp[16], float near_f, float far_f, int32_t W, int32_t H)
+{
+    Proj P;
+    P.m00 = vp[0]; P.m01 = vp[1]; P.m02 = vp[2]; P.m03 = vp[3];
+    P.m10 = vp[4]; P.m11 = vp[5]; P.m12 = vp[6]; P.m13 = vp[7];
+    P.m30 = vp[12]; P.m31 = vp[13]; P.m32 = vp[14]; P.m33 = vp[15];
+    P.near_f = near_f;
+    P.far_f = far_f;
+    P.Wf = (float)W;
+    P.Hf = (float)H;
+    P.W = W;
+    P.H = H;
+    return P;
+}
+
+hipError_t launch_clear(uint64_t *keys, int64_t npx, hipStream_t s)
+{
+    const int64_t blocks = (npx + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_fill_empty, dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                       reinterpret_cast<unsigned long long *>(keys), npx);
+    return hipGetLastError();
+}
+
+hipError_t launch_render(const float *x, const float *y, const float *z, uint64_t n, const Proj &P,
+                         uint64_t *keys, int32_t variant, int32_t grid_blocks, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    const DeviceInfo dev = device_info();
+    const uint32_t xcds = (uint32_t)dev.xcds;
+    const bool vec = ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y) |
+                       reinterpret_cast<uintptr_t>(z)) & 15u) == 0;
+    const uint64_t per_block = vec ? (uint64_t)kBlock * kQuadsPerThread * 4 : (uint64_t)kBlock;
+    uint64_t blocks = grid_blocks > 0 ? (uint64_t)grid_blocks : (n + per_block - 1) / per_block;
+    if (blocks > (1u << 30)) blocks = 1u << 30;
+    // a multiple of the XCD count keeps the block renumbering a bijection
+    blocks = (blocks + xcds - 1) / xcds * xcds;
+    auto *k = reinterpret_cast<unsigned long long *>(keys);
+    if (variant == NARVIS_RENDER_AUTO) variant = NARVIS_RENDER_EARLYZ;
+    if (vec) {
+        if (variant == NARVIS_RENDER_GLOBAL)
+            hipLaunchKernelGGL(k_render_vec<NARVIS_RENDER_GLOBAL>, dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                               x, y, z, n, P, k, xcds);
+        else
+            hipLaunchKernelGGL(k_render_vec<NARVIS_RENDER_EARLYZ>, dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                               x, y, z, n, P, k, xcds);
+    } else {
+        if (variant == NARVIS_RENDER_GLOBAL)
+            hipLaunchKernelGGL(k_render_scalar<NARVIS_RENDER_GLOBAL>, dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                               x, y, z, n, P, k, xcds);
+        else
+            hipLaunchKernelGGL(k_render_scalar<NARVIS_RENDER_EARLYZ>, dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                               x, y, z, n, P, k, xcds);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_resolve(const float *x, const float *y, const float *z, uint64_t n, const Proj &P,
+                          const AttrPack &attrs, const narvis_gbuffer &g, hipStream_t s)
+{
+    ResolveArgs R;
+    R.n = n;
+    R.keys = reinterpret_cast<const unsigned long long *>(g.keys);
+    R.X = x;
+    R.Y = y;
+    R.Z = z;
+    R.depth = g.depth;
+    R.attr = g.attr;
+    R.rgb = g.rgb;
+    R.vel = g.vel2d;
+    R.lut = g.lut;
+    R.lut_attr = g.lut_attr;
+    R.vel_attr = g.vel_attr;
+    R.lut_min = g.lut_min;
+    R.lut_inv = g.lut_inv_range;
+    R.npx = (int64_t)P.W * P.H;
+    const int64_t blocks = (R.npx + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_resolve, dim3((unsigned)blocks), dim3(kBlock), 0, s, R, attrs, P);
+    return hipGetLastError();
+}
+
+}  // namespace narvis

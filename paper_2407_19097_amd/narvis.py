@@ -1,0 +1,155 @@
+"""Python face of the C ABI: the same entry-point names, torch tensors in.
+
+Each function converts tensors to device pointers and sizes, calls the
+library on the current (or given) HIP stream and raises NarvisError on a
+non-zero status.  No arithmetic of the method happens here.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import _lib
+from ._lib import KEY_EMPTY, NarvisError  # noqa: F401
+
+RENDER_AUTO, RENDER_GLOBAL, RENDER_EARLYZ = 0, 1, 2
+
+_DTYPE_CODE = None
+
+
+def _dtype_code(t) -> int:
+    global _DTYPE_CODE
+    if _DTYPE_CODE is None:
+        import torch
+        _DTYPE_CODE = {torch.uint8: 0, torch.float16: 2, torch.float32: 3}
+        if hasattr(torch, "uint16"):
+            _DTYPE_CODE[torch.uint16] = 1
+    try:
+        return _DTYPE_CODE[t.dtype]
+    except KeyError:
+        raise TypeError(f"unsupported attribute dtype {t.dtype}") from None
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def camera_struct(cam) -> _lib.Camera:
+    c = _lib.Camera()
+    c.eye[:] = [float(v) for v in cam.eye]
+    c.target[:] = [float(v) for v in cam.target]
+    c.up[:] = [float(v) for v in cam.up]
+    c.fovy_deg = float(cam.fovy_deg)
+    c.znear = float(cam.znear)
+    c.zfar = float(cam.zfar)
+    return c
+
+
+def points_struct(points) -> _lib.Points:
+    x, y, z = points
+    return _lib.Points(_ptr(x), _ptr(y), _ptr(z))
+
+
+def attrs_struct(attrs: Sequence) -> _lib.Attrs:
+    a = _lib.Attrs()
+    a.count = len(attrs)
+    if a.count > _lib.MAX_ATTRS:
+        raise ValueError("at most 8 attribute streams")
+    for k, t in enumerate(attrs):
+        if t.dim() != 1:
+            raise ValueError("attribute streams are 1-D tensors (strided views allowed)")
+        a.a[k].data = t.data_ptr()
+        a.a[k].dtype = _dtype_code(t)
+        a.a[k].stride_bytes = t.stride(0) * t.element_size()
+    return a
+
+
+@dataclass
+class GBuffer:
+    """Caller-owned output planes (torch tensors on the device)."""
+    keys: object                  # int64 [H*W], bit pattern of the uint64 keys
+    depth: object = None          # float32 [H*W]
+    attr: object = None           # float32 [C][H*W]
+    rgb: object = None            # float32 [3][H*W]
+    vel2d: object = None          # float32 [4][H*W]
+    lut: object = None            # float32 [256][3]
+    lut_attr: int = -1
+    lut_min: float = 0.0
+    lut_inv_range: float = 1.0
+    vel_attr: int = -1
+
+    @staticmethod
+    def allocate(W: int, H: int, nattr: int = 0, depth=True, rgb=False, vel2d=False, device="cuda"):
+        import torch
+        npx = W * H
+        e = lambda *s: torch.empty(*s, device=device, dtype=torch.float32)
+        return GBuffer(keys=torch.empty(npx, device=device, dtype=torch.int64),
+                       depth=e(npx) if depth else None,
+                       attr=e(nattr, npx) if nattr else None,
+                       rgb=e(3, npx) if rgb else None,
+                       vel2d=e(4, npx) if vel2d else None)
+
+    def struct(self) -> _lib.GBuffer:
+        return _lib.GBuffer(_ptr(self.keys), _ptr(self.depth), _ptr(self.attr), _ptr(self.rgb), _ptr(self.vel2d),
+                            _ptr(self.lut), int(self.lut_attr), float(self.lut_min), float(self.lut_inv_range),
+                            int(self.vel_attr))
+
+
+def narvis_status_string(status: int) -> str:
+    return _lib.load().narvis_status_string(status).decode()
+
+
+def narvis_camera_matrix(camera, W: int, H: int):
+    """(float32[16] row-major clip matrix, near_f, far_f) composed on the host."""
+    L = _lib.load()
+    vp = (ctypes.c_float * 16)()
+    nf, ff = ctypes.c_float(), ctypes.c_float()
+    c = camera_struct(camera)
+    _lib.check(L.narvis_camera_matrix(ctypes.byref(c), W, H, vp, ctypes.byref(nf), ctypes.byref(ff)),
+               "narvis_camera_matrix")
+    return np.frombuffer(vp, dtype=np.float32).copy(), np.float32(nf.value), np.float32(ff.value)
+
+
+def _vp(vp) -> ctypes.Array:
+    arr = np.ascontiguousarray(vp, dtype=np.float32).reshape(16)
+    return (ctypes.c_float * 16)(*arr.tolist())
+
+
+def narvis_raster_clear(keys, W: int, H: int, stream=None) -> None:
+    _lib.check(_lib.load().narvis_raster_clear(_ptr(keys), W, H, _stream_ptr(stream)), "narvis_raster_clear")
+
+
+def narvis_raster_render(points, n: int, vp, near_f, far_f, W: int, H: int, keys, variant: int = RENDER_AUTO,
+                         grid_blocks: int = 0, stream=None) -> None:
+    p = points_struct(points)
+    o = _lib.RasterOpts(int(variant), int(grid_blocks))
+    _lib.check(_lib.load().narvis_raster_render(ctypes.byref(p), int(n), _vp(vp), float(near_f), float(far_f), W, H,
+                                                _ptr(keys), ctypes.byref(o), _stream_ptr(stream)),
+               "narvis_raster_render")
+
+
+def narvis_raster_resolve(points, attrs, n: int, vp, W: int, H: int, gbuf: GBuffer, stream=None) -> None:
+    p = points_struct(points) if points is not None else _lib.Points()
+    a = attrs_struct(attrs or [])
+    g = gbuf.struct()
+    _lib.check(_lib.load().narvis_raster_resolve(ctypes.byref(p), ctypes.byref(a), int(n), _vp(vp), W, H,
+                                                 ctypes.byref(g), _stream_ptr(stream)), "narvis_raster_resolve")
+
+
+def narvis_rasterize(points, attrs, n: int, camera, W: int, H: int, gbuf: GBuffer, stream=None) -> None:
+    p = points_struct(points)
+    a = attrs_struct(attrs or [])
+    c = camera_struct(camera)
+    g = gbuf.struct()
+    _lib.check(_lib.load().narvis_rasterize(ctypes.byref(p), ctypes.byref(a), int(n), ctypes.byref(c), W, H,
+                                            ctypes.byref(g), _stream_ptr(stream)), "narvis_rasterize")

@@ -1,0 +1,132 @@
+"""The C-ABI library loads, exports every symbol its header declares, and its
+host-side logic (camera composition, argument validation) behaves as
+documented.  Nothing here launches a kernel."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import camera as ocam
+from paper_2407_19097_amd import _lib, narvis, scenes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(narvis_[a-z0-9_]+)\s*\(", text))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.load()
+    decl = declared_functions()
+    assert "narvis_rasterize" in decl and "narvis_raster_render" in decl
+    for name in sorted(decl):
+        assert hasattr(L, name), name
+        assert name in _lib.SIGNATURES, name
+
+
+def test_status_strings():
+    for code in (0, -1, -2, -3, -4, -5):
+        assert narvis.narvis_status_string(code)
+    assert narvis.narvis_status_string(-99) == "unknown status"
+
+
+CAMS = [scenes.Camera(eye=(2, 2, 2), target=(0, 0, 0)),
+        scenes.Camera(eye=(0.5 + 1.5, 0.5, 0.95), target=(0.5, 0.5, 0.2)),
+        scenes.Camera(eye=(-0.5, -0.8, 0.9), target=(0.0, 0.5, 0.25)),
+        scenes.Camera(eye=(0.5, -0.3, 0.6), target=(0.5, 0.5, 0.0)),
+        scenes.Camera(eye=(0, 0, 0), target=(0, 0, -1), up=(0, 1, 0), fovy_deg=90.0),
+        scenes.Camera(eye=(-1.0, 2.5, 0.7), target=(0.5, 0.3, 0.6), up=(0.4, -0.3, 1.0), fovy_deg=45.0,
+                      znear=0.01, zfar=100.0)]
+
+
+@pytest.mark.parametrize("cam", CAMS)
+@pytest.mark.parametrize("size", [(512, 512), (1920, 1080), (3840, 2160), (37, 5)])
+def test_camera_matrix_matches_oracle_composition(cam, size):
+    W, H = size
+    vp, nf, ff = narvis.narvis_camera_matrix(cam, W, H)
+    M, near, far = ocam.clip_matrix(cam, W, H)
+    # rows 0, 1 and 3 feed the rasterizer and must agree bit for bit
+    for r in (0, 1, 3):
+        np.testing.assert_array_equal(vp[4 * r:4 * r + 4].view(np.uint32), M[4 * r:4 * r + 4].view(np.uint32))
+    np.testing.assert_allclose(vp[8:12], M[8:12], rtol=2e-7, atol=0)
+    assert nf == near and ff == far
+
+
+def test_camera_matrix_rejects_degenerate():
+    L = _lib.load()
+    vp = (ctypes.c_float * 16)()
+    nf, ff = ctypes.c_float(), ctypes.c_float()
+    bad = [scenes.Camera(eye=(1, 1, 1), target=(1, 1, 1)),
+           scenes.Camera(eye=(0, 0, 0), target=(0, 0, 3)),
+           scenes.Camera(eye=(0, 0, 0), target=(1, 0, 0), fovy_deg=0.0),
+           scenes.Camera(eye=(0, 0, 0), target=(1, 0, 0), fovy_deg=180.0),
+           scenes.Camera(eye=(0, 0, 0), target=(1, 0, 0), znear=1.0, zfar=1.0),
+           scenes.Camera(eye=(0, 0, 0), target=(1, 0, 0), znear=-1.0),
+           scenes.Camera(eye=(np.nan, 0, 0), target=(1, 0, 0))]
+    for cam in bad:
+        c = narvis.camera_struct(cam)
+        assert L.narvis_camera_matrix(ctypes.byref(c), 64, 64, vp, ctypes.byref(nf), ctypes.byref(ff)) == -1
+    c = narvis.camera_struct(CAMS[0])
+    assert L.narvis_camera_matrix(ctypes.byref(c), 0, 64, vp, None, None) == -1
+    assert L.narvis_camera_matrix(None, 64, 64, vp, None, None) == -1
+
+
+def test_invalid_arguments_rejected_before_any_launch():
+    """Each call below fails host-side validation and returns INVALID_ARG
+    without touching a device."""
+    L = _lib.load()
+    vp = (ctypes.c_float * 16)(*np.eye(4, dtype=np.float32).reshape(-1).tolist())
+    fake = 0x10000  # never dereferenced: validation fails first
+    pts = _lib.Points(fake, fake, fake)
+    assert L.narvis_raster_clear(None, 8, 8, None) == -1
+    assert L.narvis_raster_clear(fake, 0, 8, None) == -1
+    assert L.narvis_raster_clear(fake, 1 << 16, 1 << 16, None) == -1
+    assert L.narvis_raster_clear(fake + 4, 8, 8, None) == -1            # misaligned keys
+    assert L.narvis_raster_render(ctypes.byref(pts), 10, vp, 0.1, 10.0, 8, 8, None, None, None) == -1
+    assert L.narvis_raster_render(None, 10, vp, 0.1, 10.0, 8, 8, fake, None, None) == -1
+    assert L.narvis_raster_render(ctypes.byref(pts), (1 << 32) + 1, vp, 0.1, 10.0, 8, 8, fake, None, None) == -1
+    assert L.narvis_raster_render(ctypes.byref(pts), 10, vp, 0.0, 10.0, 8, 8, fake, None, None) == -1
+    assert L.narvis_raster_render(ctypes.byref(pts), 10, vp, 1.0, 0.5, 8, 8, fake, None, None) == -1
+    bad_opts = _lib.RasterOpts(7, 0)
+    assert L.narvis_raster_render(ctypes.byref(pts), 10, vp, 0.1, 10.0, 8, 8, fake, ctypes.byref(bad_opts),
+                                  None) == -1
+    nan_vp = (ctypes.c_float * 16)(*([float("nan")] * 16))
+    assert L.narvis_raster_render(ctypes.byref(pts), 10, nan_vp, 0.1, 10.0, 8, 8, fake, None, None) == -1
+    mis = _lib.Points(fake + 2, fake, fake)
+    assert L.narvis_raster_render(ctypes.byref(mis), 10, vp, 0.1, 10.0, 8, 8, fake, None, None) == -1
+    # resolve: too many attributes, bad dtype, stride smaller than the element, lut missing
+    g = _lib.GBuffer(fake, 0, fake, 0, 0, 0, 0, 0.0, 1.0, 0)
+    a = _lib.Attrs()
+    a.count = 9
+    assert L.narvis_raster_resolve(ctypes.byref(pts), ctypes.byref(a), 10, vp, 8, 8, ctypes.byref(g), None) == -1
+    a.count = 1
+    a.a[0] = _lib.Attr(fake, 9, 4)
+    assert L.narvis_raster_resolve(ctypes.byref(pts), ctypes.byref(a), 10, vp, 8, 8, ctypes.byref(g), None) == -1
+    a.a[0] = _lib.Attr(fake, 3, 2)
+    assert L.narvis_raster_resolve(ctypes.byref(pts), ctypes.byref(a), 10, vp, 8, 8, ctypes.byref(g), None) == -1
+    a.a[0] = _lib.Attr(fake, 3, 4)
+    g_rgb = _lib.GBuffer(fake, 0, 0, fake, 0, 0, 0, 0.0, 1.0, -1)
+    assert L.narvis_raster_resolve(ctypes.byref(pts), ctypes.byref(a), 10, vp, 8, 8, ctypes.byref(g_rgb),
+                                   None) == -1
+    g_vel = _lib.GBuffer(fake, 0, 0, 0, fake, 0, 0, 0.0, 1.0, 0)
+    assert L.narvis_raster_resolve(ctypes.byref(pts), ctypes.byref(a), 10, vp, 8, 8, ctypes.byref(g_vel),
+                                   None) == -1
+    cam = narvis.camera_struct(scenes.Camera(eye=(1, 1, 1), target=(1, 1, 1)))
+    assert L.narvis_rasterize(ctypes.byref(pts), ctypes.byref(a), 10, ctypes.byref(cam), 8, 8, ctypes.byref(g),
+                              None) == -1
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "absent.so"))
+    with pytest.raises(ImportError):
+        _lib.load()

@@ -1,0 +1,224 @@
+"""GPU render/resolve vs the CPU oracle, element by element (bit-exact on keys,
+depth and every G-buffer plane except theta, which is within 4 ulp).
+
+Each test prints the case it runs before touching the GPU."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import camera as ocam
+from oracle import raster as orast
+from paper_2407_19097_amd import narvis, scenes
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+EMPTY = np.uint64(0xFFFFFFFFFFFFFFFF)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def announce(msg):
+    print(f"\n[case] {msg}", flush=True)
+
+
+def ulp_diff(a, b):
+    """ulps between two float32 arrays (sign-magnitude aware)."""
+    ia = a.view(np.int32).astype(np.int64)
+    ib = b.view(np.int32).astype(np.int64)
+    ia = np.where(ia < 0, -(ia & 0x7FFFFFFF), ia)
+    ib = np.where(ib < 0, -(ib & 0x7FFFFFFF), ib)
+    return np.abs(ia - ib)
+
+
+def gpu_frame(x, y, z, attrs, cam, W, H, lut=None, lut_attr=-1, lut_min=0.0, lut_inv=1.0, vel_attr=-1,
+              variant=0, grid_blocks=0, xyz_dev=None, attrs_dev=None):
+    """Clear + render + resolve through the C ABI; returns numpy planes."""
+    n = int(x.shape[0])
+    vp, nf, ff = narvis.narvis_camera_matrix(cam, W, H)
+    X, Y, Z = xyz_dev if xyz_dev is not None else (dev(x), dev(y), dev(z))
+    A = attrs_dev if attrs_dev is not None else [dev(a) for a in attrs]
+    g = narvis.GBuffer.allocate(W, H, nattr=len(A), depth=True, rgb=lut is not None, vel2d=vel_attr >= 0)
+    if lut is not None:
+        g.lut = dev(lut)
+        g.lut_attr, g.lut_min, g.lut_inv_range = lut_attr, lut_min, lut_inv
+    g.vel_attr = vel_attr
+    narvis.narvis_raster_clear(g.keys, W, H)
+    narvis.narvis_raster_render((X, Y, Z), n, vp, nf, ff, W, H, g.keys, variant=variant, grid_blocks=grid_blocks)
+    narvis.narvis_raster_resolve((X, Y, Z), A, n, vp, W, H, g)
+    out = {"keys": host(g.keys).view(np.uint64), "depth": host(g.depth)}
+    if g.attr is not None:
+        out["attrs"] = host(g.attr)
+    if g.rgb is not None:
+        out["rgb"] = host(g.rgb)
+    if g.vel2d is not None:
+        out["vel2d"] = host(g.vel2d)
+    return out
+
+
+def oracle_frame(x, y, z, attrs, cam, W, H, lut=None, lut_attr=-1, lut_min=0.0, lut_inv=1.0, vel_attr=-1):
+    M, near, far = ocam.clip_matrix(cam, W, H)
+    keys = orast.render(x, y, z, M, near, far, W, H)
+    out = orast.resolve(keys, W, H, x, y, z, M, attrs, lut=lut, lut_attr=lut_attr, lut_min=lut_min,
+                        lut_inv_range=lut_inv, vel_attr=vel_attr)
+    out["keys"] = keys
+    return out
+
+
+def assert_same(g, o, theta_ulps=4):
+    np.testing.assert_array_equal(g["keys"], o["keys"])
+    np.testing.assert_array_equal(g["depth"].view(np.uint32), o["depth"].view(np.uint32))
+    if "attrs" in o:
+        np.testing.assert_array_equal(g["attrs"].view(np.uint32), o["attrs"].view(np.uint32))
+    if "rgb" in o:
+        np.testing.assert_array_equal(g["rgb"].view(np.uint32), o["rgb"].view(np.uint32))
+    if "vel2d" in o:
+        for c in (0, 1, 3):
+            np.testing.assert_array_equal(g["vel2d"][c].view(np.uint32), o["vel2d"][c].view(np.uint32))
+        d = ulp_diff(g["vel2d"][2], o["vel2d"][2])
+        assert int(d.max(initial=0)) <= theta_ulps, f"theta differs by {int(d.max())} ulp"
+
+
+def scene_args(sc):
+    inv = 1.0 / (sc.lut_max - sc.lut_min) if sc.lut_attr >= 0 else 1.0
+    return dict(lut=scenes.colour_lut() if sc.lut_attr >= 0 else None, lut_attr=sc.lut_attr,
+                lut_min=sc.lut_min, lut_inv=np.float32(inv), vel_attr=sc.vel_attr)
+
+
+def test_unit_cube_full_parity():
+    announce("unit cube 1M points 512x512, all planes")
+    sc = scenes.unit_cube()
+    kw = scene_args(sc)
+    g = gpu_frame(sc.x, sc.y, sc.z, sc.attrs, sc.cameras[0], sc.W, sc.H, **kw)
+    o = oracle_frame(sc.x, sc.y, sc.z, sc.attrs, sc.cameras[0], sc.W, sc.H, **kw)
+    assert (o["keys"] != EMPTY).sum() > 0.5 * sc.W * sc.H
+    assert_same(g, o)
+
+
+@pytest.mark.parametrize("n", [0, 1, 3, 4, 5, 1023, 4097, 65537, 300001])
+def test_ragged_sizes(n):
+    announce(f"ragged n={n} 97x61")
+    sc = scenes.unit_cube(n=max(n, 1), seed=n + 1, W=97, H=61)
+    x, y, z = sc.x[:n], sc.y[:n], sc.z[:n]
+    attrs = [a[:n] for a in sc.attrs]
+    kw = scene_args(sc)
+    cam = scenes.Camera(eye=(1.6, 1.4, 1.2), target=(0.5, 0.5, 0.5), up=(0.2, 0.1, 1.0))
+    g = gpu_frame(x, y, z, attrs, cam, sc.W, sc.H, **kw)
+    o = oracle_frame(x, y, z, attrs, cam, sc.W, sc.H, **kw)
+    assert_same(g, o)
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("grid", [0, 1, 7, 8, 100])
+def test_variants_and_launch_geometry(variant, grid):
+    announce(f"variant={variant} grid_blocks={grid}")
+    sc = scenes.unit_cube(n=200003, seed=9, W=160, H=90)
+    cam = scenes.Camera(eye=(1.8, 1.5, 1.3), target=(0.5, 0.5, 0.5))
+    g = gpu_frame(sc.x, sc.y, sc.z, sc.attrs, cam, sc.W, sc.H, variant=variant, grid_blocks=grid)
+    o = oracle_frame(sc.x, sc.y, sc.z, sc.attrs, cam, sc.W, sc.H)
+    assert_same(g, o)
+
+
+def test_unaligned_points_take_scalar_path():
+    announce("unaligned point arrays (offset by one element)")
+    sc = scenes.unit_cube(n=100001, seed=4, W=64, H=64)
+    cam = sc.cameras[0]
+    X, Y, Z = dev(sc.x), dev(sc.y), dev(sc.z)
+    x1, y1, z1 = X[1:], Y[1:], Z[1:]
+    g = gpu_frame(sc.x[1:], sc.y[1:], sc.z[1:], [], cam, 64, 64, xyz_dev=(x1, y1, z1), attrs_dev=[])
+    o = oracle_frame(sc.x[1:], sc.y[1:], sc.z[1:], [], cam, 64, 64)
+    assert_same(g, o)
+
+
+def test_adversarial_points():
+    announce("adversarial: ties, borders, non-finite, behind camera, near/far")
+    W, H = 40, 30
+    cam = scenes.Camera(eye=(0, 0, 0), target=(0, 0, -1), up=(0, 1, 0), fovy_deg=70.0)
+    M, near, far = ocam.clip_matrix(cam, W, H)
+    m0, m1 = float(M[0]), float(M[5])
+    pts = [(0, 0, -1), (0, 0, -1), (0.01, 0.01, -2), (0.01, 0.01, -2),  # exact ties
+           (1.0, 0, -m0), (-1.0, 0, -m0), (0, 1.0, -m1), (0, -1.0, -m1),  # borders
+           (np.nan, 0, -1), (0, np.inf, -1), (0, 0, np.nan), (0, 0, -np.inf), (0, 0, 1), (0, 0, 0),
+           (0, 0, -float(near)), (0, 0, -float(np.nextafter(near, np.float32(0)))),
+           (0, 0, -float(far)), (0.3, 0.2, -float(np.nextafter(far, np.float32(np.inf))))]
+    rng = np.random.default_rng(1)
+    extra = (rng.random((5000, 3)) * np.array([2, 2, -3]) - np.array([1, 1, 0.1])).tolist()
+    pts = np.array(pts + extra + [(0, 0, -1)] * 100, np.float32)
+    x, y, z = (np.ascontiguousarray(pts[:, k]) for k in range(3))
+    a = [np.arange(len(x), dtype=np.float32)]
+    g = gpu_frame(x, y, z, a, cam, W, H)
+    o = oracle_frame(x, y, z, a, cam, W, H)
+    assert_same(g, o)
+
+
+def test_all_points_in_one_pixel():
+    announce("all points in one pixel, 1M points, descending depth")
+    n = 1 << 20
+    W, H = 16, 16
+    cam = scenes.Camera(eye=(0, 0, 0), target=(0, 0, -1), up=(0, 1, 0))
+    z = -np.linspace(5.0, 1.0, n, dtype=np.float32)  # later points closer: worst case for early-z
+    x = np.full(n, 0.001, np.float32)
+    y = np.full(n, 0.001, np.float32)
+    g = gpu_frame(x, y, z, [], cam, W, H)
+    o = oracle_frame(x, y, z, [], cam, W, H)
+    assert_same(g, o)
+
+
+def test_attribute_formats_and_strides():
+    announce("u8/u16/f16/f32 attributes, AoS strides, NaN halves")
+    sc = scenes.unit_cube(n=120000, seed=6, W=128, H=96)
+    n = sc.n
+    rng = np.random.default_rng(2)
+    rgba = rng.integers(0, 256, size=(n, 4), dtype=np.uint8)
+    u16 = rng.integers(0, 65536, size=n, dtype=np.uint16)
+    halfs = rng.standard_normal(n).astype(np.float16)
+    halfs[::97] = np.float16(np.nan)
+    halfs[1::97] = np.array([0x7C01], np.uint16).view(np.float16)[0]  # signalling NaN
+    halfs[2::97] = np.float16(6e-8)  # subnormal
+    halfs[3::97] = -np.float16(np.inf)
+    pair = rng.standard_normal((n, 2)).astype(np.float32)
+    RGBA = dev(rgba)
+    PAIR = dev(pair)
+    attrs_dev = [RGBA[:, 0], RGBA[:, 3], dev(u16), dev(halfs), PAIR[:, 1], dev(sc.attrs[3])]
+    attrs_host = [rgba[:, 0], rgba[:, 3], u16, halfs, pair[:, 1], sc.attrs[3]]
+    cam = scenes.Camera(eye=(1.7, 1.2, 1.5), target=(0.5, 0.5, 0.5))
+    kw = dict(lut=scenes.colour_lut(), lut_attr=3, lut_min=-2.0, lut_inv=np.float32(0.25))
+    g = gpu_frame(sc.x, sc.y, sc.z, attrs_host, cam, sc.W, sc.H, attrs_dev=attrs_dev, **kw)
+    o = oracle_frame(sc.x, sc.y, sc.z, attrs_host, cam, sc.W, sc.H, **kw)
+    assert_same(g, o)
+
+
+def test_eight_attributes_and_velocity_planes():
+    announce("eight attributes, Vel2D from a tilted camera")
+    sc = scenes.unit_cube(n=250000, seed=8, W=200, H=150)
+    attrs = list(sc.attrs) + [a * np.float32(k + 2) for k, a in enumerate(sc.attrs)]
+    cam = scenes.Camera(eye=(2.0, 1.8, 1.6), target=(0.5, 0.5, 0.5), up=(0.3, -0.4, 1.0))
+    kw = dict(lut=scenes.colour_lut(), lut_attr=7, lut_min=0.0, lut_inv=np.float32(0.1), vel_attr=4)
+    g = gpu_frame(sc.x, sc.y, sc.z, attrs, cam, sc.W, sc.H, **kw)
+    o = oracle_frame(sc.x, sc.y, sc.z, attrs, cam, sc.W, sc.H, **kw)
+    assert_same(g, o)
+
+
+def test_rasterize_whole_frame_entry_point():
+    announce("narvis_rasterize (camera -> clear -> render -> resolve)")
+    sc = scenes.unit_cube(n=300000, seed=12, W=256, H=192)
+    kw = scene_args(sc)
+    X, Y, Z = dev(sc.x), dev(sc.y), dev(sc.z)
+    A = [dev(a) for a in sc.attrs]
+    g = narvis.GBuffer.allocate(sc.W, sc.H, nattr=4, rgb=True, vel2d=True)
+    g.lut = dev(kw["lut"])
+    g.lut_attr, g.lut_min, g.lut_inv_range, g.vel_attr = 3, 0.0, float(kw["lut_inv"]), 0
+    g.keys.fill_(12345)  # stale contents must be cleared by the call
+    narvis.narvis_rasterize((X, Y, Z), A, sc.n, sc.cameras[0], sc.W, sc.H, g)
+    got = {"keys": host(g.keys).view(np.uint64), "depth": host(g.depth), "attrs": host(g.attr),
+           "rgb": host(g.rgb), "vel2d": host(g.vel2d)}
+    o = oracle_frame(sc.x, sc.y, sc.z, sc.attrs, sc.cameras[0], sc.W, sc.H, **kw)
+    assert_same(got, o)
