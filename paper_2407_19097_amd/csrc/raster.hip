@@ -272,7 +272,7 @@ hipError_t launch_render(const float *x, const float *y, const float *z, uint64_
                        reinterpret_cast<uintptr_t>(z)) & 15u) == 0;
     const uint64_t per_block = vec ? (uint64_t)kBlock * kQuadsPerThread * 4 : (uint64_t)kBlock;
     uint64_t blocks = grid_blocks > 0 ? (uint64_t)grid_blocks : (n + per_block - 1) / per_block;
-    if (blocks > (1u << 30)) blocks = 1u << 30;
+    if (blocks > (1u << 22)) blocks = 1u << 22;  // grid-stride covers the rest
     // a multiple of the XCD count keeps the block renumbering a bijection
     blocks = (blocks + xcds - 1) / xcds * xcds;
     auto *k = reinterpret_cast<unsigned long long *>(keys);
