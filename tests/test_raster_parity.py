@@ -99,7 +99,7 @@ def test_unit_cube_full_parity():
     kw = scene_args(sc)
     g = gpu_frame(sc.x, sc.y, sc.z, sc.attrs, sc.cameras[0], sc.W, sc.H, **kw)
     o = oracle_frame(sc.x, sc.y, sc.z, sc.attrs, sc.cameras[0], sc.W, sc.H, **kw)
-    assert (o["keys"] != EMPTY).sum() > 0.5 * sc.W * sc.H
+    assert (o["keys"] != EMPTY).sum() > 0.15 * sc.W * sc.H
     assert_same(g, o)
 
 
