@@ -67,23 +67,35 @@ __device__ __forceinline__ void merge(unsigned long long *keys, uint32_t pix, fl
     __hip_atomic_fetch_min(keys + pix, key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Workgroups are handed to the XCDs round-robin.  Renumber them so that XCD k
-// works through one contiguous stretch of the point stream: neighbouring
-// points of a coherent cloud then hit the key lines cached in the same L2.
-__device__ __forceinline__ uint32_t logical_block(uint32_t xcds)
+// Chunk order.  Workgroups are handed to the XCDs round-robin, so blocks
+// b = k, k + X, k + 2X, ... run on XCD k (X = xcds).  XCD k is given one
+// contiguous stretch of chunks, which keeps the key lines that a coherent
+// cloud touches inside that XCD's L2; within its stretch the XCD visits the
+// chunks in a low-discrepancy order (index * stride mod per, stride coprime
+// with per and near per / golden ratio), so that early in the frame the
+// points already cover the whole image and the early depth test rejects most
+// later points instead of letting them reach the atomic.
+struct ChunkOrder {
+    uint32_t xcds;
+    uint32_t per;     // logical blocks per XCD (grid = xcds * per)
+    uint32_t stride;  // coprime with per
+};
+
+__device__ __forceinline__ uint64_t logical_block(const ChunkOrder &o)
 {
     const uint32_t b = blockIdx.x;
-    const uint32_t per = gridDim.x / xcds;
-    return (b % xcds) * per + b / xcds;
+    const uint32_t k = b % o.xcds;
+    const uint64_t j = b / o.xcds;
+    return (uint64_t)k * o.per + (j * o.stride) % o.per;
 }
 
 template <int VARIANT>
 __global__ __launch_bounds__(kBlock) void k_render_vec(const float *__restrict__ X, const float *__restrict__ Y,
                                                         const float *__restrict__ Z, uint64_t n, Proj P,
-                                                        unsigned long long *__restrict__ keys, uint32_t xcds)
+                                                        unsigned long long *__restrict__ keys, ChunkOrder order)
 {
     const uint64_t nq = n >> 2;
-    const uint64_t lb = logical_block(xcds);
+    const uint64_t lb = logical_block(order);
     const uint64_t stride = (uint64_t)gridDim.x * kBlock * kQuadsPerThread;
     for (uint64_t base = lb * kBlock * kQuadsPerThread + threadIdx.x; base < nq; base += stride) {
         f32x4 xs[kQuadsPerThread], ys[kQuadsPerThread], zs[kQuadsPerThread];
@@ -124,10 +136,10 @@ __global__ __launch_bounds__(kBlock) void k_render_vec(const float *__restrict__
 template <int VARIANT>
 __global__ __launch_bounds__(kBlock) void k_render_scalar(const float *__restrict__ X, const float *__restrict__ Y,
                                                            const float *__restrict__ Z, uint64_t n, Proj P,
-                                                           unsigned long long *__restrict__ keys, uint32_t xcds)
+                                                           unsigned long long *__restrict__ keys, ChunkOrder order)
 {
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t i = (uint64_t)logical_block(xcds) * kBlock + threadIdx.x; i < n; i += stride) {
+    for (uint64_t i = logical_block(order) * kBlock + threadIdx.x; i < n; i += stride) {
         uint32_t pix;
         float w;
         if (project(P, X[i], Y[i], Z[i], pix, w)) merge<VARIANT>(keys, pix, w, (uint32_t)i);
@@ -262,6 +274,30 @@ hipError_t launch_clear(uint64_t *keys, int64_t npx, hipStream_t s)
     return hipGetLastError();
 }
 
+namespace {
+
+uint32_t gcd_u32(uint32_t a, uint32_t b)
+{
+    while (b) {
+        const uint32_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+// The integer nearest per / golden ratio that is coprime with per.
+uint32_t coprime_stride(uint32_t per)
+{
+    if (per <= 2) return 1;
+    uint32_t s = (uint32_t)((double)per * 0.6180339887498949 + 0.5);
+    if (s < 1) s = 1;
+    while (gcd_u32(s, per) != 1) ++s;
+    return s % per ? s % per : 1;
+}
+
+}  // namespace
+
 hipError_t launch_render(const float *x, const float *y, const float *z, uint64_t n, const Proj &P,
                          uint64_t *keys, int32_t variant, int32_t grid_blocks, hipStream_t s)
 {
@@ -275,22 +311,26 @@ hipError_t launch_render(const float *x, const float *y, const float *z, uint64_
     if (blocks > (1u << 22)) blocks = 1u << 22;  // grid-stride covers the rest
     // a multiple of the XCD count keeps the block renumbering a bijection
     blocks = (blocks + xcds - 1) / xcds * xcds;
+    ChunkOrder order;
+    order.xcds = xcds;
+    order.per = (uint32_t)(blocks / xcds);
+    order.stride = coprime_stride(order.per);
     auto *k = reinterpret_cast<unsigned long long *>(keys);
     if (variant == NARVIS_RENDER_AUTO) variant = NARVIS_RENDER_EARLYZ;
     if (vec) {
         if (variant == NARVIS_RENDER_GLOBAL)
             hipLaunchKernelGGL(k_render_vec<NARVIS_RENDER_GLOBAL>, dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                               x, y, z, n, P, k, xcds);
+                               x, y, z, n, P, k, order);
         else
             hipLaunchKernelGGL(k_render_vec<NARVIS_RENDER_EARLYZ>, dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                               x, y, z, n, P, k, xcds);
+                               x, y, z, n, P, k, order);
     } else {
         if (variant == NARVIS_RENDER_GLOBAL)
             hipLaunchKernelGGL(k_render_scalar<NARVIS_RENDER_GLOBAL>, dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                               x, y, z, n, P, k, xcds);
+                               x, y, z, n, P, k, order);
         else
             hipLaunchKernelGGL(k_render_scalar<NARVIS_RENDER_EARLYZ>, dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                               x, y, z, n, P, k, xcds);
+                               x, y, z, n, P, k, order);
     }
     return hipGetLastError();
 }
