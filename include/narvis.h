@@ -117,7 +117,10 @@ typedef struct {
 typedef enum {
     NARVIS_RENDER_AUTO = 0,    /* library's choice for the device            */
     NARVIS_RENDER_GLOBAL = 1,  /* atomic min per surviving point, no z-test  */
-    NARVIS_RENDER_EARLYZ = 2   /* read the key first, atomic only if closer  */
+    NARVIS_RENDER_EARLYZ = 2,  /* read the key first, atomic only if closer  */
+    NARVIS_RENDER_LDS = 3      /* fold each workgroup's candidates per pixel
+                                  in LDS first, then early-z + atomic once per
+                                  touched pixel (scalar path: as EARLYZ)     */
 } narvis_render_variant;
 
 typedef struct {
@@ -125,6 +128,24 @@ typedef struct {
     int32_t grid_blocks;  /* 0 = automatic, otherwise the number of
                              workgroups (a grid-stride loop covers all points) */
 } narvis_raster_opts;
+
+/* Colour of a point in the splat renderer. */
+typedef enum {
+    NARVIS_COLOR_LUT = 0,   /* lut[q] of attribute color_attr, binned like the
+                               G-buffer rgb plane                              */
+    NARVIS_COLOR_RGB8 = 1   /* attributes color_attr..color_attr+2 (uint8) / 255 */
+} narvis_color_mode;
+
+/* Parameters of the Gaussian splat renderer. */
+typedef struct {
+    float sigma_px;         /* standard deviation in pixels, (0, 32]          */
+    float opacity;          /* peak opacity, (0, 1]                            */
+    int32_t color_mode;     /* narvis_color_mode                               */
+    int32_t color_attr;     /* attribute index (first of three for RGB8)       */
+    const float *lut;       /* device float[256][3] for NARVIS_COLOR_LUT       */
+    float lut_min;
+    float lut_inv_range;
+} narvis_splat_params;
 
 /* Human-readable name of a status code (static storage). */
 const char *narvis_status_string(narvis_status s);
@@ -169,6 +190,33 @@ narvis_status narvis_raster_resolve(const narvis_points *pts, const narvis_attrs
 narvis_status narvis_rasterize(const narvis_points *pts, const narvis_attrs *attrs, uint64_t n,
                                const narvis_camera *cam, int32_t W, int32_t H,
                                narvis_gbuffer *gbuf, void *stream);
+
+/* Bytes of device workspace narvis_splat needs for n points at W x H
+ * (0 if the arguments are invalid).  The size grows linearly with n: point
+ * records, tile counts, two ping-pong copies of the (key, index) pairs (at
+ * most four tiles per point for sigma <= 1.5 px, more for wider splats), the
+ * radix histograms and the per-tile ranges. */
+size_t narvis_splat_workspace_size(uint64_t n, int32_t W, int32_t H, const narvis_splat_params *p);
+
+/* Gaussian splat renderer, the target the post-process network learns to
+ * reproduce (Sec. 4.2: the forward pass of 3D Gaussian splatting over the
+ * points, depth-sorted alpha blending).  Every point that survives the
+ * rasterizer's cull becomes an isotropic screen-space Gaussian of standard
+ * deviation sigma_px centred on (sx, sy).  Pixel (px, py) samples it at its
+ * centre: d2 = ((px + 0.5) - sx)^2 + ((py + 0.5) - sy)^2 (fp32); Gaussians
+ * with d2 > (3 sigma)^2 do not reach the pixel.  The Gaussians reaching a
+ * pixel are composited nearest first, ties by lower index (the rasterizer's
+ * key order): alpha = min(0.99, opacity * exp(-d2 / (2 sigma^2))), skipped
+ * when below 1/255; with T = 1 initially, each contributor gives
+ * T' = T (1 - alpha) and stops the pixel if T' < 1e-4, otherwise adds
+ * colour * alpha * T and sets T = T'.  Background black.
+ * img: float[3][H][W] device, written entirely.  workspace: device memory of
+ * at least narvis_splat_workspace_size bytes, owned by the caller, contents
+ * scratch.  n < 2^30.  INVALID_ARG on bad arguments, WORKSPACE if ws_bytes
+ * is too small. */
+narvis_status narvis_splat(const narvis_points *pts, const narvis_attrs *attrs, uint64_t n,
+                           const narvis_camera *cam, int32_t W, int32_t H, float *img,
+                           const narvis_splat_params *p, void *workspace, size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -29,6 +29,11 @@
  * fp64; the discrete choices that depend only on exact fp32 quantities (cull,
  * footprint) are taken in fp32 exactly as the GPU does.
  *
+ * The optional `fragile` output marks pixels where one of these decisions
+ * (the 1/255 skip, the 1e-4 termination) was taken within a relative 1e-5 of
+ * its threshold: there an fp32 evaluation may legitimately decide the other
+ * way, and a comparison with fp32 code must allow for that.
+ *
  * Colour of a point: mode 0 looks its attribute `lut_attr` up in a 256-entry
  * table (same binning as the rasterizer's colour plane); mode 1 reads three
  * uint8 attributes and divides by 255.
@@ -85,7 +90,7 @@ int oracle_splat(const float *x, const float *y, const float *z, uint64_t n,
                  float sigma, float opacity, int32_t color_mode,
                  const splat_attr *attrs, int32_t nattr,
                  const float *lut, int32_t lut_attr, float lut_min, float lut_inv_range,
-                 double *img)
+                 double *img, unsigned char *fragile)
 {
     (void)nattr;
     const int64_t npx = (int64_t)W * H;
@@ -112,6 +117,7 @@ int oracle_splat(const float *x, const float *y, const float *z, uint64_t n,
     qsort(rec, m, sizeof(splat_rec), cmp_rec);
     for (int64_t p = 0; p < npx; ++p) T[p] = 1.0;
     for (int64_t p = 0; p < 3 * npx; ++p) img[p] = 0.0;
+    if (fragile) memset(fragile, 0, (size_t)npx);
     const float reach = 3.0f * sigma;
     const float cut2 = reach * reach;
     const double inv2s2 = 1.0 / (2.0 * (double)sigma * (double)sigma);
@@ -143,8 +149,10 @@ int oracle_splat(const float *x, const float *y, const float *z, uint64_t n,
                 if (!(d2 <= cut2)) continue;
                 double a = (double)opacity * exp(-(double)d2 * inv2s2);
                 if (a > 0.99) a = 0.99;
+                if (fragile && fabs(a - 1.0 / 255.0) <= 1e-5 / 255.0) fragile[p] = 1;
                 if (a < 1.0 / 255.0) continue;
                 double Tn = T[p] * (1.0 - a);
+                if (fragile && fabs(Tn - 1e-4) <= 1e-9) fragile[p] = 1;
                 if (Tn < 1e-4) { done[p] = 1; continue; }
                 for (int c = 0; c < 3; ++c) img[c * npx + p] += col[c] * a * T[p];
                 T[p] = Tn;

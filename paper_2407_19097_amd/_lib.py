@@ -53,6 +53,12 @@ class RasterOpts(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("grid_blocks", ctypes.c_int32)]
 
 
+class SplatParams(ctypes.Structure):
+    _fields_ = [("sigma_px", ctypes.c_float), ("opacity", ctypes.c_float), ("color_mode", ctypes.c_int32),
+                ("color_attr", ctypes.c_int32), ("lut", ctypes.c_void_p), ("lut_min", ctypes.c_float),
+                ("lut_inv_range", ctypes.c_float)]
+
+
 _P = ctypes.c_void_p
 _F16 = ctypes.c_float * 16
 
@@ -70,6 +76,11 @@ SIGNATURES = {
     "narvis_rasterize": (ctypes.c_int, [ctypes.POINTER(Points), ctypes.POINTER(Attrs), ctypes.c_uint64,
                                         ctypes.POINTER(Camera), ctypes.c_int32, ctypes.c_int32,
                                         ctypes.POINTER(GBuffer), _P]),
+    "narvis_splat_workspace_size": (ctypes.c_size_t, [ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32,
+                                                       ctypes.POINTER(SplatParams)]),
+    "narvis_splat": (ctypes.c_int, [ctypes.POINTER(Points), ctypes.POINTER(Attrs), ctypes.c_uint64,
+                                    ctypes.POINTER(Camera), ctypes.c_int32, ctypes.c_int32, _P,
+                                    ctypes.POINTER(SplatParams), _P, ctypes.c_size_t, _P]),
 }
 
 _lib = None

@@ -128,7 +128,7 @@ extern "C" narvis_status narvis_raster_render(const narvis_points *pts, uint64_t
     if (reinterpret_cast<uintptr_t>(keys) & 7u) return NARVIS_ERR_INVALID_ARG;
     int32_t variant = opts ? opts->variant : NARVIS_RENDER_AUTO;
     int32_t grid = opts ? opts->grid_blocks : 0;
-    if (variant < NARVIS_RENDER_AUTO || variant > NARVIS_RENDER_EARLYZ || grid < 0) return NARVIS_ERR_INVALID_ARG;
+    if (variant < NARVIS_RENDER_AUTO || variant > NARVIS_RENDER_LDS || grid < 0) return NARVIS_ERR_INVALID_ARG;
     if (n > 0 && ((reinterpret_cast<uintptr_t>(pts->x) | reinterpret_cast<uintptr_t>(pts->y) |
                    reinterpret_cast<uintptr_t>(pts->z)) & 3u))
         return NARVIS_ERR_INVALID_ARG;
@@ -190,4 +190,59 @@ extern "C" narvis_status narvis_rasterize(const narvis_points *pts, const narvis
     if (st != NARVIS_OK) return st;
     return from_hip(launch_resolve(n ? pts->x : nullptr, n ? pts->y : nullptr, n ? pts->z : nullptr, n, P, pack,
                                    *gbuf, s));
+}
+
+namespace {
+
+bool splat_params_ok(const narvis_splat_params *p, const AttrPack &pack)
+{
+    if (!p) return false;
+    if (!(p->sigma_px > 0.0f && p->sigma_px <= 32.0f)) return false;
+    if (!(p->opacity > 0.0f && p->opacity <= 1.0f)) return false;
+    if (p->color_mode == NARVIS_COLOR_LUT) {
+        if (!p->lut || p->color_attr < 0 || p->color_attr >= pack.count) return false;
+        if (!std::isfinite(p->lut_min) || !std::isfinite(p->lut_inv_range)) return false;
+    } else if (p->color_mode == NARVIS_COLOR_RGB8) {
+        if (p->color_attr < 0 || p->color_attr + 2 >= pack.count) return false;
+        for (int c = 0; c < 3; ++c)
+            if (pack.a[p->color_attr + c].dtype != NARVIS_U8) return false;
+    } else {
+        return false;
+    }
+    return true;
+}
+
+bool splat_size_ok(uint64_t n, int32_t W, int32_t H, const narvis_splat_params *p)
+{
+    if (!image_ok(W, H) || n >= (uint64_t(1) << 30) || !p || !(p->sigma_px > 0.0f && p->sigma_px <= 32.0f)) return false;
+    const SplatLayout L = splat_layout(n, W, H, p->sigma_px);
+    return L.cap < (uint64_t(1) << 32) && L.nblk < (uint64_t(1) << 31);
+}
+
+}  // namespace
+
+extern "C" size_t narvis_splat_workspace_size(uint64_t n, int32_t W, int32_t H, const narvis_splat_params *p)
+{
+    if (!splat_size_ok(n, W, H, p)) return 0;
+    return (size_t)splat_layout(n, W, H, p->sigma_px).bytes;
+}
+
+extern "C" narvis_status narvis_splat(const narvis_points *pts, const narvis_attrs *attrs, uint64_t n,
+                                      const narvis_camera *cam, int32_t W, int32_t H, float *img,
+                                      const narvis_splat_params *p, void *workspace, size_t ws_bytes, void *stream)
+{
+    float vp[16], near_f = 0.0f, far_f = 0.0f;
+    narvis_status st = narvis_camera_matrix(cam, W, H, vp, &near_f, &far_f);
+    if (st != NARVIS_OK) return st;
+    if (!img || !points_ok(pts, n) || !matrix_ok(vp, near_f, far_f) || !splat_size_ok(n, W, H, p))
+        return NARVIS_ERR_INVALID_ARG;
+    AttrPack pack;
+    if (!pack_attrs(attrs, n, pack) || !splat_params_ok(p, pack)) return NARVIS_ERR_INVALID_ARG;
+    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255u) ||
+        (reinterpret_cast<uintptr_t>(img) & 3u))
+        return NARVIS_ERR_INVALID_ARG;
+    if (ws_bytes < (size_t)splat_layout(n, W, H, p->sigma_px).bytes) return NARVIS_ERR_WORKSPACE;
+    const Proj P = make_proj(vp, near_f, far_f, W, H);
+    return from_hip(launch_splat(n ? pts->x : nullptr, n ? pts->y : nullptr, n ? pts->z : nullptr, n, P, pack, *p, img,
+                                 workspace, static_cast<hipStream_t>(stream)));
 }

@@ -46,4 +46,15 @@ hipError_t launch_render(const float *x, const float *y, const float *z, uint64_
 hipError_t launch_resolve(const float *x, const float *y, const float *z, uint64_t n, const Proj &P,
                           const AttrPack &attrs, const narvis_gbuffer &g, hipStream_t s);
 
+struct SplatLayout {
+    int32_t tiles_x, tiles_y;
+    uint64_t cap, nblk, nsums;
+    uint64_t off_ctr, off_col, off_wbits, off_cnt, off_ka, off_va, off_kb, off_vb, off_hist, off_sums, off_range;
+    uint64_t bytes;
+    int key_bits;
+};
+SplatLayout splat_layout(uint64_t n, int32_t W, int32_t H, float sigma);
+hipError_t launch_splat(const float *x, const float *y, const float *z, uint64_t n, const Proj &P, const AttrPack &A,
+                        const narvis_splat_params &prm, float *img, void *ws, hipStream_t s);
+
 }  // namespace narvis

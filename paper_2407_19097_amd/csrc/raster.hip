@@ -97,6 +97,7 @@ __global__ __launch_bounds__(kBlock) void k_render_vec(const float *__restrict__
     const uint64_t nq = n >> 2;
     const uint64_t lb = logical_block(order);
     const uint64_t stride = (uint64_t)gridDim.x * kBlock * kQuadsPerThread;
+    const uint32_t spread = (uint32_t)((lb * 2654435761ull) % (uint64_t)((uint32_t)P.W * (uint32_t)P.H));
     for (uint64_t base = lb * kBlock * kQuadsPerThread + threadIdx.x; base < nq; base += stride) {
         f32x4 xs[kQuadsPerThread], ys[kQuadsPerThread], zs[kQuadsPerThread];
 #pragma unroll
@@ -108,21 +109,52 @@ __global__ __launch_bounds__(kBlock) void k_render_vec(const float *__restrict__
                 zs[k] = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(Z) + q);
             }
         }
+        // project all points of this thread first, then issue every early-z
+        // read, and only then the atomics: an atomic may alias a later read,
+        // so interleaving them would serialise one memory round trip per point
+        constexpr int kPts = kQuadsPerThread * 4;
+        uint32_t pix[kPts];
+        unsigned long long key[kPts];
+        bool hit[kPts];
 #pragma unroll
         for (int k = 0; k < kQuadsPerThread; ++k) {
             const uint64_t q = base + (uint64_t)k * kBlock;
-            if (q >= nq) continue;
+            const bool live = q < nq;
             const uint32_t i0 = (uint32_t)(q << 2);
             const float px[4] = {xs[k].x, xs[k].y, xs[k].z, xs[k].w};
             const float py[4] = {ys[k].x, ys[k].y, ys[k].z, ys[k].w};
             const float pz[4] = {zs[k].x, zs[k].y, zs[k].z, zs[k].w};
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                uint32_t pix;
-                float w;
-                if (project(P, px[j], py[j], pz[j], pix, w)) merge<VARIANT>(keys, pix, w, i0 + (uint32_t)j);
+                float w = 0.0f;
+                uint32_t pp = 0;
+                hit[k * 4 + j] = live && project(P, px[j], py[j], pz[j], pp, w);
+                pix[k * 4 + j] = pp;
+                key[k * 4 + j] = ((unsigned long long)__float_as_uint(w) << 32) | (i0 + (uint32_t)j);
             }
         }
+        if (VARIANT == NARVIS_RENDER_EARLYZ) {
+            // Branch-free reads: a lane whose point was culled reads the pixel
+            // of the first live lane of its wave (the request merges with that
+            // lane's), or a per-workgroup pixel when the whole wave is culled.
+            // Conditional loads would each end in a wait on the memory counter.
+            uint32_t addr[kPts];
+#pragma unroll
+            for (int t = 0; t < kPts; ++t) {
+                const unsigned long long live = __ballot(hit[t]);
+                const uint32_t lead = live ? (uint32_t)__builtin_ctzll(live) : 0u;
+                const uint32_t lpix = live ? (uint32_t)__builtin_amdgcn_readlane((int)pix[t], (int)lead) : spread;
+                addr[t] = hit[t] ? pix[t] : lpix;
+            }
+            unsigned long long cur[kPts];
+#pragma unroll
+            for (int t = 0; t < kPts; ++t) cur[t] = keys[addr[t]];
+#pragma unroll
+            for (int t = 0; t < kPts; ++t) hit[t] = hit[t] && key[t] < cur[t];
+        }
+#pragma unroll
+        for (int t = 0; t < kPts; ++t)
+            if (hit[t]) __hip_atomic_fetch_min(keys + pix[t], key[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     // the last n % 4 points
     if (blockIdx.x == 0 && threadIdx.x < (n & 3)) {
@@ -130,6 +162,130 @@ __global__ __launch_bounds__(kBlock) void k_render_vec(const float *__restrict__
         uint32_t pix;
         float w;
         if (project(P, X[i], Y[i], Z[i], pix, w)) merge<VARIANT>(keys, pix, w, (uint32_t)i);
+    }
+}
+
+// LDS-binned render.  A workgroup folds the candidates of its chunk of
+// kChunk points per pixel in LDS before touching the global key buffer:
+//   insert -- every surviving point does a non-returning LDS 64-bit atomic
+//             minimum of its key into slot (pixel mod kSlots) and records its
+//             pixel in pixof[local index];
+//   check  -- after a barrier each candidate looks at its slot: the slot's key
+//             names the winning point, whose pixel is pixof[key index - first
+//             index].  If that is another pixel, the candidate lost the slot to
+//             a collision and takes the global early-z path itself;
+//   flush  -- every occupied slot is one pixel's best candidate of the chunk:
+//             early-z read of the global key, global atomic minimum if smaller.
+// Each thread owns slots t, t + kBlock, ..., so a wave flushes 64 consecutive
+// slots, i.e. runs of consecutive pixels of a row: its reads and atomics land
+// on few cache lines (a gather pays per distinct address), and the global
+// work per chunk is per touched pixel, not per point.
+constexpr int kSlots = 2048;
+constexpr int kChunk = kBlock * kQuadsPerThread * 4;
+constexpr int kPts = kQuadsPerThread * 4;
+constexpr int kPer = kSlots / kBlock;
+constexpr uint32_t kNoPixel = 0xFFFFFFFFu;
+
+// early-z reads for up to K candidates, issued together (an inactive lane reads
+// the first active lane's address, so its request merges), then the atomics
+template <int K>
+__device__ __forceinline__ void global_merge(unsigned long long *__restrict__ keys, const uint32_t (&pix)[K],
+                                             const unsigned long long (&key)[K], bool (&hit)[K], uint32_t spread)
+{
+    uint32_t addr[K];
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+        const unsigned long long live = __ballot(hit[t]);
+        const uint32_t lead = live ? (uint32_t)__builtin_ctzll(live) : 0u;
+        const uint32_t lpix = live ? (uint32_t)__builtin_amdgcn_readlane((int)pix[t], (int)lead) : spread;
+        addr[t] = hit[t] ? pix[t] : lpix;
+    }
+    unsigned long long cur[K];
+#pragma unroll
+    for (int t = 0; t < K; ++t) cur[t] = keys[addr[t]];
+#pragma unroll
+    for (int t = 0; t < K; ++t)
+        if (hit[t] && key[t] < cur[t]) __hip_atomic_fetch_min(keys + pix[t], key[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ __launch_bounds__(kBlock) void k_render_lds(const float *__restrict__ X, const float *__restrict__ Y,
+                                                        const float *__restrict__ Z, uint64_t n, Proj P,
+                                                        unsigned long long *__restrict__ keys, ChunkOrder order)
+{
+    __shared__ unsigned long long best[kSlots];
+    __shared__ uint32_t pixof[kChunk];
+    for (int s = threadIdx.x; s < kSlots; s += kBlock) best[s] = NARVIS_KEY_EMPTY;
+    const uint64_t nq = n >> 2;
+    const uint64_t lb = logical_block(order);
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock * kQuadsPerThread;
+    const uint32_t npx = (uint32_t)P.W * (uint32_t)P.H;
+    const uint32_t spread = (uint32_t)((lb * 2654435761ull) % (uint64_t)npx);
+    __syncthreads();
+    // uniform trip count for the whole workgroup: the barriers below need it
+    for (uint64_t start = lb * kBlock * kQuadsPerThread; start < nq; start += stride) {
+        const uint32_t first = (uint32_t)(start << 2);  // index of the chunk's first point (mod 2^32)
+        f32x4 xs[kQuadsPerThread], ys[kQuadsPerThread], zs[kQuadsPerThread];
+#pragma unroll
+        for (int k = 0; k < kQuadsPerThread; ++k) {
+            const uint64_t q = start + threadIdx.x + (uint64_t)k * kBlock;
+            if (q < nq) {
+                xs[k] = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(X) + q);
+                ys[k] = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(Y) + q);
+                zs[k] = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(Z) + q);
+            }
+        }
+        uint32_t pix[kPts];
+        unsigned long long key[kPts];
+        bool hit[kPts];
+#pragma unroll
+        for (int k = 0; k < kQuadsPerThread; ++k) {
+            const uint32_t lq = threadIdx.x + (uint32_t)k * kBlock;  // quad within the chunk
+            const bool live = start + lq < nq;
+            const float px[4] = {xs[k].x, xs[k].y, xs[k].z, xs[k].w};
+            const float py[4] = {ys[k].x, ys[k].y, ys[k].z, ys[k].w};
+            const float pz[4] = {zs[k].x, zs[k].y, zs[k].z, zs[k].w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int t = k * 4 + j;
+                float w = 0.0f;
+                uint32_t pp = 0;
+                hit[t] = live && project(P, px[j], py[j], pz[j], pp, w);
+                pix[t] = pp;
+                key[t] = ((unsigned long long)__float_as_uint(w) << 32) | (first + lq * 4 + (uint32_t)j);
+                pixof[lq * 4 + j] = hit[t] ? pp : kNoPixel;
+                if (hit[t]) atomicMin(&best[pp & (kSlots - 1)], key[t]);
+            }
+        }
+        __syncthreads();
+        // collision check: did my slot's winner come from my pixel?
+        unsigned long long won[kPts];
+#pragma unroll
+        for (int t = 0; t < kPts; ++t) won[t] = best[pix[t] & (kSlots - 1)];
+#pragma unroll
+        for (int t = 0; t < kPts; ++t) hit[t] = hit[t] && pixof[((uint32_t)won[t] - first) & (kChunk - 1)] != pix[t];
+        // my slots' winners
+        uint32_t fpix[kPer];
+        unsigned long long fkey[kPer];
+        bool fhit[kPer];
+#pragma unroll
+        for (int t = 0; t < kPer; ++t) {
+            fkey[t] = best[threadIdx.x + t * kBlock];
+            fhit[t] = fkey[t] != NARVIS_KEY_EMPTY;
+            fpix[t] = fhit[t] ? pixof[((uint32_t)fkey[t] - first) & (kChunk - 1)] : 0u;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < kPer; ++t) best[threadIdx.x + t * kBlock] = NARVIS_KEY_EMPTY;
+        global_merge<kPer>(keys, fpix, fkey, fhit, spread);
+        global_merge<kPts>(keys, pix, key, hit, spread);
+        __syncthreads();
+    }
+    // the last n % 4 points
+    if (blockIdx.x == 0 && threadIdx.x < (n & 3)) {
+        const uint64_t i = (nq << 2) + threadIdx.x;
+        uint32_t pix;
+        float w;
+        if (project(P, X[i], Y[i], Z[i], pix, w)) merge<NARVIS_RENDER_EARLYZ>(keys, pix, w, (uint32_t)i);
     }
 }
 
@@ -316,8 +472,11 @@ hipError_t launch_render(const float *x, const float *y, const float *z, uint64_
     order.per = (uint32_t)(blocks / xcds);
     order.stride = coprime_stride(order.per);
     auto *k = reinterpret_cast<unsigned long long *>(keys);
-    if (variant == NARVIS_RENDER_AUTO) variant = NARVIS_RENDER_EARLYZ;
-    if (vec) {
+    if (variant == NARVIS_RENDER_AUTO) variant = vec ? NARVIS_RENDER_LDS : NARVIS_RENDER_EARLYZ;
+    if (variant == NARVIS_RENDER_LDS && !vec) variant = NARVIS_RENDER_EARLYZ;
+    if (vec && variant == NARVIS_RENDER_LDS) {
+        hipLaunchKernelGGL(k_render_lds, dim3((unsigned)blocks), dim3(kBlock), 0, s, x, y, z, n, P, k, order);
+    } else if (vec) {
         if (variant == NARVIS_RENDER_GLOBAL)
             hipLaunchKernelGGL(k_render_vec<NARVIS_RENDER_GLOBAL>, dim3((unsigned)blocks), dim3(kBlock), 0, s,
                                x, y, z, n, P, k, order);

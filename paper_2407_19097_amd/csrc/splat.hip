@@ -1,0 +1,575 @@
+// Isotropic screen-space Gaussian splat renderer for gfx950.
+//
+// The paper's target renderer is the forward pass of 3D Gaussian splatting
+// applied to the points (Sec. 4.2, "Gaussian Renderer"): each point becomes a
+// Gaussian, the Gaussians reaching a pixel are taken nearest first and
+// alpha-blended front to back.  Here every point is a screen-space Gaussian of
+// standard deviation sigma pixels at its projected position.  Pipeline:
+//   project -- same fp32 transform and cull as the rasterizer; the Gaussian's
+//              3-sigma footprint gives a rectangle of screen tiles;
+//   scan    -- exclusive prefix sum of the per-point tile counts;
+//   emit    -- one (tile << 32 | depth bits, point index) pair per covered tile,
+//              written in point order;
+//   sort    -- stable least-significant-digit radix sort on the 64-bit key, so
+//              equal (tile, depth) keep the point order: within a tile the list
+//              is ordered exactly like the rasterizer's (depth, index) key;
+//   ranges  -- first and one-past-last pair of every tile;
+//   blend   -- one workgroup per 16x16 tile, one thread per pixel; batches of
+//              the tile's list are staged through LDS and composited front to
+//              back (alpha = min(0.99, o exp(-d^2 / 2 sigma^2)), skipped below
+//              1/255, stop once transmittance would fall under 1e-4).
+// No step needs the host: counts stay on the device and kernels whose size
+// depends on them are launched for the worst case and read the count.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+#pragma clang fp contract(off)
+
+namespace narvis {
+
+namespace {
+
+constexpr int kT = 256;            // threads per workgroup everywhere here
+constexpr int kScanItems = 16;     // elements per thread in scans and the sort
+constexpr int kScanTile = kT * kScanItems;
+constexpr int kTile = 16;          // splat screen tile edge in pixels
+
+__device__ __forceinline__ bool project(const Proj &P, float x, float y, float z, float &sx, float &sy, float &w)
+{
+    float cx = P.m00 * x;
+    cx = cx + P.m01 * y;
+    cx = cx + P.m02 * z;
+    cx = cx + P.m03;
+    float cy = P.m10 * x;
+    cy = cy + P.m11 * y;
+    cy = cy + P.m12 * z;
+    cy = cy + P.m13;
+    float ww = P.m30 * x;
+    ww = ww + P.m31 * y;
+    ww = ww + P.m32 * z;
+    ww = ww + P.m33;
+    if (!(ww >= P.near_f && ww <= P.far_f)) return false;
+    float nx = cx / ww;
+    float ny = cy / ww;
+    float a = nx * 0.5f;
+    a = a + 0.5f;
+    a = a * P.Wf;
+    float b = ny * 0.5f;
+    b = 0.5f - b;
+    b = b * P.Hf;
+    if (!(a >= 0.0f && a < P.Wf && b >= 0.0f && b < P.Hf)) return false;
+    sx = a;
+    sy = b;
+    w = ww;
+    return true;
+}
+
+__device__ __forceinline__ float attr_f32(const AttrArg &a, uint32_t i)
+{
+    const unsigned char *p = a.p + (size_t)i * (size_t)a.stride;
+    switch (a.dtype) {
+    case NARVIS_U8: return (float)(*p);
+    case NARVIS_U16: return (float)(*reinterpret_cast<const uint16_t *>(p));
+    case NARVIS_F16: return (float)(*reinterpret_cast<const _Float16 *>(p));
+    default: return *reinterpret_cast<const float *>(p);
+    }
+}
+
+struct SplatArgs {
+    const float *X, *Y, *Z;
+    uint64_t n;
+    Proj P;
+    AttrPack A;
+    int32_t color_mode, color_attr;
+    const float *lut;
+    float lut_min, lut_inv;
+    float reach;          // 3 sigma, in pixels
+    int32_t tiles_x, tiles_y;
+    float2 *ctr;          // [n] centre
+    float4 *col;          // [n] colour
+    uint32_t *wbits;      // [n] depth bits
+    uint32_t *cnt;        // [n + 1] tile counts, scanned in place to offsets
+    uint64_t cap;         // capacity of the pair arrays
+};
+
+// footprint rectangle in tiles (conservative: every pixel whose centre can be
+// within `reach` of (sx, sy) is inside)
+__device__ __forceinline__ void tile_rect(const SplatArgs &S, float sx, float sy, int &tx0, int &tx1, int &ty0, int &ty1)
+{
+    const int W = S.P.W, H = S.P.H;
+    int x0 = (int)floorf(sx - S.reach - 1.0f), x1 = (int)floorf(sx + S.reach + 1.0f);
+    int y0 = (int)floorf(sy - S.reach - 1.0f), y1 = (int)floorf(sy + S.reach + 1.0f);
+    x0 = max(x0, 0);
+    y0 = max(y0, 0);
+    x1 = min(x1, W - 1);
+    y1 = min(y1, H - 1);
+    tx0 = x0 / kTile;
+    tx1 = x1 / kTile;
+    ty0 = y0 / kTile;
+    ty1 = y1 / kTile;
+}
+
+__global__ __launch_bounds__(kT) void k_splat_project(SplatArgs S)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * kT + threadIdx.x;
+    if (i > S.n) return;
+    if (i == S.n) {  // the scan's extra slot, so that cnt[n] becomes the total
+        S.cnt[i] = 0;
+        return;
+    }
+    float sx, sy, w;
+    if (!project(S.P, S.X[i], S.Y[i], S.Z[i], sx, sy, w)) {
+        S.cnt[i] = 0;
+        return;
+    }
+    float4 c;
+    if (S.color_mode == NARVIS_COLOR_LUT) {
+        float t = attr_f32(S.A.a[S.color_attr], (uint32_t)i) - S.lut_min;
+        t = t * S.lut_inv;
+        t = t * 256.0f;
+        int q;
+        if (!(t > 0.0f)) q = 0;
+        else if (t >= 255.0f) q = 255;
+        else q = (int)t;
+        c = make_float4(S.lut[q * 3], S.lut[q * 3 + 1], S.lut[q * 3 + 2], 0.0f);
+    } else {
+        const float s = 1.0f / 255.0f;
+        c = make_float4(attr_f32(S.A.a[S.color_attr], (uint32_t)i) * s,
+                        attr_f32(S.A.a[S.color_attr + 1], (uint32_t)i) * s,
+                        attr_f32(S.A.a[S.color_attr + 2], (uint32_t)i) * s, 0.0f);
+    }
+    int tx0, tx1, ty0, ty1;
+    tile_rect(S, sx, sy, tx0, tx1, ty0, ty1);
+    S.ctr[i] = make_float2(sx, sy);
+    S.col[i] = c;
+    S.wbits[i] = __float_as_uint(w);
+    S.cnt[i] = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+}
+
+__global__ __launch_bounds__(kT) void k_splat_emit(SplatArgs S, unsigned long long *keys, uint32_t *vals)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * kT + threadIdx.x;
+    if (i >= S.n) return;
+    const uint32_t start = S.cnt[i], stop = S.cnt[i + 1];
+    if (start == stop) return;
+    const float2 c = S.ctr[i];
+    int tx0, tx1, ty0, ty1;
+    tile_rect(S, c.x, c.y, tx0, tx1, ty0, ty1);
+    const unsigned long long d = S.wbits[i];
+    uint32_t o = start;
+    for (int ty = ty0; ty <= ty1; ++ty)
+        for (int tx = tx0; tx <= tx1; ++tx, ++o) {
+            if (o >= stop || o >= S.cap) return;  // the count bounds the rectangle; guard anyway
+            keys[o] = ((unsigned long long)(uint32_t)(ty * S.tiles_x + tx) << 32) | d;
+            vals[o] = (uint32_t)i;
+        }
+}
+
+// ---------------------------------------------------------------------------
+// exclusive prefix sum of uint32 (three passes: tile sums, scan of sums, apply)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(v, d, 64);
+        if (lane >= d) v += o;
+    }
+    return v;
+}
+
+// block-wide exclusive scan of one value per thread; returns the block total in *total
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *lds4, uint32_t *total)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const uint32_t inc = wave_incl_scan(v);
+    if (lane == 63) lds4[wid] = inc;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int k = 0; k < kT / 64; ++k) {
+        const uint32_t s = lds4[k];
+        if (k < wid) before += s;
+        all += s;
+    }
+    __syncthreads();
+    *total = all;
+    return before + inc - v;
+}
+
+__global__ __launch_bounds__(kT) void k_scan_sums(const uint32_t *in, uint64_t len, uint32_t *sums)
+{
+    __shared__ uint32_t lds4[kT / 64];
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k)
+        if (base + k < len) s += in[base + k];
+    uint32_t total;
+    block_excl_scan(s, lds4, &total);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kT) void k_scan_top(uint32_t *sums, uint32_t nb)
+{
+    __shared__ uint32_t lds4[kT / 64];
+    __shared__ uint32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (uint32_t base = 0; base < nb; base += kT) {
+        const uint32_t i = base + threadIdx.x;
+        const uint32_t v = i < nb ? sums[i] : 0u;
+        uint32_t total;
+        const uint32_t ex = block_excl_scan(v, lds4, &total);
+        const uint32_t c = carry;
+        if (i < nb) sums[i] = c + ex;
+        __syncthreads();
+        if (threadIdx.x == 0) carry = c + total;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kT) void k_scan_apply(const uint32_t *in, uint32_t *out, uint64_t len, const uint32_t *sums)
+{
+    __shared__ uint32_t lds4[kT / 64];
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = base + k < len ? in[base + k] : 0u;
+        s += v[k];
+    }
+    uint32_t total;
+    uint32_t run = block_excl_scan(s, lds4, &total) + sums[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < len) out[base + k] = run;
+        run += v[k];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// stable LSD radix sort, 8-bit digits, 4096 elements per workgroup
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kT) void k_radix_hist(const unsigned long long *keys, const uint32_t *count, int shift,
+                                                   uint32_t *hist, uint32_t nblk)
+{
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t N = *count;
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile + threadIdx.x;
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) {
+        const uint64_t e = base + (uint64_t)r * kT;
+        if (e < N) atomicAdd(&h[(uint32_t)(keys[e] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(uint64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kT) void k_radix_scatter(const unsigned long long *kin, const uint32_t *vin,
+                                                      unsigned long long *kout, uint32_t *vout, const uint32_t *count,
+                                                      int shift, const uint32_t *offs, uint32_t nblk)
+{
+    __shared__ unsigned long long skey[kScanTile];
+    __shared__ uint32_t sval[kScanTile];
+    __shared__ uint32_t wcnt[kT / 64][256];  // (round << 8) | count, so stale rounds read as 0
+    __shared__ uint32_t woff[kT / 64][256];
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t bstart[256];
+    __shared__ uint32_t lds4[kT / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const uint64_t N = *count;
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+    if (base >= N) return;  // uniform for the workgroup
+    run[threadIdx.x] = 0;
+#pragma unroll
+    for (int w = 0; w < kT / 64; ++w) wcnt[w][threadIdx.x] = 0xFFFFFFFFu;
+    unsigned long long k[kScanItems];
+    uint32_t v[kScanItems], rank[kScanItems], dig[kScanItems];
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) {
+        const uint64_t e = base + (uint64_t)r * kT + threadIdx.x;
+        const bool ok = e < N;
+        k[r] = ok ? kin[e] : 0ull;
+        v[r] = ok ? vin[e] : 0u;
+        dig[r] = ok ? ((uint32_t)(k[r] >> shift) & 255u) : 256u;
+    }
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    __syncthreads();
+    // rank every element among equal digits in block order (round, wave, lane)
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) {
+        const uint32_t d = dig[r];
+        unsigned long long m = __ballot(d < 256u);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const unsigned long long bb = __ballot((d >> b) & 1u);
+            m &= ((d >> b) & 1u) ? bb : ~bb;
+        }
+        const uint32_t inwave = (uint32_t)__popcll(m & below);
+        if (d < 256u && inwave == 0) wcnt[wid][d] = ((uint32_t)r << 8) | (uint32_t)__popcll(m);
+        __syncthreads();
+        {
+            uint32_t acc = run[threadIdx.x];
+#pragma unroll
+            for (int w = 0; w < kT / 64; ++w) {
+                const uint32_t c = wcnt[w][threadIdx.x];
+                woff[w][threadIdx.x] = acc;
+                acc += (c >> 8) == (uint32_t)r ? (c & 255u) : 0u;
+            }
+            run[threadIdx.x] = acc;
+        }
+        __syncthreads();
+        rank[r] = d < 256u ? woff[wid][d] + inwave : 0u;
+    }
+    // block-local start of every digit
+    uint32_t total;
+    const uint32_t ex = block_excl_scan(run[threadIdx.x], lds4, &total);
+    bstart[threadIdx.x] = ex;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) {
+        if (dig[r] < 256u) {
+            const uint32_t pos = bstart[dig[r]] + rank[r];
+            if (pos < (uint32_t)kScanTile) {
+                skey[pos] = k[r];
+                sval[pos] = v[r];
+            }
+        }
+    }
+    __syncthreads();
+    const uint32_t inblock = (uint32_t)min((uint64_t)kScanTile, N - base);
+    for (uint32_t i = threadIdx.x; i < inblock; i += kT) {
+        const unsigned long long key = skey[i];
+        const uint32_t d = (uint32_t)(key >> shift) & 255u;
+        const uint64_t dst = (uint64_t)offs[(uint64_t)d * nblk + blockIdx.x] + (i - bstart[d]);
+        if (dst < N) {  // always true for a consistent histogram; guards the buffer regardless
+            kout[dst] = key;
+            vout[dst] = sval[i];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// tile ranges and blending
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kT) void k_fill_u32(uint32_t *p, uint64_t cnt, uint32_t v)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * kT + threadIdx.x;
+    if (i < cnt) p[i] = v;
+}
+
+__global__ __launch_bounds__(kT) void k_tile_ranges(const unsigned long long *keys, const uint32_t *count, uint32_t *range,
+                                                    uint32_t ntiles)
+{
+    const uint64_t p = (uint64_t)blockIdx.x * kT + threadIdx.x;
+    const uint64_t N = *count;
+    if (p >= N) return;
+    const uint32_t t = (uint32_t)(keys[p] >> 32);
+    if (t >= ntiles) return;
+    if (p == 0 || (uint32_t)(keys[p - 1] >> 32) != t) range[2 * t] = (uint32_t)p;
+    if (p + 1 == N || (uint32_t)(keys[p + 1] >> 32) != t) range[2 * t + 1] = (uint32_t)(p + 1);
+}
+
+struct BlendArgs {
+    uint64_t n;
+    const uint32_t *count;
+    const uint32_t *range;
+    const uint32_t *vals;
+    const float2 *ctr;
+    const float4 *col;
+    float *img;
+    int32_t W, H, tiles_x;
+    float cut2, inv2s2, opacity;
+};
+
+__global__ __launch_bounds__(kT) void k_splat_blend(BlendArgs B)
+{
+    __shared__ float2 sc[kT];
+    __shared__ float4 scol[kT];
+    const int tile = blockIdx.x;
+    const int tx = tile % B.tiles_x, ty = tile / B.tiles_x;
+    const int px = tx * kTile + (threadIdx.x % kTile);
+    const int py = ty * kTile + (threadIdx.x / kTile);
+    const bool inside = px < B.W && py < B.H;
+    const uint32_t N = *B.count;
+    const uint32_t start = B.range[2 * tile], stop = min(B.range[2 * tile + 1], N);
+    const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+    float T = 1.0f, r = 0.0f, g = 0.0f, b = 0.0f;
+    bool done = !inside;
+    for (uint32_t s0 = start; s0 < stop; s0 += kT) {
+        if (__syncthreads_count(!done) == 0) break;
+        const uint32_t e = s0 + threadIdx.x;
+        if (e < stop) {
+            const uint32_t i = B.vals[e];
+            const bool ok = i < B.n;  // always true for consistent lists
+            sc[threadIdx.x] = ok ? B.ctr[i] : make_float2(-1e30f, -1e30f);
+            scol[threadIdx.x] = ok ? B.col[i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
+        __syncthreads();
+        const int m = (int)min((uint32_t)kT, stop - s0);
+        for (int j = 0; j < m && !done; ++j) {
+            const float2 c = sc[j];
+            const float dx = fx - c.x;
+            const float dy = fy - c.y;
+            float d2 = dx * dx;
+            d2 = d2 + dy * dy;
+            if (!(d2 <= B.cut2)) continue;
+            float a = B.opacity * expf(-d2 * B.inv2s2);
+            a = fminf(a, 0.99f);
+            if (a < 1.0f / 255.0f) continue;
+            const float Tn = T * (1.0f - a);
+            if (Tn < 1e-4f) {
+                done = true;
+                break;
+            }
+            const float4 cc = scol[j];
+            const float at = a * T;
+            r = r + cc.x * at;
+            g = g + cc.y * at;
+            b = b + cc.z * at;
+            T = Tn;
+        }
+    }
+    if (inside) {
+        const int64_t npx = (int64_t)B.W * B.H;
+        const int64_t p = (int64_t)py * B.W + px;
+        B.img[p] = r;
+        B.img[npx + p] = g;
+        B.img[2 * npx + p] = b;
+    }
+}
+
+uint64_t align256(uint64_t v) { return (v + 255) & ~uint64_t(255); }
+
+}  // namespace
+
+// Workspace carve-up, shared by the size query and the launcher.
+SplatLayout splat_layout(uint64_t n, int32_t W, int32_t H, float sigma)
+{
+    SplatLayout L{};
+    // the footprint rectangle spans x1 - x0 <= 2 reach + 3 pixels in exact
+    // arithmetic (+1 for fp32 rounding of its ends), so it touches at most
+    // floor((2 reach + 4) / kTile) + 2 tiles per axis
+    const float reach = 3.0f * sigma;
+    const uint64_t per_axis = (uint64_t)((2.0f * reach + 4.0f) / (float)kTile) + 2;
+    L.tiles_x = (W + kTile - 1) / kTile;
+    L.tiles_y = (H + kTile - 1) / kTile;
+    L.cap = n * per_axis * per_axis;
+    L.nblk = (L.cap + kScanTile - 1) / kScanTile;
+    if (L.nblk == 0) L.nblk = 1;
+    const uint64_t histlen = L.nblk * 256;
+    const uint64_t scanlen = histlen > n + 1 ? histlen : n + 1;
+    L.nsums = (scanlen + kScanTile - 1) / kScanTile;
+    uint64_t o = 0;
+    L.off_ctr = o; o = align256(o + n * sizeof(float2));
+    L.off_col = o; o = align256(o + n * sizeof(float4));
+    L.off_wbits = o; o = align256(o + n * 4);
+    L.off_cnt = o; o = align256(o + (n + 1) * 4);
+    L.off_ka = o; o = align256(o + L.cap * 8);
+    L.off_va = o; o = align256(o + L.cap * 4);
+    L.off_kb = o; o = align256(o + L.cap * 8);
+    L.off_vb = o; o = align256(o + L.cap * 4);
+    L.off_hist = o; o = align256(o + histlen * 4);
+    L.off_sums = o; o = align256(o + L.nsums * 4);
+    L.off_range = o; o = align256(o + (uint64_t)L.tiles_x * L.tiles_y * 8);
+    L.bytes = o;
+    int bits = 0;
+    while ((1ull << bits) < (uint64_t)L.tiles_x * L.tiles_y) ++bits;
+    L.key_bits = 32 + bits;
+    return L;
+}
+
+static hipError_t scan_excl(const uint32_t *in, uint32_t *out, uint64_t len, uint32_t *sums, hipStream_t s)
+{
+    const uint64_t nb = (len + kScanTile - 1) / kScanTile;
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nb), dim3(kT), 0, s, in, len, sums);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kT), 0, s, sums, (uint32_t)nb);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kT), 0, s, in, out, len, sums);
+    return hipGetLastError();
+}
+
+hipError_t launch_splat(const float *x, const float *y, const float *z, uint64_t n, const Proj &P, const AttrPack &A,
+                        const narvis_splat_params &prm, float *img, void *ws, hipStream_t s)
+{
+    const SplatLayout L = splat_layout(n, P.W, P.H, prm.sigma_px);
+    char *base = static_cast<char *>(ws);
+    SplatArgs S;
+    S.X = x;
+    S.Y = y;
+    S.Z = z;
+    S.n = n;
+    S.P = P;
+    S.A = A;
+    S.color_mode = prm.color_mode;
+    S.color_attr = prm.color_attr;
+    S.lut = prm.lut;
+    S.lut_min = prm.lut_min;
+    S.lut_inv = prm.lut_inv_range;
+    S.reach = 3.0f * prm.sigma_px;
+    S.tiles_x = L.tiles_x;
+    S.tiles_y = L.tiles_y;
+    S.ctr = reinterpret_cast<float2 *>(base + L.off_ctr);
+    S.col = reinterpret_cast<float4 *>(base + L.off_col);
+    S.wbits = reinterpret_cast<uint32_t *>(base + L.off_wbits);
+    S.cnt = reinterpret_cast<uint32_t *>(base + L.off_cnt);
+    S.cap = L.cap;
+    auto *ka = reinterpret_cast<unsigned long long *>(base + L.off_ka);
+    auto *kb = reinterpret_cast<unsigned long long *>(base + L.off_kb);
+    auto *va = reinterpret_cast<uint32_t *>(base + L.off_va);
+    auto *vb = reinterpret_cast<uint32_t *>(base + L.off_vb);
+    auto *hist = reinterpret_cast<uint32_t *>(base + L.off_hist);
+    auto *sums = reinterpret_cast<uint32_t *>(base + L.off_sums);
+    auto *range = reinterpret_cast<uint32_t *>(base + L.off_range);
+    const uint64_t ntiles = (uint64_t)L.tiles_x * L.tiles_y;
+    const uint32_t *total = S.cnt + n;  // after the scan
+
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((2 * ntiles + kT - 1) / kT)), dim3(kT), 0, s, range, 2 * ntiles, 0u);
+    hipLaunchKernelGGL(k_splat_project, dim3((unsigned)((n + 1 + kT - 1) / kT)), dim3(kT), 0, s, S);
+    hipError_t e = scan_excl(S.cnt, S.cnt, n + 1, sums, s);
+    if (e != hipSuccess) return e;
+    if (n > 0) hipLaunchKernelGGL(k_splat_emit, dim3((unsigned)((n + kT - 1) / kT)), dim3(kT), 0, s, S, ka, va);
+    const uint32_t nblk = (uint32_t)L.nblk;
+    for (int shift = 0; shift < L.key_bits; shift += 8) {
+        hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kT), 0, s, ka, total, shift, hist, nblk);
+        e = scan_excl(hist, hist, (uint64_t)nblk * 256, sums, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(kT), 0, s, ka, va, kb, vb, total, shift, hist, nblk);
+        unsigned long long *tk = ka;
+        ka = kb;
+        kb = tk;
+        uint32_t *tv = va;
+        va = vb;
+        vb = tv;
+    }
+    hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)((L.cap + kT - 1) / kT > 0 ? (L.cap + kT - 1) / kT : 1)), dim3(kT),
+                       0, s, ka, total, range, (uint32_t)ntiles);
+    BlendArgs B;
+    B.n = n;
+    B.count = total;
+    B.range = range;
+    B.vals = va;
+    B.ctr = S.ctr;
+    B.col = S.col;
+    B.img = img;
+    B.W = P.W;
+    B.H = P.H;
+    B.tiles_x = L.tiles_x;
+    const float reach = 3.0f * prm.sigma_px;
+    B.cut2 = reach * reach;
+    B.inv2s2 = 1.0f / (2.0f * prm.sigma_px * prm.sigma_px);
+    B.opacity = prm.opacity;
+    hipLaunchKernelGGL(k_splat_blend, dim3((unsigned)ntiles), dim3(kT), 0, s, B);
+    return hipGetLastError();
+}
+
+}  // namespace narvis

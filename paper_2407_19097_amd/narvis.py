@@ -15,7 +15,7 @@ import numpy as np
 from . import _lib
 from ._lib import KEY_EMPTY, NarvisError  # noqa: F401
 
-RENDER_AUTO, RENDER_GLOBAL, RENDER_EARLYZ = 0, 1, 2
+RENDER_AUTO, RENDER_GLOBAL, RENDER_EARLYZ, RENDER_LDS = 0, 1, 2, 3
 
 _DTYPE_CODE = None
 
@@ -153,3 +153,40 @@ def narvis_rasterize(points, attrs, n: int, camera, W: int, H: int, gbuf: GBuffe
     g = gbuf.struct()
     _lib.check(_lib.load().narvis_rasterize(ctypes.byref(p), ctypes.byref(a), int(n), ctypes.byref(c), W, H,
                                             ctypes.byref(g), _stream_ptr(stream)), "narvis_rasterize")
+
+
+COLOR_LUT, COLOR_RGB8 = 0, 1
+
+
+@dataclass
+class SplatParams:
+    sigma_px: float = 1.5
+    opacity: float = 1.0
+    color_mode: int = COLOR_LUT
+    color_attr: int = 0
+    lut: object = None            # float32 [256][3] device tensor for COLOR_LUT
+    lut_min: float = 0.0
+    lut_inv_range: float = 1.0
+
+    def struct(self) -> _lib.SplatParams:
+        return _lib.SplatParams(float(self.sigma_px), float(self.opacity), int(self.color_mode),
+                                int(self.color_attr), _ptr(self.lut), float(self.lut_min), float(self.lut_inv_range))
+
+
+def narvis_splat_workspace_size(n: int, W: int, H: int, params: SplatParams) -> int:
+    p = params.struct()
+    return int(_lib.load().narvis_splat_workspace_size(int(n), W, H, ctypes.byref(p)))
+
+
+def narvis_splat(points, attrs, n: int, camera, W: int, H: int, img, params: SplatParams, workspace,
+                 stream=None) -> None:
+    """img: float32 [3][H*W] device tensor; workspace: uint8 device tensor of
+    at least narvis_splat_workspace_size bytes."""
+    pt = points_struct(points)
+    a = attrs_struct(attrs or [])
+    c = camera_struct(camera)
+    p = params.struct()
+    nbytes = workspace.numel() * workspace.element_size()
+    _lib.check(_lib.load().narvis_splat(ctypes.byref(pt), ctypes.byref(a), int(n), ctypes.byref(c), W, H, _ptr(img),
+                                        ctypes.byref(p), _ptr(workspace), nbytes, _stream_ptr(stream)),
+               "narvis_splat")

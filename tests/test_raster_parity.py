@@ -116,7 +116,7 @@ def test_ragged_sizes(n):
     assert_same(g, o)
 
 
-@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("variant", [1, 2, 3])
 @pytest.mark.parametrize("grid", [0, 1, 7, 8, 100])
 def test_variants_and_launch_geometry(variant, grid):
     announce(f"variant={variant} grid_blocks={grid}")

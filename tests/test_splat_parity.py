@@ -1,0 +1,142 @@
+"""GPU Gaussian splat vs the CPU oracle.
+
+Tolerance (derived from the arithmetic): the GPU blends in fp32 with expf,
+the oracle in fp64.  Each contribution carries a relative error of a few fp32
+ulps; over at most a few hundred contributors per pixel that stays below
+1e-5 absolute, so every pixel whose threshold decisions are not marked
+fragile by the oracle must agree within 1e-4.  A fragile pixel had a 1/255
+skip or a 1e-4 termination within 1e-5 (relative) of its threshold, where fp32
+may decide the other way; such a flip changes the pixel by at most one
+contribution (< 0.0101 for alpha <= 0.99), which is the bound used there."""
+import numpy as np
+import pytest
+
+from oracle import camera as ocam
+from oracle import splat as osplat
+from paper_2407_19097_amd import narvis, scenes
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL, TOL_FRAGILE = 1e-4, 0.0101
+
+
+def announce(msg):
+    print(f"\n[case] {msg}", flush=True)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def gpu_splat(x, y, z, attrs, cam, W, H, params, attrs_dev=None):
+    X, Y, Z = dev(x), dev(y), dev(z)
+    A = attrs_dev if attrs_dev is not None else [dev(a) for a in attrs]
+    n = int(x.shape[0])
+    ws = torch.empty(max(1, narvis.narvis_splat_workspace_size(n, W, H, params)), dtype=torch.uint8, device="cuda")
+    img = torch.full((3, W * H), float("nan"), dtype=torch.float32, device="cuda")
+    narvis.narvis_splat((X, Y, Z), A, n, cam, W, H, img, params, ws)
+    torch.cuda.synchronize()
+    return img.cpu().numpy().astype(np.float64)
+
+
+def compare(got, want, fragile):
+    assert np.isfinite(got).all()
+    d = np.abs(got - want).max(axis=0)
+    strict = fragile == 0
+    assert d[strict].max(initial=0) <= TOL, f"max err {d[strict].max()} on non-fragile pixels"
+    assert d.max(initial=0) <= TOL_FRAGILE
+    return d
+
+
+def lut_params(sc, lut_t):
+    return narvis.SplatParams(sigma_px=1.5, opacity=1.0, color_mode=narvis.COLOR_LUT, color_attr=sc.lut_attr,
+                              lut=lut_t, lut_min=sc.lut_min,
+                              lut_inv_range=float(np.float32(1.0 / (sc.lut_max - sc.lut_min))))
+
+
+@pytest.mark.parametrize("n,W,H", [(1, 16, 16), (5, 33, 17), (2000, 64, 48), (300000, 256, 200), (100003, 97, 61)])
+def test_unit_cube_splat(n, W, H):
+    announce(f"unit cube splat n={n} {W}x{H}")
+    sc = scenes.unit_cube(n=n, seed=n, W=W, H=H)
+    cam = scenes.Camera(eye=(1.7, 1.5, 1.3), target=(0.5, 0.5, 0.5))
+    lut = scenes.colour_lut()
+    params = lut_params(sc, dev(lut))
+    got = gpu_splat(sc.x, sc.y, sc.z, sc.attrs, cam, W, H, params)
+    M, near, far = ocam.clip_matrix(cam, W, H)
+    want, frag = osplat.splat(sc.x, sc.y, sc.z, M, near, far, W, H, sc.attrs, color_mode=osplat.COLOR_LUT, lut=lut,
+                              lut_attr=sc.lut_attr, lut_min=sc.lut_min, lut_inv_range=params.lut_inv_range,
+                              with_fragile=True)
+    compare(got, want, frag)
+
+
+def test_empty_and_all_culled():
+    announce("splat with n=0 and with every point behind the camera")
+    W, H = 40, 24
+    cam = scenes.Camera(eye=(0, 0, 0), target=(0, 0, -1), up=(0, 1, 0))
+    lut = dev(scenes.colour_lut())
+    params = narvis.SplatParams(color_mode=narvis.COLOR_LUT, color_attr=0, lut=lut)
+    e = np.zeros(0, np.float32)
+    got = gpu_splat(e, e, e, [e], cam, W, H, params)
+    assert (got == 0).all()
+    z = np.full(1000, 3.0, np.float32)
+    got = gpu_splat(z * 0, z * 0, z, [z], cam, W, H, params)
+    assert (got == 0).all()
+
+
+def test_rgb8_dense_overlap_and_termination():
+    announce("RGB8 colours, 200k points in a small image: deep overlap, early termination")
+    rng = np.random.default_rng(4)
+    n, W, H = 200000, 48, 40
+    x = (rng.random(n) * 1.6 - 0.8).astype(np.float32)
+    y = (rng.random(n) * 1.6 - 0.8).astype(np.float32)
+    z = (-1.0 - rng.random(n) * 3).astype(np.float32)
+    z[::7] = z[0]  # many exact depth ties
+    rgba = rng.integers(0, 256, size=(n, 4), dtype=np.uint8)
+    cam = scenes.Camera(eye=(0, 0, 0), target=(0, 0, -1), up=(0, 1, 0))
+    R = dev(rgba)
+    params = narvis.SplatParams(sigma_px=1.5, opacity=0.8, color_mode=narvis.COLOR_RGB8, color_attr=1)
+    attrs_host = [rgba[:, 0], rgba[:, 1], rgba[:, 2], rgba[:, 3]]
+    got = gpu_splat(x, y, z, attrs_host, cam, W, H, params, attrs_dev=[R[:, 0], R[:, 1], R[:, 2], R[:, 3]])
+    M, near, far = ocam.clip_matrix(cam, W, H)
+    want, frag = osplat.splat(x, y, z, M, near, far, W, H, attrs_host[1:4], opacity=0.8,
+                              color_mode=osplat.COLOR_RGB8, with_fragile=True)
+    compare(got, want, frag)
+
+
+@pytest.mark.parametrize("sigma", [0.7, 3.0])
+def test_sigma_and_opacity(sigma):
+    announce(f"sigma={sigma} opacity=0.3")
+    sc = scenes.unit_cube(n=50000, seed=3, W=120, H=90)
+    cam = scenes.Camera(eye=(1.9, 1.2, 1.4), target=(0.5, 0.5, 0.5), up=(0.1, 0.2, 1.0))
+    lut = scenes.colour_lut()
+    params = lut_params(sc, dev(lut))
+    params.sigma_px, params.opacity = sigma, 0.3
+    got = gpu_splat(sc.x, sc.y, sc.z, sc.attrs, cam, sc.W, sc.H, params)
+    M, near, far = ocam.clip_matrix(cam, sc.W, sc.H)
+    want, frag = osplat.splat(sc.x, sc.y, sc.z, M, near, far, sc.W, sc.H, sc.attrs, sigma=sigma, opacity=0.3,
+                              color_mode=osplat.COLOR_LUT, lut=lut, lut_attr=sc.lut_attr, lut_min=sc.lut_min,
+                              lut_inv_range=params.lut_inv_range, with_fragile=True)
+    compare(got, want, frag)
+
+
+def test_vector_field_full_frame():
+    announce("vector field 50M points splat at 1920x1080 (orbit frame 0)")
+    sc = scenes.vector_field(device="cuda")
+    lut = scenes.colour_lut()
+    params = lut_params(sc, dev(lut))
+    W, H = sc.W, sc.H
+    ws = torch.empty(narvis.narvis_splat_workspace_size(sc.n, W, H, params), dtype=torch.uint8, device="cuda")
+    img = torch.empty((3, W * H), dtype=torch.float32, device="cuda")
+    narvis.narvis_splat((sc.x, sc.y, sc.z), sc.attrs, sc.n, sc.cameras[0], W, H, img, params, ws)
+    torch.cuda.synchronize()
+    got = img.cpu().numpy().astype(np.float64)
+    del ws
+    M, near, far = ocam.clip_matrix(sc.cameras[0], W, H)
+    xh, yh, zh = (t.cpu().numpy() for t in (sc.x, sc.y, sc.z))
+    ah = [a.cpu().numpy() for a in sc.attrs]
+    want, frag = osplat.splat(xh, yh, zh, M, near, far, W, H, ah, color_mode=osplat.COLOR_LUT, lut=lut,
+                              lut_attr=sc.lut_attr, lut_min=sc.lut_min, lut_inv_range=params.lut_inv_range,
+                              with_fragile=True)
+    d = compare(got, want, frag)
+    print(f"  max err {d.max():.3g}, fragile pixels {int(frag.sum())}", flush=True)
