@@ -256,13 +256,13 @@ __global__ __launch_bounds__(kT) void k_scan_apply(const uint32_t *in, uint32_t 
 // stable LSD radix sort, 8-bit digits, 4096 elements per workgroup
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kT) void k_radix_hist(const unsigned long long *keys, const uint32_t *count, int shift,
-                                                   uint32_t *hist, uint32_t nblk)
+__global__ __launch_bounds__(kT) void k_radix_hist(const unsigned long long *keys, const uint32_t *count, uint64_t cap,
+                                                   int shift, uint32_t *hist, uint32_t nblk)
 {
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
     __syncthreads();
-    const uint64_t N = *count;
+    const uint64_t N = min((uint64_t)*count, cap);
     const uint64_t base = (uint64_t)blockIdx.x * kScanTile + threadIdx.x;
 #pragma unroll
     for (int r = 0; r < kScanItems; ++r) {
@@ -275,7 +275,7 @@ __global__ __launch_bounds__(kT) void k_radix_hist(const unsigned long long *key
 
 __global__ __launch_bounds__(kT) void k_radix_scatter(const unsigned long long *kin, const uint32_t *vin,
                                                       unsigned long long *kout, uint32_t *vout, const uint32_t *count,
-                                                      int shift, const uint32_t *offs, uint32_t nblk)
+                                                      uint64_t cap, int shift, const uint32_t *offs, uint32_t nblk)
 {
     __shared__ unsigned long long skey[kScanTile];
     __shared__ uint32_t sval[kScanTile];
@@ -285,7 +285,7 @@ __global__ __launch_bounds__(kT) void k_radix_scatter(const unsigned long long *
     __shared__ uint32_t bstart[256];
     __shared__ uint32_t lds4[kT / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const uint64_t N = *count;
+    const uint64_t N = min((uint64_t)*count, cap);
     const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
     if (base >= N) return;  // uniform for the workgroup
     run[threadIdx.x] = 0;
@@ -367,11 +367,11 @@ __global__ __launch_bounds__(kT) void k_fill_u32(uint32_t *p, uint64_t cnt, uint
     if (i < cnt) p[i] = v;
 }
 
-__global__ __launch_bounds__(kT) void k_tile_ranges(const unsigned long long *keys, const uint32_t *count, uint32_t *range,
-                                                    uint32_t ntiles)
+__global__ __launch_bounds__(kT) void k_tile_ranges(const unsigned long long *keys, const uint32_t *count, uint64_t cap,
+                                                    uint32_t *range, uint32_t ntiles)
 {
     const uint64_t p = (uint64_t)blockIdx.x * kT + threadIdx.x;
-    const uint64_t N = *count;
+    const uint64_t N = min((uint64_t)*count, cap);
     if (p >= N) return;
     const uint32_t t = (uint32_t)(keys[p] >> 32);
     if (t >= ntiles) return;
@@ -380,7 +380,7 @@ __global__ __launch_bounds__(kT) void k_tile_ranges(const unsigned long long *ke
 }
 
 struct BlendArgs {
-    uint64_t n;
+    uint64_t n, cap;
     const uint32_t *count;
     const uint32_t *range;
     const uint32_t *vals;
@@ -400,7 +400,7 @@ __global__ __launch_bounds__(kT) void k_splat_blend(BlendArgs B)
     const int px = tx * kTile + (threadIdx.x % kTile);
     const int py = ty * kTile + (threadIdx.x / kTile);
     const bool inside = px < B.W && py < B.H;
-    const uint32_t N = *B.count;
+    const uint32_t N = (uint32_t)min((uint64_t)*B.count, B.cap);
     const uint32_t start = B.range[2 * tile], stop = min(B.range[2 * tile + 1], N);
     const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
     float T = 1.0f, r = 0.0f, g = 0.0f, b = 0.0f;
@@ -540,10 +540,10 @@ hipError_t launch_splat(const float *x, const float *y, const float *z, uint64_t
     if (n > 0) hipLaunchKernelGGL(k_splat_emit, dim3((unsigned)((n + kT - 1) / kT)), dim3(kT), 0, s, S, ka, va);
     const uint32_t nblk = (uint32_t)L.nblk;
     for (int shift = 0; shift < L.key_bits; shift += 8) {
-        hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kT), 0, s, ka, total, shift, hist, nblk);
+        hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kT), 0, s, ka, total, L.cap, shift, hist, nblk);
         e = scan_excl(hist, hist, (uint64_t)nblk * 256, sums, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(kT), 0, s, ka, va, kb, vb, total, shift, hist, nblk);
+        hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(kT), 0, s, ka, va, kb, vb, total, L.cap, shift, hist, nblk);
         unsigned long long *tk = ka;
         ka = kb;
         kb = tk;
@@ -552,9 +552,10 @@ hipError_t launch_splat(const float *x, const float *y, const float *z, uint64_t
         vb = tv;
     }
     hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)((L.cap + kT - 1) / kT > 0 ? (L.cap + kT - 1) / kT : 1)), dim3(kT),
-                       0, s, ka, total, range, (uint32_t)ntiles);
+                       0, s, ka, total, L.cap, range, (uint32_t)ntiles);
     BlendArgs B;
     B.n = n;
+    B.cap = L.cap;
     B.count = total;
     B.range = range;
     B.vals = va;

@@ -70,7 +70,8 @@ def attrs_struct(attrs: Sequence) -> _lib.Attrs:
             raise ValueError("attribute streams are 1-D tensors (strided views allowed)")
         a.a[k].data = t.data_ptr()
         a.a[k].dtype = _dtype_code(t)
-        a.a[k].stride_bytes = t.stride(0) * t.element_size()
+        # a stride means nothing for a tensor of at most one element (torch may report 0)
+        a.a[k].stride_bytes = (t.stride(0) if t.numel() > 1 else 1) * t.element_size()
     return a
 
 
