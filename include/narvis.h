@@ -218,6 +218,79 @@ narvis_status narvis_splat(const narvis_points *pts, const narvis_attrs *attrs, 
                            const narvis_camera *cam, int32_t W, int32_t H, float *img,
                            const narvis_splat_params *p, void *workspace, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Learned post-process (after the U-Net post-processor of Sec. 3.3): a
+ * four-level encoder-decoder, 32-64-128-256 channels, two 3x3 conv + ReLU
+ * per level, 2x2 average pooling down, bilinear x2 upsampling up with
+ * [upsampled, skip] concatenation, a 1x1 head to RGB.  Convolutions run as
+ * implicit GEMM on the matrix cores in bfloat16 with fp32 accumulation.
+ *
+ * Parameter blob (host fp32, narvis_net_param_count() values): for each
+ * layer in the order e1a e1b e2a e2b e3a e3b e4a e4b d3a d3b d2a d2b d1a d1b
+ * head, the weights [Cout][Cin][k][k] followed by the bias [Cout].  Layer
+ * shapes (Cin -> Cout, k): 8->32,3  32->32,3  32->64,3  64->64,3
+ * 64->128,3  128->128,3  128->256,3  256->256,3  384->128,3  128->128,3
+ * 192->64,3  64->64,3  96->32,3  32->32,3  32->3,1.
+ *
+ * Network input: planar fp32 [B][8][H][W] G-buffer planes in the order
+ * r, g, b, depth, v'x, v'y, theta, |v'| (the RGB+D+Vel2D set of Sec. 4.5.3);
+ * the network sees 1/depth (0 where depth is 0).  Output: planar fp32
+ * [B][3][H][W].  H and W must be multiples of 8.
+ * ------------------------------------------------------------------------ */
+
+typedef enum { NARVIS_PRECISION_BF16 = 0, NARVIS_PRECISION_FP8 = 1 } narvis_precision;
+
+/* Opaque, library-owned network parameters on the device that was current
+ * at creation (fp32 master copy, bf16 working copies, Adam moments). */
+typedef struct narvis_weights narvis_weights;
+
+/* Number of floats in the parameter blob. */
+size_t narvis_net_param_count(void);
+
+/* Create a parameter handle from a host blob of exactly
+ * narvis_net_param_count() finite floats.  Allocates device memory and
+ * synchronises the device.  INVALID_ARG on a wrong count or non-finite
+ * values, OUT_OF_MEMORY if the allocation fails. */
+narvis_status narvis_weights_create(const float *host_blob, size_t count, narvis_weights **out);
+
+/* Release a handle (synchronises its device).  NULL is ignored. */
+void narvis_weights_destroy(narvis_weights *w);
+
+/* Copy the fp32 master parameters back to a host blob (synchronises). */
+narvis_status narvis_weights_read(const narvis_weights *w, float *host_blob, size_t count);
+
+/* Device workspace bytes for narvis_postprocess on B images of W x H
+ * (0 if the dimensions are invalid). */
+size_t narvis_postprocess_workspace_size(int32_t B, int32_t W, int32_t H);
+
+/* Forward pass: feat [B][8][H][W] fp32 -> img [B][3][H][W] fp32 (device).
+ * precision: NARVIS_PRECISION_BF16 (FP8 is UNSUPPORTED in this build).
+ * WORKSPACE if ws_bytes is too small. */
+narvis_status narvis_postprocess(const narvis_weights *w, const float *feat, int32_t B, int32_t W, int32_t H,
+                                 float *img, int32_t precision, void *ws, size_t ws_bytes, void *stream);
+
+/* Device workspace bytes for narvis_train_step / narvis_train_gradients. */
+size_t narvis_train_workspace_size(int32_t B, int32_t W, int32_t H);
+
+/* One training step on a batch: forward (activations kept in the
+ * workspace), loss = mean squared error against target [B][3][H][W] plus
+ * lam_tv * (mean |horizontal difference| + mean |vertical difference|) of
+ * the output (Eq. 1 without its perceptual term), backward through every
+ * layer, and an Adam update (beta 0.9 / 0.999, eps 1e-8, bias-corrected) of
+ * the fp32 master parameters with learning rate lr.  The loss value is
+ * written to *loss_out (device float).  Weight gradients are reduced in a
+ * fixed order, so a step is bit-reproducible. */
+narvis_status narvis_train_step(narvis_weights *w, const float *feat, const float *target, int32_t B, int32_t W,
+                                int32_t H, float lr, float lam_tv, float *loss_out, void *ws, size_t ws_bytes,
+                                void *stream);
+
+/* The same forward, loss and backward without the update: the gradient of
+ * the loss with respect to every parameter is written to grad_out (device
+ * fp32, blob order) and the loss to *loss_out. */
+narvis_status narvis_train_gradients(narvis_weights *w, const float *feat, const float *target, int32_t B, int32_t W,
+                                     int32_t H, float lam_tv, float *grad_out, float *loss_out, void *ws,
+                                     size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -59,6 +59,31 @@ def layer_table(widths=WIDTHS, in_ch=IN_CH, out_ch=OUT_CH):
             ("d1a", b + a, a, 3), ("d1b", a, a, 3), ("head", a, out_ch, 1)]
 
 
+def features(planes):
+    """Network input from G-buffer planes [N, 8, H, W] (r, g, b, depth, v'x, v'y,
+    theta, |v'|): the depth plane becomes inverse depth, 0 where no point."""
+    x = np.array(planes, dtype=np.float64, copy=True)
+    d = x[:, 3]
+    x[:, 3] = np.where(d > 0, 1.0 / np.where(d > 0, d, 1.0), 0.0)
+    return x
+
+
+def to_blob(P, table=None):
+    """Parameters as one flat float64 vector: per layer W [Co, Ci, k, k] then b."""
+    table = table or LAYERS
+    return np.concatenate([np.concatenate([P[n][0].reshape(-1), P[n][1]]) for n, *_ in table])
+
+
+def from_blob(blob, table=None):
+    table = table or LAYERS
+    P, o = {}, 0
+    for name, ci, co, k in table:
+        nw = co * ci * k * k
+        P[name] = (np.asarray(blob[o:o + nw], np.float64).reshape(co, ci, k, k), np.asarray(blob[o + nw:o + nw + co], np.float64))
+        o += nw + co
+    return P
+
+
 def init_params(rng, table=None):
     """He-normal weights, zero biases: {name: (W [Co, Ci, k, k], b [Co])}."""
     table = table or LAYERS

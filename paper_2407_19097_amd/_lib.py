@@ -81,6 +81,18 @@ SIGNATURES = {
     "narvis_splat": (ctypes.c_int, [ctypes.POINTER(Points), ctypes.POINTER(Attrs), ctypes.c_uint64,
                                     ctypes.POINTER(Camera), ctypes.c_int32, ctypes.c_int32, _P,
                                     ctypes.POINTER(SplatParams), _P, ctypes.c_size_t, _P]),
+    "narvis_net_param_count": (ctypes.c_size_t, []),
+    "narvis_weights_create": (ctypes.c_int, [_P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p)]),
+    "narvis_weights_destroy": (None, [_P]),
+    "narvis_weights_read": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
+    "narvis_postprocess_workspace_size": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "narvis_postprocess": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P,
+                                          ctypes.c_int32, _P, ctypes.c_size_t, _P]),
+    "narvis_train_workspace_size": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "narvis_train_step": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_float, ctypes.c_float, _P, _P, ctypes.c_size_t, _P]),
+    "narvis_train_gradients": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                              ctypes.c_float, _P, _P, _P, ctypes.c_size_t, _P]),
 }
 
 _lib = None

@@ -1,0 +1,557 @@
+// Host side of the post-processing network: layer table, weight handle,
+// workspace plan and the forward / backward / Adam sequences.
+//
+// The network (a small U-shaped encoder-decoder, after the post-processor of
+// Sec. 3.3): four levels of 32-64-128-256 channels with two 3x3 conv + ReLU
+// each and 2x2 average pooling between levels; the decoder upsamples x2
+// (bilinear), concatenates [upsampled, skip] and applies two 3x3 conv + ReLU;
+// a 1x1 head maps 32 channels to RGB.  Training minimises mean squared error
+// plus a small total-variation term (Eq. 1 without its perceptual term) with
+// Adam.  Skip tensors are written straight into the channel slice of the
+// decoder's concat buffer, so concatenation costs nothing.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+#include "narvis.h"
+#include "net_internal.h"
+
+using namespace narvis;
+using namespace narvis::net;
+
+namespace {
+
+struct LayerDef {
+    int cin, cout, ks, relu;
+};
+
+// forward order, identical to the parameter blob order
+const LayerDef kLayers[] = {
+    {8, 32, 3, 1},    {32, 32, 3, 1},    // e1a e1b
+    {32, 64, 3, 1},   {64, 64, 3, 1},    // e2a e2b
+    {64, 128, 3, 1},  {128, 128, 3, 1},  // e3a e3b
+    {128, 256, 3, 1}, {256, 256, 3, 1},  // e4a e4b
+    {384, 128, 3, 1}, {128, 128, 3, 1},  // d3a d3b
+    {192, 64, 3, 1},  {64, 64, 3, 1},    // d2a d2b
+    {96, 32, 3, 1},   {32, 32, 3, 1},    // d1a d1b
+    {32, 3, 1, 0},                       // head
+};
+constexpr int kNumLayers = sizeof(kLayers) / sizeof(kLayers[0]);
+enum { E1A, E1B, E2A, E2B, E3A, E3B, E4A, E4B, D3A, D3B, D2A, D2B, D1A, D1B, HEAD };
+
+int round_up(int v, int m) { return (v + m - 1) / m * m; }
+uint64_t align256(uint64_t v) { return (v + 255) & ~uint64_t(255); }
+
+struct LayerBuf {
+    int cin, cout, ks, relu;
+    int rows, kpad;          // forward matrix
+    int brows, bcin, bkpad;  // input-gradient matrix
+    int64_t blob_w, blob_b;  // offsets (floats) in the parameter blob
+    __bf16 *wf, *wb;
+    float *bias;             // [rows]
+    float *dw, *db;          // gradient matrix [rows][kpad] and [rows]
+};
+
+}  // namespace
+
+struct narvis_weights {
+    int device;
+    LayerBuf L[kNumLayers];
+    int64_t nparams;
+    float *master, *grad, *m, *v;
+    void *pool;              // one device allocation for everything above
+    int64_t step;
+};
+
+namespace {
+
+int64_t param_count()
+{
+    int64_t n = 0;
+    for (const LayerDef &d : kLayers) n += (int64_t)d.cout * d.cin * d.ks * d.ks + d.cout;
+    return n;
+}
+
+// Workspace plan for a batch of B images of H x W (multiples of 8).
+struct Plan {
+    int B, H, W;
+    int64_t P[4];  // pixels per level
+    uint64_t feat, e1a, cat1, pool1, e2a, cat2, pool2, e3a, cat3, pool3, e4a, e4b, d3a, d3b, d2a, d2b, d1a, d1b;
+    uint64_t out;  // fp32 planar [B][3][H][W] (training only)
+    // training
+    uint64_t gy, g_d1b, g_d1a, g_cat1, g_d2b, g_d2a, g_cat2, g_d3b, g_d3a, g_cat3, g_e4b, g_e4a, g_pool3, g_e3b,
+        g_e3a, g_pool2, g_e2b, g_e2a, g_pool1, g_e1b, g_e1a;
+    uint64_t part, bpart, lpart;
+    int64_t part_floats, bpart_floats;
+    uint64_t bytes;
+};
+
+Plan make_plan(int B, int H, int W, bool train)
+{
+    Plan p{};
+    p.B = B;
+    p.H = H;
+    p.W = W;
+    for (int l = 0; l < 4; ++l) p.P[l] = (int64_t)B * (H >> l) * (W >> l);
+    uint64_t o = 0;
+    auto bf = [&](int64_t px, int ch) {
+        const uint64_t at = o;
+        o = align256(o + (uint64_t)px * ch * 2);
+        return at;
+    };
+    p.feat = bf(p.P[0], 8);
+    p.e1a = bf(p.P[0], 32);
+    p.cat1 = bf(p.P[0], 96);
+    p.pool1 = bf(p.P[1], 32);
+    p.e2a = bf(p.P[1], 64);
+    p.cat2 = bf(p.P[1], 192);
+    p.pool2 = bf(p.P[2], 64);
+    p.e3a = bf(p.P[2], 128);
+    p.cat3 = bf(p.P[2], 384);
+    p.pool3 = bf(p.P[3], 128);
+    p.e4a = bf(p.P[3], 256);
+    p.e4b = bf(p.P[3], 256);
+    p.d3a = bf(p.P[2], 128);
+    p.d3b = bf(p.P[2], 128);
+    p.d2a = bf(p.P[1], 64);
+    p.d2b = bf(p.P[1], 64);
+    p.d1a = bf(p.P[0], 32);
+    p.d1b = bf(p.P[0], 32);
+    if (train) {
+        p.out = o;
+        o = align256(o + (uint64_t)p.P[0] * 3 * 4);
+        p.gy = bf(p.P[0], 8);
+        p.g_d1b = bf(p.P[0], 32);
+        p.g_d1a = bf(p.P[0], 32);
+        p.g_cat1 = bf(p.P[0], 96);
+        p.g_d2b = bf(p.P[1], 64);
+        p.g_d2a = bf(p.P[1], 64);
+        p.g_cat2 = bf(p.P[1], 192);
+        p.g_d3b = bf(p.P[2], 128);
+        p.g_d3a = bf(p.P[2], 128);
+        p.g_cat3 = bf(p.P[2], 384);
+        p.g_e4b = bf(p.P[3], 256);
+        p.g_e4a = bf(p.P[3], 256);
+        p.g_pool3 = bf(p.P[3], 128);
+        p.g_e3b = bf(p.P[2], 128);
+        p.g_e3a = bf(p.P[2], 128);
+        p.g_pool2 = bf(p.P[2], 64);
+        p.g_e2b = bf(p.P[1], 64);
+        p.g_e2a = bf(p.P[1], 64);
+        p.g_pool1 = bf(p.P[1], 32);
+        p.g_e1b = bf(p.P[0], 32);
+        p.g_e1a = bf(p.P[0], 32);
+        // split-K partials for the weight gradients: at most kMaxSplits splits
+        int64_t pf = 0, bfl = 0;
+        for (const LayerDef &d : kLayers) {
+            const int rows = round_up(d.cout, 16), kpad = round_up(d.ks * d.ks * d.cin, 32);
+            pf = std::max<int64_t>(pf, (int64_t)64 * rows * kpad);
+            bfl = std::max<int64_t>(bfl, (int64_t)64 * rows);
+        }
+        p.part_floats = pf;
+        p.bpart_floats = bfl;
+        p.part = o;
+        o = align256(o + (uint64_t)pf * 4);
+        p.bpart = o;
+        o = align256(o + (uint64_t)bfl * 4);
+        p.lpart = o;
+        o = align256(o + (uint64_t)((p.P[0] + 255) / 256 + 1) * 4);
+    }
+    p.bytes = o;
+    return p;
+}
+
+struct Ctx {
+    char *ws;
+    const Plan &p;
+    __bf16 *b(uint64_t off) const { return reinterpret_cast<__bf16 *>(ws + off); }
+};
+
+ConvArgs conv_args(const LayerBuf &l, const __bf16 *in, int in_stride, int in_off, __bf16 *out, int out_stride,
+                   int out_off, int B, int H, int W)
+{
+    ConvArgs a{};
+    a.in = in;
+    a.in_stride = in_stride;
+    a.in_off = in_off;
+    a.Cin = l.cin;
+    a.wt = l.wf;
+    a.Kpad = l.kpad;
+    a.bias = l.bias;
+    a.Cout = l.cout;
+    a.Cout_pad = l.rows;
+    a.B = B;
+    a.H = H;
+    a.W = W;
+    a.relu = l.relu;
+    a.out = out;
+    a.out_stride = out_stride;
+    a.out_off = out_off;
+    return a;
+}
+
+SliceArgs slice(const __bf16 *in, int is, int io, __bf16 *out, int os, int oo, int C, int B, int H, int W)
+{
+    SliceArgs s{};
+    s.in = in;
+    s.in_stride = is;
+    s.in_off = io;
+    s.out = out;
+    s.out_stride = os;
+    s.out_off = oo;
+    s.C = C;
+    s.B = B;
+    s.H = H;
+    s.W = W;
+    return s;
+}
+
+#define TRY(x)                                  \
+    do {                                        \
+        hipError_t e_ = (x);                    \
+        if (e_ != hipSuccess) return e_;        \
+    } while (0)
+
+// Forward pass; the head writes fp32 planar [B][3][H][W] to `img`.
+hipError_t forward(const narvis_weights *w, const float *feat_planes, char *ws, const Plan &p, float *img, hipStream_t s)
+{
+    Ctx c{ws, p};
+    const int B = p.B, H = p.H, W = p.W;
+    const int H1 = H / 2, W1 = W / 2, H2 = H / 4, W2 = W / 4, H3 = H / 8, W3 = W / 8;
+    const LayerBuf *L = w->L;
+    TRY(features(feat_planes, c.b(p.feat), B, H, W, s));
+    TRY(conv(conv_args(L[E1A], c.b(p.feat), 8, 0, c.b(p.e1a), 32, 0, B, H, W), 3, s));
+    TRY(conv(conv_args(L[E1B], c.b(p.e1a), 32, 0, c.b(p.cat1), 96, 64, B, H, W), 3, s));
+    TRY(pool2(slice(c.b(p.cat1), 96, 64, c.b(p.pool1), 32, 0, 32, B, H, W), s));
+    TRY(conv(conv_args(L[E2A], c.b(p.pool1), 32, 0, c.b(p.e2a), 64, 0, B, H1, W1), 3, s));
+    TRY(conv(conv_args(L[E2B], c.b(p.e2a), 64, 0, c.b(p.cat2), 192, 128, B, H1, W1), 3, s));
+    TRY(pool2(slice(c.b(p.cat2), 192, 128, c.b(p.pool2), 64, 0, 64, B, H1, W1), s));
+    TRY(conv(conv_args(L[E3A], c.b(p.pool2), 64, 0, c.b(p.e3a), 128, 0, B, H2, W2), 3, s));
+    TRY(conv(conv_args(L[E3B], c.b(p.e3a), 128, 0, c.b(p.cat3), 384, 256, B, H2, W2), 3, s));
+    TRY(pool2(slice(c.b(p.cat3), 384, 256, c.b(p.pool3), 128, 0, 128, B, H2, W2), s));
+    TRY(conv(conv_args(L[E4A], c.b(p.pool3), 128, 0, c.b(p.e4a), 256, 0, B, H3, W3), 3, s));
+    TRY(conv(conv_args(L[E4B], c.b(p.e4a), 256, 0, c.b(p.e4b), 256, 0, B, H3, W3), 3, s));
+    TRY(upsample2(slice(c.b(p.e4b), 256, 0, c.b(p.cat3), 384, 0, 256, B, H3, W3), s));
+    TRY(conv(conv_args(L[D3A], c.b(p.cat3), 384, 0, c.b(p.d3a), 128, 0, B, H2, W2), 3, s));
+    TRY(conv(conv_args(L[D3B], c.b(p.d3a), 128, 0, c.b(p.d3b), 128, 0, B, H2, W2), 3, s));
+    TRY(upsample2(slice(c.b(p.d3b), 128, 0, c.b(p.cat2), 192, 0, 128, B, H2, W2), s));
+    TRY(conv(conv_args(L[D2A], c.b(p.cat2), 192, 0, c.b(p.d2a), 64, 0, B, H1, W1), 3, s));
+    TRY(conv(conv_args(L[D2B], c.b(p.d2a), 64, 0, c.b(p.d2b), 64, 0, B, H1, W1), 3, s));
+    TRY(upsample2(slice(c.b(p.d2b), 64, 0, c.b(p.cat1), 96, 0, 64, B, H1, W1), s));
+    TRY(conv(conv_args(L[D1A], c.b(p.cat1), 96, 0, c.b(p.d1a), 32, 0, B, H, W), 3, s));
+    TRY(conv(conv_args(L[D1B], c.b(p.d1a), 32, 0, c.b(p.d1b), 32, 0, B, H, W), 3, s));
+    ConvArgs head = conv_args(L[HEAD], c.b(p.d1b), 32, 0, nullptr, 0, 0, B, H, W);
+    head.out_f32 = img;
+    TRY(conv(head, 1, s));
+    return hipSuccess;
+}
+
+// Backward of one conv layer: weight gradient into l.dw / l.db and, when dx is
+// given, the input gradient.  dy is masked by the layer's own output (ReLU).
+hipError_t layer_backward(const LayerBuf &l, const __bf16 *dy, int dy_stride, int dy_off, const __bf16 *own,
+                          int own_stride, int own_off, const __bf16 *x, int x_stride, int x_off, __bf16 *dx,
+                          int dx_stride, int dx_off, int B, int H, int W, const Plan &p, char *ws, hipStream_t s)
+{
+    const __bf16 *mask = l.relu ? own : nullptr;
+    WgradArgs a{};
+    a.dy = dy;
+    a.dy_stride = dy_stride;
+    a.dy_off = dy_off;
+    a.mask = mask;
+    a.mask_stride = own_stride;
+    a.mask_off = own_off;
+    a.x = x;
+    a.x_stride = x_stride;
+    a.x_off = x_off;
+    a.Cin = l.cin;
+    a.KS = l.ks;
+    a.Cout = l.cout;
+    a.Cout_pad = l.rows;
+    a.Kpad = l.kpad;
+    a.B = B;
+    a.H = H;
+    a.W = W;
+    const int64_t P = (int64_t)B * H * W;
+    const int tiles = ((l.kpad + 63) / 64) * ((l.rows + 63) / 64);
+    int splits = (int)std::min<int64_t>(64, std::max<int64_t>(1, 2048 / tiles));
+    int64_t per = (P + splits - 1) / splits;
+    per = (per + 31) / 32 * 32;
+    splits = (int)((P + per - 1) / per);
+    a.splits = splits;
+    a.pix_per_split = per;
+    a.part = reinterpret_cast<float *>(ws + p.part);
+    a.bpart = reinterpret_cast<float *>(ws + p.bpart);
+    TRY(wgrad(a, l.dw, l.db, s));
+    if (dx) {
+        ConvArgs c{};
+        c.in = dy;
+        c.in_stride = dy_stride;
+        c.in_off = dy_off;
+        c.Cin = l.bcin;
+        c.in_mask = mask;
+        c.mask_stride = own_stride;
+        c.mask_off = own_off;
+        c.wt = l.wb;
+        c.Kpad = l.bkpad;
+        c.bias = nullptr;
+        c.Cout = l.cin;
+        c.Cout_pad = l.brows;
+        c.B = B;
+        c.H = H;
+        c.W = W;
+        c.relu = 0;
+        c.out = dx;
+        c.out_stride = dx_stride;
+        c.out_off = dx_off;
+        TRY(conv(c, l.ks, s));
+    }
+    return hipSuccess;
+}
+
+hipError_t backward(const narvis_weights *w, char *ws, const Plan &p, hipStream_t s)
+{
+    Ctx c{ws, p};
+    const int B = p.B, H = p.H, W = p.W;
+    const int H1 = H / 2, W1 = W / 2, H2 = H / 4, W2 = W / 4, H3 = H / 8, W3 = W / 8;
+    const LayerBuf *L = w->L;
+    // head (1x1, linear): dy = loss gradient [P][8]
+    TRY(layer_backward(L[HEAD], c.b(p.gy), 8, 0, nullptr, 0, 0, c.b(p.d1b), 32, 0, c.b(p.g_d1b), 32, 0, B, H, W, p, ws, s));
+    TRY(layer_backward(L[D1B], c.b(p.g_d1b), 32, 0, c.b(p.d1b), 32, 0, c.b(p.d1a), 32, 0, c.b(p.g_d1a), 32, 0, B, H, W, p, ws, s));
+    TRY(layer_backward(L[D1A], c.b(p.g_d1a), 32, 0, c.b(p.d1a), 32, 0, c.b(p.cat1), 96, 0, c.b(p.g_cat1), 96, 0, B, H, W, p, ws, s));
+    TRY(upsample2_bwd(slice(c.b(p.g_cat1), 96, 0, c.b(p.g_d2b), 64, 0, 64, B, H1, W1), s));
+    TRY(layer_backward(L[D2B], c.b(p.g_d2b), 64, 0, c.b(p.d2b), 64, 0, c.b(p.d2a), 64, 0, c.b(p.g_d2a), 64, 0, B, H1, W1, p, ws, s));
+    TRY(layer_backward(L[D2A], c.b(p.g_d2a), 64, 0, c.b(p.d2a), 64, 0, c.b(p.cat2), 192, 0, c.b(p.g_cat2), 192, 0, B, H1, W1, p, ws, s));
+    TRY(upsample2_bwd(slice(c.b(p.g_cat2), 192, 0, c.b(p.g_d3b), 128, 0, 128, B, H2, W2), s));
+    TRY(layer_backward(L[D3B], c.b(p.g_d3b), 128, 0, c.b(p.d3b), 128, 0, c.b(p.d3a), 128, 0, c.b(p.g_d3a), 128, 0, B, H2, W2, p, ws, s));
+    TRY(layer_backward(L[D3A], c.b(p.g_d3a), 128, 0, c.b(p.d3a), 128, 0, c.b(p.cat3), 384, 0, c.b(p.g_cat3), 384, 0, B, H2, W2, p, ws, s));
+    TRY(upsample2_bwd(slice(c.b(p.g_cat3), 384, 0, c.b(p.g_e4b), 256, 0, 256, B, H3, W3), s));
+    TRY(layer_backward(L[E4B], c.b(p.g_e4b), 256, 0, c.b(p.e4b), 256, 0, c.b(p.e4a), 256, 0, c.b(p.g_e4a), 256, 0, B, H3, W3, p, ws, s));
+    TRY(layer_backward(L[E4A], c.b(p.g_e4a), 256, 0, c.b(p.e4a), 256, 0, c.b(p.pool3), 128, 0, c.b(p.g_pool3), 128, 0, B, H3, W3, p, ws, s));
+    {
+        SliceArgs a = slice(c.b(p.g_pool3), 128, 0, c.b(p.g_e3b), 128, 0, 128, B, H2, W2);
+        a.in2 = c.b(p.g_cat3);
+        a.in2_stride = 384;
+        a.in2_off = 256;
+        TRY(pool2_bwd_add(a, s));
+    }
+    TRY(layer_backward(L[E3B], c.b(p.g_e3b), 128, 0, c.b(p.cat3), 384, 256, c.b(p.e3a), 128, 0, c.b(p.g_e3a), 128, 0, B, H2, W2, p, ws, s));
+    TRY(layer_backward(L[E3A], c.b(p.g_e3a), 128, 0, c.b(p.e3a), 128, 0, c.b(p.pool2), 64, 0, c.b(p.g_pool2), 64, 0, B, H2, W2, p, ws, s));
+    {
+        SliceArgs a = slice(c.b(p.g_pool2), 64, 0, c.b(p.g_e2b), 64, 0, 64, B, H1, W1);
+        a.in2 = c.b(p.g_cat2);
+        a.in2_stride = 192;
+        a.in2_off = 128;
+        TRY(pool2_bwd_add(a, s));
+    }
+    TRY(layer_backward(L[E2B], c.b(p.g_e2b), 64, 0, c.b(p.cat2), 192, 128, c.b(p.e2a), 64, 0, c.b(p.g_e2a), 64, 0, B, H1, W1, p, ws, s));
+    TRY(layer_backward(L[E2A], c.b(p.g_e2a), 64, 0, c.b(p.e2a), 64, 0, c.b(p.pool1), 32, 0, c.b(p.g_pool1), 32, 0, B, H1, W1, p, ws, s));
+    {
+        SliceArgs a = slice(c.b(p.g_pool1), 32, 0, c.b(p.g_e1b), 32, 0, 32, B, H, W);
+        a.in2 = c.b(p.g_cat1);
+        a.in2_stride = 96;
+        a.in2_off = 64;
+        TRY(pool2_bwd_add(a, s));
+    }
+    TRY(layer_backward(L[E1B], c.b(p.g_e1b), 32, 0, c.b(p.cat1), 96, 64, c.b(p.e1a), 32, 0, c.b(p.g_e1a), 32, 0, B, H, W, p, ws, s));
+    TRY(layer_backward(L[E1A], c.b(p.g_e1a), 32, 0, c.b(p.e1a), 32, 0, c.b(p.feat), 8, 0, nullptr, 0, 0, B, H, W, p, ws, s));
+    // gradient matrices -> blob order
+    for (int i = 0; i < kNumLayers; ++i) {
+        const LayerBuf &l = L[i];
+        TRY(grad_to_blob(l.dw, l.kpad, l.cout, l.cin, l.ks, w->grad + l.blob_w, s));
+        TRY(copy_f32(l.db, w->grad + l.blob_b, l.cout, s));
+    }
+    return hipSuccess;
+}
+
+hipError_t refresh(narvis_weights *w, hipStream_t s)
+{
+    for (int i = 0; i < kNumLayers; ++i) {
+        LayerBuf &l = w->L[i];
+        TRY(prep_weights(w->master + l.blob_w, l.cout, l.cin, l.ks, l.wf, l.rows, l.kpad, l.wb, l.brows, l.bcin, l.bkpad, s));
+        TRY(copy_f32(w->master + l.blob_b, l.bias, l.cout, s));
+    }
+    return hipSuccess;
+}
+
+bool dims_ok(int B, int W, int H)
+{
+    return B >= 1 && W >= 8 && H >= 8 && W % 8 == 0 && H % 8 == 0 && (int64_t)B * W * H < (int64_t(1) << 31);
+}
+
+narvis_status st(hipError_t e) { return e == hipSuccess ? NARVIS_OK : NARVIS_ERR_DEVICE; }
+
+}  // namespace
+
+extern "C" size_t narvis_net_param_count(void) { return (size_t)param_count(); }
+
+extern "C" narvis_status narvis_weights_create(const float *host_blob, size_t count, narvis_weights **out)
+{
+    if (!host_blob || !out || count != (size_t)param_count()) return NARVIS_ERR_INVALID_ARG;
+    for (size_t i = 0; i < count; ++i)
+        if (!std::isfinite(host_blob[i])) return NARVIS_ERR_INVALID_ARG;
+    narvis_weights *w = new narvis_weights();
+    if (hipGetDevice(&w->device) != hipSuccess) {
+        delete w;
+        return NARVIS_ERR_DEVICE;
+    }
+    w->nparams = param_count();
+    // carve one allocation: master, grad, m, v (fp32 blob each), then per layer
+    uint64_t o = 0;
+    const uint64_t blob_bytes = align256((uint64_t)w->nparams * 4);
+    o = 4 * blob_bytes;
+    int64_t boff = 0;
+    std::vector<uint64_t> offs(kNumLayers * 5);
+    for (int i = 0; i < kNumLayers; ++i) {
+        const LayerDef &d = kLayers[i];
+        LayerBuf &l = w->L[i];
+        l.cin = d.cin;
+        l.cout = d.cout;
+        l.ks = d.ks;
+        l.relu = d.relu;
+        l.rows = round_up(d.cout, 16);
+        l.kpad = round_up(d.ks * d.ks * d.cin, 32);
+        l.bcin = round_up(d.cout, 8);
+        l.brows = round_up(d.cin, 16);
+        l.bkpad = round_up(d.ks * d.ks * l.bcin, 32);
+        l.blob_w = boff;
+        boff += (int64_t)d.cout * d.cin * d.ks * d.ks;
+        l.blob_b = boff;
+        boff += d.cout;
+        offs[i * 5 + 0] = o; o = align256(o + (uint64_t)l.rows * l.kpad * 2);
+        offs[i * 5 + 1] = o; o = align256(o + (uint64_t)l.brows * l.bkpad * 2);
+        offs[i * 5 + 2] = o; o = align256(o + (uint64_t)l.rows * 4);
+        offs[i * 5 + 3] = o; o = align256(o + (uint64_t)l.rows * l.kpad * 4);
+        offs[i * 5 + 4] = o; o = align256(o + (uint64_t)l.rows * 4);
+    }
+    if (hipMalloc(&w->pool, o) != hipSuccess) {
+        delete w;
+        return NARVIS_ERR_OUT_OF_MEMORY;
+    }
+    char *base = static_cast<char *>(w->pool);
+    w->master = reinterpret_cast<float *>(base);
+    w->grad = reinterpret_cast<float *>(base + blob_bytes);
+    w->m = reinterpret_cast<float *>(base + 2 * blob_bytes);
+    w->v = reinterpret_cast<float *>(base + 3 * blob_bytes);
+    for (int i = 0; i < kNumLayers; ++i) {
+        LayerBuf &l = w->L[i];
+        l.wf = reinterpret_cast<__bf16 *>(base + offs[i * 5 + 0]);
+        l.wb = reinterpret_cast<__bf16 *>(base + offs[i * 5 + 1]);
+        l.bias = reinterpret_cast<float *>(base + offs[i * 5 + 2]);
+        l.dw = reinterpret_cast<float *>(base + offs[i * 5 + 3]);
+        l.db = reinterpret_cast<float *>(base + offs[i * 5 + 4]);
+    }
+    hipError_t e = hipMemset(w->pool, 0, o);
+    if (e == hipSuccess) e = hipMemcpy(w->master, host_blob, count * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = refresh(w, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        hipFree(w->pool);
+        delete w;
+        return NARVIS_ERR_DEVICE;
+    }
+    w->step = 0;
+    *out = w;
+    return NARVIS_OK;
+}
+
+extern "C" void narvis_weights_destroy(narvis_weights *w)
+{
+    if (!w) return;
+    int cur = 0;
+    hipGetDevice(&cur);
+    hipSetDevice(w->device);
+    hipDeviceSynchronize();
+    hipFree(w->pool);
+    hipSetDevice(cur);
+    delete w;
+}
+
+extern "C" narvis_status narvis_weights_read(const narvis_weights *w, float *host_blob, size_t count)
+{
+    if (!w || !host_blob || count != (size_t)w->nparams) return NARVIS_ERR_INVALID_ARG;
+    if (hipDeviceSynchronize() != hipSuccess) return NARVIS_ERR_DEVICE;
+    return st(hipMemcpy(host_blob, w->master, count * 4, hipMemcpyDeviceToHost));
+}
+
+extern "C" size_t narvis_postprocess_workspace_size(int32_t B, int32_t W, int32_t H)
+{
+    if (!dims_ok(B, W, H)) return 0;
+    return (size_t)make_plan(B, H, W, false).bytes;
+}
+
+extern "C" narvis_status narvis_postprocess(const narvis_weights *w, const float *feat, int32_t B, int32_t W, int32_t H,
+                                            float *img, int32_t precision, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!w || !feat || !img || !ws || !dims_ok(B, W, H)) return NARVIS_ERR_INVALID_ARG;
+    if (precision != NARVIS_PRECISION_BF16) return NARVIS_ERR_UNSUPPORTED;
+    if ((reinterpret_cast<uintptr_t>(ws) & 255u) || (reinterpret_cast<uintptr_t>(feat) & 3u) ||
+        (reinterpret_cast<uintptr_t>(img) & 3u))
+        return NARVIS_ERR_INVALID_ARG;
+    const Plan p = make_plan(B, H, W, false);
+    if (ws_bytes < p.bytes) return NARVIS_ERR_WORKSPACE;
+    return st(forward(w, feat, static_cast<char *>(ws), p, img, static_cast<hipStream_t>(stream)));
+}
+
+extern "C" size_t narvis_train_workspace_size(int32_t B, int32_t W, int32_t H)
+{
+    if (!dims_ok(B, W, H)) return 0;
+    return (size_t)make_plan(B, H, W, true).bytes;
+}
+
+namespace {
+
+narvis_status train_common(narvis_weights *w, const float *feat, const float *target, int32_t B, int32_t W, int32_t H,
+                           float lam_tv, float *loss_out, void *ws, size_t ws_bytes, hipStream_t s, Plan &p)
+{
+    if (!w || !feat || !target || !loss_out || !ws || !dims_ok(B, W, H) || !std::isfinite(lam_tv) || lam_tv < 0)
+        return NARVIS_ERR_INVALID_ARG;
+    if (reinterpret_cast<uintptr_t>(ws) & 255u) return NARVIS_ERR_INVALID_ARG;
+    p = make_plan(B, H, W, true);
+    if (ws_bytes < p.bytes) return NARVIS_ERR_WORKSPACE;
+    char *base = static_cast<char *>(ws);
+    float *y = reinterpret_cast<float *>(base + p.out);
+    hipError_t e = forward(w, feat, base, p, y, s);
+    if (e == hipSuccess) {
+        e = zero_bf16(reinterpret_cast<__bf16 *>(base + p.gy), p.P[0] * 8, s);
+    }
+    if (e == hipSuccess)
+        e = loss(y, target, B, H, W, lam_tv, reinterpret_cast<__bf16 *>(base + p.gy),
+                 reinterpret_cast<float *>(base + p.lpart), loss_out, s);
+    if (e == hipSuccess) e = backward(w, base, p, s);
+    return st(e);
+}
+
+}  // namespace
+
+extern "C" narvis_status narvis_train_gradients(narvis_weights *w, const float *feat, const float *target, int32_t B,
+                                                int32_t W, int32_t H, float lam_tv, float *grad_out, float *loss_out,
+                                                void *ws, size_t ws_bytes, void *stream)
+{
+    if (!grad_out) return NARVIS_ERR_INVALID_ARG;
+    Plan p;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    narvis_status r = train_common(w, feat, target, B, W, H, lam_tv, loss_out, ws, ws_bytes, s, p);
+    if (r != NARVIS_OK) return r;
+    return st(copy_f32(w->grad, grad_out, w->nparams, s));
+}
+
+extern "C" narvis_status narvis_train_step(narvis_weights *w, const float *feat, const float *target, int32_t B,
+                                           int32_t W, int32_t H, float lr, float lam_tv, float *loss_out, void *ws,
+                                           size_t ws_bytes, void *stream)
+{
+    if (!(lr > 0.0f) || !std::isfinite(lr)) return NARVIS_ERR_INVALID_ARG;
+    Plan p;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    narvis_status r = train_common(w, feat, target, B, W, H, lam_tv, loss_out, ws, ws_bytes, s, p);
+    if (r != NARVIS_OK) return r;
+    w->step += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = (float)(1.0 - std::pow(0.9, (double)w->step));
+    const float c2 = (float)(1.0 - std::pow(0.999, (double)w->step));
+    hipError_t e = adam(w->master, w->grad, w->m, w->v, w->nparams, lr, b1, b2, 1e-8f, c1, c2, s);
+    if (e == hipSuccess) e = refresh(w, s);
+    return st(e);
+}

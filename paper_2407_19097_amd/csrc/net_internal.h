@@ -1,0 +1,74 @@
+// Internal interfaces of the post-processing network.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace narvis {
+namespace net {
+
+// Convolution (implicit GEMM).  Input and output are NHWC bf16 slices;
+// in_mask (optional) zeroes input elements whose mask element is not > 0
+// (the ReLU derivative in the input-gradient pass).
+struct ConvArgs {
+    const __bf16 *in;
+    int in_stride, in_off, Cin;        // Cin: multiple of 8
+    const __bf16 *in_mask;
+    int mask_stride, mask_off;
+    const __bf16 *wt;                  // [Cout_pad][Kpad]
+    int Kpad;                          // multiple of 32
+    const float *bias;                 // [Cout_pad] or null
+    int Cout, Cout_pad;                // Cout_pad: multiple of 16
+    int B, H, W;
+    int relu;
+    __bf16 *out;                       // NHWC slice (when out_f32 is null)
+    int out_stride, out_off;           // multiples of 4
+    float *out_f32;                    // planar [B][Cout][H][W]
+};
+
+// Pooling / upsampling / gradient-sum kernels over channel slices (C multiple of 8).
+struct SliceArgs {
+    const __bf16 *in;
+    int in_stride, in_off;
+    const __bf16 *in2;
+    int in2_stride, in2_off;
+    __bf16 *out;
+    int out_stride, out_off;
+    int C, B, H, W;                    // H, W: the larger grid except for k_upsample2
+};
+
+struct WgradArgs {
+    const __bf16 *dy;
+    int dy_stride, dy_off;
+    const __bf16 *mask;                // the layer's own output (ReLU derivative) or null
+    int mask_stride, mask_off;
+    const __bf16 *x;                   // the layer's input
+    int x_stride, x_off;
+    int Cin, KS, Cout, Cout_pad, Kpad;
+    int B, H, W;
+    int splits;
+    int64_t pix_per_split;             // multiple of 32
+    float *part;                       // [splits][Cout_pad][Kpad]
+    float *bpart;                      // [splits][Cout_pad]
+};
+
+hipError_t conv(const ConvArgs &a, int KS, hipStream_t s);
+hipError_t features(const float *in, __bf16 *out, int B, int H, int W, hipStream_t s);
+hipError_t pool2(const SliceArgs &a, hipStream_t s);
+hipError_t upsample2(const SliceArgs &a, hipStream_t s);
+hipError_t upsample2_bwd(const SliceArgs &a, hipStream_t s);
+hipError_t pool2_bwd_add(const SliceArgs &a, hipStream_t s);
+hipError_t wgrad(const WgradArgs &a, float *dw, float *db, hipStream_t s);
+hipError_t loss(const float *y, const float *t, int B, int H, int W, float lam, __bf16 *grad, float *partial,
+                float *out, hipStream_t s);
+hipError_t prep_weights(const float *master, int Cout, int Cin, int KS, __bf16 *fwd, int fwd_rows, int fwd_kpad,
+                        __bf16 *bwd, int bwd_rows, int bwd_cin, int bwd_kpad, hipStream_t s);
+hipError_t adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2, float eps,
+                float c1, float c2, hipStream_t s);
+hipError_t grad_to_blob(const float *dw, int Kpad, int Cout, int Cin, int KS, float *blob, hipStream_t s);
+hipError_t copy_f32(const float *src, float *dst, int64_t n, hipStream_t s);
+hipError_t zero_bf16(__bf16 *p, int64_t n, hipStream_t s);
+
+}  // namespace net
+}  // namespace narvis

@@ -1,0 +1,686 @@
+// Kernels of the post-processing network (gfx950): implicit-GEMM convolution
+// on MFMA (v_mfma_f32_16x16x32_bf16), pooling, bilinear upsampling, their
+// backward passes, weight gradients, loss and Adam.
+//
+// Layouts.  Activations are NHWC bfloat16; a tensor may be a channel slice of
+// a wider buffer (stride = channels per pixel of the buffer, off = first
+// channel), which is how skip connections are concatenated without copies.
+// Weights of a layer are a [Cout_pad][Kpad] bfloat16 matrix whose row holds
+// the taps in (ky, kx, ci) order (K = taps * Cin, padded with zeros to a
+// multiple of 32; rows padded to the output tile).
+//
+// MFMA operands (16x16x32, bf16, 64 lanes; lane l, g = l / 16, r = l % 16):
+// A[m][k] is supplied by lane r + 16 g as its elements k = 8g .. 8g+7 of row
+// m = r; B[k][n] likewise for column n = r; lane l receives D[4g + e][r],
+// e = 0..3.  The convolution uses A = weights (m = output channel) and
+// B = im2col^T (n = pixel), so each lane ends with 4 consecutive output
+// channels of one pixel: one 8-byte store per fragment.
+#include <hip/hip_runtime.h>
+
+#include "net_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace narvis {
+namespace net {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int kWaves = 4;
+
+__device__ __forceinline__ bf16x8 zero8()
+{
+    bf16x8 z;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) z[j] = (__bf16)0.0f;
+    return z;
+}
+
+__device__ __forceinline__ bf16x8 load8(const __bf16 *p) { return *reinterpret_cast<const bf16x8 *>(p); }
+
+// ---------------------------------------------------------------------------
+// convolution (forward and input-gradient)
+// ---------------------------------------------------------------------------
+
+template <int FCO, int FPX, int KS>
+__global__ __launch_bounds__(64 * kWaves) void k_conv(ConvArgs a)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, r = lane & 15;
+    constexpr int TP = 16 * FPX;
+    const int64_t P = (int64_t)a.B * a.H * a.W;
+    const int64_t p0 = ((int64_t)blockIdx.x * kWaves + wave) * TP;
+    const int co0 = blockIdx.y * 16 * FCO;
+    if (p0 >= P) return;  // whole wave idle (no barriers in this kernel)
+
+    int bb[FPX], yy[FPX], xx[FPX];
+    bool pv[FPX];
+#pragma unroll
+    for (int f = 0; f < FPX; ++f) {
+        const int64_t p = p0 + 16 * f + r;
+        pv[f] = p < P;
+        const int64_t pc = pv[f] ? p : 0;
+        const int64_t hw = (int64_t)a.H * a.W;
+        bb[f] = (int)(pc / hw);
+        const int64_t rem = pc - (int64_t)bb[f] * hw;
+        yy[f] = (int)(rem / a.W);
+        xx[f] = (int)(rem - (int64_t)yy[f] * a.W);
+    }
+    f32x4 acc[FCO][FPX];
+#pragma unroll
+    for (int i = 0; i < FCO; ++i)
+#pragma unroll
+        for (int f = 0; f < FPX; ++f) acc[i][f] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+
+    const int K = KS * KS * a.Cin;
+    for (int k0 = 0; k0 < a.Kpad; k0 += 32) {
+        const int kk = k0 + 8 * g;
+        const bool kvalid = kk < K;
+        const int tap = kvalid ? kk / a.Cin : 0;
+        const int ci = kvalid ? kk - tap * a.Cin : 0;
+        const int dy = KS == 3 ? tap / 3 - 1 : 0;
+        const int dx = KS == 3 ? tap % 3 - 1 : 0;
+        bf16x8 av[FCO], bv[FPX];
+#pragma unroll
+        for (int i = 0; i < FCO; ++i) av[i] = load8(a.wt + (int64_t)(co0 + 16 * i + r) * a.Kpad + kk);
+#pragma unroll
+        for (int f = 0; f < FPX; ++f) {
+            const int y2 = yy[f] + dy, x2 = xx[f] + dx;
+            const bool ok = kvalid && pv[f] && y2 >= 0 && y2 < a.H && x2 >= 0 && x2 < a.W;
+            bv[f] = zero8();
+            if (ok) {
+                const int64_t q = ((int64_t)bb[f] * a.H + y2) * a.W + x2;
+                bv[f] = load8(a.in + q * a.in_stride + a.in_off + ci);
+                if (a.in_mask) {
+                    const bf16x8 m = load8(a.in_mask + q * a.mask_stride + a.mask_off + ci);
+#pragma unroll
+                    for (int j = 0; j < 8; ++j)
+                        if (!((float)m[j] > 0.0f)) bv[f][j] = (__bf16)0.0f;
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < FCO; ++i)
+#pragma unroll
+            for (int f = 0; f < FPX; ++f)
+                acc[i][f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[f], acc[i][f], 0, 0, 0);
+    }
+    // epilogue: lane holds channels co0 + 16 i + 4 g + e of pixel p0 + 16 f + r
+#pragma unroll
+    for (int i = 0; i < FCO; ++i) {
+        const int cb = co0 + 16 * i + 4 * g;
+        float bias[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) bias[e] = a.bias ? a.bias[cb + e] : 0.0f;
+#pragma unroll
+        for (int f = 0; f < FPX; ++f) {
+            if (!pv[f]) continue;
+            const int64_t p = p0 + 16 * f + r;
+            float v[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                v[e] = acc[i][f][e] + bias[e];
+                if (a.relu) v[e] = fmaxf(v[e], 0.0f);
+            }
+            if (a.out_f32) {
+                // planar fp32 [B][Cout][H][W]
+                const int64_t hw = (int64_t)a.H * a.W;
+                const int64_t b = p / hw, pix = p - b * hw;
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (cb + e < a.Cout) a.out_f32[(b * a.Cout + cb + e) * hw + pix] = v[e];
+            } else if (cb < a.Cout) {
+                __bf16 *o = a.out + p * a.out_stride + a.out_off + cb;
+                typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+                bf16x4 w4;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) w4[e] = (__bf16)v[e];
+                *reinterpret_cast<bf16x4 *>(o) = w4;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// features, pooling, upsampling
+// ---------------------------------------------------------------------------
+
+// planar fp32 G-buffer planes [B][8][H][W] (r, g, b, depth, v'x, v'y, theta, |v'|)
+// -> NHWC bf16 [B*H*W][8]; depth becomes inverse depth (0 where empty)
+__global__ __launch_bounds__(256) void k_features(const float *in, __bf16 *out, int64_t P, int64_t hw)
+{
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= P) return;
+    const int64_t b = p / hw, pix = p - b * hw;
+    const float *src = in + b * 8 * hw + pix;
+    bf16x8 v;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        float x = src[c * hw];
+        if (c == 3) x = x > 0.0f ? 1.0f / x : 0.0f;
+        v[c] = (__bf16)x;
+    }
+    *reinterpret_cast<bf16x8 *>(out + p * 8) = v;
+}
+
+// one thread per (output pixel, group of 8 channels)
+__global__ __launch_bounds__(256) void k_pool2(SliceArgs s)
+{
+    const int groups = s.C / 8;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int Ho = s.H / 2, Wo = s.W / 2;
+    const int64_t total = (int64_t)s.B * Ho * Wo * groups;
+    if (t >= total) return;
+    const int c8 = (int)(t % groups);
+    const int64_t po = t / groups;
+    const int64_t b = po / ((int64_t)Ho * Wo);
+    const int64_t rem = po - b * Ho * Wo;
+    const int y = (int)(rem / Wo), x = (int)(rem % Wo);
+    float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const int64_t q = ((b * s.H) + 2 * y + (d >> 1)) * s.W + 2 * x + (d & 1);
+        const bf16x8 v = load8(s.in + q * s.in_stride + s.in_off + c8 * 8);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[j] = acc[j] + (float)v[j];
+    }
+    bf16x8 o;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) o[j] = (__bf16)(acc[j] * 0.25f);
+    *reinterpret_cast<bf16x8 *>(s.out + po * s.out_stride + s.out_off + c8 * 8) = o;
+}
+
+// source index and weight of output o for a x2 bilinear upsample of n samples
+// (half-pixel centres, clamped): out[o] = (1 - f) in[i0] + f in[i1]
+__device__ __forceinline__ void up_src(int o, int n, int &i0, int &i1, float &f)
+{
+    float src = ((float)o + 0.5f) * 0.5f - 0.5f;
+    src = fmaxf(src, 0.0f);
+    i0 = min((int)src, n - 1);
+    i1 = min(i0 + 1, n - 1);
+    f = src - (float)i0;
+}
+
+// in: [B][H][W] slice, out: [B][2H][2W] slice
+__global__ __launch_bounds__(256) void k_upsample2(SliceArgs s)
+{
+    const int groups = s.C / 8;
+    const int Ho = 2 * s.H, Wo = 2 * s.W;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t total = (int64_t)s.B * Ho * Wo * groups;
+    if (t >= total) return;
+    const int c8 = (int)(t % groups);
+    const int64_t po = t / groups;
+    const int64_t b = po / ((int64_t)Ho * Wo);
+    const int64_t rem = po - b * Ho * Wo;
+    const int y = (int)(rem / Wo), x = (int)(rem % Wo);
+    int y0, y1, x0, x1;
+    float fy, fx;
+    up_src(y, s.H, y0, y1, fy);
+    up_src(x, s.W, x0, x1, fx);
+    const int64_t rb = b * s.H;
+    const bf16x8 v00 = load8(s.in + ((rb + y0) * s.W + x0) * s.in_stride + s.in_off + c8 * 8);
+    const bf16x8 v01 = load8(s.in + ((rb + y0) * s.W + x1) * s.in_stride + s.in_off + c8 * 8);
+    const bf16x8 v10 = load8(s.in + ((rb + y1) * s.W + x0) * s.in_stride + s.in_off + c8 * 8);
+    const bf16x8 v11 = load8(s.in + ((rb + y1) * s.W + x1) * s.in_stride + s.in_off + c8 * 8);
+    bf16x8 o;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const float top = (1.0f - fx) * (float)v00[j] + fx * (float)v01[j];
+        const float bot = (1.0f - fx) * (float)v10[j] + fx * (float)v11[j];
+        o[j] = (__bf16)((1.0f - fy) * top + fy * bot);
+    }
+    *reinterpret_cast<bf16x8 *>(s.out + po * s.out_stride + s.out_off + c8 * 8) = o;
+}
+
+// gradient of k_upsample2, gather form: in-grad [B][H][W] from out-grad [B][2H][2W]
+// (s.in = out-grad slice at 2H x 2W, s.out = in-grad slice at H x W)
+__global__ __launch_bounds__(256) void k_upsample2_bwd(SliceArgs s)
+{
+    const int groups = s.C / 8;
+    const int Ho = 2 * s.H, Wo = 2 * s.W;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t total = (int64_t)s.B * s.H * s.W * groups;
+    if (t >= total) return;
+    const int c8 = (int)(t % groups);
+    const int64_t pi = t / groups;
+    const int64_t b = pi / ((int64_t)s.H * s.W);
+    const int64_t rem = pi - b * s.H * s.W;
+    const int i = (int)(rem / s.W), j = (int)(rem % s.W);
+    float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int oy = max(0, 2 * i - 2); oy <= min(Ho - 1, 2 * i + 3); ++oy) {
+        int y0, y1;
+        float fy;
+        up_src(oy, s.H, y0, y1, fy);
+        const float wy = (y0 == i ? 1.0f - fy : 0.0f) + (y1 == i ? fy : 0.0f);
+        if (wy == 0.0f) continue;
+        for (int ox = max(0, 2 * j - 2); ox <= min(Wo - 1, 2 * j + 3); ++ox) {
+            int x0, x1;
+            float fx;
+            up_src(ox, s.W, x0, x1, fx);
+            const float wx = (x0 == j ? 1.0f - fx : 0.0f) + (x1 == j ? fx : 0.0f);
+            if (wx == 0.0f) continue;
+            const bf16x8 v = load8(s.in + ((b * Ho + oy) * Wo + ox) * s.in_stride + s.in_off + c8 * 8);
+            const float w = wy * wx;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc[q] = acc[q] + w * (float)v[q];
+        }
+    }
+    bf16x8 o;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) o[q] = (__bf16)acc[q];
+    *reinterpret_cast<bf16x8 *>(s.out + pi * s.out_stride + s.out_off + c8 * 8) = o;
+}
+
+// out[p] = 0.25 * pooled_grad[p / 2] + skip_grad[p]  (gradient of a level's
+// output that feeds both the next level's pooling and a decoder concat)
+// s.in = pooled grad [B][H/2][W/2], s.in2 = skip grad slice [B][H][W], s.out [B][H][W]
+__global__ __launch_bounds__(256) void k_pool2_bwd_add(SliceArgs s)
+{
+    const int groups = s.C / 8;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t total = (int64_t)s.B * s.H * s.W * groups;
+    if (t >= total) return;
+    const int c8 = (int)(t % groups);
+    const int64_t p = t / groups;
+    const int64_t b = p / ((int64_t)s.H * s.W);
+    const int64_t rem = p - b * s.H * s.W;
+    const int y = (int)(rem / s.W), x = (int)(rem % s.W);
+    const int64_t q = (b * (s.H / 2) + y / 2) * (s.W / 2) + x / 2;
+    const bf16x8 g = load8(s.in + q * s.in_stride + s.in_off + c8 * 8);
+    const bf16x8 k = load8(s.in2 + p * s.in2_stride + s.in2_off + c8 * 8);
+    bf16x8 o;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) o[j] = (__bf16)(0.25f * (float)g[j] + (float)k[j]);
+    *reinterpret_cast<bf16x8 *>(s.out + p * s.out_stride + s.out_off + c8 * 8) = o;
+}
+
+// ---------------------------------------------------------------------------
+// weight gradient: dW[co][k] = sum_p dy_eff[p][co] * im2col(x)[p][k],
+// db[co] = sum_p dy_eff[p][co], dy_eff = dy * (mask > 0) where a mask is given.
+// Workgroup: 64 output channels x 64 k-columns over a pixel range (split-K);
+// chunks of 32 pixels are staged transposed in LDS so that every MFMA
+// operand is 8 consecutive pixels of one row.
+// ---------------------------------------------------------------------------
+
+constexpr int kWgPix = 32;  // pixels per LDS chunk (= MFMA K)
+
+__global__ __launch_bounds__(256) void k_wgrad(WgradArgs a)
+{
+    __shared__ __bf16 sdy[64][kWgPix + 8];   // [co][pixel], padded row
+    __shared__ __bf16 sx[64][kWgPix + 8];    // [k][pixel]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, r = lane & 15;
+    const int co0 = blockIdx.y * 64;
+    const int k0 = blockIdx.x * 64;
+    const int64_t P = (int64_t)a.B * a.H * a.W;
+    const int64_t chunk_per_split = a.pix_per_split;
+    const int64_t pbeg = (int64_t)blockIdx.z * chunk_per_split;
+    const int64_t pend = min(P, pbeg + chunk_per_split);
+    const int K = a.KS * a.KS * a.Cin;
+    // wave w computes co rows [16 (w), +16) x all 64 k columns (4 fragments)
+    f32x4 acc[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) acc[f] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    float bsum = 0.0f;
+    for (int64_t pc = pbeg; pc < pend; pc += kWgPix) {
+        // stage dy: 32 pixels x 64 channels, thread -> (pixel, group of 8 channels)
+        {
+            const int px = threadIdx.x >> 3, cg = threadIdx.x & 7;
+            const int64_t p = pc + px;
+            bf16x8 v = zero8();
+            const int c = co0 + cg * 8;
+            if (p < pend && c < a.Cout) {
+                v = load8(a.dy + p * a.dy_stride + a.dy_off + c);
+                if (a.mask) {
+                    const bf16x8 m = load8(a.mask + p * a.mask_stride + a.mask_off + c);
+#pragma unroll
+                    for (int j = 0; j < 8; ++j)
+                        if (!((float)m[j] > 0.0f)) v[j] = (__bf16)0.0f;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) sdy[cg * 8 + j][px] = v[j];
+        }
+        // stage im2col: 32 pixels x 64 k, thread -> (pixel, group of 8 k)
+        {
+            const int px = threadIdx.x >> 3, kg = threadIdx.x & 7;
+            const int64_t p = pc + px;
+            const int kk = k0 + kg * 8;
+            bf16x8 v = zero8();
+            if (p < pend && kk < K) {
+                const int tap = kk / a.Cin, ci = kk - tap * a.Cin;
+                const int dy = a.KS == 3 ? tap / 3 - 1 : 0, dx = a.KS == 3 ? tap % 3 - 1 : 0;
+                const int64_t hw = (int64_t)a.H * a.W;
+                const int64_t b = p / hw, rem = p - b * hw;
+                const int y = (int)(rem / a.W) + dy, x = (int)(rem % a.W) + dx;
+                if (y >= 0 && y < a.H && x >= 0 && x < a.W)
+                    v = load8(a.x + ((b * a.H + y) * a.W + x) * a.x_stride + a.x_off + ci);
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) sx[kg * 8 + j][px] = v[j];
+        }
+        __syncthreads();
+        // A = dy^T rows co (16 per wave), B = im2col columns k; K = 32 pixels
+        bf16x8 av;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) av[j] = sdy[wave * 16 + r][8 * g + j];
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            bf16x8 bv;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) bv[j] = sx[f * 16 + r][8 * g + j];
+            acc[f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[f], 0, 0, 0);
+        }
+        if (blockIdx.x == 0 && threadIdx.x < 64) {
+#pragma unroll 8
+            for (int j = 0; j < kWgPix; ++j) bsum = bsum + (float)sdy[threadIdx.x][j];
+        }
+        __syncthreads();
+    }
+    // partial results: part[split][co][k] (fp32), reduced in split order later
+    float *out = a.part + (int64_t)blockIdx.z * a.Cout_pad * a.Kpad;
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int co = co0 + wave * 16 + 4 * g + e;
+            const int k = k0 + f * 16 + r;
+            if (co < a.Cout_pad && k < a.Kpad) out[(int64_t)co * a.Kpad + k] = acc[f][e];
+        }
+    if (blockIdx.x == 0 && threadIdx.x < 64 && co0 + threadIdx.x < a.Cout_pad)
+        a.bpart[(int64_t)blockIdx.z * a.Cout_pad + co0 + threadIdx.x] = bsum;
+}
+
+// sum the split partials in split order (deterministic)
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float *part, const float *bpart, int splits,
+                                                      int64_t nw, int nb, float *dw, float *db)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < nw) {
+        float s = 0.0f;
+        for (int z = 0; z < splits; ++z) s = s + part[(int64_t)z * nw + i];
+        dw[i] = s;
+    }
+    if (i < nb) {
+        float s = 0.0f;
+        for (int z = 0; z < splits; ++z) s = s + bpart[(int64_t)z * nb + i];
+        db[i] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// loss: mean squared error + lam * (mean |horizontal diff| + mean |vertical diff|)
+// y, t planar fp32 [B][3][H][W]; grad written as NHWC bf16 [B*H*W][8] (channels
+// 3..7 zero) for the head's backward; per-block partial sums of the loss.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_loss(const float *y, const float *t, int B, int H, int W, float lam,
+                                              __bf16 *grad, float *partial)
+{
+    __shared__ float red[256];
+    const int64_t hw = (int64_t)H * W;
+    const int64_t P = (int64_t)B * hw;
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const double n_all = 3.0 * (double)P;
+    const double n_hx = 3.0 * (double)B * H * (W - 1);
+    const double n_hy = 3.0 * (double)B * (H - 1) * W;
+    const float c_mse = (float)(2.0 / n_all);
+    const float c_hx = W > 1 ? (float)((double)lam / n_hx) : 0.0f;
+    const float c_hy = H > 1 ? (float)((double)lam / n_hy) : 0.0f;
+    float l = 0.0f;
+    bf16x8 go = zero8();
+    if (p < P) {
+        const int64_t b = p / hw, pix = p - b * hw;
+        const int yy = (int)(pix / W), xx = (int)(pix % W);
+        for (int c = 0; c < 3; ++c) {
+            const float *yc = y + (b * 3 + c) * hw;
+            const float d = yc[pix] - t[(b * 3 + c) * hw + pix];
+            float gsum = c_mse * d;
+            l = l + d * d * (float)(1.0 / n_all);
+            if (xx + 1 < W) {
+                const float h = yc[pix + 1] - yc[pix];
+                l = l + fabsf(h) * c_hx;
+                gsum = gsum - c_hx * (h > 0.0f ? 1.0f : (h < 0.0f ? -1.0f : 0.0f));
+            }
+            if (xx > 0) {
+                const float h = yc[pix] - yc[pix - 1];
+                gsum = gsum + c_hx * (h > 0.0f ? 1.0f : (h < 0.0f ? -1.0f : 0.0f));
+            }
+            if (yy + 1 < H) {
+                const float h = yc[pix + W] - yc[pix];
+                l = l + fabsf(h) * c_hy;
+                gsum = gsum - c_hy * (h > 0.0f ? 1.0f : (h < 0.0f ? -1.0f : 0.0f));
+            }
+            if (yy > 0) {
+                const float h = yc[pix] - yc[pix - W];
+                gsum = gsum + c_hy * (h > 0.0f ? 1.0f : (h < 0.0f ? -1.0f : 0.0f));
+            }
+            go[c] = (__bf16)gsum;
+        }
+        *reinterpret_cast<bf16x8 *>(grad + p * 8) = go;
+    }
+    red[threadIdx.x] = l;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_sum(const float *partial, int64_t n, float *out)
+{
+    __shared__ float red[256];
+    float s = 0.0f;
+    for (int64_t i = threadIdx.x; i < n; i += 256) s = s + partial[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// parameters: fp32 master copies -> bf16 forward and input-gradient matrices
+// ---------------------------------------------------------------------------
+
+// master W in the blob's [Cout][Cin][k][k] order
+__global__ __launch_bounds__(256) void k_prep_weights(const float *master, int Cout, int Cin, int KS, __bf16 *fwd,
+                                                      int fwd_rows, int fwd_kpad, __bf16 *bwd, int bwd_rows,
+                                                      int bwd_cin, int bwd_kpad)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t nf = (int64_t)fwd_rows * fwd_kpad;
+    const int64_t nb = (int64_t)bwd_rows * bwd_kpad;
+    const int T = KS * KS;
+    if (i < nf) {
+        const int co = (int)(i / fwd_kpad), k = (int)(i % fwd_kpad);
+        float v = 0.0f;
+        if (co < Cout && k < T * Cin) {
+            const int tap = k / Cin, ci = k % Cin;
+            v = master[((int64_t)co * Cin + ci) * T + tap];
+        }
+        fwd[i] = (__bf16)v;
+    }
+    if (bwd && i < nb) {
+        // input-gradient conv: in-channels = Cout (padded to bwd_cin), out-channels = Cin,
+        // taps flipped: Wb[ci][tap'][co] = W[co][ci][T - 1 - tap']
+        const int ci = (int)(i / bwd_kpad), k = (int)(i % bwd_kpad);
+        float v = 0.0f;
+        if (ci < Cin && k < T * bwd_cin) {
+            const int tapb = k / bwd_cin, co = k % bwd_cin;
+            if (co < Cout) v = master[((int64_t)co * Cin + ci) * T + (T - 1 - tapb)];
+        }
+        bwd[i] = (__bf16)v;
+    }
+}
+
+// Adam on the fp32 master parameters (blob order) with gradients in blob order
+__global__ __launch_bounds__(256) void k_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr,
+                                              float b1, float b2, float eps, float c1, float c2)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * (gi * gi);
+    m[i] = mi;
+    v[i] = vi;
+    const float mh = mi / c1;
+    const float vh = vi / c2;
+    p[i] = p[i] - lr * mh / (sqrtf(vh) + eps);
+}
+
+// gradient matrix [Cout_pad][Kpad] in (tap, ci) order -> blob order [Cout][Cin][k][k]
+__global__ __launch_bounds__(256) void k_grad_to_blob(const float *dw, int Kpad, int Cout, int Cin, int KS, float *blob)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int T = KS * KS;
+    if (i >= (int64_t)Cout * Cin * T) return;
+    const int tap = (int)(i % T);
+    const int ci = (int)((i / T) % Cin);
+    const int co = (int)(i / ((int64_t)T * Cin));
+    blob[i] = dw[(int64_t)co * Kpad + tap * Cin + ci];
+}
+
+__global__ __launch_bounds__(256) void k_copy_f32(const float *src, float *dst, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+__global__ __launch_bounds__(256) void k_zero_bf16(__bf16 *p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = (__bf16)0.0f;
+}
+
+unsigned nblocks(int64_t n, int per = 256) { return (unsigned)((n + per - 1) / per); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+hipError_t conv(const ConvArgs &a, int KS, hipStream_t s)
+{
+    const int64_t P = (int64_t)a.B * a.H * a.W;
+    const int cop = a.Cout_pad;
+    // wave tile: FCO x 16 output channels by FPX x 16 pixels
+    if (cop % 64 == 0) {
+        dim3 grid(nblocks(P, 32 * kWaves), cop / 64);
+        if (KS == 3) hipLaunchKernelGGL((k_conv<4, 2, 3>), grid, dim3(64 * kWaves), 0, s, a);
+        else hipLaunchKernelGGL((k_conv<4, 2, 1>), grid, dim3(64 * kWaves), 0, s, a);
+    } else if (cop % 32 == 0) {
+        dim3 grid(nblocks(P, 64 * kWaves), cop / 32);
+        if (KS == 3) hipLaunchKernelGGL((k_conv<2, 4, 3>), grid, dim3(64 * kWaves), 0, s, a);
+        else hipLaunchKernelGGL((k_conv<2, 4, 1>), grid, dim3(64 * kWaves), 0, s, a);
+    } else {
+        dim3 grid(nblocks(P, 64 * kWaves), cop / 16);
+        if (KS == 3) hipLaunchKernelGGL((k_conv<1, 4, 3>), grid, dim3(64 * kWaves), 0, s, a);
+        else hipLaunchKernelGGL((k_conv<1, 4, 1>), grid, dim3(64 * kWaves), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t features(const float *in, __bf16 *out, int B, int H, int W, hipStream_t s)
+{
+    const int64_t P = (int64_t)B * H * W;
+    hipLaunchKernelGGL(k_features, dim3(nblocks(P)), dim3(256), 0, s, in, out, P, (int64_t)H * W);
+    return hipGetLastError();
+}
+
+hipError_t pool2(const SliceArgs &a, hipStream_t s)
+{
+    const int64_t n = (int64_t)a.B * (a.H / 2) * (a.W / 2) * (a.C / 8);
+    hipLaunchKernelGGL(k_pool2, dim3(nblocks(n)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t upsample2(const SliceArgs &a, hipStream_t s)
+{
+    const int64_t n = (int64_t)a.B * (2 * a.H) * (2 * a.W) * (a.C / 8);
+    hipLaunchKernelGGL(k_upsample2, dim3(nblocks(n)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t upsample2_bwd(const SliceArgs &a, hipStream_t s)
+{
+    const int64_t n = (int64_t)a.B * a.H * a.W * (a.C / 8);
+    hipLaunchKernelGGL(k_upsample2_bwd, dim3(nblocks(n)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t pool2_bwd_add(const SliceArgs &a, hipStream_t s)
+{
+    const int64_t n = (int64_t)a.B * a.H * a.W * (a.C / 8);
+    hipLaunchKernelGGL(k_pool2_bwd_add, dim3(nblocks(n)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t wgrad(const WgradArgs &a, float *dw, float *db, hipStream_t s)
+{
+    dim3 grid((unsigned)((a.Kpad + 63) / 64), (unsigned)((a.Cout_pad + 63) / 64), (unsigned)a.splits);
+    hipLaunchKernelGGL(k_wgrad, grid, dim3(256), 0, s, a);
+    const int64_t nw = (int64_t)a.Cout_pad * a.Kpad;
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblocks(nw > a.Cout_pad ? nw : a.Cout_pad)), dim3(256), 0, s, a.part,
+                       a.bpart, a.splits, nw, a.Cout_pad, dw, db);
+    return hipGetLastError();
+}
+
+hipError_t loss(const float *y, const float *t, int B, int H, int W, float lam, __bf16 *grad, float *partial,
+                float *out, hipStream_t s)
+{
+    const int64_t P = (int64_t)B * H * W;
+    const unsigned nb = nblocks(P);
+    hipLaunchKernelGGL(k_loss, dim3(nb), dim3(256), 0, s, y, t, B, H, W, lam, grad, partial);
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, partial, (int64_t)nb, out);
+    return hipGetLastError();
+}
+
+hipError_t prep_weights(const float *master, int Cout, int Cin, int KS, __bf16 *fwd, int fwd_rows, int fwd_kpad,
+                        __bf16 *bwd, int bwd_rows, int bwd_cin, int bwd_kpad, hipStream_t s)
+{
+    const int64_t nf = (int64_t)fwd_rows * fwd_kpad, nb = bwd ? (int64_t)bwd_rows * bwd_kpad : 0;
+    hipLaunchKernelGGL(k_prep_weights, dim3(nblocks(nf > nb ? nf : nb)), dim3(256), 0, s, master, Cout, Cin, KS, fwd,
+                       fwd_rows, fwd_kpad, bwd, bwd_rows, bwd_cin, bwd_kpad);
+    return hipGetLastError();
+}
+
+hipError_t adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2, float eps,
+                float c1, float c2, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_adam, dim3(nblocks(n)), dim3(256), 0, s, p, g, m, v, n, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t grad_to_blob(const float *dw, int Kpad, int Cout, int Cin, int KS, float *blob, hipStream_t s)
+{
+    const int64_t n = (int64_t)Cout * Cin * KS * KS;
+    hipLaunchKernelGGL(k_grad_to_blob, dim3(nblocks(n)), dim3(256), 0, s, dw, Kpad, Cout, Cin, KS, blob);
+    return hipGetLastError();
+}
+
+hipError_t copy_f32(const float *src, float *dst, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy_f32, dim3(nblocks(n)), dim3(256), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t zero_bf16(__bf16 *p, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_bf16, dim3(nblocks(n)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+}  // namespace net
+}  // namespace narvis

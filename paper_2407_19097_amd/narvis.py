@@ -191,3 +191,69 @@ def narvis_splat(points, attrs, n: int, camera, W: int, H: int, img, params: Spl
     _lib.check(_lib.load().narvis_splat(ctypes.byref(pt), ctypes.byref(a), int(n), ctypes.byref(c), W, H, _ptr(img),
                                         ctypes.byref(p), _ptr(workspace), nbytes, _stream_ptr(stream)),
                "narvis_splat")
+
+
+PRECISION_BF16, PRECISION_FP8 = 0, 1
+
+
+def narvis_net_param_count() -> int:
+    return int(_lib.load().narvis_net_param_count())
+
+
+class NetWeights:
+    """Owner of a library parameter handle (narvis_weights_create / _destroy)."""
+
+    def __init__(self, blob):
+        blob = np.ascontiguousarray(blob, dtype=np.float32).reshape(-1)
+        h = ctypes.c_void_p()
+        _lib.check(_lib.load().narvis_weights_create(blob.ctypes.data, blob.size, ctypes.byref(h)),
+                   "narvis_weights_create")
+        self.handle = h.value
+        self.count = blob.size
+
+    def read(self) -> np.ndarray:
+        out = np.empty(self.count, dtype=np.float32)
+        _lib.check(_lib.load().narvis_weights_read(self.handle, out.ctypes.data, self.count), "narvis_weights_read")
+        return out
+
+    def close(self):
+        if self.handle:
+            _lib.load().narvis_weights_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def narvis_postprocess_workspace_size(B: int, W: int, H: int) -> int:
+    return int(_lib.load().narvis_postprocess_workspace_size(B, W, H))
+
+
+def narvis_postprocess(weights: NetWeights, feat, B: int, W: int, H: int, img, workspace,
+                       precision: int = PRECISION_BF16, stream=None) -> None:
+    nbytes = workspace.numel() * workspace.element_size()
+    _lib.check(_lib.load().narvis_postprocess(weights.handle, _ptr(feat), B, W, H, _ptr(img), precision,
+                                              _ptr(workspace), nbytes, _stream_ptr(stream)), "narvis_postprocess")
+
+
+def narvis_train_workspace_size(B: int, W: int, H: int) -> int:
+    return int(_lib.load().narvis_train_workspace_size(B, W, H))
+
+
+def narvis_train_step(weights: NetWeights, feat, target, B: int, W: int, H: int, lr: float, lam_tv: float,
+                      loss_out, workspace, stream=None) -> None:
+    nbytes = workspace.numel() * workspace.element_size()
+    _lib.check(_lib.load().narvis_train_step(weights.handle, _ptr(feat), _ptr(target), B, W, H, float(lr),
+                                             float(lam_tv), _ptr(loss_out), _ptr(workspace), nbytes,
+                                             _stream_ptr(stream)), "narvis_train_step")
+
+
+def narvis_train_gradients(weights: NetWeights, feat, target, B: int, W: int, H: int, lam_tv: float, grad_out,
+                           loss_out, workspace, stream=None) -> None:
+    nbytes = workspace.numel() * workspace.element_size()
+    _lib.check(_lib.load().narvis_train_gradients(weights.handle, _ptr(feat), _ptr(target), B, W, H, float(lam_tv),
+                                                  _ptr(grad_out), _ptr(loss_out), _ptr(workspace), nbytes,
+                                                  _stream_ptr(stream)), "narvis_train_gradients")

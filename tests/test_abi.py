@@ -130,3 +130,29 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "absent.so"))
     with pytest.raises(ImportError):
         _lib.load()
+
+
+def test_net_host_logic():
+    from oracle import net as onet
+    L = _lib.load()
+    n = int(L.narvis_net_param_count())
+    assert n == onet.to_blob(onet.init_params(np.random.default_rng(0))).size
+    h = ctypes.c_void_p()
+    blob = np.zeros(n - 1, np.float32)
+    assert L.narvis_weights_create(blob.ctypes.data, n - 1, ctypes.byref(h)) == -1
+    bad = np.zeros(n, np.float32)
+    bad[5] = np.nan
+    assert L.narvis_weights_create(bad.ctypes.data, n, ctypes.byref(h)) == -1
+    assert L.narvis_postprocess_workspace_size(1, 12, 16) == 0      # W not a multiple of 8
+    assert L.narvis_postprocess_workspace_size(0, 16, 16) == 0
+    assert L.narvis_postprocess_workspace_size(1, 1920, 1080) > 0
+    assert L.narvis_train_workspace_size(16, 512, 512) > L.narvis_postprocess_workspace_size(16, 512, 512)
+
+
+def test_splat_host_logic():
+    L = _lib.load()
+    p = _lib.SplatParams(1.5, 1.0, 0, 0, 0x1000, 0.0, 1.0)
+    assert L.narvis_splat_workspace_size(1000, 64, 64, ctypes.byref(p)) > 0
+    assert L.narvis_splat_workspace_size(1 << 30, 64, 64, ctypes.byref(p)) == 0
+    bad = _lib.SplatParams(0.0, 1.0, 0, 0, 0x1000, 0.0, 1.0)
+    assert L.narvis_splat_workspace_size(1000, 64, 64, ctypes.byref(bad)) == 0
