@@ -1,0 +1,152 @@
+"""Training and evaluation driver of the learned post-process.
+
+Training pairs follow Sec. 3.3 and the viewpoint strategy of the
+supplementary material: views on a hemisphere around the point cloud's
+bounding-box centre with radius 0.75 x the box diagonal, rendered at
+512 x 512 with a 60 degree field of view; the input is the rasterizer's
+RGB + depth + Vel2D G-buffer and the target is the Gaussian splat renderer's
+image; 9:1 train/validation split; Adam, learning rate 1e-3, batch 16.
+Every step runs in the library (narvis_rasterize, narvis_splat,
+narvis_train_step, narvis_postprocess); this module only orchestrates.
+"""
+from __future__ import annotations
+
+import math
+import time
+from typing import List, Optional
+
+import numpy as np
+
+from . import metrics, narvis, scenes
+
+
+def hemisphere_views(n: int, centre, radius: float, seed: int, min_elev=0.08, max_elev=math.pi / 2 - 0.12) -> List[scenes.Camera]:
+    """Random cameras on the upper hemisphere (azimuth uniform in [0, 2 pi),
+    elevation uniform in [min_elev, max_elev]), looking at the centre."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cams = []
+    for _ in range(n):
+        th = rng.uniform(0.0, 2.0 * math.pi)
+        ph = rng.uniform(min_elev, max_elev)
+        eye = (centre[0] + radius * math.cos(ph) * math.cos(th), centre[1] + radius * math.cos(ph) * math.sin(th),
+               centre[2] + radius * math.sin(ph))
+        cams.append(scenes.Camera(eye=eye, target=tuple(centre)))
+    return cams
+
+
+class Renderer:
+    """Rasterizer G-buffer planes and splat targets for one scene."""
+
+    def __init__(self, sc: scenes.Scene, W: int, H: int, sigma=1.5, device="cuda"):
+        import torch
+        self.torch = torch
+        self.sc, self.W, self.H = sc, W, H
+        self.lut = torch.from_numpy(scenes.colour_lut()).to(device)
+        self.inv = float(np.float32(1.0 / (sc.lut_max - sc.lut_min)))
+        self.keys = torch.empty(W * H, dtype=torch.int64, device=device)
+        self.params = narvis.SplatParams(sigma_px=sigma, opacity=1.0, color_mode=narvis.COLOR_LUT,
+                                         color_attr=sc.lut_attr, lut=self.lut, lut_min=sc.lut_min,
+                                         lut_inv_range=self.inv)
+        self.ws = torch.empty(max(1, narvis.narvis_splat_workspace_size(sc.n, W, H, self.params)), dtype=torch.uint8,
+                              device=device)
+
+    def gbuffer(self, cam, out):
+        """out: float32 [8, H*W] view (r, g, b, depth, v'x, v'y, theta, |v'|)."""
+        g = narvis.GBuffer(keys=self.keys, depth=out[3], rgb=out[0:3], vel2d=out[4:8], lut=self.lut,
+                           lut_attr=self.sc.lut_attr, lut_min=self.sc.lut_min, lut_inv_range=self.inv,
+                           vel_attr=self.sc.vel_attr)
+        narvis.narvis_rasterize((self.sc.x, self.sc.y, self.sc.z), self.sc.attrs, self.sc.n, cam, self.W, self.H, g)
+
+    def splat(self, cam, out):
+        """out: float32 [3, H*W]."""
+        narvis.narvis_splat((self.sc.x, self.sc.y, self.sc.z), self.sc.attrs, self.sc.n, cam, self.W, self.H, out,
+                            self.params, self.ws)
+
+
+def render_dataset(r: Renderer, cams, log=print):
+    torch = r.torch
+    n = len(cams)
+    feats = torch.empty((n, 8, r.H * r.W), dtype=torch.float32, device="cuda")
+    targets = torch.empty((n, 3, r.H * r.W), dtype=torch.float32, device="cuda")
+    t0 = time.time()
+    for i, cam in enumerate(cams):
+        r.gbuffer(cam, feats[i])
+        r.splat(cam, targets[i])
+        if (i + 1) % 250 == 0:
+            torch.cuda.synchronize()
+            log(f"rendered {i + 1}/{n} views ({time.time() - t0:.1f}s)")
+    torch.cuda.synchronize()
+    return feats.view(n, 8, r.H, r.W), targets.view(n, 3, r.H, r.W)
+
+
+def init_blob(seed: int) -> np.ndarray:
+    """He-normal weights and zero biases in the library's blob order."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    shapes = [(8, 32, 3), (32, 32, 3), (32, 64, 3), (64, 64, 3), (64, 128, 3), (128, 128, 3), (128, 256, 3),
+              (256, 256, 3), (384, 128, 3), (128, 128, 3), (192, 64, 3), (64, 64, 3), (96, 32, 3), (32, 32, 3),
+              (32, 3, 1)]
+    parts = []
+    for ci, co, k in shapes:
+        parts.append((rng.standard_normal(co * ci * k * k) * math.sqrt(2.0 / (ci * k * k))).astype(np.float32))
+        parts.append(np.zeros(co, np.float32))
+    blob = np.concatenate(parts)
+    assert blob.size == narvis.narvis_net_param_count()
+    return blob
+
+
+def train(weights: narvis.NetWeights, feats, targets, steps: int, batch=16, lr=1e-3, lam_tv=1e-3, seed=0,
+          log=print, log_every=50, time_budget_s: Optional[float] = None):
+    torch = feats.__class__  # noqa: F841  (torch tensor class; keep the import local)
+    import torch
+    n, _, H, W = feats.shape
+    ws = torch.empty(narvis.narvis_train_workspace_size(batch, W, H), dtype=torch.uint8, device="cuda")
+    lossv = torch.empty(1, dtype=torch.float32, device="cuda")
+    fb = torch.empty((batch, 8, H, W), dtype=torch.float32, device="cuda")
+    tb = torch.empty((batch, 3, H, W), dtype=torch.float32, device="cuda")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    perm = torch.randperm(n, generator=gen, device="cuda")
+    pos = 0
+    losses = []
+    t0 = time.time()
+    for s in range(steps):
+        if pos + batch > n:
+            perm = torch.randperm(n, generator=gen, device="cuda")
+            pos = 0
+        idx = perm[pos:pos + batch]
+        pos += batch
+        torch.index_select(feats, 0, idx, out=fb)
+        torch.index_select(targets, 0, idx, out=tb)
+        narvis.narvis_train_step(weights, fb, tb, batch, W, H, lr, lam_tv, lossv, ws)
+        if (s + 1) % log_every == 0 or s + 1 == steps:
+            l = float(lossv.item())
+            losses.append((s + 1, l))
+            log(f"step {s + 1}/{steps} loss {l:.5f} ({time.time() - t0:.1f}s)")
+            if not math.isfinite(l):
+                raise FloatingPointError("training loss is not finite")
+        if time_budget_s is not None and time.time() - t0 > time_budget_s:
+            torch.cuda.synchronize()
+            log(f"time budget reached after {s + 1} steps")
+            break
+    torch.cuda.synchronize()
+    return losses, time.time() - t0
+
+
+def evaluate(weights: narvis.NetWeights, feats, targets, chunk=8):
+    """(psnr of the network output, psnr of the raster's RGB planes alone, ssim net, ssim raster) vs targets."""
+    import torch
+    n, _, H, W = feats.shape
+    ws = torch.empty(narvis.narvis_postprocess_workspace_size(chunk, W, H), dtype=torch.uint8, device="cuda")
+    out = torch.empty((chunk, 3, H, W), dtype=torch.float32, device="cuda")
+    p_net, p_ras, s_net, s_ras = [], [], [], []
+    for i in range(0, n, chunk):
+        b = min(chunk, n - i)
+        narvis.narvis_postprocess(weights, feats[i:i + b].contiguous(), b, W, H, out, ws)
+        y = out[:b].clamp(0.0, 1.0)
+        t = targets[i:i + b]
+        p_net.append(metrics.psnr(y, t))
+        p_ras.append(metrics.psnr(feats[i:i + b, 0:3], t))
+        s_net.append(metrics.ssim(y, t))
+        s_ras.append(metrics.ssim(feats[i:i + b, 0:3], t))
+    cat = lambda xs: torch.cat(xs).mean().item()
+    return cat(p_net), cat(p_ras), cat(s_net), cat(s_ras)
