@@ -17,6 +17,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -108,6 +109,68 @@ def cpu_baseline(sc, cam, budget_s=15.0):
                       f"single-threaded C oracle, {dt:.1f} s"}
 
 
+def frame_section(torch, log_fn, frames=12, train_views=400, train_steps=200):
+    """1080p frame of the vector-field orbit: raster G-buffer + BF16 network
+    vs the Gaussian splat.  The network is first trained by the library's own
+    kernels on 512 x 512 hemisphere views (not timed)."""
+    from paper_2407_19097_amd import metrics, narvis, scenes, train
+    sc = scenes.vector_field(device="cuda")
+    diag = math.sqrt(1.0 + 1.0 + 0.4 * 0.4)
+    r512 = train.Renderer(sc, 512, 512)
+    cams = train.hemisphere_views(train_views, (0.5, 0.5, 0.2), 0.75 * diag, seed=4)
+    feats, targets = train.render_dataset(r512, cams, log=log_fn)
+    ntr = int(0.9 * train_views)
+    w = narvis.NetWeights(train.init_blob(0))
+    _, train_s = train.train(w, feats[:ntr], targets[:ntr], train_steps, batch=16, lr=1e-3, lam_tv=1e-3,
+                             log=log_fn, log_every=100)
+    val = train.evaluate(w, feats[ntr:], targets[ntr:])
+    del feats, targets, r512
+    W, H = 1920, 1080
+    r = train.Renderer(sc, W, H)
+    feat = torch.empty((1, 8, H * W), dtype=torch.float32, device="cuda")
+    img = torch.empty((1, 3, H, W), dtype=torch.float32, device="cuda")
+    tgt = torch.empty((3, H * W), dtype=torch.float32, device="cuda")
+    ws = torch.empty(narvis.narvis_postprocess_workspace_size(1, W, H), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    picks = [int(k * len(sc.cameras) / frames) for k in range(frames)]
+    t_r, t_n, t_s, p_net, p_ras, s_net, s_ras = [], [], [], [], [], [], []
+    for rep, k in enumerate([picks[0]] + picks):  # first pass warms up
+        cam = sc.cameras[k]
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record(stream)
+        r.gbuffer(cam, feat[0])
+        ev[1].record(stream)
+        narvis.narvis_postprocess(w, feat, 1, W, H, img, ws, stream=stream)
+        ev[2].record(stream)
+        r.splat(cam, tgt)
+        ev[3].record(stream)
+        torch.cuda.synchronize()
+        if rep == 0:
+            continue
+        t_r.append(ev[0].elapsed_time(ev[1]))
+        t_n.append(ev[1].elapsed_time(ev[2]))
+        t_s.append(ev[2].elapsed_time(ev[3]))
+        y = img.clamp(0.0, 1.0)
+        t3 = tgt.view(1, 3, H, W)
+        p_net.append(metrics.psnr(y, t3).item())
+        p_ras.append(metrics.psnr(feat[:, 0:3].view(1, 3, H, W), t3).item())
+        s_net.append(metrics.ssim(y, t3).item())
+        s_ras.append(metrics.ssim(feat[:, 0:3].view(1, 3, H, W), t3).item())
+    w.close()
+    m = lambda xs: float(np.mean(xs))
+    raster_ms, net_ms, splat_ms = m(t_r), m(t_n), m(t_s)
+    net_gflop = 327360.0 * W * H / 1e9
+    return {"workload": "vector field 50M points, 1920x1080, 12 orbit frames; network trained on "
+                        f"{ntr} 512x512 hemisphere views for {train_steps} Adam steps ({train_s:.0f} s)",
+            "raster_ms": round(raster_ms, 4), "net_bf16_ms": round(net_ms, 4),
+            "frame_ms": round(raster_ms + net_ms, 4), "splat_ms": round(splat_ms, 3),
+            "frame_fraction_of_splat": round((raster_ms + net_ms) / splat_ms, 4),
+            "psnr_db": round(m(p_net), 3), "ssim": round(m(s_net), 4),
+            "psnr_raster_only_db": round(m(p_ras), 3), "ssim_raster_only": round(m(s_ras), 4),
+            "val_512_psnr_db": round(val[0], 3), "val_512_psnr_raster_only_db": round(val[1], 3),
+            "net_tflops": round(net_gflop / net_ms, 2), "net_gflop_per_frame": round(net_gflop, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +179,7 @@ def main():
     ap.add_argument("--workload", default="trajectories",
                     choices=["trajectories", "vector_field", "unit_cube", "terrain", "terrain25"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-frame", action="store_true", help="skip the 1080p raster+network vs splat frame section")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the rasterizer runs on a single device "
@@ -223,6 +287,9 @@ def main():
                      "algorithmic_bytes_per_launch": alg_bytes},
         "stream_copy_GBps": round(copy_gbps, 1),
     }
+    if not args.no_frame:
+        log("1080p frame section: training the network, then raster + network vs splat")
+        out["frame_1080p"] = frame_section(torch, log)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline(sc, cams[0])
