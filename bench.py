@@ -124,7 +124,10 @@ def frame_section(torch, log_fn, frames=12, train_views=400, train_steps=200):
     _, train_s = train.train(w, feats[:ntr], targets[:ntr], train_steps, batch=16, lr=1e-3, lam_tv=1e-3,
                              log=log_fn, log_every=100)
     val = train.evaluate(w, feats[ntr:], targets[ntr:])
-    del feats, targets, r512
+    # FP8: static activation scales calibrated on 4 training views
+    cal_ws = torch.empty(narvis.narvis_train_workspace_size(4, 512, 512), dtype=torch.uint8, device="cuda")
+    narvis.narvis_weights_calibrate_fp8(w, feats[:4].contiguous(), 4, 512, 512, cal_ws)
+    del feats, targets, r512, cal_ws
     W, H = 1920, 1080
     r = train.Renderer(sc, W, H)
     feat = torch.empty((1, 8, H * W), dtype=torch.float32, device="cuda")
@@ -134,9 +137,11 @@ def frame_section(torch, log_fn, frames=12, train_views=400, train_steps=200):
     stream = torch.cuda.current_stream()
     picks = [int(k * len(sc.cameras) / frames) for k in range(frames)]
     t_r, t_n, t_s, p_net, p_ras, s_net, s_ras = [], [], [], [], [], [], []
+    t_n8, p_net8 = [], []
+    img8 = torch.empty_like(img)
     for rep, k in enumerate([picks[0]] + picks):  # first pass warms up
         cam = sc.cameras[k]
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
         ev[0].record(stream)
         r.gbuffer(cam, feat[0])
         ev[1].record(stream)
@@ -144,9 +149,13 @@ def frame_section(torch, log_fn, frames=12, train_views=400, train_steps=200):
         ev[2].record(stream)
         r.splat(cam, tgt)
         ev[3].record(stream)
+        narvis.narvis_postprocess(w, feat, 1, W, H, img8, ws, precision=narvis.PRECISION_FP8, stream=stream)
+        ev[4].record(stream)
         torch.cuda.synchronize()
         if rep == 0:
             continue
+        t_n8.append(ev[3].elapsed_time(ev[4]))
+        p_net8.append(metrics.psnr(img8.clamp(0.0, 1.0), tgt.view(1, 3, H, W)).item())
         t_r.append(ev[0].elapsed_time(ev[1]))
         t_n.append(ev[1].elapsed_time(ev[2]))
         t_s.append(ev[2].elapsed_time(ev[3]))
@@ -168,7 +177,9 @@ def frame_section(torch, log_fn, frames=12, train_views=400, train_steps=200):
             "psnr_db": round(m(p_net), 3), "ssim": round(m(s_net), 4),
             "psnr_raster_only_db": round(m(p_ras), 3), "ssim_raster_only": round(m(s_ras), 4),
             "val_512_psnr_db": round(val[0], 3), "val_512_psnr_raster_only_db": round(val[1], 3),
-            "net_tflops": round(net_gflop / net_ms, 2), "net_gflop_per_frame": round(net_gflop, 1)}
+            "net_tflops": round(net_gflop / net_ms, 2), "net_gflop_per_frame": round(net_gflop, 1),
+            "net_fp8_ms": round(m(t_n8), 4), "frame_fp8_ms": round(raster_ms + m(t_n8), 4),
+            "psnr_fp8_db": round(m(p_net8), 3)}
 
 
 def main():

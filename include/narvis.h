@@ -264,10 +264,21 @@ narvis_status narvis_weights_read(const narvis_weights *w, float *host_blob, siz
 size_t narvis_postprocess_workspace_size(int32_t B, int32_t W, int32_t H);
 
 /* Forward pass: feat [B][8][H][W] fp32 -> img [B][3][H][W] fp32 (device).
- * precision: NARVIS_PRECISION_BF16 (FP8 is UNSUPPORTED in this build).
- * WORKSPACE if ws_bytes is too small. */
+ * precision: NARVIS_PRECISION_BF16, or NARVIS_PRECISION_FP8 after
+ * narvis_weights_calibrate_fp8 (UNSUPPORTED before it, and again after a
+ * training step changed the parameters).  WORKSPACE if ws_bytes is too
+ * small. */
 narvis_status narvis_postprocess(const narvis_weights *w, const float *feat, int32_t B, int32_t W, int32_t H,
                                  float *img, int32_t precision, void *ws, size_t ws_bytes, void *stream);
+
+/* Prepare FP8 inference (OCP e4m3 on the matrix cores, fp32 accumulation):
+ * run the bfloat16 forward on the calibration batch feat [B][8][H][W],
+ * take each layer's input max-abs as its static activation scale (max/448)
+ * and quantise each layer's weights with one scale per output channel
+ * (max |W[co]| / 448).  Needs narvis_train_workspace_size(B, W, H) bytes of
+ * workspace; synchronises the stream (the scales are read back). */
+narvis_status narvis_weights_calibrate_fp8(narvis_weights *w, const float *feat, int32_t B, int32_t W, int32_t H,
+                                           void *ws, size_t ws_bytes, void *stream);
 
 /* Device workspace bytes for narvis_train_step / narvis_train_gradients. */
 size_t narvis_train_workspace_size(int32_t B, int32_t W, int32_t H);

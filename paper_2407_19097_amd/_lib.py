@@ -88,6 +88,8 @@ SIGNATURES = {
     "narvis_postprocess_workspace_size": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "narvis_postprocess": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P,
                                           ctypes.c_int32, _P, ctypes.c_size_t, _P]),
+    "narvis_weights_calibrate_fp8": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P,
+                                                    ctypes.c_size_t, _P]),
     "narvis_train_workspace_size": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "narvis_train_step": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_float, ctypes.c_float, _P, _P, ctypes.c_size_t, _P]),

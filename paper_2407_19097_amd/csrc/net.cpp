@@ -53,6 +53,9 @@ struct LayerBuf {
     __bf16 *wf, *wb;
     float *bias;             // [rows]
     float *dw, *db;          // gradient matrix [rows][kpad] and [rows]
+    uint8_t *wq;             // FP8 forward matrix [rows][kpad]
+    float *sw;               // FP8 per-row weight scales [rows]
+    float sa;                // FP8 activation scale of the layer input
 };
 
 }  // namespace
@@ -63,7 +66,9 @@ struct narvis_weights {
     int64_t nparams;
     float *master, *grad, *m, *v;
     void *pool;              // one device allocation for everything above
+    unsigned int *amax;      // [kNumLayers] activation max-abs (calibration)
     int64_t step;
+    bool fp8_ready;
 };
 
 namespace {
@@ -216,36 +221,43 @@ SliceArgs slice(const __bf16 *in, int is, int io, __bf16 *out, int os, int oo, i
     } while (0)
 
 // Forward pass; the head writes fp32 planar [B][3][H][W] to `img`.
-hipError_t forward(const narvis_weights *w, const float *feat_planes, char *ws, const Plan &p, float *img, hipStream_t s)
+hipError_t run_conv(const narvis_weights *w, int layer, const ConvArgs &a, bool fp8, hipStream_t s)
+{
+    const LayerBuf &l = w->L[layer];
+    return fp8 ? conv_fp8(a, l.ks, l.wq, l.sw, l.sa, s) : conv(a, l.ks, s);
+}
+
+hipError_t forward(const narvis_weights *w, const float *feat_planes, char *ws, const Plan &p, float *img, hipStream_t s,
+                   bool fp8 = false)
 {
     Ctx c{ws, p};
     const int B = p.B, H = p.H, W = p.W;
     const int H1 = H / 2, W1 = W / 2, H2 = H / 4, W2 = W / 4, H3 = H / 8, W3 = W / 8;
     const LayerBuf *L = w->L;
     TRY(features(feat_planes, c.b(p.feat), B, H, W, s));
-    TRY(conv(conv_args(L[E1A], c.b(p.feat), 8, 0, c.b(p.e1a), 32, 0, B, H, W), 3, s));
-    TRY(conv(conv_args(L[E1B], c.b(p.e1a), 32, 0, c.b(p.cat1), 96, 64, B, H, W), 3, s));
+    TRY(run_conv(w, E1A, conv_args(L[E1A], c.b(p.feat), 8, 0, c.b(p.e1a), 32, 0, B, H, W), fp8, s));
+    TRY(run_conv(w, E1B, conv_args(L[E1B], c.b(p.e1a), 32, 0, c.b(p.cat1), 96, 64, B, H, W), fp8, s));
     TRY(pool2(slice(c.b(p.cat1), 96, 64, c.b(p.pool1), 32, 0, 32, B, H, W), s));
-    TRY(conv(conv_args(L[E2A], c.b(p.pool1), 32, 0, c.b(p.e2a), 64, 0, B, H1, W1), 3, s));
-    TRY(conv(conv_args(L[E2B], c.b(p.e2a), 64, 0, c.b(p.cat2), 192, 128, B, H1, W1), 3, s));
+    TRY(run_conv(w, E2A, conv_args(L[E2A], c.b(p.pool1), 32, 0, c.b(p.e2a), 64, 0, B, H1, W1), fp8, s));
+    TRY(run_conv(w, E2B, conv_args(L[E2B], c.b(p.e2a), 64, 0, c.b(p.cat2), 192, 128, B, H1, W1), fp8, s));
     TRY(pool2(slice(c.b(p.cat2), 192, 128, c.b(p.pool2), 64, 0, 64, B, H1, W1), s));
-    TRY(conv(conv_args(L[E3A], c.b(p.pool2), 64, 0, c.b(p.e3a), 128, 0, B, H2, W2), 3, s));
-    TRY(conv(conv_args(L[E3B], c.b(p.e3a), 128, 0, c.b(p.cat3), 384, 256, B, H2, W2), 3, s));
+    TRY(run_conv(w, E3A, conv_args(L[E3A], c.b(p.pool2), 64, 0, c.b(p.e3a), 128, 0, B, H2, W2), fp8, s));
+    TRY(run_conv(w, E3B, conv_args(L[E3B], c.b(p.e3a), 128, 0, c.b(p.cat3), 384, 256, B, H2, W2), fp8, s));
     TRY(pool2(slice(c.b(p.cat3), 384, 256, c.b(p.pool3), 128, 0, 128, B, H2, W2), s));
-    TRY(conv(conv_args(L[E4A], c.b(p.pool3), 128, 0, c.b(p.e4a), 256, 0, B, H3, W3), 3, s));
-    TRY(conv(conv_args(L[E4B], c.b(p.e4a), 256, 0, c.b(p.e4b), 256, 0, B, H3, W3), 3, s));
+    TRY(run_conv(w, E4A, conv_args(L[E4A], c.b(p.pool3), 128, 0, c.b(p.e4a), 256, 0, B, H3, W3), fp8, s));
+    TRY(run_conv(w, E4B, conv_args(L[E4B], c.b(p.e4a), 256, 0, c.b(p.e4b), 256, 0, B, H3, W3), fp8, s));
     TRY(upsample2(slice(c.b(p.e4b), 256, 0, c.b(p.cat3), 384, 0, 256, B, H3, W3), s));
-    TRY(conv(conv_args(L[D3A], c.b(p.cat3), 384, 0, c.b(p.d3a), 128, 0, B, H2, W2), 3, s));
-    TRY(conv(conv_args(L[D3B], c.b(p.d3a), 128, 0, c.b(p.d3b), 128, 0, B, H2, W2), 3, s));
+    TRY(run_conv(w, D3A, conv_args(L[D3A], c.b(p.cat3), 384, 0, c.b(p.d3a), 128, 0, B, H2, W2), fp8, s));
+    TRY(run_conv(w, D3B, conv_args(L[D3B], c.b(p.d3a), 128, 0, c.b(p.d3b), 128, 0, B, H2, W2), fp8, s));
     TRY(upsample2(slice(c.b(p.d3b), 128, 0, c.b(p.cat2), 192, 0, 128, B, H2, W2), s));
-    TRY(conv(conv_args(L[D2A], c.b(p.cat2), 192, 0, c.b(p.d2a), 64, 0, B, H1, W1), 3, s));
-    TRY(conv(conv_args(L[D2B], c.b(p.d2a), 64, 0, c.b(p.d2b), 64, 0, B, H1, W1), 3, s));
+    TRY(run_conv(w, D2A, conv_args(L[D2A], c.b(p.cat2), 192, 0, c.b(p.d2a), 64, 0, B, H1, W1), fp8, s));
+    TRY(run_conv(w, D2B, conv_args(L[D2B], c.b(p.d2a), 64, 0, c.b(p.d2b), 64, 0, B, H1, W1), fp8, s));
     TRY(upsample2(slice(c.b(p.d2b), 64, 0, c.b(p.cat1), 96, 0, 64, B, H1, W1), s));
-    TRY(conv(conv_args(L[D1A], c.b(p.cat1), 96, 0, c.b(p.d1a), 32, 0, B, H, W), 3, s));
-    TRY(conv(conv_args(L[D1B], c.b(p.d1a), 32, 0, c.b(p.d1b), 32, 0, B, H, W), 3, s));
+    TRY(run_conv(w, D1A, conv_args(L[D1A], c.b(p.cat1), 96, 0, c.b(p.d1a), 32, 0, B, H, W), fp8, s));
+    TRY(run_conv(w, D1B, conv_args(L[D1B], c.b(p.d1a), 32, 0, c.b(p.d1b), 32, 0, B, H, W), fp8, s));
     ConvArgs head = conv_args(L[HEAD], c.b(p.d1b), 32, 0, nullptr, 0, 0, B, H, W);
     head.out_f32 = img;
-    TRY(conv(head, 1, s));
+    TRY(run_conv(w, HEAD, head, fp8, s));
     return hipSuccess;
 }
 
@@ -403,7 +415,7 @@ extern "C" narvis_status narvis_weights_create(const float *host_blob, size_t co
     const uint64_t blob_bytes = align256((uint64_t)w->nparams * 4);
     o = 4 * blob_bytes;
     int64_t boff = 0;
-    std::vector<uint64_t> offs(kNumLayers * 5);
+    std::vector<uint64_t> offs(kNumLayers * 7);
     for (int i = 0; i < kNumLayers; ++i) {
         const LayerDef &d = kLayers[i];
         LayerBuf &l = w->L[i];
@@ -420,12 +432,17 @@ extern "C" narvis_status narvis_weights_create(const float *host_blob, size_t co
         boff += (int64_t)d.cout * d.cin * d.ks * d.ks;
         l.blob_b = boff;
         boff += d.cout;
-        offs[i * 5 + 0] = o; o = align256(o + (uint64_t)l.rows * l.kpad * 2);
-        offs[i * 5 + 1] = o; o = align256(o + (uint64_t)l.brows * l.bkpad * 2);
-        offs[i * 5 + 2] = o; o = align256(o + (uint64_t)l.rows * 4);
-        offs[i * 5 + 3] = o; o = align256(o + (uint64_t)l.rows * l.kpad * 4);
-        offs[i * 5 + 4] = o; o = align256(o + (uint64_t)l.rows * 4);
+        offs[i * 7 + 0] = o; o = align256(o + (uint64_t)l.rows * l.kpad * 2);
+        offs[i * 7 + 1] = o; o = align256(o + (uint64_t)l.brows * l.bkpad * 2);
+        offs[i * 7 + 2] = o; o = align256(o + (uint64_t)l.rows * 4);
+        offs[i * 7 + 3] = o; o = align256(o + (uint64_t)l.rows * l.kpad * 4);
+        offs[i * 7 + 4] = o; o = align256(o + (uint64_t)l.rows * 4);
+        offs[i * 7 + 5] = o; o = align256(o + (uint64_t)l.rows * l.kpad);
+        offs[i * 7 + 6] = o; o = align256(o + (uint64_t)l.rows * 4);
+        l.sa = 1.0f;
     }
+    const uint64_t off_amax = o;
+    o = align256(o + kNumLayers * 4);
     if (hipMalloc(&w->pool, o) != hipSuccess) {
         delete w;
         return NARVIS_ERR_OUT_OF_MEMORY;
@@ -437,12 +454,16 @@ extern "C" narvis_status narvis_weights_create(const float *host_blob, size_t co
     w->v = reinterpret_cast<float *>(base + 3 * blob_bytes);
     for (int i = 0; i < kNumLayers; ++i) {
         LayerBuf &l = w->L[i];
-        l.wf = reinterpret_cast<__bf16 *>(base + offs[i * 5 + 0]);
-        l.wb = reinterpret_cast<__bf16 *>(base + offs[i * 5 + 1]);
-        l.bias = reinterpret_cast<float *>(base + offs[i * 5 + 2]);
-        l.dw = reinterpret_cast<float *>(base + offs[i * 5 + 3]);
-        l.db = reinterpret_cast<float *>(base + offs[i * 5 + 4]);
+        l.wf = reinterpret_cast<__bf16 *>(base + offs[i * 7 + 0]);
+        l.wb = reinterpret_cast<__bf16 *>(base + offs[i * 7 + 1]);
+        l.bias = reinterpret_cast<float *>(base + offs[i * 7 + 2]);
+        l.dw = reinterpret_cast<float *>(base + offs[i * 7 + 3]);
+        l.db = reinterpret_cast<float *>(base + offs[i * 7 + 4]);
+        l.wq = reinterpret_cast<uint8_t *>(base + offs[i * 7 + 5]);
+        l.sw = reinterpret_cast<float *>(base + offs[i * 7 + 6]);
     }
+    w->amax = reinterpret_cast<unsigned int *>(base + off_amax);
+    w->fp8_ready = false;
     hipError_t e = hipMemset(w->pool, 0, o);
     if (e == hipSuccess) e = hipMemcpy(w->master, host_blob, count * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = refresh(w, nullptr);
@@ -486,13 +507,15 @@ extern "C" narvis_status narvis_postprocess(const narvis_weights *w, const float
                                             float *img, int32_t precision, void *ws, size_t ws_bytes, void *stream)
 {
     if (!w || !feat || !img || !ws || !dims_ok(B, W, H)) return NARVIS_ERR_INVALID_ARG;
-    if (precision != NARVIS_PRECISION_BF16) return NARVIS_ERR_UNSUPPORTED;
+    if (precision != NARVIS_PRECISION_BF16 && precision != NARVIS_PRECISION_FP8) return NARVIS_ERR_INVALID_ARG;
+    if (precision == NARVIS_PRECISION_FP8 && !w->fp8_ready) return NARVIS_ERR_UNSUPPORTED;
     if ((reinterpret_cast<uintptr_t>(ws) & 255u) || (reinterpret_cast<uintptr_t>(feat) & 3u) ||
         (reinterpret_cast<uintptr_t>(img) & 3u))
         return NARVIS_ERR_INVALID_ARG;
     const Plan p = make_plan(B, H, W, false);
     if (ws_bytes < p.bytes) return NARVIS_ERR_WORKSPACE;
-    return st(forward(w, feat, static_cast<char *>(ws), p, img, static_cast<hipStream_t>(stream)));
+    return st(forward(w, feat, static_cast<char *>(ws), p, img, static_cast<hipStream_t>(stream),
+                      precision == NARVIS_PRECISION_FP8));
 }
 
 extern "C" size_t narvis_train_workspace_size(int32_t B, int32_t W, int32_t H)
@@ -553,5 +576,42 @@ extern "C" narvis_status narvis_train_step(narvis_weights *w, const float *feat,
     const float c2 = (float)(1.0 - std::pow(0.999, (double)w->step));
     hipError_t e = adam(w->master, w->grad, w->m, w->v, w->nparams, lr, b1, b2, 1e-8f, c1, c2, s);
     if (e == hipSuccess) e = refresh(w, s);
+    w->fp8_ready = false;  // the FP8 copies describe the old parameters
     return st(e);
+}
+
+extern "C" narvis_status narvis_weights_calibrate_fp8(narvis_weights *w, const float *feat, int32_t B, int32_t W,
+                                                      int32_t H, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!w || !feat || !ws || !dims_ok(B, W, H) || (reinterpret_cast<uintptr_t>(ws) & 255u))
+        return NARVIS_ERR_INVALID_ARG;
+    const Plan p = make_plan(B, H, W, true);
+    if (ws_bytes < p.bytes) return NARVIS_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char *base = static_cast<char *>(ws);
+    hipError_t e = forward(w, feat, base, p, reinterpret_cast<float *>(base + p.out), s, false);
+    // input tensor of every layer, in layer order
+    const struct { uint64_t off; int64_t px; int ch; } in[kNumLayers] = {
+        {p.feat, p.P[0], 8},    {p.e1a, p.P[0], 32},   {p.pool1, p.P[1], 32}, {p.e2a, p.P[1], 64},
+        {p.pool2, p.P[2], 64},  {p.e3a, p.P[2], 128},  {p.pool3, p.P[3], 128}, {p.e4a, p.P[3], 256},
+        {p.cat3, p.P[2], 384},  {p.d3a, p.P[2], 128},  {p.cat2, p.P[1], 192}, {p.d2a, p.P[1], 64},
+        {p.cat1, p.P[0], 96},   {p.d1a, p.P[0], 32},   {p.d1b, p.P[0], 32}};
+    if (e == hipSuccess) e = hipMemsetAsync(w->amax, 0, kNumLayers * 4, s);
+    for (int i = 0; i < kNumLayers && e == hipSuccess; ++i)
+        e = absmax_bf16(reinterpret_cast<const __bf16 *>(base + in[i].off), in[i].px * in[i].ch, w->amax + i, s);
+    unsigned int host[kNumLayers];
+    if (e == hipSuccess) e = hipMemcpyAsync(host, w->amax, sizeof(host), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return NARVIS_ERR_DEVICE;
+    for (int i = 0; i < kNumLayers && e == hipSuccess; ++i) {
+        LayerBuf &l = w->L[i];
+        float m;
+        std::memcpy(&m, &host[i], 4);
+        l.sa = (m > 0.0f && std::isfinite(m)) ? m / 448.0f : 1.0f;
+        e = quant_weights(w->master + l.blob_w, l.cout, l.cin, l.ks, l.rows, l.kpad, l.wq, l.sw, s);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return NARVIS_ERR_DEVICE;
+    w->fp8_ready = true;
+    return NARVIS_OK;
 }

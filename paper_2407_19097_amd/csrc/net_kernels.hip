@@ -17,6 +17,8 @@
 // channels of one pixel: one 8-byte store per fragment.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "net_internal.h"
 
 #pragma clang fp contract(off)
@@ -561,6 +563,173 @@ __global__ __launch_bounds__(256) void k_zero_bf16(__bf16 *p, int64_t n)
     if (i < n) p[i] = (__bf16)0.0f;
 }
 
+// ---------------------------------------------------------------------------
+// FP8 (OCP e4m3, largest finite 448) inference: per-output-channel weight
+// scales, one static activation scale per layer input, fp32 accumulation.
+// y = (sum_k q_w[co][k] * q_x[p][k]) * s_w[co] * s_a + b[co]
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ long pack_fp8x8(const float (&f)[8])
+{
+    int lo = __builtin_amdgcn_cvt_pk_fp8_f32(f[0], f[1], 0, false);
+    lo = __builtin_amdgcn_cvt_pk_fp8_f32(f[2], f[3], lo, true);
+    int hi = __builtin_amdgcn_cvt_pk_fp8_f32(f[4], f[5], 0, false);
+    hi = __builtin_amdgcn_cvt_pk_fp8_f32(f[6], f[7], hi, true);
+    return (long)(uint32_t)lo | ((long)(uint32_t)hi << 32);
+}
+
+__device__ __forceinline__ float clamp448(float v) { return fminf(fmaxf(v, -448.0f), 448.0f); }
+
+template <int FCO, int FPX, int KS>
+__global__ __launch_bounds__(64 * kWaves) void k_conv_fp8(ConvArgs a, const uint8_t *wq, const float *sw, float sa)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, r = lane & 15;
+    constexpr int TP = 16 * FPX;
+    const int64_t P = (int64_t)a.B * a.H * a.W;
+    const int64_t p0 = ((int64_t)blockIdx.x * kWaves + wave) * TP;
+    const int co0 = blockIdx.y * 16 * FCO;
+    if (p0 >= P) return;
+    const float inv_sa = 1.0f / sa;
+    int bb[FPX], yy[FPX], xx[FPX];
+    bool pv[FPX];
+#pragma unroll
+    for (int f = 0; f < FPX; ++f) {
+        const int64_t p = p0 + 16 * f + r;
+        pv[f] = p < P;
+        const int64_t pc = pv[f] ? p : 0;
+        const int64_t hw = (int64_t)a.H * a.W;
+        bb[f] = (int)(pc / hw);
+        const int64_t rem = pc - (int64_t)bb[f] * hw;
+        yy[f] = (int)(rem / a.W);
+        xx[f] = (int)(rem - (int64_t)yy[f] * a.W);
+    }
+    f32x4 acc[FCO][FPX];
+#pragma unroll
+    for (int i = 0; i < FCO; ++i)
+#pragma unroll
+        for (int f = 0; f < FPX; ++f) acc[i][f] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    const int K = KS * KS * a.Cin;
+    for (int k0 = 0; k0 < a.Kpad; k0 += 32) {
+        const int kk = k0 + 8 * g;
+        const bool kvalid = kk < K;
+        const int tap = kvalid ? kk / a.Cin : 0;
+        const int ci = kvalid ? kk - tap * a.Cin : 0;
+        const int dy = KS == 3 ? tap / 3 - 1 : 0;
+        const int dx = KS == 3 ? tap % 3 - 1 : 0;
+        long av[FCO], bv[FPX];
+#pragma unroll
+        for (int i = 0; i < FCO; ++i) av[i] = *reinterpret_cast<const long *>(wq + (int64_t)(co0 + 16 * i + r) * a.Kpad + kk);
+#pragma unroll
+        for (int f = 0; f < FPX; ++f) {
+            const int y2 = yy[f] + dy, x2 = xx[f] + dx;
+            const bool ok = kvalid && pv[f] && y2 >= 0 && y2 < a.H && x2 >= 0 && x2 < a.W;
+            bv[f] = 0;
+            if (ok) {
+                const int64_t q = ((int64_t)bb[f] * a.H + y2) * a.W + x2;
+                const bf16x8 v = load8(a.in + q * a.in_stride + a.in_off + ci);
+                float t[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) t[j] = clamp448((float)v[j] * inv_sa);
+                bv[f] = pack_fp8x8(t);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < FCO; ++i)
+#pragma unroll
+            for (int f = 0; f < FPX; ++f)
+                acc[i][f] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av[i], bv[f], acc[i][f], 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < FCO; ++i) {
+        const int cb = co0 + 16 * i + 4 * g;
+        float scale[4], bias[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            scale[e] = sw[cb + e] * sa;
+            bias[e] = a.bias ? a.bias[cb + e] : 0.0f;
+        }
+#pragma unroll
+        for (int f = 0; f < FPX; ++f) {
+            if (!pv[f]) continue;
+            const int64_t p = p0 + 16 * f + r;
+            float v[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                v[e] = acc[i][f][e] * scale[e] + bias[e];
+                if (a.relu) v[e] = fmaxf(v[e], 0.0f);
+            }
+            if (a.out_f32) {
+                const int64_t hw = (int64_t)a.H * a.W;
+                const int64_t b = p / hw, pix = p - b * hw;
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (cb + e < a.Cout) a.out_f32[(b * a.Cout + cb + e) * hw + pix] = v[e];
+            } else if (cb < a.Cout) {
+                __bf16 *o = a.out + p * a.out_stride + a.out_off + cb;
+                typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+                bf16x4 w4;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) w4[e] = (__bf16)v[e];
+                *reinterpret_cast<bf16x4 *>(o) = w4;
+            }
+        }
+    }
+}
+
+// per output row: s_w = max |W[co][k]| / 448 (1 for an all-zero row), q = fp8(W / s_w)
+__global__ __launch_bounds__(256) void k_quant_weights(const float *master, int Cout, int Cin, int KS, int rows,
+                                                       int kpad, uint8_t *wq, float *sw)
+{
+    __shared__ float red[256];
+    const int co = blockIdx.x;
+    const int T = KS * KS;
+    float m = 0.0f;
+    for (int k = threadIdx.x; k < kpad; k += 256) {
+        if (co < Cout && k < T * Cin) {
+            const int tap = k / Cin, ci = k % Cin;
+            m = fmaxf(m, fabsf(master[((int64_t)co * Cin + ci) * T + tap]));
+        }
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int s2 = 128; s2 > 0; s2 >>= 1) {
+        if (threadIdx.x < s2) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s2]);
+        __syncthreads();
+    }
+    const float mx = red[0];
+    const float scale = mx > 0.0f ? mx / 448.0f : 1.0f;
+    if (threadIdx.x == 0) sw[co] = scale;
+    for (int k = threadIdx.x; k < kpad; k += 256) {
+        float v = 0.0f;
+        if (co < Cout && k < T * Cin) {
+            const int tap = k / Cin, ci = k % Cin;
+            v = clamp448(master[((int64_t)co * Cin + ci) * T + tap] / scale);
+        }
+        const int b = __builtin_amdgcn_cvt_pk_fp8_f32(v, 0.0f, 0, false);
+        wq[(int64_t)co * kpad + k] = (uint8_t)(b & 0xFF);
+    }
+}
+
+// max |x| over a bf16 buffer (order-free: atomic max on the bit pattern of a
+// non-negative float)
+__global__ __launch_bounds__(256) void k_absmax_bf16(const __bf16 *x, int64_t n, unsigned int *out)
+{
+    __shared__ float red[256];
+    float m = 0.0f;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const float v = fabsf((float)x[i]);
+        if (v == v) m = fmaxf(m, v);
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int s2 = 128; s2 > 0; s2 >>= 1) {
+        if (threadIdx.x < s2) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s2]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(out, __float_as_uint(red[0]));
+}
+
 unsigned nblocks(int64_t n, int per = 256) { return (unsigned)((n + per - 1) / per); }
 
 }  // namespace
@@ -587,6 +756,40 @@ hipError_t conv(const ConvArgs &a, int KS, hipStream_t s)
         if (KS == 3) hipLaunchKernelGGL((k_conv<1, 4, 3>), grid, dim3(64 * kWaves), 0, s, a);
         else hipLaunchKernelGGL((k_conv<1, 4, 1>), grid, dim3(64 * kWaves), 0, s, a);
     }
+    return hipGetLastError();
+}
+
+hipError_t conv_fp8(const ConvArgs &a, int KS, const uint8_t *wq, const float *sw, float sa, hipStream_t s)
+{
+    const int64_t P = (int64_t)a.B * a.H * a.W;
+    const int cop = a.Cout_pad;
+    if (cop % 64 == 0) {
+        dim3 grid(nblocks(P, 32 * kWaves), cop / 64);
+        if (KS == 3) hipLaunchKernelGGL((k_conv_fp8<4, 2, 3>), grid, dim3(64 * kWaves), 0, s, a, wq, sw, sa);
+        else hipLaunchKernelGGL((k_conv_fp8<4, 2, 1>), grid, dim3(64 * kWaves), 0, s, a, wq, sw, sa);
+    } else if (cop % 32 == 0) {
+        dim3 grid(nblocks(P, 64 * kWaves), cop / 32);
+        if (KS == 3) hipLaunchKernelGGL((k_conv_fp8<2, 4, 3>), grid, dim3(64 * kWaves), 0, s, a, wq, sw, sa);
+        else hipLaunchKernelGGL((k_conv_fp8<2, 4, 1>), grid, dim3(64 * kWaves), 0, s, a, wq, sw, sa);
+    } else {
+        dim3 grid(nblocks(P, 64 * kWaves), cop / 16);
+        if (KS == 3) hipLaunchKernelGGL((k_conv_fp8<1, 4, 3>), grid, dim3(64 * kWaves), 0, s, a, wq, sw, sa);
+        else hipLaunchKernelGGL((k_conv_fp8<1, 4, 1>), grid, dim3(64 * kWaves), 0, s, a, wq, sw, sa);
+    }
+    return hipGetLastError();
+}
+
+hipError_t quant_weights(const float *master, int Cout, int Cin, int KS, int rows, int kpad, uint8_t *wq, float *sw,
+                         hipStream_t s)
+{
+    hipLaunchKernelGGL(k_quant_weights, dim3((unsigned)rows), dim3(256), 0, s, master, Cout, Cin, KS, rows, kpad, wq, sw);
+    return hipGetLastError();
+}
+
+hipError_t absmax_bf16(const __bf16 *x, int64_t n, unsigned int *out, hipStream_t s)
+{
+    const int64_t blocks = std::min<int64_t>(4096, (n + 255) / 256);
+    hipLaunchKernelGGL(k_absmax_bf16, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(256), 0, s, x, n, out);
     return hipGetLastError();
 }
 

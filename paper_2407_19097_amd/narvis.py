@@ -257,3 +257,9 @@ def narvis_train_gradients(weights: NetWeights, feat, target, B: int, W: int, H:
     _lib.check(_lib.load().narvis_train_gradients(weights.handle, _ptr(feat), _ptr(target), B, W, H, float(lam_tv),
                                                   _ptr(grad_out), _ptr(loss_out), _ptr(workspace), nbytes,
                                                   _stream_ptr(stream)), "narvis_train_gradients")
+
+
+def narvis_weights_calibrate_fp8(weights: NetWeights, feat, B: int, W: int, H: int, workspace, stream=None) -> None:
+    nbytes = workspace.numel() * workspace.element_size()
+    _lib.check(_lib.load().narvis_weights_calibrate_fp8(weights.handle, _ptr(feat), B, W, H, _ptr(workspace), nbytes,
+                                                        _stream_ptr(stream)), "narvis_weights_calibrate_fp8")

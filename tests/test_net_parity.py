@@ -152,3 +152,30 @@ def test_training_reduces_loss():
     assert all(np.isfinite(losses))
     assert losses[-1] < 0.8 * losses[0]
     w.close()
+
+
+@pytest.mark.parametrize("B,H,W", [(1, 32, 32), (2, 64, 96)])
+def test_fp8_forward_matches_oracle(B, H, W):
+    """FP8 (e4m3, per-output-channel weight scales, static per-layer
+    activation scales calibrated on the batch itself) within 6e-2 max-abs of
+    the FP64 forward."""
+    announce(f"FP8 network forward B={B} {H}x{W}")
+    P = random_net(B * 77 + H)
+    rng = np.random.default_rng(W + 5)
+    planes = random_planes(rng, B, H, W)
+    w = narvis.NetWeights(onet.to_blob(P).astype(np.float32))
+    feat = torch.from_numpy(planes).cuda()
+    ws = torch.empty(narvis.narvis_train_workspace_size(B, W, H), dtype=torch.uint8, device="cuda")
+    img = torch.empty((B, 3, H, W), dtype=torch.float32, device="cuda")
+    with pytest.raises(narvis.NarvisError):
+        narvis.narvis_postprocess(w, feat, B, W, H, img, ws, precision=narvis.PRECISION_FP8)
+    narvis.narvis_weights_calibrate_fp8(w, feat, B, W, H, ws)
+    narvis.narvis_postprocess(w, feat, B, W, H, img, ws, precision=narvis.PRECISION_FP8)
+    torch.cuda.synchronize()
+    got = img.cpu().numpy().astype(np.float64)
+    want, _ = onet.forward(P, onet.features(planes))
+    err = np.abs(got - want).max()
+    print(f"  FP8 max |gpu - fp64| = {err:.3g}", flush=True)
+    assert np.isfinite(got).all()
+    assert err <= 6e-2
+    w.close()

@@ -29,6 +29,7 @@ def run_pair(sc, cams, with_planes=True):
     print(f"  host copy {time.time() - t0:.1f}s", flush=True)
     inv = np.float32(1.0 / (sc.lut_max - sc.lut_min))
     lut = scenes.colour_lut()
+    with_planes = with_planes and sc.lut_attr >= 0
     for cam in cams:
         g = narvis.GBuffer.allocate(W, H, nattr=len(sc.attrs), rgb=with_planes, vel2d=with_planes and sc.vel_attr >= 0)
         if with_planes:
@@ -68,3 +69,13 @@ def test_trajectories_350m_full():
     announce("trajectories 3.5M particles x 100 steps = 350M points, 1920x1080, fly-through frame 60 + overview")
     sc = scenes.trajectories(device="cuda")
     run_pair(sc, [sc.cameras[60], sc.cameras[-1]], with_planes=True)
+
+
+def test_terrain_1b_full_and_quarter():
+    announce("terrain 1B points (RGBA u8, strided AoS views), 3840x2160, and its every-4th-point variant")
+    from paper_2407_19097_amd import scenes as sc_mod
+    sc = sc_mod.terrain(device="cuda")
+    run_pair(sc, [sc.cameras[0]], with_planes=False)
+    quarter = sc_mod.subsample(sc, 4)
+    del sc
+    run_pair(quarter, [quarter.cameras[0]], with_planes=False)
