@@ -221,10 +221,14 @@ SliceArgs slice(const __bf16 *in, int is, int io, __bf16 *out, int os, int oo, i
     } while (0)
 
 // Forward pass; the head writes fp32 planar [B][3][H][W] to `img`.
+// Under FP8 the first layer (raw G-buffer features of mixed ranges) and the
+// head (the output image) stay in bfloat16; the 13 layers between run in FP8.
+bool fp8_layer(int layer) { return layer != E1A && layer != HEAD; }
+
 hipError_t run_conv(const narvis_weights *w, int layer, const ConvArgs &a, bool fp8, hipStream_t s)
 {
     const LayerBuf &l = w->L[layer];
-    return fp8 ? conv_fp8(a, l.ks, l.wq, l.sw, l.sa, s) : conv(a, l.ks, s);
+    return (fp8 && fp8_layer(layer)) ? conv_fp8(a, l.ks, l.wq, l.sw, l.sa, s) : conv(a, l.ks, s);
 }
 
 hipError_t forward(const narvis_weights *w, const float *feat_planes, char *ws, const Plan &p, float *img, hipStream_t s,
