@@ -47,9 +47,59 @@ __device__ __forceinline__ bf16x8 load8(const __bf16 *p) { return *reinterpret_c
 // convolution (forward and input-gradient)
 // ---------------------------------------------------------------------------
 
-template <int FCO, int FPX, int KS>
-__global__ __launch_bounds__(64 * kWaves) void k_conv(ConvArgs a)
+// Convolution kernel (bf16 or FP8 operands).  Each wave computes FCO x 16
+// output channels for FPX x 16 pixels; the next k-step's operands are loaded
+// while the current MFMAs run.  A lane's group of 8 consecutive k values
+// (one tap, 8 input channels) is tracked incrementally as (tap, ci).
+template <bool FP8>
+struct ConvOps;
+
+template <>
+struct ConvOps<false> {
+    typedef bf16x8 A;
+    typedef bf16x8 Bv;
+    static __device__ __forceinline__ A load_a(const ConvArgs &a, const uint8_t *, int row, int kk)
+    {
+        return load8(a.wt + (int64_t)row * a.Kpad + kk);
+    }
+    static __device__ __forceinline__ Bv zero() { return zero8(); }
+    static __device__ __forceinline__ Bv to_b(bf16x8 v, float) { return v; }
+    static __device__ __forceinline__ f32x4 mfma(A x, Bv y, f32x4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, c, 0, 0, 0);
+    }
+};
+
+template <>
+struct ConvOps<true> {
+    typedef long A;
+    typedef long Bv;
+    static __device__ __forceinline__ A load_a(const ConvArgs &a, const uint8_t *wq, int row, int kk)
+    {
+        return *reinterpret_cast<const long *>(wq + (int64_t)row * a.Kpad + kk);
+    }
+    static __device__ __forceinline__ Bv zero() { return 0; }
+    static __device__ __forceinline__ Bv to_b(bf16x8 v, float inv_sa)
+    {
+        float t[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) t[j] = fminf(fmaxf((float)v[j] * inv_sa, -448.0f), 448.0f);
+        int lo = __builtin_amdgcn_cvt_pk_fp8_f32(t[0], t[1], 0, false);
+        lo = __builtin_amdgcn_cvt_pk_fp8_f32(t[2], t[3], lo, true);
+        int hi = __builtin_amdgcn_cvt_pk_fp8_f32(t[4], t[5], 0, false);
+        hi = __builtin_amdgcn_cvt_pk_fp8_f32(t[6], t[7], hi, true);
+        return (long)(uint32_t)lo | ((long)(uint32_t)hi << 32);
+    }
+    static __device__ __forceinline__ f32x4 mfma(A x, Bv y, f32x4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(x, y, c, 0, 0, 0);
+    }
+};
+
+template <int FCO, int FPX, int KS, bool FP8>
+__global__ __launch_bounds__(64 * kWaves) void k_conv(ConvArgs a, const uint8_t *wq, const float *sw, float sa)
 {
+    typedef ConvOps<FP8> Ops;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, r = lane & 15;
     constexpr int TP = 16 * FPX;
@@ -57,6 +107,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_conv(ConvArgs a)
     const int64_t p0 = ((int64_t)blockIdx.x * kWaves + wave) * TP;
     const int co0 = blockIdx.y * 16 * FCO;
     if (p0 >= P) return;  // whole wave idle (no barriers in this kernel)
+    const float inv_sa = FP8 ? 1.0f / sa : 1.0f;
 
     int bb[FPX], yy[FPX], xx[FPX];
     bool pv[FPX];
@@ -77,46 +128,67 @@ __global__ __launch_bounds__(64 * kWaves) void k_conv(ConvArgs a)
 #pragma unroll
         for (int f = 0; f < FPX; ++f) acc[i][f] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 
-    const int K = KS * KS * a.Cin;
-    for (int k0 = 0; k0 < a.Kpad; k0 += 32) {
-        const int kk = k0 + 8 * g;
-        const bool kvalid = kk < K;
-        const int tap = kvalid ? kk / a.Cin : 0;
-        const int ci = kvalid ? kk - tap * a.Cin : 0;
+    constexpr int T = KS * KS;
+    auto load_step = [&](int kk, int tap, int ci, typename Ops::A (&A)[FCO], typename Ops::Bv (&Bv)[FPX]) {
+#pragma unroll
+        for (int i = 0; i < FCO; ++i) A[i] = Ops::load_a(a, wq, co0 + 16 * i + r, kk);
+        const bool kvalid = tap < T;
         const int dy = KS == 3 ? tap / 3 - 1 : 0;
         const int dx = KS == 3 ? tap % 3 - 1 : 0;
-        bf16x8 av[FCO], bv[FPX];
-#pragma unroll
-        for (int i = 0; i < FCO; ++i) av[i] = load8(a.wt + (int64_t)(co0 + 16 * i + r) * a.Kpad + kk);
 #pragma unroll
         for (int f = 0; f < FPX; ++f) {
             const int y2 = yy[f] + dy, x2 = xx[f] + dx;
             const bool ok = kvalid && pv[f] && y2 >= 0 && y2 < a.H && x2 >= 0 && x2 < a.W;
-            bv[f] = zero8();
+            Bv[f] = Ops::zero();
             if (ok) {
                 const int64_t q = ((int64_t)bb[f] * a.H + y2) * a.W + x2;
-                bv[f] = load8(a.in + q * a.in_stride + a.in_off + ci);
+                bf16x8 v = load8(a.in + q * a.in_stride + a.in_off + ci);
                 if (a.in_mask) {
                     const bf16x8 m = load8(a.in_mask + q * a.mask_stride + a.mask_off + ci);
 #pragma unroll
                     for (int j = 0; j < 8; ++j)
-                        if (!((float)m[j] > 0.0f)) bv[f][j] = (__bf16)0.0f;
+                        if (!((float)m[j] > 0.0f)) v[j] = (__bf16)0.0f;
                 }
+                Bv[f] = Ops::to_b(v, inv_sa);
             }
         }
+    };
+    int tap = (8 * g) / a.Cin;
+    int ci = 8 * g - tap * a.Cin;
+    typename Ops::A av[FCO], an[FCO];
+    typename Ops::Bv bv[FPX], bn[FPX];
+    load_step(8 * g, tap, ci, av, bv);
+    for (int k0 = 0; k0 < a.Kpad; k0 += 32) {
+        int ntap = tap, nci = ci + 32;
+        while (nci >= a.Cin) {
+            nci -= a.Cin;
+            ++ntap;
+        }
+        const bool more = k0 + 32 < a.Kpad;
+        if (more) load_step(k0 + 32 + 8 * g, ntap, nci, an, bn);
 #pragma unroll
         for (int i = 0; i < FCO; ++i)
 #pragma unroll
-            for (int f = 0; f < FPX; ++f)
-                acc[i][f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[f], acc[i][f], 0, 0, 0);
+            for (int f = 0; f < FPX; ++f) acc[i][f] = Ops::mfma(av[i], bv[f], acc[i][f]);
+        if (more) {
+#pragma unroll
+            for (int i = 0; i < FCO; ++i) av[i] = an[i];
+#pragma unroll
+            for (int f = 0; f < FPX; ++f) bv[f] = bn[f];
+            tap = ntap;
+            ci = nci;
+        }
     }
     // epilogue: lane holds channels co0 + 16 i + 4 g + e of pixel p0 + 16 f + r
 #pragma unroll
     for (int i = 0; i < FCO; ++i) {
         const int cb = co0 + 16 * i + 4 * g;
-        float bias[4];
+        float bias[4], scale[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) bias[e] = a.bias ? a.bias[cb + e] : 0.0f;
+        for (int e = 0; e < 4; ++e) {
+            bias[e] = a.bias ? a.bias[cb + e] : 0.0f;
+            scale[e] = FP8 ? sw[cb + e] * sa : 1.0f;
+        }
 #pragma unroll
         for (int f = 0; f < FPX; ++f) {
             if (!pv[f]) continue;
@@ -124,7 +196,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_conv(ConvArgs a)
             float v[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                v[e] = acc[i][f][e] + bias[e];
+                v[e] = FP8 ? acc[i][f][e] * scale[e] + bias[e] : acc[i][f][e] + bias[e];
                 if (a.relu) v[e] = fmaxf(v[e], 0.0f);
             }
             if (a.out_f32) {
@@ -569,113 +641,7 @@ __global__ __launch_bounds__(256) void k_zero_bf16(__bf16 *p, int64_t n)
 // y = (sum_k q_w[co][k] * q_x[p][k]) * s_w[co] * s_a + b[co]
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ long pack_fp8x8(const float (&f)[8])
-{
-    int lo = __builtin_amdgcn_cvt_pk_fp8_f32(f[0], f[1], 0, false);
-    lo = __builtin_amdgcn_cvt_pk_fp8_f32(f[2], f[3], lo, true);
-    int hi = __builtin_amdgcn_cvt_pk_fp8_f32(f[4], f[5], 0, false);
-    hi = __builtin_amdgcn_cvt_pk_fp8_f32(f[6], f[7], hi, true);
-    return (long)(uint32_t)lo | ((long)(uint32_t)hi << 32);
-}
-
 __device__ __forceinline__ float clamp448(float v) { return fminf(fmaxf(v, -448.0f), 448.0f); }
-
-template <int FCO, int FPX, int KS>
-__global__ __launch_bounds__(64 * kWaves) void k_conv_fp8(ConvArgs a, const uint8_t *wq, const float *sw, float sa)
-{
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int g = lane >> 4, r = lane & 15;
-    constexpr int TP = 16 * FPX;
-    const int64_t P = (int64_t)a.B * a.H * a.W;
-    const int64_t p0 = ((int64_t)blockIdx.x * kWaves + wave) * TP;
-    const int co0 = blockIdx.y * 16 * FCO;
-    if (p0 >= P) return;
-    const float inv_sa = 1.0f / sa;
-    int bb[FPX], yy[FPX], xx[FPX];
-    bool pv[FPX];
-#pragma unroll
-    for (int f = 0; f < FPX; ++f) {
-        const int64_t p = p0 + 16 * f + r;
-        pv[f] = p < P;
-        const int64_t pc = pv[f] ? p : 0;
-        const int64_t hw = (int64_t)a.H * a.W;
-        bb[f] = (int)(pc / hw);
-        const int64_t rem = pc - (int64_t)bb[f] * hw;
-        yy[f] = (int)(rem / a.W);
-        xx[f] = (int)(rem - (int64_t)yy[f] * a.W);
-    }
-    f32x4 acc[FCO][FPX];
-#pragma unroll
-    for (int i = 0; i < FCO; ++i)
-#pragma unroll
-        for (int f = 0; f < FPX; ++f) acc[i][f] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    const int K = KS * KS * a.Cin;
-    for (int k0 = 0; k0 < a.Kpad; k0 += 32) {
-        const int kk = k0 + 8 * g;
-        const bool kvalid = kk < K;
-        const int tap = kvalid ? kk / a.Cin : 0;
-        const int ci = kvalid ? kk - tap * a.Cin : 0;
-        const int dy = KS == 3 ? tap / 3 - 1 : 0;
-        const int dx = KS == 3 ? tap % 3 - 1 : 0;
-        long av[FCO], bv[FPX];
-#pragma unroll
-        for (int i = 0; i < FCO; ++i) av[i] = *reinterpret_cast<const long *>(wq + (int64_t)(co0 + 16 * i + r) * a.Kpad + kk);
-#pragma unroll
-        for (int f = 0; f < FPX; ++f) {
-            const int y2 = yy[f] + dy, x2 = xx[f] + dx;
-            const bool ok = kvalid && pv[f] && y2 >= 0 && y2 < a.H && x2 >= 0 && x2 < a.W;
-            bv[f] = 0;
-            if (ok) {
-                const int64_t q = ((int64_t)bb[f] * a.H + y2) * a.W + x2;
-                const bf16x8 v = load8(a.in + q * a.in_stride + a.in_off + ci);
-                float t[8];
-#pragma unroll
-                for (int j = 0; j < 8; ++j) t[j] = clamp448((float)v[j] * inv_sa);
-                bv[f] = pack_fp8x8(t);
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < FCO; ++i)
-#pragma unroll
-            for (int f = 0; f < FPX; ++f)
-                acc[i][f] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av[i], bv[f], acc[i][f], 0, 0, 0);
-    }
-#pragma unroll
-    for (int i = 0; i < FCO; ++i) {
-        const int cb = co0 + 16 * i + 4 * g;
-        float scale[4], bias[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            scale[e] = sw[cb + e] * sa;
-            bias[e] = a.bias ? a.bias[cb + e] : 0.0f;
-        }
-#pragma unroll
-        for (int f = 0; f < FPX; ++f) {
-            if (!pv[f]) continue;
-            const int64_t p = p0 + 16 * f + r;
-            float v[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                v[e] = acc[i][f][e] * scale[e] + bias[e];
-                if (a.relu) v[e] = fmaxf(v[e], 0.0f);
-            }
-            if (a.out_f32) {
-                const int64_t hw = (int64_t)a.H * a.W;
-                const int64_t b = p / hw, pix = p - b * hw;
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    if (cb + e < a.Cout) a.out_f32[(b * a.Cout + cb + e) * hw + pix] = v[e];
-            } else if (cb < a.Cout) {
-                __bf16 *o = a.out + p * a.out_stride + a.out_off + cb;
-                typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-                bf16x4 w4;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) w4[e] = (__bf16)v[e];
-                *reinterpret_cast<bf16x4 *>(o) = w4;
-            }
-        }
-    }
-}
 
 // per output row: s_w = max |W[co][k]| / 448 (1 for an all-zero row), q = fp8(W / s_w)
 __global__ __launch_bounds__(256) void k_quant_weights(const float *master, int Cout, int Cin, int KS, int rows,
@@ -738,45 +704,33 @@ unsigned nblocks(int64_t n, int per = 256) { return (unsigned)((n + per - 1) / p
 // launchers
 // ---------------------------------------------------------------------------
 
-hipError_t conv(const ConvArgs &a, int KS, hipStream_t s)
+template <bool FP8>
+static hipError_t launch_conv(const ConvArgs &a, int KS, const uint8_t *wq, const float *sw, float sa, hipStream_t s)
 {
     const int64_t P = (int64_t)a.B * a.H * a.W;
     const int cop = a.Cout_pad;
     // wave tile: FCO x 16 output channels by FPX x 16 pixels
     if (cop % 64 == 0) {
         dim3 grid(nblocks(P, 32 * kWaves), cop / 64);
-        if (KS == 3) hipLaunchKernelGGL((k_conv<4, 2, 3>), grid, dim3(64 * kWaves), 0, s, a);
-        else hipLaunchKernelGGL((k_conv<4, 2, 1>), grid, dim3(64 * kWaves), 0, s, a);
+        if (KS == 3) hipLaunchKernelGGL((k_conv<4, 2, 3, FP8>), grid, dim3(64 * kWaves), 0, s, a, wq, sw, sa);
+        else hipLaunchKernelGGL((k_conv<4, 2, 1, FP8>), grid, dim3(64 * kWaves), 0, s, a, wq, sw, sa);
     } else if (cop % 32 == 0) {
         dim3 grid(nblocks(P, 64 * kWaves), cop / 32);
-        if (KS == 3) hipLaunchKernelGGL((k_conv<2, 4, 3>), grid, dim3(64 * kWaves), 0, s, a);
-        else hipLaunchKernelGGL((k_conv<2, 4, 1>), grid, dim3(64 * kWaves), 0, s, a);
+        if (KS == 3) hipLaunchKernelGGL((k_conv<2, 4, 3, FP8>), grid, dim3(64 * kWaves), 0, s, a, wq, sw, sa);
+        else hipLaunchKernelGGL((k_conv<2, 4, 1, FP8>), grid, dim3(64 * kWaves), 0, s, a, wq, sw, sa);
     } else {
         dim3 grid(nblocks(P, 64 * kWaves), cop / 16);
-        if (KS == 3) hipLaunchKernelGGL((k_conv<1, 4, 3>), grid, dim3(64 * kWaves), 0, s, a);
-        else hipLaunchKernelGGL((k_conv<1, 4, 1>), grid, dim3(64 * kWaves), 0, s, a);
+        if (KS == 3) hipLaunchKernelGGL((k_conv<1, 4, 3, FP8>), grid, dim3(64 * kWaves), 0, s, a, wq, sw, sa);
+        else hipLaunchKernelGGL((k_conv<1, 4, 1, FP8>), grid, dim3(64 * kWaves), 0, s, a, wq, sw, sa);
     }
     return hipGetLastError();
 }
 
+hipError_t conv(const ConvArgs &a, int KS, hipStream_t s) { return launch_conv<false>(a, KS, nullptr, nullptr, 1.0f, s); }
+
 hipError_t conv_fp8(const ConvArgs &a, int KS, const uint8_t *wq, const float *sw, float sa, hipStream_t s)
 {
-    const int64_t P = (int64_t)a.B * a.H * a.W;
-    const int cop = a.Cout_pad;
-    if (cop % 64 == 0) {
-        dim3 grid(nblocks(P, 32 * kWaves), cop / 64);
-        if (KS == 3) hipLaunchKernelGGL((k_conv_fp8<4, 2, 3>), grid, dim3(64 * kWaves), 0, s, a, wq, sw, sa);
-        else hipLaunchKernelGGL((k_conv_fp8<4, 2, 1>), grid, dim3(64 * kWaves), 0, s, a, wq, sw, sa);
-    } else if (cop % 32 == 0) {
-        dim3 grid(nblocks(P, 64 * kWaves), cop / 32);
-        if (KS == 3) hipLaunchKernelGGL((k_conv_fp8<2, 4, 3>), grid, dim3(64 * kWaves), 0, s, a, wq, sw, sa);
-        else hipLaunchKernelGGL((k_conv_fp8<2, 4, 1>), grid, dim3(64 * kWaves), 0, s, a, wq, sw, sa);
-    } else {
-        dim3 grid(nblocks(P, 64 * kWaves), cop / 16);
-        if (KS == 3) hipLaunchKernelGGL((k_conv_fp8<1, 4, 3>), grid, dim3(64 * kWaves), 0, s, a, wq, sw, sa);
-        else hipLaunchKernelGGL((k_conv_fp8<1, 4, 1>), grid, dim3(64 * kWaves), 0, s, a, wq, sw, sa);
-    }
-    return hipGetLastError();
+    return launch_conv<true>(a, KS, wq, sw, sa, s);
 }
 
 hipError_t quant_weights(const float *master, int Cout, int Cin, int KS, int rows, int kpad, uint8_t *wq, float *sw,
