@@ -272,8 +272,9 @@ narvis_status narvis_postprocess(const narvis_weights *w, const float *feat, int
                                  float *img, int32_t precision, void *ws, size_t ws_bytes, void *stream);
 
 /* Prepare FP8 inference (OCP e4m3 on the matrix cores, fp32 accumulation;
- * the first layer and the 1x1 head stay in bfloat16, the 13 layers between
- * run in FP8): run the bfloat16 forward on the calibration batch feat [B][8][H][W],
+ * the ten layers below full resolution run in FP8, the full-resolution
+ * layers and the 1x1 head stay in bfloat16): run the bfloat16 forward on the
+ * calibration batch feat [B][8][H][W],
  * take each layer's input max-abs as its static activation scale (max/448)
  * and quantise each layer's weights with one scale per output channel
  * (max |W[co]| / 448).  Needs narvis_train_workspace_size(B, W, H) bytes of

@@ -221,9 +221,10 @@ SliceArgs slice(const __bf16 *in, int is, int io, __bf16 *out, int os, int oo, i
     } while (0)
 
 // Forward pass; the head writes fp32 planar [B][3][H][W] to `img`.
-// Under FP8 the first layer (raw G-buffer features of mixed ranges) and the
-// head (the output image) stay in bfloat16; the 13 layers between run in FP8.
-bool fp8_layer(int layer) { return layer != E1A && layer != HEAD; }
+// Under FP8 the ten layers below full resolution (the matrix-core bound part)
+// run in FP8; the full-resolution layers (bandwidth bound, and closest to the
+// raw features and to the output image) and the head stay in bfloat16.
+bool fp8_layer(int layer) { return layer >= E2A && layer <= D2B; }
 
 hipError_t run_conv(const narvis_weights *w, int layer, const ConvArgs &a, bool fp8, hipStream_t s)
 {
