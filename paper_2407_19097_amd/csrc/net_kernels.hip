@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "net_internal.h"
 
@@ -201,6 +202,189 @@ __global__ __launch_bounds__(64 * kWaves) void k_conv(ConvArgs a, const uint8_t 
             }
             if (a.out_f32) {
                 // planar fp32 [B][Cout][H][W]
+                const int64_t hw = (int64_t)a.H * a.W;
+                const int64_t b = p / hw, pix = p - b * hw;
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (cb + e < a.Cout) a.out_f32[(b * a.Cout + cb + e) * hw + pix] = v[e];
+            } else if (cb < a.Cout) {
+                __bf16 *o = a.out + p * a.out_stride + a.out_off + cb;
+                typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+                bf16x4 w4;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) w4[e] = (__bf16)v[e];
+                *reinterpret_cast<bf16x4 *>(o) = w4;
+            }
+        }
+    }
+}
+
+// LDS-staged convolution for the large layers.  A workgroup (4 waves) owns a
+// tile of TCO output channels x TPX pixels and walks K in chunks of 64: each
+// chunk of weights (TCO x 64) and of the im2col input (TPX x 64, eight k per
+// 16-byte piece: one tap, eight channels) is loaded with every lane reading 16
+// consecutive bytes (a wave reads 1 KB over 8 cache lines instead of one
+// line per lane), stored in LDS (double-buffered, rows padded against bank
+// conflicts), and the MFMA operands are read back with 16-byte LDS reads.
+// Each wave computes 32 output channels x 64 pixels (2 x 4 fragments).
+constexpr int kKC = 64;           // K per LDS chunk
+
+// LDS address (in elements) of 8-element piece p of row `row`.  bf16 rows are
+// 128 bytes with the piece index XOR-swizzled by the row (conflict-free
+// 16-byte reads down a fragment's 16 rows and conflict-free stores along a
+// row); FP8 rows are 64 bytes padded to 72, which spreads 8-byte reads over
+// the banks.
+template <bool FP8>
+__device__ __forceinline__ int lds_at(int row, int p)
+{
+    if constexpr (FP8) return row * 72 + 8 * p;
+    else return row * 64 + 8 * (p ^ (row & 7));
+}
+
+template <int TCO, int TPX, int KS, bool FP8, bool MASK>
+__global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a, const uint8_t *wq, const float *sw, float sa)
+{
+    typedef typename std::conditional<FP8, uint8_t, __bf16>::type E;
+    constexpr int RS = FP8 ? 72 : 64;                 // LDS row stride (elements)
+    __shared__ __attribute__((aligned(16))) E la[2][TCO * RS];
+    __shared__ __attribute__((aligned(16))) E lb[2][TPX * RS];
+    constexpr int WCO = TCO / 32;                     // waves along output channels
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, r = lane & 15;
+    const int wco = (wave % WCO) * 32, wpx = (wave / WCO) * 64;
+    const int64_t P = (int64_t)a.B * a.H * a.W;
+    const int64_t p0 = (int64_t)blockIdx.x * TPX;
+    const int co0 = blockIdx.y * TCO;
+    const float inv_sa = FP8 ? 1.0f / sa : 1.0f;
+    constexpr int T = KS * KS;
+    const int K = T * a.Cin;
+    // staging roles: piece kc (8 k values) of rows t / 8 + 32 j
+    const int kc = threadIdx.x & 7;
+    constexpr int AJ = TCO / 32, BJ = TPX / 32;
+    int bb[BJ], yy[BJ], xx[BJ];
+    bool pv[BJ];
+#pragma unroll
+    for (int j = 0; j < BJ; ++j) {
+        const int64_t p = p0 + (threadIdx.x >> 3) + 32 * j;
+        pv[j] = p < P;
+        const int64_t pc = pv[j] ? p : 0;
+        const int64_t hw = (int64_t)a.H * a.W;
+        bb[j] = (int)(pc / hw);
+        const int64_t rem = pc - (int64_t)bb[j] * hw;
+        yy[j] = (int)(rem / a.W);
+        xx[j] = (int)(rem - (int64_t)yy[j] * a.W);
+    }
+    // registers holding the next chunk between its global load and its LDS
+    // store; the ReLU mask and the FP8 conversion are applied at the store so
+    // the loads stay in flight behind the MFMAs of the current chunk
+    typedef typename std::conditional<FP8, long, bf16x8>::type Piece;
+    Piece ra[AJ];
+    bf16x8 rb[BJ];
+    bf16x8 rm[MASK ? BJ : 1];
+    int tap = (8 * kc) / a.Cin;
+    int ci = 8 * kc - tap * a.Cin;
+    auto gload = [&](int k0, int tp, int c) {
+        const int kk = k0 + 8 * kc;
+#pragma unroll
+        for (int j = 0; j < AJ; ++j) {
+            const int row = co0 + (threadIdx.x >> 3) + 32 * j;
+            if constexpr (FP8) {
+                ra[j] = kk < a.Kpad ? *reinterpret_cast<const long *>(wq + (int64_t)row * a.Kpad + kk) : 0;
+            } else {
+                ra[j] = kk < a.Kpad ? load8(a.wt + (int64_t)row * a.Kpad + kk) : zero8();
+            }
+        }
+        const bool kvalid = tp < T && kk < K;
+        const int dy = KS == 3 ? tp / 3 - 1 : 0, dx = KS == 3 ? tp % 3 - 1 : 0;
+#pragma unroll
+        for (int j = 0; j < BJ; ++j) {
+            const int y2 = yy[j] + dy, x2 = xx[j] + dx;
+            rb[j] = zero8();
+            if (kvalid && pv[j] && y2 >= 0 && y2 < a.H && x2 >= 0 && x2 < a.W) {
+                const int64_t q = ((int64_t)bb[j] * a.H + y2) * a.W + x2;
+                rb[j] = load8(a.in + q * a.in_stride + a.in_off + c);
+                if constexpr (MASK) rm[j] = load8(a.in_mask + q * a.mask_stride + a.mask_off + c);
+            }
+        }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+        for (int j = 0; j < AJ; ++j)
+            *reinterpret_cast<Piece *>(&la[buf][lds_at<FP8>((threadIdx.x >> 3) + 32 * j, kc)]) = ra[j];
+#pragma unroll
+        for (int j = 0; j < BJ; ++j) {
+            bf16x8 v = rb[j];
+            if constexpr (MASK) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                    if (!((float)rm[j][e] > 0.0f)) v[e] = (__bf16)0.0f;
+            }
+            if constexpr (FP8)
+                *reinterpret_cast<long *>(&lb[buf][lds_at<FP8>((threadIdx.x >> 3) + 32 * j, kc)]) =
+                    ConvOps<true>::to_b(v, inv_sa);
+            else
+                *reinterpret_cast<bf16x8 *>(&lb[buf][lds_at<FP8>((threadIdx.x >> 3) + 32 * j, kc)]) = v;
+        }
+    };
+    f32x4 acc[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int f = 0; f < 4; ++f) acc[i][f] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    const int nchunks = (a.Kpad + kKC - 1) / kKC;
+    gload(0, tap, ci);
+    lstore(0);
+    __syncthreads();
+    for (int c = 0; c < nchunks; ++c) {
+        const int buf = c & 1;
+        const bool more = c + 1 < nchunks;
+        if (more) {
+            ci += kKC;
+            while (ci >= a.Cin) {
+                ci -= a.Cin;
+                ++tap;
+            }
+            gload((c + 1) * kKC, tap, ci);
+        }
+#pragma unroll
+        for (int s = 0; s < kKC / 32; ++s) {
+            typename ConvOps<FP8>::A av[2];
+            typename ConvOps<FP8>::Bv bv[4];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+                av[i] = *reinterpret_cast<const typename ConvOps<FP8>::A *>(&la[buf][lds_at<FP8>(wco + 16 * i + r, 4 * s + g)]);
+#pragma unroll
+            for (int f = 0; f < 4; ++f)
+                bv[f] = *reinterpret_cast<const typename ConvOps<FP8>::Bv *>(&lb[buf][lds_at<FP8>(wpx + 16 * f + r, 4 * s + g)]);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int f = 0; f < 4; ++f) acc[i][f] = ConvOps<FP8>::mfma(av[i], bv[f], acc[i][f]);
+        }
+        if (more) lstore(buf ^ 1);
+        __syncthreads();
+    }
+    // epilogue: lane holds channels co0 + wco + 16 i + 4 g + e of pixel p0 + wpx + 16 f + r
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int cb = co0 + wco + 16 * i + 4 * g;
+        float bias[4], scale[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            bias[e] = a.bias ? a.bias[cb + e] : 0.0f;
+            scale[e] = FP8 ? sw[cb + e] * sa : 1.0f;
+        }
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            const int64_t p = p0 + wpx + 16 * f + r;
+            if (p >= P) continue;
+            float v[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                v[e] = FP8 ? acc[i][f][e] * scale[e] + bias[e] : acc[i][f][e] + bias[e];
+                if (a.relu) v[e] = fmaxf(v[e], 0.0f);
+            }
+            if (a.out_f32) {
                 const int64_t hw = (int64_t)a.H * a.W;
                 const int64_t b = p / hw, pix = p - b * hw;
 #pragma unroll
@@ -709,6 +893,17 @@ static hipError_t launch_conv(const ConvArgs &a, int KS, const uint8_t *wq, cons
 {
     const int64_t P = (int64_t)a.B * a.H * a.W;
     const int cop = a.Cout_pad;
+    // 3x3 layers with 64 or more output channels: LDS-staged tiles.  With 32
+    // channels the B tile is shared by only two MFMA rows and the staging costs
+    // more than it saves, so those layers read their operands directly.
+    if (KS == 3 && cop % 64 == 0) {
+        dim3 grid(nblocks(P, 128), cop / 64);
+        if (a.in_mask)
+            hipLaunchKernelGGL((k_conv_lds<64, 128, 3, FP8, true>), grid, dim3(256), 0, s, a, wq, sw, sa);
+        else
+            hipLaunchKernelGGL((k_conv_lds<64, 128, 3, FP8, false>), grid, dim3(256), 0, s, a, wq, sw, sa);
+        return hipGetLastError();
+    }
     // wave tile: FCO x 16 output channels by FPX x 16 pixels
     if (cop % 64 == 0) {
         dim3 grid(nblocks(P, 32 * kWaves), cop / 64);
