@@ -193,6 +193,7 @@ __device__ __forceinline__ void global_merge(unsigned long long *__restrict__ ke
                                              const unsigned long long (&key)[K], bool (&hit)[K], uint32_t spread)
 {
     uint32_t addr[K];
+    bool any[K];
 #pragma unroll
     for (int t = 0; t < K; ++t) {
         const unsigned long long live = __ballot(hit[t]);
@@ -200,9 +201,16 @@ __device__ __forceinline__ void global_merge(unsigned long long *__restrict__ ke
         const uint32_t lpix = live ? (uint32_t)__builtin_amdgcn_readlane((int)pix[t], (int)lead) : spread;
         addr[t] = hit[t] ? pix[t] : lpix;
     }
+    // a read that no lane of the wave needs is skipped (wave-uniform branch)
     unsigned long long cur[K];
 #pragma unroll
-    for (int t = 0; t < K; ++t) cur[t] = keys[addr[t]];
+    for (int t = 0; t < K; ++t) {
+        any[t] = __ballot(hit[t]) != 0;
+        cur[t] = 0;
+    }
+#pragma unroll
+    for (int t = 0; t < K; ++t)
+        if (any[t]) cur[t] = keys[addr[t]];
 #pragma unroll
     for (int t = 0; t < K; ++t)
         if (hit[t] && key[t] < cur[t]) __hip_atomic_fetch_min(keys + pix[t], key[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
