@@ -235,7 +235,8 @@ narvis_status narvis_splat(const narvis_points *pts, const narvis_attrs *attrs, 
  * Network input: planar fp32 [B][8][H][W] G-buffer planes in the order
  * r, g, b, depth, v'x, v'y, theta, |v'| (the RGB+D+Vel2D set of Sec. 4.5.3);
  * the network sees 1/depth (0 where depth is 0).  Output: planar fp32
- * [B][3][H][W].  H and W must be multiples of 8.
+ * [B][3][H][W].  H and W must be multiples of 8 and at most 32768, and
+ * B*W*H < 2^31 (INVALID_ARG otherwise).
  * ------------------------------------------------------------------------ */
 
 typedef enum { NARVIS_PRECISION_BF16 = 0, NARVIS_PRECISION_FP8 = 1 } narvis_precision;

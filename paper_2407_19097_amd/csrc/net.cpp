@@ -84,7 +84,10 @@ int64_t param_count()
 struct Plan {
     int B, H, W;
     int64_t P[4];  // pixels per level
-    uint64_t feat, e1a, cat1, pool1, e2a, cat2, pool2, e3a, cat3, pool3, e4a, e4b, d3a, d3b, d2a, d2b, d1a, d1b;
+    // sk*: encoder outputs kept for the skip connections; up*: upsampled decoder
+    // inputs (a decoder layer reads [up | sk] as its input channels)
+    uint64_t feat, e1a, sk1, pool1, e2a, sk2, pool2, e3a, sk3, pool3, e4a, e4b, up3, d3a, d3b, up2, d2a, d2b, up1, d1a,
+        d1b;
     uint64_t out;  // fp32 planar [B][3][H][W] (training only)
     // training
     uint64_t gy, g_d1b, g_d1a, g_cat1, g_d2b, g_d2a, g_cat2, g_d3b, g_d3a, g_cat3, g_e4b, g_e4a, g_pool3, g_e3b,
@@ -109,20 +112,23 @@ Plan make_plan(int B, int H, int W, bool train)
     };
     p.feat = bf(p.P[0], 8);
     p.e1a = bf(p.P[0], 32);
-    p.cat1 = bf(p.P[0], 96);
+    p.sk1 = bf(p.P[0], 32);
     p.pool1 = bf(p.P[1], 32);
     p.e2a = bf(p.P[1], 64);
-    p.cat2 = bf(p.P[1], 192);
+    p.sk2 = bf(p.P[1], 64);
     p.pool2 = bf(p.P[2], 64);
     p.e3a = bf(p.P[2], 128);
-    p.cat3 = bf(p.P[2], 384);
+    p.sk3 = bf(p.P[2], 128);
     p.pool3 = bf(p.P[3], 128);
     p.e4a = bf(p.P[3], 256);
     p.e4b = bf(p.P[3], 256);
+    p.up3 = bf(p.P[2], 256);
     p.d3a = bf(p.P[2], 128);
     p.d3b = bf(p.P[2], 128);
+    p.up2 = bf(p.P[1], 128);
     p.d2a = bf(p.P[1], 64);
     p.d2b = bf(p.P[1], 64);
+    p.up1 = bf(p.P[0], 64);
     p.d1a = bf(p.P[0], 32);
     p.d1b = bf(p.P[0], 32);
     if (train) {
@@ -198,6 +204,16 @@ ConvArgs conv_args(const LayerBuf &l, const __bf16 *in, int in_stride, int in_of
     return a;
 }
 
+// a decoder layer's input: channels [0, cin1) from a.in, the rest from `skip`
+ConvArgs with_skip(ConvArgs a, const __bf16 *skip, int skip_stride, int cin1)
+{
+    a.in2 = skip;
+    a.in2_stride = skip_stride;
+    a.in2_off = 0;
+    a.Cin1 = cin1;
+    return a;
+}
+
 SliceArgs slice(const __bf16 *in, int is, int io, __bf16 *out, int os, int oo, int C, int B, int H, int W)
 {
     SliceArgs s{};
@@ -233,7 +249,7 @@ hipError_t run_conv(const narvis_weights *w, int layer, const ConvArgs &a, bool 
 }
 
 hipError_t forward(const narvis_weights *w, const float *feat_planes, char *ws, const Plan &p, float *img, hipStream_t s,
-                   bool fp8 = false)
+                   bool fp8, bool keep_acts)
 {
     Ctx c{ws, p};
     const int B = p.B, H = p.H, W = p.W;
@@ -241,28 +257,65 @@ hipError_t forward(const narvis_weights *w, const float *feat_planes, char *ws, 
     const LayerBuf *L = w->L;
     TRY(features(feat_planes, c.b(p.feat), B, H, W, s));
     TRY(run_conv(w, E1A, conv_args(L[E1A], c.b(p.feat), 8, 0, c.b(p.e1a), 32, 0, B, H, W), fp8, s));
-    TRY(run_conv(w, E1B, conv_args(L[E1B], c.b(p.e1a), 32, 0, c.b(p.cat1), 96, 64, B, H, W), fp8, s));
-    TRY(pool2(slice(c.b(p.cat1), 96, 64, c.b(p.pool1), 32, 0, 32, B, H, W), s));
+    TRY(run_conv(w, E1B, conv_args(L[E1B], c.b(p.e1a), 32, 0, c.b(p.sk1), 32, 0, B, H, W), fp8, s));
+    TRY(pool2(slice(c.b(p.sk1), 32, 0, c.b(p.pool1), 32, 0, 32, B, H, W), s));
     TRY(run_conv(w, E2A, conv_args(L[E2A], c.b(p.pool1), 32, 0, c.b(p.e2a), 64, 0, B, H1, W1), fp8, s));
-    TRY(run_conv(w, E2B, conv_args(L[E2B], c.b(p.e2a), 64, 0, c.b(p.cat2), 192, 128, B, H1, W1), fp8, s));
-    TRY(pool2(slice(c.b(p.cat2), 192, 128, c.b(p.pool2), 64, 0, 64, B, H1, W1), s));
+    TRY(run_conv(w, E2B, conv_args(L[E2B], c.b(p.e2a), 64, 0, c.b(p.sk2), 64, 0, B, H1, W1), fp8, s));
+    TRY(pool2(slice(c.b(p.sk2), 64, 0, c.b(p.pool2), 64, 0, 64, B, H1, W1), s));
     TRY(run_conv(w, E3A, conv_args(L[E3A], c.b(p.pool2), 64, 0, c.b(p.e3a), 128, 0, B, H2, W2), fp8, s));
-    TRY(run_conv(w, E3B, conv_args(L[E3B], c.b(p.e3a), 128, 0, c.b(p.cat3), 384, 256, B, H2, W2), fp8, s));
-    TRY(pool2(slice(c.b(p.cat3), 384, 256, c.b(p.pool3), 128, 0, 128, B, H2, W2), s));
+    TRY(run_conv(w, E3B, conv_args(L[E3B], c.b(p.e3a), 128, 0, c.b(p.sk3), 128, 0, B, H2, W2), fp8, s));
+    TRY(pool2(slice(c.b(p.sk3), 128, 0, c.b(p.pool3), 128, 0, 128, B, H2, W2), s));
     TRY(run_conv(w, E4A, conv_args(L[E4A], c.b(p.pool3), 128, 0, c.b(p.e4a), 256, 0, B, H3, W3), fp8, s));
     TRY(run_conv(w, E4B, conv_args(L[E4B], c.b(p.e4a), 256, 0, c.b(p.e4b), 256, 0, B, H3, W3), fp8, s));
-    TRY(upsample2(slice(c.b(p.e4b), 256, 0, c.b(p.cat3), 384, 0, 256, B, H3, W3), s));
-    TRY(run_conv(w, D3A, conv_args(L[D3A], c.b(p.cat3), 384, 0, c.b(p.d3a), 128, 0, B, H2, W2), fp8, s));
+    // A decoder layer's input is [2x upsample of the layer below | skip].  In
+    // inference with bf16 decoder layers the upsample is done while the
+    // layer stages its input; training (and the FP8 path, whose kernels read
+    // a plain input) materialises it.
+    const bool fuse_up = !keep_acts && !fp8;
+    if (fuse_up) {
+        ConvArgs a = with_skip(conv_args(L[D3A], c.b(p.e4b), 256, 0, c.b(p.d3a), 128, 0, B, H2, W2), c.b(p.sk3), 128, 256);
+        a.up_in = 1;
+        TRY(run_conv(w, D3A, a, fp8, s));
+    } else {
+        TRY(upsample2(slice(c.b(p.e4b), 256, 0, c.b(p.up3), 256, 0, 256, B, H3, W3), s));
+        TRY(run_conv(w, D3A, with_skip(conv_args(L[D3A], c.b(p.up3), 256, 0, c.b(p.d3a), 128, 0, B, H2, W2), c.b(p.sk3), 128, 256),
+                     fp8, s));
+    }
     TRY(run_conv(w, D3B, conv_args(L[D3B], c.b(p.d3a), 128, 0, c.b(p.d3b), 128, 0, B, H2, W2), fp8, s));
-    TRY(upsample2(slice(c.b(p.d3b), 128, 0, c.b(p.cat2), 192, 0, 128, B, H2, W2), s));
-    TRY(run_conv(w, D2A, conv_args(L[D2A], c.b(p.cat2), 192, 0, c.b(p.d2a), 64, 0, B, H1, W1), fp8, s));
+    if (fuse_up) {
+        ConvArgs a = with_skip(conv_args(L[D2A], c.b(p.d3b), 128, 0, c.b(p.d2a), 64, 0, B, H1, W1), c.b(p.sk2), 64, 128);
+        a.up_in = 1;
+        TRY(run_conv(w, D2A, a, fp8, s));
+    } else {
+        TRY(upsample2(slice(c.b(p.d3b), 128, 0, c.b(p.up2), 128, 0, 128, B, H2, W2), s));
+        TRY(run_conv(w, D2A, with_skip(conv_args(L[D2A], c.b(p.up2), 128, 0, c.b(p.d2a), 64, 0, B, H1, W1), c.b(p.sk2), 64, 128),
+                     fp8, s));
+    }
     TRY(run_conv(w, D2B, conv_args(L[D2B], c.b(p.d2a), 64, 0, c.b(p.d2b), 64, 0, B, H1, W1), fp8, s));
-    TRY(upsample2(slice(c.b(p.d2b), 64, 0, c.b(p.cat1), 96, 0, 64, B, H1, W1), s));
-    TRY(run_conv(w, D1A, conv_args(L[D1A], c.b(p.cat1), 96, 0, c.b(p.d1a), 32, 0, B, H, W), fp8, s));
-    TRY(run_conv(w, D1B, conv_args(L[D1B], c.b(p.d1a), 32, 0, c.b(p.d1b), 32, 0, B, H, W), fp8, s));
-    ConvArgs head = conv_args(L[HEAD], c.b(p.d1b), 32, 0, nullptr, 0, 0, B, H, W);
-    head.out_f32 = img;
-    TRY(run_conv(w, HEAD, head, fp8, s));
+    if (!fuse_up) {
+        TRY(upsample2(slice(c.b(p.d2b), 64, 0, c.b(p.up1), 64, 0, 64, B, H1, W1), s));
+        TRY(run_conv(w, D1A, with_skip(conv_args(L[D1A], c.b(p.up1), 64, 0, c.b(p.d1a), 32, 0, B, H, W), c.b(p.sk1), 32, 64),
+                     fp8, s));
+    } else {
+        ConvArgs a = with_skip(conv_args(L[D1A], c.b(p.d2b), 64, 0, c.b(p.d1a), 32, 0, B, H, W), c.b(p.sk1), 32, 64);
+        a.up_in = 1;
+        TRY(run_conv(w, D1A, a, fp8, s));
+    }
+    if (keep_acts) {
+        // training: the last layer's output is kept for the backward pass
+        TRY(run_conv(w, D1B, conv_args(L[D1B], c.b(p.d1a), 32, 0, c.b(p.d1b), 32, 0, B, H, W), fp8, s));
+        ConvArgs head = conv_args(L[HEAD], c.b(p.d1b), 32, 0, nullptr, 0, 0, B, H, W);
+        head.out_f32 = img;
+        TRY(run_conv(w, HEAD, head, fp8, s));
+    } else {
+        // inference: the 1x1 head is applied in the last layer's epilogue
+        ConvArgs a = conv_args(L[D1B], c.b(p.d1a), 32, 0, nullptr, 0, 0, B, H, W);
+        a.head_w = L[HEAD].wf;
+        a.head_kpad = L[HEAD].kpad;
+        a.head_b = L[HEAD].bias;
+        a.head_out = img;
+        TRY(run_conv(w, D1B, a, fp8, s));
+    }
     return hipSuccess;
 }
 
@@ -270,7 +323,8 @@ hipError_t forward(const narvis_weights *w, const float *feat_planes, char *ws, 
 // given, the input gradient.  dy is masked by the layer's own output (ReLU).
 hipError_t layer_backward(const LayerBuf &l, const __bf16 *dy, int dy_stride, int dy_off, const __bf16 *own,
                           int own_stride, int own_off, const __bf16 *x, int x_stride, int x_off, __bf16 *dx,
-                          int dx_stride, int dx_off, int B, int H, int W, const Plan &p, char *ws, hipStream_t s)
+                          int dx_stride, int dx_off, int B, int H, int W, const Plan &p, char *ws, hipStream_t s,
+                          const __bf16 *x2 = nullptr, int x2_stride = 0, int xcin1 = 0)
 {
     const __bf16 *mask = l.relu ? own : nullptr;
     WgradArgs a{};
@@ -283,6 +337,10 @@ hipError_t layer_backward(const LayerBuf &l, const __bf16 *dy, int dy_stride, in
     a.x = x;
     a.x_stride = x_stride;
     a.x_off = x_off;
+    a.x2 = x2;
+    a.x2_stride = x2_stride;
+    a.x2_off = 0;
+    a.xCin1 = xcin1;
     a.Cin = l.cin;
     a.KS = l.ks;
     a.Cout = l.cout;
@@ -337,13 +395,16 @@ hipError_t backward(const narvis_weights *w, char *ws, const Plan &p, hipStream_
     // head (1x1, linear): dy = loss gradient [P][8]
     TRY(layer_backward(L[HEAD], c.b(p.gy), 8, 0, nullptr, 0, 0, c.b(p.d1b), 32, 0, c.b(p.g_d1b), 32, 0, B, H, W, p, ws, s));
     TRY(layer_backward(L[D1B], c.b(p.g_d1b), 32, 0, c.b(p.d1b), 32, 0, c.b(p.d1a), 32, 0, c.b(p.g_d1a), 32, 0, B, H, W, p, ws, s));
-    TRY(layer_backward(L[D1A], c.b(p.g_d1a), 32, 0, c.b(p.d1a), 32, 0, c.b(p.cat1), 96, 0, c.b(p.g_cat1), 96, 0, B, H, W, p, ws, s));
+    TRY(layer_backward(L[D1A], c.b(p.g_d1a), 32, 0, c.b(p.d1a), 32, 0, c.b(p.up1), 64, 0, c.b(p.g_cat1), 96, 0, B, H, W, p, ws, s,
+                       c.b(p.sk1), 32, 64));
     TRY(upsample2_bwd(slice(c.b(p.g_cat1), 96, 0, c.b(p.g_d2b), 64, 0, 64, B, H1, W1), s));
     TRY(layer_backward(L[D2B], c.b(p.g_d2b), 64, 0, c.b(p.d2b), 64, 0, c.b(p.d2a), 64, 0, c.b(p.g_d2a), 64, 0, B, H1, W1, p, ws, s));
-    TRY(layer_backward(L[D2A], c.b(p.g_d2a), 64, 0, c.b(p.d2a), 64, 0, c.b(p.cat2), 192, 0, c.b(p.g_cat2), 192, 0, B, H1, W1, p, ws, s));
+    TRY(layer_backward(L[D2A], c.b(p.g_d2a), 64, 0, c.b(p.d2a), 64, 0, c.b(p.up2), 128, 0, c.b(p.g_cat2), 192, 0, B, H1, W1, p, ws,
+                       s, c.b(p.sk2), 64, 128));
     TRY(upsample2_bwd(slice(c.b(p.g_cat2), 192, 0, c.b(p.g_d3b), 128, 0, 128, B, H2, W2), s));
     TRY(layer_backward(L[D3B], c.b(p.g_d3b), 128, 0, c.b(p.d3b), 128, 0, c.b(p.d3a), 128, 0, c.b(p.g_d3a), 128, 0, B, H2, W2, p, ws, s));
-    TRY(layer_backward(L[D3A], c.b(p.g_d3a), 128, 0, c.b(p.d3a), 128, 0, c.b(p.cat3), 384, 0, c.b(p.g_cat3), 384, 0, B, H2, W2, p, ws, s));
+    TRY(layer_backward(L[D3A], c.b(p.g_d3a), 128, 0, c.b(p.d3a), 128, 0, c.b(p.up3), 256, 0, c.b(p.g_cat3), 384, 0, B, H2, W2, p,
+                       ws, s, c.b(p.sk3), 128, 256));
     TRY(upsample2_bwd(slice(c.b(p.g_cat3), 384, 0, c.b(p.g_e4b), 256, 0, 256, B, H3, W3), s));
     TRY(layer_backward(L[E4B], c.b(p.g_e4b), 256, 0, c.b(p.e4b), 256, 0, c.b(p.e4a), 256, 0, c.b(p.g_e4a), 256, 0, B, H3, W3, p, ws, s));
     TRY(layer_backward(L[E4A], c.b(p.g_e4a), 256, 0, c.b(p.e4a), 256, 0, c.b(p.pool3), 128, 0, c.b(p.g_pool3), 128, 0, B, H3, W3, p, ws, s));
@@ -354,7 +415,7 @@ hipError_t backward(const narvis_weights *w, char *ws, const Plan &p, hipStream_
         a.in2_off = 256;
         TRY(pool2_bwd_add(a, s));
     }
-    TRY(layer_backward(L[E3B], c.b(p.g_e3b), 128, 0, c.b(p.cat3), 384, 256, c.b(p.e3a), 128, 0, c.b(p.g_e3a), 128, 0, B, H2, W2, p, ws, s));
+    TRY(layer_backward(L[E3B], c.b(p.g_e3b), 128, 0, c.b(p.sk3), 128, 0, c.b(p.e3a), 128, 0, c.b(p.g_e3a), 128, 0, B, H2, W2, p, ws, s));
     TRY(layer_backward(L[E3A], c.b(p.g_e3a), 128, 0, c.b(p.e3a), 128, 0, c.b(p.pool2), 64, 0, c.b(p.g_pool2), 64, 0, B, H2, W2, p, ws, s));
     {
         SliceArgs a = slice(c.b(p.g_pool2), 64, 0, c.b(p.g_e2b), 64, 0, 64, B, H1, W1);
@@ -363,7 +424,7 @@ hipError_t backward(const narvis_weights *w, char *ws, const Plan &p, hipStream_
         a.in2_off = 128;
         TRY(pool2_bwd_add(a, s));
     }
-    TRY(layer_backward(L[E2B], c.b(p.g_e2b), 64, 0, c.b(p.cat2), 192, 128, c.b(p.e2a), 64, 0, c.b(p.g_e2a), 64, 0, B, H1, W1, p, ws, s));
+    TRY(layer_backward(L[E2B], c.b(p.g_e2b), 64, 0, c.b(p.sk2), 64, 0, c.b(p.e2a), 64, 0, c.b(p.g_e2a), 64, 0, B, H1, W1, p, ws, s));
     TRY(layer_backward(L[E2A], c.b(p.g_e2a), 64, 0, c.b(p.e2a), 64, 0, c.b(p.pool1), 32, 0, c.b(p.g_pool1), 32, 0, B, H1, W1, p, ws, s));
     {
         SliceArgs a = slice(c.b(p.g_pool1), 32, 0, c.b(p.g_e1b), 32, 0, 32, B, H, W);
@@ -372,7 +433,7 @@ hipError_t backward(const narvis_weights *w, char *ws, const Plan &p, hipStream_
         a.in2_off = 64;
         TRY(pool2_bwd_add(a, s));
     }
-    TRY(layer_backward(L[E1B], c.b(p.g_e1b), 32, 0, c.b(p.cat1), 96, 64, c.b(p.e1a), 32, 0, c.b(p.g_e1a), 32, 0, B, H, W, p, ws, s));
+    TRY(layer_backward(L[E1B], c.b(p.g_e1b), 32, 0, c.b(p.sk1), 32, 0, c.b(p.e1a), 32, 0, c.b(p.g_e1a), 32, 0, B, H, W, p, ws, s));
     TRY(layer_backward(L[E1A], c.b(p.g_e1a), 32, 0, c.b(p.e1a), 32, 0, c.b(p.feat), 8, 0, nullptr, 0, 0, B, H, W, p, ws, s));
     // gradient matrices -> blob order
     for (int i = 0; i < kNumLayers; ++i) {
@@ -395,7 +456,8 @@ hipError_t refresh(narvis_weights *w, hipStream_t s)
 
 bool dims_ok(int B, int W, int H)
 {
-    return B >= 1 && W >= 8 && H >= 8 && W % 8 == 0 && H % 8 == 0 && (int64_t)B * W * H < (int64_t(1) << 31);
+    return B >= 1 && W >= 8 && H >= 8 && W <= 32768 && H <= 32768 && W % 8 == 0 && H % 8 == 0 &&
+           (int64_t)B * W * H < (int64_t(1) << 31);
 }
 
 narvis_status st(hipError_t e) { return e == hipSuccess ? NARVIS_OK : NARVIS_ERR_DEVICE; }
@@ -520,7 +582,7 @@ extern "C" narvis_status narvis_postprocess(const narvis_weights *w, const float
     const Plan p = make_plan(B, H, W, false);
     if (ws_bytes < p.bytes) return NARVIS_ERR_WORKSPACE;
     return st(forward(w, feat, static_cast<char *>(ws), p, img, static_cast<hipStream_t>(stream),
-                      precision == NARVIS_PRECISION_FP8));
+                      precision == NARVIS_PRECISION_FP8, false));
 }
 
 extern "C" size_t narvis_train_workspace_size(int32_t B, int32_t W, int32_t H)
@@ -541,7 +603,7 @@ narvis_status train_common(narvis_weights *w, const float *feat, const float *ta
     if (ws_bytes < p.bytes) return NARVIS_ERR_WORKSPACE;
     char *base = static_cast<char *>(ws);
     float *y = reinterpret_cast<float *>(base + p.out);
-    hipError_t e = forward(w, feat, base, p, y, s);
+    hipError_t e = forward(w, feat, base, p, y, s, false, true);
     if (e == hipSuccess) {
         e = zero_bf16(reinterpret_cast<__bf16 *>(base + p.gy), p.P[0] * 8, s);
     }
@@ -594,16 +656,21 @@ extern "C" narvis_status narvis_weights_calibrate_fp8(narvis_weights *w, const f
     if (ws_bytes < p.bytes) return NARVIS_ERR_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     char *base = static_cast<char *>(ws);
-    hipError_t e = forward(w, feat, base, p, reinterpret_cast<float *>(base + p.out), s, false);
+    hipError_t e = forward(w, feat, base, p, reinterpret_cast<float *>(base + p.out), s, false, true);
     // input tensor of every layer, in layer order
-    const struct { uint64_t off; int64_t px; int ch; } in[kNumLayers] = {
-        {p.feat, p.P[0], 8},    {p.e1a, p.P[0], 32},   {p.pool1, p.P[1], 32}, {p.e2a, p.P[1], 64},
-        {p.pool2, p.P[2], 64},  {p.e3a, p.P[2], 128},  {p.pool3, p.P[3], 128}, {p.e4a, p.P[3], 256},
-        {p.cat3, p.P[2], 384},  {p.d3a, p.P[2], 128},  {p.cat2, p.P[1], 192}, {p.d2a, p.P[1], 64},
-        {p.cat1, p.P[0], 96},   {p.d1a, p.P[0], 32},   {p.d1b, p.P[0], 32}};
+    // (a decoder layer's input is two tensors: the upsampled one and the skip)
+    const struct { uint64_t off; int64_t px; int ch; uint64_t off2; int ch2; } in[kNumLayers] = {
+        {p.feat, p.P[0], 8, 0, 0},     {p.e1a, p.P[0], 32, 0, 0},    {p.pool1, p.P[1], 32, 0, 0},
+        {p.e2a, p.P[1], 64, 0, 0},     {p.pool2, p.P[2], 64, 0, 0},  {p.e3a, p.P[2], 128, 0, 0},
+        {p.pool3, p.P[3], 128, 0, 0},  {p.e4a, p.P[3], 256, 0, 0},   {p.up3, p.P[2], 256, p.sk3, 128},
+        {p.d3a, p.P[2], 128, 0, 0},    {p.up2, p.P[1], 128, p.sk2, 64}, {p.d2a, p.P[1], 64, 0, 0},
+        {p.up1, p.P[0], 64, p.sk1, 32}, {p.d1a, p.P[0], 32, 0, 0},    {p.d1b, p.P[0], 32, 0, 0}};
     if (e == hipSuccess) e = hipMemsetAsync(w->amax, 0, kNumLayers * 4, s);
-    for (int i = 0; i < kNumLayers && e == hipSuccess; ++i)
+    for (int i = 0; i < kNumLayers && e == hipSuccess; ++i) {
         e = absmax_bf16(reinterpret_cast<const __bf16 *>(base + in[i].off), in[i].px * in[i].ch, w->amax + i, s);
+        if (e == hipSuccess && in[i].ch2)
+            e = absmax_bf16(reinterpret_cast<const __bf16 *>(base + in[i].off2), in[i].px * in[i].ch2, w->amax + i, s);
+    }
     unsigned int host[kNumLayers];
     if (e == hipSuccess) e = hipMemcpyAsync(host, w->amax, sizeof(host), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);

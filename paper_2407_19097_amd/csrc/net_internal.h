@@ -14,6 +14,11 @@ namespace net {
 struct ConvArgs {
     const __bf16 *in;
     int in_stride, in_off, Cin;        // Cin: multiple of 8
+    // optional second input: channels [Cin1, Cin) come from in2 (a decoder
+    // layer reads the upsampled tensor and the skip tensor without a concat)
+    const __bf16 *in2;
+    int in2_stride, in2_off, Cin1;     // Cin1: multiple of 8 (of 32 for the halo kernel)
+    int up_in;                         // nonzero: `in` is at H/2 x W/2 and is 2x bilinear-upsampled on load
     const __bf16 *in_mask;
     int mask_stride, mask_off;
     const __bf16 *wt;                  // [Cout_pad][Kpad]
@@ -25,6 +30,13 @@ struct ConvArgs {
     __bf16 *out;                       // NHWC slice (when out_f32 is null)
     int out_stride, out_off;           // multiples of 4
     float *out_f32;                    // planar [B][Cout][H][W]
+    // optional fused 1x1 head on the (bf16-rounded) output, 3 x Cout weights
+    // (row stride head_kpad) and 3 biases, written planar fp32 [B][3][H][W]
+    // instead of `out` (3x3 layers with 32 output channels only)
+    const __bf16 *head_w;
+    int head_kpad;
+    const float *head_b;
+    float *head_out;
 };
 
 // Pooling / upsampling / gradient-sum kernels over channel slices (C multiple of 8).
@@ -45,6 +57,8 @@ struct WgradArgs {
     int mask_stride, mask_off;
     const __bf16 *x;                   // the layer's input
     int x_stride, x_off;
+    const __bf16 *x2;                  // optional second input: channels [xCin1, Cin)
+    int x2_stride, x2_off, xCin1;
     int Cin, KS, Cout, Cout_pad, Kpad;
     int B, H, W;
     int splits;

@@ -44,6 +44,13 @@ __device__ __forceinline__ bf16x8 zero8()
 
 __device__ __forceinline__ bf16x8 load8(const __bf16 *p) { return *reinterpret_cast<const bf16x8 *>(p); }
 
+// element (pixel q, channel c) of a convolution's input (one or two sources)
+__device__ __forceinline__ const __bf16 *in_at(const ConvArgs &a, int64_t q, int c)
+{
+    if (a.in2 && c >= a.Cin1) return a.in2 + q * a.in2_stride + a.in2_off + (c - a.Cin1);
+    return a.in + q * a.in_stride + a.in_off + c;
+}
+
 // ---------------------------------------------------------------------------
 // convolution (forward and input-gradient)
 // ---------------------------------------------------------------------------
@@ -143,7 +150,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_conv(ConvArgs a, const uint8_t 
             Bv[f] = Ops::zero();
             if (ok) {
                 const int64_t q = ((int64_t)bb[f] * a.H + y2) * a.W + x2;
-                bf16x8 v = load8(a.in + q * a.in_stride + a.in_off + ci);
+                bf16x8 v = load8(in_at(a, q, ci));
                 if (a.in_mask) {
                     const bf16x8 m = load8(a.in_mask + q * a.mask_stride + a.mask_off + ci);
 #pragma unroll
@@ -302,7 +309,7 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a, const uint8_t *wq,
             rb[j] = zero8();
             if (kvalid && pv[j] && y2 >= 0 && y2 < a.H && x2 >= 0 && x2 < a.W) {
                 const int64_t q = ((int64_t)bb[j] * a.H + y2) * a.W + x2;
-                rb[j] = load8(a.in + q * a.in_stride + a.in_off + c);
+                rb[j] = load8(in_at(a, q, c));
                 if constexpr (MASK) rm[j] = load8(a.in_mask + q * a.mask_stride + a.mask_off + c);
             }
         }
@@ -402,6 +409,315 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a, const uint8_t *wq,
     }
 }
 
+// source index and weight of output o for a x2 bilinear upsample of n samples
+// (half-pixel centres, clamped): out[o] = (1 - f) in[i0] + f in[i1]
+__device__ __forceinline__ void up_src(int o, int n, int &i0, int &i1, float &f)
+{
+    float src = ((float)o + 0.5f) * 0.5f - 0.5f;
+    src = fmaxf(src, 0.0f);
+    i0 = min((int)src, n - 1);
+    i1 = min(i0 + 1, n - 1);
+    f = src - (float)i0;
+}
+
+// 8 channels of the 2x bilinear upsample of a [B][h][w] slice at output pixel
+// (y, x) of the [B][2h][2w] grid (the same arithmetic as k_upsample2)
+__device__ __forceinline__ bf16x8 upsample_piece(const __bf16 *in, int stride, int off, int b, int h, int w, int y,
+                                                 int x, int c)
+{
+    int y0, y1, x0, x1;
+    float fy, fx;
+    up_src(y, h, y0, y1, fy);
+    up_src(x, w, x0, x1, fx);
+    const int64_t rb = (int64_t)b * h;
+    const bf16x8 v00 = load8(in + ((rb + y0) * w + x0) * stride + off + c);
+    const bf16x8 v01 = load8(in + ((rb + y0) * w + x1) * stride + off + c);
+    const bf16x8 v10 = load8(in + ((rb + y1) * w + x0) * stride + off + c);
+    const bf16x8 v11 = load8(in + ((rb + y1) * w + x1) * stride + off + c);
+    bf16x8 o;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const float top = (1.0f - fx) * (float)v00[j] + fx * (float)v01[j];
+        const float bot = (1.0f - fx) * (float)v10[j] + fx * (float)v11[j];
+        o[j] = (__bf16)((1.0f - fy) * top + fy * bot);
+    }
+    return o;
+}
+
+// Direct 3x3 convolution for layers with 32 output channels and Cin a
+// multiple of 32 (the full-resolution layers).  A workgroup of 4 waves owns 4
+// output rows x 64 pixels; for each group of 32 input channels it stages the
+// 6 x 66 pixel halo tile in LDS once, and all nine taps read their B
+// fragments from it at shifted positions (the im2col matrix is never formed).
+// The group's weights (9 taps x 32 x 32) are staged in LDS beside the tile.
+// Within a pixel's 64 bytes the four 16-byte pieces are XOR-swizzled by
+// pixel bits 1-2, so eight lanes reading eight consecutive pixels at the same
+// channel offset hit distinct banks, for every tap shift.
+constexpr int kHaloRows = 4;
+constexpr int kHaloCols = 64;
+
+__device__ __forceinline__ int halo_at(int p, int part) { return p * 32 + 8 * (part ^ ((p >> 1) & 3)); }
+
+template <int CO, bool MASK, bool HEAD, bool UP>
+__global__ __launch_bounds__(128 * CO / 16) void k_conv_halo(ConvArgs a)
+{
+    constexpr int NCH = CO / 32;                  // waves per output row (32 channels each)
+    constexpr int NT = 64 * kHaloRows * NCH;      // threads
+    constexpr int HR = kHaloRows + 2, HC = kHaloCols + 2;
+    constexpr int NPIECE = HR * HC * 4;           // 16-byte pieces of the halo tile
+    constexpr int SJ = (NPIECE + NT - 1) / NT;
+    constexpr int NWPIECE = 9 * CO * 4;           // pieces of the weights (9 taps x CO x 32 ci)
+    constexpr int WJ = (NWPIECE + NT - 1) / NT;
+    __shared__ __attribute__((aligned(16))) __bf16 xs[HR * HC * 32];
+    __shared__ __attribute__((aligned(16))) __bf16 ws[9 * CO * 32];   // row (tap * CO + co), 32 ci
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, r = lane & 15;
+    const int wch = wave % NCH, wrow = wave / NCH;  // this wave: channels 32 wch.., output row wrow
+    const int ctiles = a.Cout_pad / CO;
+    const int x0 = blockIdx.x * kHaloCols, y0 = blockIdx.y * kHaloRows;
+    const int b = blockIdx.z / ctiles, co0 = (blockIdx.z - b * ctiles) * CO;
+    f32x4 acc[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int f = 0; f < 4; ++f) acc[i][f] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    const int nchunks = a.Cin / 32;
+    for (int c = 0; c < nchunks; ++c) {
+        // the group's source (uniform): `in`, or `in2` past Cin1
+        const bool second = a.in2 && 32 * c >= a.Cin1;
+        const __bf16 *src = second ? a.in2 : a.in;
+        const int sstride = second ? a.in2_stride : a.in_stride;
+        const int soff = second ? a.in2_off + 32 * c - a.Cin1 : a.in_off + 32 * c;
+        const bool up = UP && !second;
+        bf16x8 wv[WJ];
+#pragma unroll
+        for (int j = 0; j < WJ; ++j) {
+            const int piece = threadIdx.x + NT * j;
+            const int row = piece >> 2, part = piece & 3;   // row = tap * CO + co
+            const int tap = row / CO, co = row - tap * CO;
+            wv[j] = zero8();
+            if (piece < NWPIECE)
+                wv[j] = load8(a.wt + (int64_t)(co0 + co) * a.Kpad + tap * a.Cin + 32 * c + 8 * part);
+        }
+        if (up) {
+            // upsampled group: each piece is interpolated and stored in turn
+            if (c) __syncthreads();  // the previous group's taps are done with the tiles
+#pragma unroll 1
+            for (int piece = threadIdx.x; piece < NPIECE; piece += NT) {
+                const int p = piece >> 2, part = piece & 3;
+                const int hy = p / HC, hx = p - hy * HC;
+                const int y = y0 - 1 + hy, x = x0 - 1 + hx;
+                bf16x8 v = zero8();
+                if (y >= 0 && y < a.H && x >= 0 && x < a.W)
+                    v = upsample_piece(src, sstride, soff, b, a.H / 2, a.W / 2, y, x, 8 * part);
+                *reinterpret_cast<bf16x8 *>(&xs[halo_at(p, part)]) = v;
+            }
+        } else {
+            bf16x8 v[SJ];
+#pragma unroll
+            for (int j = 0; j < SJ; ++j) {
+                const int piece = threadIdx.x + NT * j;
+                const int p = piece >> 2, part = piece & 3;
+                const int hy = p / HC, hx = p - hy * HC;
+                const int y = y0 - 1 + hy, x = x0 - 1 + hx;
+                v[j] = zero8();
+                if (piece < NPIECE && y >= 0 && y < a.H && x >= 0 && x < a.W) {
+                    const int64_t q = ((int64_t)b * a.H + y) * a.W + x;
+                    v[j] = load8(src + q * sstride + soff + 8 * part);
+                    if constexpr (MASK) {
+                        const bf16x8 m = load8(a.in_mask + q * a.mask_stride + a.mask_off + 32 * c + 8 * part);
+#pragma unroll
+                        for (int e = 0; e < 8; ++e)
+                            if (!((float)m[e] > 0.0f)) v[j][e] = (__bf16)0.0f;
+                    }
+                }
+            }
+            if (c) __syncthreads();  // the previous group's taps are done with the tiles
+#pragma unroll
+            for (int j = 0; j < SJ; ++j) {
+                const int piece = threadIdx.x + NT * j;
+                if (piece < NPIECE) *reinterpret_cast<bf16x8 *>(&xs[halo_at(piece >> 2, piece & 3)]) = v[j];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < WJ; ++j) {
+            const int piece = threadIdx.x + NT * j;
+            if (piece < NWPIECE) *reinterpret_cast<bf16x8 *>(&ws[halo_at(piece >> 2, piece & 3)]) = wv[j];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int dy = tap / 3, dx = tap % 3;
+            bf16x8 av[2], bv[4];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+                av[i] = *reinterpret_cast<const bf16x8 *>(&ws[halo_at(tap * CO + 32 * wch + 16 * i + r, g)]);
+#pragma unroll
+            for (int f = 0; f < 4; ++f)
+                bv[f] = *reinterpret_cast<const bf16x8 *>(&xs[halo_at((wrow + dy) * HC + 16 * f + r + dx, g)]);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int f = 0; f < 4; ++f)
+                    acc[i][f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[f], acc[i][f], 0, 0, 0);
+        }
+    }
+    // lane holds channels co0 + 32 wch + 16 i + 4 g + e of pixel (y0 + wrow, x0 + 16 f + r)
+    const int y = y0 + wrow;
+    if constexpr (HEAD) {
+        static_assert(CO == 32, "the fused head needs all 32 channels in one wave");
+        // 1x1 head: each lane dots its 8 channels with the head rows, the four
+        // lane groups (g) are summed with two butterfly shuffles, group 0 writes
+        float hw[3][8], hb[3];
+#pragma unroll
+        for (int o = 0; o < 3; ++o) {
+            hb[o] = a.head_b[o];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) hw[o][4 * i + e] = (float)a.head_w[o * a.head_kpad + 16 * i + 4 * g + e];
+        }
+        float cbias[8];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) cbias[4 * i + e] = a.bias ? a.bias[16 * i + 4 * g + e] : 0.0f;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            float part[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    float t = acc[i][f][e] + cbias[4 * i + e];
+                    if (a.relu) t = fmaxf(t, 0.0f);
+                    t = (float)(__bf16)t;
+#pragma unroll
+                    for (int o = 0; o < 3; ++o) part[o] += t * hw[o][4 * i + e];
+                }
+#pragma unroll
+            for (int o = 0; o < 3; ++o) {
+                part[o] += __shfl_xor(part[o], 16);
+                part[o] += __shfl_xor(part[o], 32);
+            }
+            const int x = x0 + 16 * f + r;
+            if (g == 0 && y < a.H && x < a.W) {
+                const int64_t hw_ = (int64_t)a.H * a.W, pix = (int64_t)y * a.W + x;
+#pragma unroll
+                for (int o = 0; o < 3; ++o) a.head_out[((int64_t)b * 3 + o) * hw_ + pix] = part[o] + hb[o];
+            }
+        }
+        return;
+    }
+    if (y >= a.H) return;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int cb = co0 + 32 * wch + 16 * i + 4 * g;
+        float bias[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) bias[e] = a.bias ? a.bias[cb + e] : 0.0f;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            const int x = x0 + 16 * f + r;
+            if (x >= a.W || cb >= a.Cout) continue;
+            const int64_t p = ((int64_t)b * a.H + y) * a.W + x;
+            typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+            bf16x4 w4;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                float t = acc[i][f][e] + bias[e];
+                if (a.relu) t = fmaxf(t, 0.0f);
+                w4[e] = (__bf16)t;
+            }
+            *reinterpret_cast<bf16x4 *>(a.out + p * a.out_stride + a.out_off + cb) = w4;
+        }
+    }
+}
+
+// Direct 3x3 convolution of the 8-channel feature image (first layer, 32
+// output channels).  A pixel is one 16-byte piece, so a K step of 32 covers
+// four taps: lane group g of step s takes tap 4 s + g (K = 72 padded to 96).
+// Tile as above: 4 output rows x 64 pixels per workgroup, the 6 x 66 halo
+// tile and the 32 x 96 weight matrix staged in LDS (weight rows padded to 104
+// elements so that 16-byte reads down 8 rows hit distinct banks).
+__global__ __launch_bounds__(256) void k_conv_c8(ConvArgs a)
+{
+    constexpr int HR = kHaloRows + 2, HC = kHaloCols + 2;
+    constexpr int NPIECE = HR * HC;
+    constexpr int RSW = 104;
+    __shared__ __attribute__((aligned(16))) __bf16 xs[NPIECE * 8];
+    __shared__ __attribute__((aligned(16))) __bf16 ws[32 * RSW];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, r = lane & 15;
+    const int x0 = blockIdx.x * kHaloCols, y0 = blockIdx.y * kHaloRows, b = blockIdx.z;
+    bf16x8 v[2], wv[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int p = threadIdx.x + 256 * j;
+        const int hy = p / HC, hx = p - hy * HC;
+        const int y = y0 - 1 + hy, x = x0 - 1 + hx;
+        v[j] = zero8();
+        if (p < NPIECE && y >= 0 && y < a.H && x >= 0 && x < a.W)
+            v[j] = load8(a.in + (((int64_t)b * a.H + y) * a.W + x) * a.in_stride + a.in_off);
+        const int row = p / 12, part = p - row * 12;
+        wv[j] = zero8();
+        if (p < 32 * 12) wv[j] = load8(a.wt + (int64_t)row * a.Kpad + 8 * part);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int p = threadIdx.x + 256 * j;
+        if (p < NPIECE) *reinterpret_cast<bf16x8 *>(&xs[p * 8]) = v[j];
+        const int row = p / 12, part = p - row * 12;
+        if (p < 32 * 12) *reinterpret_cast<bf16x8 *>(&ws[row * RSW + 8 * part]) = wv[j];
+    }
+    __syncthreads();
+    f32x4 acc[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int f = 0; f < 4; ++f) acc[i][f] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int st = 0; st < 3; ++st) {
+        const int tap = 4 * st + g;
+        const int dy = tap / 3, dx = tap % 3;
+        bf16x8 av[2], bv[4];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) av[i] = *reinterpret_cast<const bf16x8 *>(&ws[(16 * i + r) * RSW + 32 * st + 8 * g]);
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+            bv[f] = tap < 9 ? *reinterpret_cast<const bf16x8 *>(&xs[((wave + dy) * HC + 16 * f + r + dx) * 8]) : zero8();
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int f = 0; f < 4; ++f)
+                acc[i][f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[f], acc[i][f], 0, 0, 0);
+    }
+    const int y = y0 + wave;
+    if (y >= a.H) return;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int cb = 16 * i + 4 * g;
+        float bias[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) bias[e] = a.bias ? a.bias[cb + e] : 0.0f;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            const int x = x0 + 16 * f + r;
+            if (x >= a.W || cb >= a.Cout) continue;
+            const int64_t p = ((int64_t)b * a.H + y) * a.W + x;
+            typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+            bf16x4 w4;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                float t = acc[i][f][e] + bias[e];
+                if (a.relu) t = fmaxf(t, 0.0f);
+                w4[e] = (__bf16)t;
+            }
+            *reinterpret_cast<bf16x4 *>(a.out + p * a.out_stride + a.out_off + cb) = w4;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // features, pooling, upsampling
 // ---------------------------------------------------------------------------
@@ -424,74 +740,67 @@ __global__ __launch_bounds__(256) void k_features(const float *in, __bf16 *out, 
     *reinterpret_cast<bf16x8 *>(out + p * 8) = v;
 }
 
-// one thread per (output pixel, group of 8 channels)
+// Pooling and upsampling: blockIdx.y walks output rows (b, y) (uniform, so
+// the row arithmetic is scalar), x and the 8-channel group come from the
+// thread index within the row.
+
+// 2x2 average pooling: one thread per (output pixel, group of 8 channels)
 __global__ __launch_bounds__(256) void k_pool2(SliceArgs s)
 {
     const int groups = s.C / 8;
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int Ho = s.H / 2, Wo = s.W / 2;
-    const int64_t total = (int64_t)s.B * Ho * Wo * groups;
-    if (t >= total) return;
-    const int c8 = (int)(t % groups);
-    const int64_t po = t / groups;
-    const int64_t b = po / ((int64_t)Ho * Wo);
-    const int64_t rem = po - b * Ho * Wo;
-    const int y = (int)(rem / Wo), x = (int)(rem % Wo);
-    float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int Wo = s.W / 2;
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= Wo * groups) return;
+    const int x = t / groups, c8 = t - x * groups;
+    const int64_t rows = (int64_t)s.B * (s.H / 2);
+    for (int64_t ro = blockIdx.y; ro < rows; ro += gridDim.y) {
+        float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
-    for (int d = 0; d < 4; ++d) {
-        const int64_t q = ((b * s.H) + 2 * y + (d >> 1)) * s.W + 2 * x + (d & 1);
-        const bf16x8 v = load8(s.in + q * s.in_stride + s.in_off + c8 * 8);
+        for (int d = 0; d < 4; ++d) {
+            const int64_t q = (2 * ro + (d >> 1)) * s.W + 2 * x + (d & 1);  // input row 2 ro + dy of the same image
+            const bf16x8 v = load8(s.in + q * s.in_stride + s.in_off + c8 * 8);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) acc[j] = acc[j] + (float)v[j];
+            for (int j = 0; j < 8; ++j) acc[j] = acc[j] + (float)v[j];
+        }
+        bf16x8 o;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) o[j] = (__bf16)(acc[j] * 0.25f);
+        *reinterpret_cast<bf16x8 *>(s.out + (ro * Wo + x) * s.out_stride + s.out_off + c8 * 8) = o;
     }
-    bf16x8 o;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) o[j] = (__bf16)(acc[j] * 0.25f);
-    *reinterpret_cast<bf16x8 *>(s.out + po * s.out_stride + s.out_off + c8 * 8) = o;
 }
 
-// source index and weight of output o for a x2 bilinear upsample of n samples
-// (half-pixel centres, clamped): out[o] = (1 - f) in[i0] + f in[i1]
-__device__ __forceinline__ void up_src(int o, int n, int &i0, int &i1, float &f)
-{
-    float src = ((float)o + 0.5f) * 0.5f - 0.5f;
-    src = fmaxf(src, 0.0f);
-    i0 = min((int)src, n - 1);
-    i1 = min(i0 + 1, n - 1);
-    f = src - (float)i0;
-}
-
-// in: [B][H][W] slice, out: [B][2H][2W] slice
+// 2x bilinear upsample, in: [B][H][W] slice, out: [B][2H][2W] slice
 __global__ __launch_bounds__(256) void k_upsample2(SliceArgs s)
 {
     const int groups = s.C / 8;
     const int Ho = 2 * s.H, Wo = 2 * s.W;
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t total = (int64_t)s.B * Ho * Wo * groups;
-    if (t >= total) return;
-    const int c8 = (int)(t % groups);
-    const int64_t po = t / groups;
-    const int64_t b = po / ((int64_t)Ho * Wo);
-    const int64_t rem = po - b * Ho * Wo;
-    const int y = (int)(rem / Wo), x = (int)(rem % Wo);
-    int y0, y1, x0, x1;
-    float fy, fx;
-    up_src(y, s.H, y0, y1, fy);
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= Wo * groups) return;
+    const int x = t / groups, c8 = t - x * groups;
+    int x0, x1;
+    float fx;
     up_src(x, s.W, x0, x1, fx);
-    const int64_t rb = b * s.H;
-    const bf16x8 v00 = load8(s.in + ((rb + y0) * s.W + x0) * s.in_stride + s.in_off + c8 * 8);
-    const bf16x8 v01 = load8(s.in + ((rb + y0) * s.W + x1) * s.in_stride + s.in_off + c8 * 8);
-    const bf16x8 v10 = load8(s.in + ((rb + y1) * s.W + x0) * s.in_stride + s.in_off + c8 * 8);
-    const bf16x8 v11 = load8(s.in + ((rb + y1) * s.W + x1) * s.in_stride + s.in_off + c8 * 8);
-    bf16x8 o;
+    const int64_t rows = (int64_t)s.B * Ho;
+    for (int64_t ro = blockIdx.y; ro < rows; ro += gridDim.y) {
+        const int64_t b = ro / Ho;
+        const int y = (int)(ro - b * Ho);
+        int y0, y1;
+        float fy;
+        up_src(y, s.H, y0, y1, fy);
+        const int64_t rb = b * s.H;
+        const bf16x8 v00 = load8(s.in + ((rb + y0) * s.W + x0) * s.in_stride + s.in_off + c8 * 8);
+        const bf16x8 v01 = load8(s.in + ((rb + y0) * s.W + x1) * s.in_stride + s.in_off + c8 * 8);
+        const bf16x8 v10 = load8(s.in + ((rb + y1) * s.W + x0) * s.in_stride + s.in_off + c8 * 8);
+        const bf16x8 v11 = load8(s.in + ((rb + y1) * s.W + x1) * s.in_stride + s.in_off + c8 * 8);
+        bf16x8 o;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const float top = (1.0f - fx) * (float)v00[j] + fx * (float)v01[j];
-        const float bot = (1.0f - fx) * (float)v10[j] + fx * (float)v11[j];
-        o[j] = (__bf16)((1.0f - fy) * top + fy * bot);
+        for (int j = 0; j < 8; ++j) {
+            const float top = (1.0f - fx) * (float)v00[j] + fx * (float)v01[j];
+            const float bot = (1.0f - fx) * (float)v10[j] + fx * (float)v11[j];
+            o[j] = (__bf16)((1.0f - fy) * top + fy * bot);
+        }
+        *reinterpret_cast<bf16x8 *>(s.out + (ro * Wo + x) * s.out_stride + s.out_off + c8 * 8) = o;
     }
-    *reinterpret_cast<bf16x8 *>(s.out + po * s.out_stride + s.out_off + c8 * 8) = o;
 }
 
 // gradient of k_upsample2, gather form: in-grad [B][H][W] from out-grad [B][2H][2W]
@@ -616,7 +925,11 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a)
                 const int64_t b = p / hw, rem = p - b * hw;
                 const int y = (int)(rem / a.W) + dy, x = (int)(rem % a.W) + dx;
                 if (y >= 0 && y < a.H && x >= 0 && x < a.W)
-                    v = load8(a.x + ((b * a.H + y) * a.W + x) * a.x_stride + a.x_off + ci);
+                    {
+                        const int64_t q = (b * a.H + y) * a.W + x;
+                        v = load8(a.x2 && ci >= a.xCin1 ? a.x2 + q * a.x2_stride + a.x2_off + (ci - a.xCin1)
+                                                        : a.x + q * a.x_stride + a.x_off + ci);
+                    }
             }
 #pragma unroll
             for (int j = 0; j < 8; ++j) sx[kg * 8 + j][px] = v[j];
@@ -893,9 +1206,48 @@ static hipError_t launch_conv(const ConvArgs &a, int KS, const uint8_t *wq, cons
 {
     const int64_t P = (int64_t)a.B * a.H * a.W;
     const int cop = a.Cout_pad;
-    // 3x3 layers with 64 or more output channels: LDS-staged tiles.  With 32
-    // channels the B tile is shared by only two MFMA rows and the staging costs
-    // more than it saves, so those layers read their operands directly.
+    if (a.head_out && (FP8 || KS != 3 || cop != 32 || a.Cin % 32 != 0 || a.out_f32)) return hipErrorInvalidValue;
+    if (a.in2 && (a.in_mask || a.Cin1 <= 0 || a.Cin1 >= a.Cin || a.Cin1 % 8 != 0)) return hipErrorInvalidValue;
+    // the upsampling input is read by the halo kernel only
+    if (a.up_in && (FP8 || KS != 3 || !a.in2 || a.Cin1 % 32 != 0 || a.Cin % 32 != 0 || a.out_f32 || a.in_mask ||
+                    a.H % 2 || a.W % 2))
+        return hipErrorInvalidValue;
+    const unsigned gx = (unsigned)((a.W + kHaloCols - 1) / kHaloCols);
+    const unsigned gy = (unsigned)((a.H + kHaloRows - 1) / kHaloRows);
+    // first layer (8 input channels, 32 output channels)
+    if (!FP8 && KS == 3 && cop == 32 && a.Cin == 8 && a.Kpad == 96 && !a.in_mask && !a.in2 && !a.out_f32) {
+        hipLaunchKernelGGL(k_conv_c8, dim3(gx, gy, (unsigned)a.B), dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
+    // bf16 3x3 layers with Cin a multiple of 32: direct convolution from halo
+    // tiles (32 output channels per 4 waves, or 64 per 8 waves)
+    const bool halo = !FP8 && KS == 3 && a.Cin % 32 == 0 && (!a.in2 || a.Cin1 % 32 == 0) && !a.out_f32 &&
+                      (cop == 32 || cop % 64 == 0) && (int64_t)a.B * (cop == 32 ? 1 : cop / 64) <= 65535;
+    if (halo && cop == 32) {
+        const dim3 grid(gx, gy, (unsigned)a.B);
+        if (a.head_out) {
+            if (a.in_mask || a.Cout != 32 || a.up_in) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((k_conv_halo<32, false, true, false>), grid, dim3(256), 0, s, a);
+        } else if (a.in_mask) {
+            hipLaunchKernelGGL((k_conv_halo<32, true, false, false>), grid, dim3(256), 0, s, a);
+        } else if (a.up_in) {
+            hipLaunchKernelGGL((k_conv_halo<32, false, false, true>), grid, dim3(256), 0, s, a);
+        } else {
+            hipLaunchKernelGGL((k_conv_halo<32, false, false, false>), grid, dim3(256), 0, s, a);
+        }
+        return hipGetLastError();
+    }
+    if (a.head_out) return hipErrorInvalidValue;
+    if (halo) {
+        const dim3 grid(gx, gy, (unsigned)(a.B * (cop / 64)));
+        if (a.in_mask) hipLaunchKernelGGL((k_conv_halo<64, true, false, false>), grid, dim3(512), 0, s, a);
+        else if (a.up_in) hipLaunchKernelGGL((k_conv_halo<64, false, false, true>), grid, dim3(512), 0, s, a);
+        else hipLaunchKernelGGL((k_conv_halo<64, false, false, false>), grid, dim3(512), 0, s, a);
+        return hipGetLastError();
+    }
+    if (a.up_in) return hipErrorInvalidValue;
+    // other 3x3 layers with 64 or more output channels (FP8, or Cin not a
+    // multiple of 32): LDS-staged im2col tiles
     if (KS == 3 && cop % 64 == 0) {
         dim3 grid(nblocks(P, 128), cop / 64);
         if (a.in_mask)
@@ -949,17 +1301,23 @@ hipError_t features(const float *in, __bf16 *out, int B, int H, int W, hipStream
     return hipGetLastError();
 }
 
+// grid for the row-walking kernels: x covers one row's (pixel, group) pairs
+static dim3 row_grid(int64_t row_items, int64_t rows)
+{
+    return dim3(nblocks(row_items), (unsigned)std::min<int64_t>(rows, 65535));
+}
+
 hipError_t pool2(const SliceArgs &a, hipStream_t s)
 {
-    const int64_t n = (int64_t)a.B * (a.H / 2) * (a.W / 2) * (a.C / 8);
-    hipLaunchKernelGGL(k_pool2, dim3(nblocks(n)), dim3(256), 0, s, a);
+    if ((int64_t)a.B * a.H * a.W == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pool2, row_grid((int64_t)(a.W / 2) * (a.C / 8), (int64_t)a.B * (a.H / 2)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t upsample2(const SliceArgs &a, hipStream_t s)
 {
-    const int64_t n = (int64_t)a.B * (2 * a.H) * (2 * a.W) * (a.C / 8);
-    hipLaunchKernelGGL(k_upsample2, dim3(nblocks(n)), dim3(256), 0, s, a);
+    if ((int64_t)a.B * a.H * a.W == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_upsample2, row_grid((int64_t)(2 * a.W) * (a.C / 8), (int64_t)a.B * 2 * a.H), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

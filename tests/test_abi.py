@@ -144,6 +144,8 @@ def test_net_host_logic():
     bad[5] = np.nan
     assert L.narvis_weights_create(bad.ctypes.data, n, ctypes.byref(h)) == -1
     assert L.narvis_postprocess_workspace_size(1, 12, 16) == 0      # W not a multiple of 8
+    assert L.narvis_postprocess_workspace_size(1, 32776, 8) == 0    # W above 32768
+    assert L.narvis_postprocess_workspace_size(1, 32768, 8) > 0
     assert L.narvis_postprocess_workspace_size(0, 16, 16) == 0
     assert L.narvis_postprocess_workspace_size(1, 1920, 1080) > 0
     assert L.narvis_train_workspace_size(16, 512, 512) > L.narvis_postprocess_workspace_size(16, 512, 512)
