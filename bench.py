@@ -191,6 +191,9 @@ def main():
                     choices=["trajectories", "vector_field", "unit_cube", "terrain", "terrain25"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-frame", action="store_true", help="skip the 1080p raster+network vs splat frame section")
+    ap.add_argument("--frame-only", action="store_true",
+                    help="run only the 1080p frame section (for profiling the network kernels)")
+    ap.add_argument("--train-steps", type=int, default=200, help="Adam steps of the frame section's training")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the rasterizer runs on a single device "
@@ -199,6 +202,10 @@ def main():
 
     import torch
     from paper_2407_19097_amd import narvis, scenes
+
+    if args.frame_only:
+        print(json.dumps({"frame_1080p": frame_section(torch, log, train_steps=args.train_steps)}), flush=True)
+        return
 
     dev = "cuda"
     t0 = time.time()
@@ -300,7 +307,7 @@ def main():
     }
     if not args.no_frame:
         log("1080p frame section: training the network, then raster + network vs splat")
-        out["frame_1080p"] = frame_section(torch, log)
+        out["frame_1080p"] = frame_section(torch, log, train_steps=args.train_steps)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline(sc, cams[0])

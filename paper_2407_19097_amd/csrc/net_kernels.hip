@@ -453,28 +453,34 @@ __device__ __forceinline__ bf16x8 upsample_piece(const __bf16 *in, int stride, i
 // Within a pixel's 64 bytes the four 16-byte pieces are XOR-swizzled by
 // pixel bits 1-2, so eight lanes reading eight consecutive pixels at the same
 // channel offset hit distinct banks, for every tap shift.
-constexpr int kHaloRows = 4;
-constexpr int kHaloCols = 64;
+constexpr int kHaloRows = 4;   // output rows per workgroup of the first-layer kernel
+constexpr int kHaloCols = 64;  // output pixels per row of a tile
 
 __device__ __forceinline__ int halo_at(int p, int part) { return p * 32 + 8 * (part ^ ((p >> 1) & 3)); }
 
-template <int CO, bool MASK, bool HEAD, bool UP>
-__global__ __launch_bounds__(128 * CO / 16) void k_conv_halo(ConvArgs a)
+template <int CO, int ROWS, bool MASK, bool HEAD, bool UP>
+__global__ __launch_bounds__(64 * ROWS * CO / 32, 4) void k_conv_halo(ConvArgs a)
 {
     constexpr int NCH = CO / 32;                  // waves per output row (32 channels each)
-    constexpr int NT = 64 * kHaloRows * NCH;      // threads
-    constexpr int HR = kHaloRows + 2, HC = kHaloCols + 2;
+    constexpr int NT = 64 * ROWS * NCH;           // threads
+    constexpr int HR = ROWS + 2, HC = kHaloCols + 2;
     constexpr int NPIECE = HR * HC * 4;           // 16-byte pieces of the halo tile
     constexpr int SJ = (NPIECE + NT - 1) / NT;
     constexpr int NWPIECE = 9 * CO * 4;           // pieces of the weights (9 taps x CO x 32 ci)
     constexpr int WJ = (NWPIECE + NT - 1) / NT;
+    // upsampled groups: the low-resolution source rows y0/2 - 1 .. y0/2 + ROWS/2
+    // and columns x0/2 - 1 .. x0/2 + 32 cover every source the tile needs
+    constexpr int SR = UP ? ROWS / 2 + 2 : 1, SC = UP ? kHaloCols / 2 + 2 : 1;
+    constexpr int NLPIECE = SR * SC * 4;
+    constexpr int LJ = (NLPIECE + NT - 1) / NT;
     __shared__ __attribute__((aligned(16))) __bf16 xs[HR * HC * 32];
     __shared__ __attribute__((aligned(16))) __bf16 ws[9 * CO * 32];   // row (tap * CO + co), 32 ci
+    __shared__ __attribute__((aligned(16))) __bf16 lo[SR * SC * 32];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, r = lane & 15;
     const int wch = wave % NCH, wrow = wave / NCH;  // this wave: channels 32 wch.., output row wrow
     const int ctiles = a.Cout_pad / CO;
-    const int x0 = blockIdx.x * kHaloCols, y0 = blockIdx.y * kHaloRows;
+    const int x0 = blockIdx.x * kHaloCols, y0 = blockIdx.y * ROWS;
     const int b = blockIdx.z / ctiles, co0 = (blockIdx.z - b * ctiles) * CO;
     f32x4 acc[2][4];
 #pragma unroll
@@ -488,7 +494,6 @@ __global__ __launch_bounds__(128 * CO / 16) void k_conv_halo(ConvArgs a)
         const __bf16 *src = second ? a.in2 : a.in;
         const int sstride = second ? a.in2_stride : a.in_stride;
         const int soff = second ? a.in2_off + 32 * c - a.Cin1 : a.in_off + 32 * c;
-        const bool up = UP && !second;
         bf16x8 wv[WJ];
 #pragma unroll
         for (int j = 0; j < WJ; ++j) {
@@ -499,18 +504,61 @@ __global__ __launch_bounds__(128 * CO / 16) void k_conv_halo(ConvArgs a)
             if (piece < NWPIECE)
                 wv[j] = load8(a.wt + (int64_t)(co0 + co) * a.Kpad + tap * a.Cin + 32 * c + 8 * part);
         }
-        if (up) {
-            // upsampled group: each piece is interpolated and stored in turn
+        auto store_w = [&]() {
+#pragma unroll
+            for (int j = 0; j < WJ; ++j) {
+                const int piece = threadIdx.x + NT * j;
+                if (piece < NWPIECE) *reinterpret_cast<bf16x8 *>(&ws[halo_at(piece >> 2, piece & 3)]) = wv[j];
+            }
+        };
+        if (UP && !second) {
+            // upsampled group: stage the low-resolution source tile (rows and
+            // columns clamped to the source image), then interpolate from LDS
+            const int h = a.H / 2, w = a.W / 2;
+            const int sy0 = y0 / 2 - 1, sx0 = x0 / 2 - 1;
+            bf16x8 lv[LJ];
+#pragma unroll
+            for (int j = 0; j < LJ; ++j) {
+                const int piece = threadIdx.x + NT * j;
+                const int p = piece >> 2, part = piece & 3;
+                const int ly = p / SC, lx = p - ly * SC;
+                const int sy = min(max(sy0 + ly, 0), h - 1), sx = min(max(sx0 + lx, 0), w - 1);
+                lv[j] = zero8();
+                if (piece < NLPIECE)
+                    lv[j] = load8(src + (((int64_t)b * h + sy) * w + sx) * sstride + soff + 8 * part);
+            }
             if (c) __syncthreads();  // the previous group's taps are done with the tiles
+            store_w();
+#pragma unroll
+            for (int j = 0; j < LJ; ++j) {
+                const int piece = threadIdx.x + NT * j;
+                if (piece < NLPIECE) *reinterpret_cast<bf16x8 *>(&lo[halo_at(piece >> 2, piece & 3)]) = lv[j];
+            }
+            __syncthreads();
 #pragma unroll 1
             for (int piece = threadIdx.x; piece < NPIECE; piece += NT) {
                 const int p = piece >> 2, part = piece & 3;
                 const int hy = p / HC, hx = p - hy * HC;
                 const int y = y0 - 1 + hy, x = x0 - 1 + hx;
-                bf16x8 v = zero8();
-                if (y >= 0 && y < a.H && x >= 0 && x < a.W)
-                    v = upsample_piece(src, sstride, soff, b, a.H / 2, a.W / 2, y, x, 8 * part);
-                *reinterpret_cast<bf16x8 *>(&xs[halo_at(p, part)]) = v;
+                bf16x8 t = zero8();
+                if (y >= 0 && y < a.H && x >= 0 && x < a.W) {
+                    int iy0, iy1, ix0, ix1;
+                    float fy, fx;
+                    up_src(y, h, iy0, iy1, fy);
+                    up_src(x, w, ix0, ix1, fx);
+                    iy0 -= sy0, iy1 -= sy0, ix0 -= sx0, ix1 -= sx0;
+                    const bf16x8 v00 = *reinterpret_cast<const bf16x8 *>(&lo[halo_at(iy0 * SC + ix0, part)]);
+                    const bf16x8 v01 = *reinterpret_cast<const bf16x8 *>(&lo[halo_at(iy0 * SC + ix1, part)]);
+                    const bf16x8 v10 = *reinterpret_cast<const bf16x8 *>(&lo[halo_at(iy1 * SC + ix0, part)]);
+                    const bf16x8 v11 = *reinterpret_cast<const bf16x8 *>(&lo[halo_at(iy1 * SC + ix1, part)]);
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        const float top = (1.0f - fx) * (float)v00[j] + fx * (float)v01[j];
+                        const float bot = (1.0f - fx) * (float)v10[j] + fx * (float)v11[j];
+                        t[j] = (__bf16)((1.0f - fy) * top + fy * bot);
+                    }
+                }
+                *reinterpret_cast<bf16x8 *>(&xs[halo_at(p, part)]) = t;
             }
         } else {
             bf16x8 v[SJ];
@@ -533,16 +581,12 @@ __global__ __launch_bounds__(128 * CO / 16) void k_conv_halo(ConvArgs a)
                 }
             }
             if (c) __syncthreads();  // the previous group's taps are done with the tiles
+            store_w();
 #pragma unroll
             for (int j = 0; j < SJ; ++j) {
                 const int piece = threadIdx.x + NT * j;
                 if (piece < NPIECE) *reinterpret_cast<bf16x8 *>(&xs[halo_at(piece >> 2, piece & 3)]) = v[j];
             }
-        }
-#pragma unroll
-        for (int j = 0; j < WJ; ++j) {
-            const int piece = threadIdx.x + NT * j;
-            if (piece < NWPIECE) *reinterpret_cast<bf16x8 *>(&ws[halo_at(piece >> 2, piece & 3)]) = wv[j];
         }
         __syncthreads();
 #pragma unroll
@@ -1224,25 +1268,27 @@ static hipError_t launch_conv(const ConvArgs &a, int KS, const uint8_t *wq, cons
     const bool halo = !FP8 && KS == 3 && a.Cin % 32 == 0 && (!a.in2 || a.Cin1 % 32 == 0) && !a.out_f32 &&
                       (cop == 32 || cop % 64 == 0) && (int64_t)a.B * (cop == 32 ? 1 : cop / 64) <= 65535;
     if (halo && cop == 32) {
-        const dim3 grid(gx, gy, (unsigned)a.B);
+        // 8 rows x 64 pixels x 32 channels per workgroup of 8 waves
+        const dim3 grid(gx, (unsigned)((a.H + 7) / 8), (unsigned)a.B);
         if (a.head_out) {
             if (a.in_mask || a.Cout != 32 || a.up_in) return hipErrorInvalidValue;
-            hipLaunchKernelGGL((k_conv_halo<32, false, true, false>), grid, dim3(256), 0, s, a);
+            hipLaunchKernelGGL((k_conv_halo<32, 8, false, true, false>), grid, dim3(512), 0, s, a);
         } else if (a.in_mask) {
-            hipLaunchKernelGGL((k_conv_halo<32, true, false, false>), grid, dim3(256), 0, s, a);
+            hipLaunchKernelGGL((k_conv_halo<32, 8, true, false, false>), grid, dim3(512), 0, s, a);
         } else if (a.up_in) {
-            hipLaunchKernelGGL((k_conv_halo<32, false, false, true>), grid, dim3(256), 0, s, a);
+            hipLaunchKernelGGL((k_conv_halo<32, 8, false, false, true>), grid, dim3(512), 0, s, a);
         } else {
-            hipLaunchKernelGGL((k_conv_halo<32, false, false, false>), grid, dim3(256), 0, s, a);
+            hipLaunchKernelGGL((k_conv_halo<32, 8, false, false, false>), grid, dim3(512), 0, s, a);
         }
         return hipGetLastError();
     }
     if (a.head_out) return hipErrorInvalidValue;
     if (halo) {
-        const dim3 grid(gx, gy, (unsigned)(a.B * (cop / 64)));
-        if (a.in_mask) hipLaunchKernelGGL((k_conv_halo<64, true, false, false>), grid, dim3(512), 0, s, a);
-        else if (a.up_in) hipLaunchKernelGGL((k_conv_halo<64, false, false, true>), grid, dim3(512), 0, s, a);
-        else hipLaunchKernelGGL((k_conv_halo<64, false, false, false>), grid, dim3(512), 0, s, a);
+        // 4 rows x 64 pixels x 64 channels per workgroup of 8 waves
+        const dim3 grid(gx, (unsigned)((a.H + 3) / 4), (unsigned)(a.B * (cop / 64)));
+        if (a.in_mask) hipLaunchKernelGGL((k_conv_halo<64, 4, true, false, false>), grid, dim3(512), 0, s, a);
+        else if (a.up_in) hipLaunchKernelGGL((k_conv_halo<64, 4, false, false, true>), grid, dim3(512), 0, s, a);
+        else hipLaunchKernelGGL((k_conv_halo<64, 4, false, false, false>), grid, dim3(512), 0, s, a);
         return hipGetLastError();
     }
     if (a.up_in) return hipErrorInvalidValue;
