@@ -78,12 +78,14 @@ def read_traffic(launch_points, W, H):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(sc, cam, budget_s=15.0):
-    """The oracle as it stands (single thread) on the first S points of one frame."""
+def cpu_baseline(sc, cams, budget_s=15.0):
+    """The oracle as it stands (single thread) on a bounded sample of the
+    workload: the first S points of one frame, or, when a whole frame takes
+    less than the budget, whole frames along the camera path."""
     from oracle import camera as ocam
     from oracle import raster as orast
     n, W, H = sc.n, sc.W, sc.H
-    M, near, far = ocam.clip_matrix(cam, W, H)
+    M, near, far = ocam.clip_matrix(cams[0], W, H)
     cal = min(n, 2_000_000)
     xs = sc.x[:cal].cpu().numpy()
     ys = sc.y[:cal].cpu().numpy()
@@ -93,6 +95,7 @@ def cpu_baseline(sc, cam, budget_s=15.0):
     rate = cal / max(time.perf_counter() - t0, 1e-6)
     S = int(min(n, max(cal, rate * budget_s)))
     S -= S % 4
+    frames = max(1, min(len(cams), int(rate * budget_s / max(n, 1)))) if S == n else 1
     xs = sc.x[:S].cpu().numpy()
     ys = sc.y[:S].cpu().numpy()
     zs = sc.z[:S].cpu().numpy()
@@ -101,12 +104,16 @@ def cpu_baseline(sc, cam, budget_s=15.0):
         h = a[:S].cpu().numpy()
         attrs.append(h.view(np.uint16) if h.dtype == np.int16 else h)
     t0 = time.perf_counter()
-    keys = orast.render(xs, ys, zs, M, near, far, W, H)
-    orast.resolve(keys, W, H, xs, ys, zs, M, attrs)
+    for f in range(frames):
+        M, near, far = ocam.clip_matrix(cams[f], W, H)
+        keys = orast.render(xs, ys, zs, M, near, far, W, H)
+        orast.resolve(keys, W, H, xs, ys, zs, M, attrs)
     dt = time.perf_counter() - t0
-    return {"value": S / dt / 1e9, "unit": "Gpoints/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {S} of {n} points, one frame ({W}x{H}), render + resolve (depth, attributes), "
-                      f"single-threaded C oracle, {dt:.1f} s"}
+    what = (f"first {S} of {n} points of frame 0" if frames == 1 and S < n
+            else f"all {n} points, frames 0-{frames - 1} of the camera path")
+    return {"value": frames * S / dt / 1e9, "unit": "Gpoints/s", "cores": 1, "kind": "oracle",
+            "sample": f"{what} ({W}x{H}), render + resolve (depth, attributes), single-threaded C oracle, "
+                      f"{dt:.1f} s"}
 
 
 def frame_section(torch, log_fn, frames=12, train_views=400, train_steps=200):
@@ -165,6 +172,7 @@ def frame_section(torch, log_fn, frames=12, train_views=400, train_steps=200):
         p_ras.append(metrics.psnr(feat[:, 0:3].view(1, 3, H, W), t3).item())
         s_net.append(metrics.ssim(y, t3).item())
         s_ras.append(metrics.ssim(feat[:, 0:3].view(1, 3, H, W), t3).item())
+    pairs = narvis.narvis_splat_pair_count(r.ws, sc.n, W, H, r.params)  # of the last frame
     w.close()
     m = lambda xs: float(np.mean(xs))
     raster_ms, net_ms, splat_ms = m(t_r), m(t_n), m(t_s)
@@ -174,6 +182,7 @@ def frame_section(torch, log_fn, frames=12, train_views=400, train_steps=200):
             "raster_ms": round(raster_ms, 4), "net_bf16_ms": round(net_ms, 4),
             "frame_ms": round(raster_ms + net_ms, 4), "splat_ms": round(splat_ms, 3),
             "frame_fraction_of_splat": round((raster_ms + net_ms) / splat_ms, 4),
+            "splat_pairs_last_frame": pairs, "splat_gpairs_per_s": round(pairs / (splat_ms / 1e3) / 1e9, 3),
             "psnr_db": round(m(p_net), 3), "ssim": round(m(s_net), 4),
             "psnr_raster_only_db": round(m(p_ras), 3), "ssim_raster_only": round(m(s_ras), 4),
             "val_512_psnr_db": round(val[0], 3), "val_512_psnr_raster_only_db": round(val[1], 3),
@@ -305,12 +314,38 @@ def main():
                      "algorithmic_bytes_per_launch": alg_bytes},
         "stream_copy_GBps": round(copy_gbps, 1),
     }
+    if sc.name == "terrain" and W * H >= 3840 * 2160 and g.attr is not None and g.attr.shape[0] >= 3:
+        # end-to-end 4K frame: the raster step above + the BF16 network on its
+        # G-buffer (RGB from the resolved RGBA planes, depth, no velocity);
+        # untrained weights: the network's time does not depend on them
+        log("end-to-end frame: network at the terrain's resolution")
+        from paper_2407_19097_amd import train
+        feat = torch.zeros((1, 8, W * H), dtype=torch.float32, device=dev)
+        feat[0, 0:3] = g.attr[0:3] * (1.0 / 255.0)
+        feat[0, 3] = g.depth
+        img = torch.empty((1, 3, H, W), dtype=torch.float32, device=dev)
+        ws = torch.empty(narvis.narvis_postprocess_workspace_size(1, W, H), dtype=torch.uint8, device=dev)
+        wts = narvis.NetWeights(train.init_blob(0))
+        for _ in range(2):
+            narvis.narvis_postprocess(wts, feat, 1, W, H, img, ws, stream=stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(5):
+            narvis.narvis_postprocess(wts, feat, 1, W, H, img, ws, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        net_ms = e0.elapsed_time(e1) / 5
+        wts.close()
+        del feat, img, ws
+        out["end_to_end_frame"] = {"W": W, "H": H, "raster_step_ms": round(ms_per_step, 4),
+                                   "net_bf16_ms": round(net_ms, 4), "frame_ms": round(ms_per_step + net_ms, 4),
+                                   "net_tflops": round(327360.0 * W * H / (net_ms / 1e3) / 1e12, 1)}
     if not args.no_frame:
         log("1080p frame section: training the network, then raster + network vs splat")
         out["frame_1080p"] = frame_section(torch, log, train_steps=args.train_steps)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample")
-        out["cpu_baseline"] = cpu_baseline(sc, cams[0])
+        out["cpu_baseline"] = cpu_baseline(sc, cams)
         out["cpu_baseline"]["value"] = round(out["cpu_baseline"]["value"], 5)
     print(json.dumps(out), flush=True)
 

@@ -218,12 +218,24 @@ narvis_status narvis_splat(const narvis_points *pts, const narvis_attrs *attrs, 
                            const narvis_camera *cam, int32_t W, int32_t H, float *img,
                            const narvis_splat_params *p, void *workspace, size_t ws_bytes, void *stream);
 
+/* Number of (tile, key) pairs that the last narvis_splat call on `workspace`
+ * emitted and depth-sorted (with the same n, W, H and *p): for every point
+ * that survives the cull, one pair per 16 x 16 pixel tile touched by the
+ * pixel rectangle [floor(sx - 3 sigma - 1), floor(sx + 3 sigma + 1)] x
+ * [floor(sy - 3 sigma - 1), floor(sy + 3 sigma + 1)] clipped to the image
+ * (fp32; the extra pixel covers the rounding of the footprint's ends).  For
+ * measurement (the sort's keys per second).  Copies one counter from the workspace to *pairs and synchronises
+ * `stream`.  INVALID_ARG on bad arguments, WORKSPACE if ws_bytes is too small,
+ * DEVICE if the copy fails. */
+narvis_status narvis_splat_pair_count(const void *workspace, size_t ws_bytes, uint64_t n, int32_t W, int32_t H,
+                                      const narvis_splat_params *p, uint64_t *pairs, void *stream);
+
 /* ------------------------------------------------------------------------
  * Learned post-process (after the U-Net post-processor of Sec. 3.3): a
  * four-level encoder-decoder, 32-64-128-256 channels, two 3x3 conv + ReLU
  * per level, 2x2 average pooling down, bilinear x2 upsampling up with
- * [upsampled, skip] concatenation, a 1x1 head to RGB.  Convolutions run as
- * implicit GEMM on the matrix cores in bfloat16 with fp32 accumulation.
+ * [upsampled, skip] concatenation, a 1x1 head to RGB.  Convolutions run on
+ * the matrix cores with bfloat16 operands and fp32 accumulation.
  *
  * Parameter blob (host fp32, narvis_net_param_count() values): for each
  * layer in the order e1a e1b e2a e2b e3a e3b e4a e4b d3a d3b d2a d2b d1a d1b

@@ -81,6 +81,9 @@ SIGNATURES = {
     "narvis_splat": (ctypes.c_int, [ctypes.POINTER(Points), ctypes.POINTER(Attrs), ctypes.c_uint64,
                                     ctypes.POINTER(Camera), ctypes.c_int32, ctypes.c_int32, _P,
                                     ctypes.POINTER(SplatParams), _P, ctypes.c_size_t, _P]),
+    "narvis_splat_pair_count": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint64, ctypes.c_int32,
+                                                ctypes.c_int32, ctypes.POINTER(SplatParams),
+                                                ctypes.POINTER(ctypes.c_uint64), ctypes.c_void_p]),
     "narvis_net_param_count": (ctypes.c_size_t, []),
     "narvis_weights_create": (ctypes.c_int, [_P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p)]),
     "narvis_weights_destroy": (None, [_P]),

@@ -246,3 +246,22 @@ extern "C" narvis_status narvis_splat(const narvis_points *pts, const narvis_att
     return from_hip(launch_splat(n ? pts->x : nullptr, n ? pts->y : nullptr, n ? pts->z : nullptr, n, P, pack, *p, img,
                                  workspace, static_cast<hipStream_t>(stream)));
 }
+
+extern "C" narvis_status narvis_splat_pair_count(const void *workspace, size_t ws_bytes, uint64_t n, int32_t W,
+                                                 int32_t H, const narvis_splat_params *p, uint64_t *pairs,
+                                                 void *stream)
+{
+    if (!workspace || !pairs || !splat_size_ok(n, W, H, p) || (reinterpret_cast<uintptr_t>(workspace) & 255u))
+        return NARVIS_ERR_INVALID_ARG;
+    const SplatLayout L = splat_layout(n, W, H, p->sigma_px);
+    if (ws_bytes < (size_t)L.bytes) return NARVIS_ERR_WORKSPACE;
+    // the exclusive scan of the per-point tile counts leaves the total at cnt[n]
+    uint32_t total = 0;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const char *src = static_cast<const char *>(workspace) + L.off_cnt + n * sizeof(uint32_t);
+    if (hipMemcpyAsync(&total, src, sizeof(total), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return NARVIS_ERR_DEVICE;
+    *pairs = total < L.cap ? total : L.cap;
+    return NARVIS_OK;
+}

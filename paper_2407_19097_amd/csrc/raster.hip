@@ -42,19 +42,22 @@ __device__ __forceinline__ bool project(const Proj &P, float x, float y, float z
     ww = ww + P.m31 * y;
     ww = ww + P.m32 * z;
     ww = ww + P.m33;
-    if (!(ww >= P.near_f && ww <= P.far_f)) return false;
-    float nx = cx / ww;
-    float ny = cy / ww;
+    // evaluated without branches (a culled point's values are discarded), so
+    // the independent points of a thread interleave
+    const float nx = cx / ww;
+    const float ny = cy / ww;
     float sx = nx * 0.5f;
     sx = sx + 0.5f;
     sx = sx * P.Wf;
     float sy = ny * 0.5f;
     sy = 0.5f - sy;
     sy = sy * P.Hf;
-    if (!(sx >= 0.0f && sx < P.Wf && sy >= 0.0f && sy < P.Hf)) return false;
-    pix = (uint32_t)(int32_t)sy * (uint32_t)P.W + (uint32_t)(int32_t)sx;
+    const bool ok = (ww >= P.near_f) & (ww <= P.far_f) & (sx >= 0.0f) & (sx < P.Wf) & (sy >= 0.0f) & (sy < P.Hf);
+    // clamped before the conversion; equal to sx, sy whenever ok
+    const float xs = fminf(fmaxf(sx, 0.0f), P.Wf), ys = fminf(fmaxf(sy, 0.0f), P.Hf);
+    pix = (uint32_t)(int32_t)ys * (uint32_t)P.W + (uint32_t)(int32_t)xs;
     w = ww;
-    return true;
+    return ok;
 }
 
 template <int VARIANT>
@@ -216,7 +219,8 @@ __device__ __forceinline__ void global_merge(unsigned long long *__restrict__ ke
         if (hit[t] && key[t] < cur[t]) __hip_atomic_fetch_min(keys + pix[t], key[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ __launch_bounds__(kBlock) void k_render_lds(const float *__restrict__ X, const float *__restrict__ Y,
+// (4 waves per SIMD: the compiler keeps it within 128 registers)
+__global__ __launch_bounds__(kBlock, 4) void k_render_lds(const float *__restrict__ X, const float *__restrict__ Y,
                                                         const float *__restrict__ Z, uint64_t n, Proj P,
                                                         unsigned long long *__restrict__ keys, ChunkOrder order)
 {
@@ -257,7 +261,7 @@ __global__ __launch_bounds__(kBlock) void k_render_lds(const float *__restrict__
                 const int t = k * 4 + j;
                 float w = 0.0f;
                 uint32_t pp = 0;
-                hit[t] = live && project(P, px[j], py[j], pz[j], pp, w);
+                hit[t] = project(P, px[j], py[j], pz[j], pp, w) & live;
                 pix[t] = pp;
                 key[t] = ((unsigned long long)__float_as_uint(w) << 32) | (first + lq * 4 + (uint32_t)j);
                 pixof[lq * 4 + j] = hit[t] ? pp : kNoPixel;

@@ -193,6 +193,16 @@ def narvis_splat(points, attrs, n: int, camera, W: int, H: int, img, params: Spl
                "narvis_splat")
 
 
+def narvis_splat_pair_count(workspace, n: int, W: int, H: int, params: SplatParams, stream=None) -> int:
+    """(tile, key) pairs the last narvis_splat on `workspace` sorted (synchronises the stream)."""
+    p = params.struct()
+    out = ctypes.c_uint64()
+    nbytes = workspace.numel() * workspace.element_size()
+    _lib.check(_lib.load().narvis_splat_pair_count(_ptr(workspace), nbytes, int(n), W, H, ctypes.byref(p),
+                                                   ctypes.byref(out), _stream_ptr(stream)), "narvis_splat_pair_count")
+    return int(out.value)
+
+
 PRECISION_BF16, PRECISION_FP8 = 0, 1
 
 

@@ -140,3 +140,40 @@ def test_vector_field_full_frame():
                               with_fragile=True)
     d = compare(got, want, frag)
     print(f"  max err {d.max():.3g}, fragile pixels {int(frag.sum())}", flush=True)
+
+
+@pytest.mark.parametrize("sigma", [1.5, 4.0])
+def test_splat_pair_count(sigma):
+    """narvis_splat_pair_count equals the documented per-point tile count."""
+    announce(f"splat pair count sigma={sigma}")
+    W, H = 70, 45
+    sc = scenes.unit_cube(n=3000, seed=11, W=W, H=H)
+    cam = scenes.Camera(eye=(1.7, 1.5, 1.3), target=(0.5, 0.5, 0.5))
+    params = narvis.SplatParams(sigma_px=sigma, opacity=1.0, color_mode=narvis.COLOR_LUT, color_attr=sc.lut_attr,
+                                lut=dev(scenes.colour_lut()), lut_min=sc.lut_min, lut_inv_range=1.0)
+    X, Y, Z = dev(sc.x), dev(sc.y), dev(sc.z)
+    n = int(sc.x.shape[0])
+    ws = torch.empty(narvis.narvis_splat_workspace_size(n, W, H, params), dtype=torch.uint8, device="cuda")
+    img = torch.empty((3, W * H), dtype=torch.float32, device="cuda")
+    narvis.narvis_splat((X, Y, Z), [dev(a) for a in sc.attrs], n, cam, W, H, img, params, ws)
+    got = narvis.narvis_splat_pair_count(ws, n, W, H, params)
+    # screen position of every point, the documented fp32 arithmetic (numpy
+    # float32 operations are single rounded ops, none fused)
+    M, near, far = ocam.clip_matrix(cam, W, H)
+    M = np.asarray(M, np.float32).reshape(4, 4)
+    f = np.float32
+    row = lambda r: ((M[r, 0] * sc.x + M[r, 1] * sc.y) + M[r, 2] * sc.z) + M[r, 3]
+    cx, cy, w = row(0), row(1), row(3)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        sx = ((cx / w) * f(0.5) + f(0.5)) * f(W)
+        sy = (f(0.5) - (cy / w) * f(0.5)) * f(H)
+    keep = (w >= near) & (w <= far) & (sx >= 0) & (sx < W) & (sy >= 0) & (sy < H)
+    reach = f(3.0) * f(sigma)
+    sx, sy = sx[keep], sy[keep]
+    x0 = np.maximum(np.floor(sx - reach - f(1)).astype(np.int64), 0)
+    x1 = np.minimum(np.floor(sx + reach + f(1)).astype(np.int64), W - 1)
+    y0 = np.maximum(np.floor(sy - reach - f(1)).astype(np.int64), 0)
+    y1 = np.minimum(np.floor(sy + reach + f(1)).astype(np.int64), H - 1)
+    want = int(((x1 // 16 - x0 // 16 + 1) * (y1 // 16 - y0 // 16 + 1)).sum())
+    assert keep.sum() > 100
+    assert got == want
