@@ -268,10 +268,9 @@ hipError_t forward(const narvis_weights *w, const float *feat_planes, char *ws, 
     TRY(run_conv(w, E4A, conv_args(L[E4A], c.b(p.pool3), 128, 0, c.b(p.e4a), 256, 0, B, H3, W3), fp8, s));
     TRY(run_conv(w, E4B, conv_args(L[E4B], c.b(p.e4a), 256, 0, c.b(p.e4b), 256, 0, B, H3, W3), fp8, s));
     // A decoder layer's input is [2x upsample of the layer below | skip].  In
-    // inference with bf16 decoder layers the upsample is done while the
-    // layer stages its input; training (and the FP8 path, whose kernels read
-    // a plain input) materialises it.
-    const bool fuse_up = !keep_acts && !fp8;
+    // inference the upsample is done while the layer stages its input;
+    // training materialises it (the backward pass reads it).
+    const bool fuse_up = !keep_acts;
     if (fuse_up) {
         ConvArgs a = with_skip(conv_args(L[D3A], c.b(p.e4b), 256, 0, c.b(p.d3a), 128, 0, B, H2, W2), c.b(p.sk3), 128, 256);
         a.up_in = 1;

@@ -458,9 +458,17 @@ constexpr int kHaloCols = 64;  // output pixels per row of a tile
 
 __device__ __forceinline__ int halo_at(int p, int part) { return p * 32 + 8 * (part ^ ((p >> 1) & 3)); }
 
-template <int CO, int ROWS, bool MASK, bool HEAD, bool UP>
-__global__ __launch_bounds__(64 * ROWS * CO / 32, 4) void k_conv_halo(ConvArgs a)
+template <int CO, int ROWS, bool MASK, bool HEAD, bool UP, bool FP8>
+__global__ __launch_bounds__(64 * ROWS * CO / 32, 4) void k_conv_halo(ConvArgs a, const uint8_t *wq, const float *sw,
+                                                                      float sa)
 {
+    static_assert(!FP8 || (!MASK && !HEAD), "FP8 runs inference layers without the fused head");
+    typedef ConvOps<FP8> Ops;
+    // LDS holds bf16, or e4m3 for FP8 (activations converted on the way in)
+    constexpr int EB = FP8 ? 1 : 2;
+    typedef typename std::conditional<FP8, long, bf16x8>::type Piece;  // 8 channels
+    const float inv_sa = FP8 ? 1.0f / sa : 1.0f;
+
     constexpr int NCH = CO / 32;                  // waves per output row (32 channels each)
     constexpr int NT = 64 * ROWS * NCH;           // threads
     constexpr int HR = ROWS + 2, HC = kHaloCols + 2;
@@ -473,9 +481,19 @@ __global__ __launch_bounds__(64 * ROWS * CO / 32, 4) void k_conv_halo(ConvArgs a
     constexpr int SR = UP ? ROWS / 2 + 2 : 1, SC = UP ? kHaloCols / 2 + 2 : 1;
     constexpr int NLPIECE = SR * SC * 4;
     constexpr int LJ = (NLPIECE + NT - 1) / NT;
-    __shared__ __attribute__((aligned(16))) __bf16 xs[HR * HC * 32];
-    __shared__ __attribute__((aligned(16))) __bf16 ws[9 * CO * 32];   // row (tap * CO + co), 32 ci
+    __shared__ __attribute__((aligned(16))) uint8_t xs[HR * HC * 32 * EB];
+    __shared__ __attribute__((aligned(16))) uint8_t ws[9 * CO * 32 * EB];   // row (tap * CO + co), 32 ci
     __shared__ __attribute__((aligned(16))) __bf16 lo[SR * SC * 32];
+    // byte offset of the 8-channel piece `part` of LDS row p: 64-byte bf16
+    // rows swizzled by row bits 1-2, 32-byte FP8 rows by row bits 2-3 (16
+    // lanes reading 8 bytes from 16 consecutive rows hit distinct banks)
+    auto at = [](int p, int part) {
+        return FP8 ? p * 32 + 8 * (part ^ ((p >> 2) & 3)) : 2 * halo_at(p, part);
+    };
+    auto put = [&](uint8_t *base, int off, bf16x8 v) {
+        if constexpr (FP8) *reinterpret_cast<long *>(base + off) = Ops::to_b(v, inv_sa);
+        else *reinterpret_cast<bf16x8 *>(base + off) = v;
+    };
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, r = lane & 15;
     const int wch = wave % NCH, wrow = wave / NCH;  // this wave: channels 32 wch.., output row wrow
@@ -494,21 +512,21 @@ __global__ __launch_bounds__(64 * ROWS * CO / 32, 4) void k_conv_halo(ConvArgs a
         const __bf16 *src = second ? a.in2 : a.in;
         const int sstride = second ? a.in2_stride : a.in_stride;
         const int soff = second ? a.in2_off + 32 * c - a.Cin1 : a.in_off + 32 * c;
-        bf16x8 wv[WJ];
+        Piece wv[WJ];
 #pragma unroll
         for (int j = 0; j < WJ; ++j) {
             const int piece = threadIdx.x + NT * j;
             const int row = piece >> 2, part = piece & 3;   // row = tap * CO + co
             const int tap = row / CO, co = row - tap * CO;
-            wv[j] = zero8();
-            if (piece < NWPIECE)
-                wv[j] = load8(a.wt + (int64_t)(co0 + co) * a.Kpad + tap * a.Cin + 32 * c + 8 * part);
+            const int64_t k = (int64_t)(co0 + co) * a.Kpad + tap * a.Cin + 32 * c + 8 * part;
+            if constexpr (FP8) wv[j] = piece < NWPIECE ? *reinterpret_cast<const long *>(wq + k) : 0;
+            else wv[j] = piece < NWPIECE ? load8(a.wt + k) : zero8();
         }
         auto store_w = [&]() {
 #pragma unroll
             for (int j = 0; j < WJ; ++j) {
                 const int piece = threadIdx.x + NT * j;
-                if (piece < NWPIECE) *reinterpret_cast<bf16x8 *>(&ws[halo_at(piece >> 2, piece & 3)]) = wv[j];
+                if (piece < NWPIECE) *reinterpret_cast<Piece *>(ws + at(piece >> 2, piece & 3)) = wv[j];
             }
         };
         if (UP && !second) {
@@ -558,7 +576,7 @@ __global__ __launch_bounds__(64 * ROWS * CO / 32, 4) void k_conv_halo(ConvArgs a
                         t[j] = (__bf16)((1.0f - fy) * top + fy * bot);
                     }
                 }
-                *reinterpret_cast<bf16x8 *>(&xs[halo_at(p, part)]) = t;
+                put(xs, at(p, part), t);
             }
         } else {
             bf16x8 v[SJ];
@@ -585,25 +603,25 @@ __global__ __launch_bounds__(64 * ROWS * CO / 32, 4) void k_conv_halo(ConvArgs a
 #pragma unroll
             for (int j = 0; j < SJ; ++j) {
                 const int piece = threadIdx.x + NT * j;
-                if (piece < NPIECE) *reinterpret_cast<bf16x8 *>(&xs[halo_at(piece >> 2, piece & 3)]) = v[j];
+                if (piece < NPIECE) put(xs, at(piece >> 2, piece & 3), v[j]);
             }
         }
         __syncthreads();
 #pragma unroll
         for (int tap = 0; tap < 9; ++tap) {
             const int dy = tap / 3, dx = tap % 3;
-            bf16x8 av[2], bv[4];
+            typename Ops::A av[2];
+            typename Ops::Bv bv[4];
 #pragma unroll
             for (int i = 0; i < 2; ++i)
-                av[i] = *reinterpret_cast<const bf16x8 *>(&ws[halo_at(tap * CO + 32 * wch + 16 * i + r, g)]);
+                av[i] = *reinterpret_cast<const typename Ops::A *>(ws + at(tap * CO + 32 * wch + 16 * i + r, g));
 #pragma unroll
             for (int f = 0; f < 4; ++f)
-                bv[f] = *reinterpret_cast<const bf16x8 *>(&xs[halo_at((wrow + dy) * HC + 16 * f + r + dx, g)]);
+                bv[f] = *reinterpret_cast<const typename Ops::Bv *>(xs + at((wrow + dy) * HC + 16 * f + r + dx, g));
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int f = 0; f < 4; ++f)
-                    acc[i][f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[f], acc[i][f], 0, 0, 0);
+                for (int f = 0; f < 4; ++f) acc[i][f] = Ops::mfma(av[i], bv[f], acc[i][f]);
         }
     }
     // lane holds channels co0 + 32 wch + 16 i + 4 g + e of pixel (y0 + wrow, x0 + 16 f + r)
@@ -657,9 +675,12 @@ __global__ __launch_bounds__(64 * ROWS * CO / 32, 4) void k_conv_halo(ConvArgs a
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
         const int cb = co0 + 32 * wch + 16 * i + 4 * g;
-        float bias[4];
+        float bias[4], scale[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) bias[e] = a.bias ? a.bias[cb + e] : 0.0f;
+        for (int e = 0; e < 4; ++e) {
+            bias[e] = a.bias ? a.bias[cb + e] : 0.0f;
+            scale[e] = FP8 ? sw[cb + e] * sa : 1.0f;  // FP8: dequantise (weight scale x activation scale)
+        }
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
             const int x = x0 + 16 * f + r;
@@ -669,7 +690,7 @@ __global__ __launch_bounds__(64 * ROWS * CO / 32, 4) void k_conv_halo(ConvArgs a
             bf16x4 w4;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                float t = acc[i][f][e] + bias[e];
+                float t = FP8 ? acc[i][f][e] * scale[e] + bias[e] : acc[i][f][e] + bias[e];
                 if (a.relu) t = fmaxf(t, 0.0f);
                 w4[e] = (__bf16)t;
             }
@@ -1253,7 +1274,7 @@ static hipError_t launch_conv(const ConvArgs &a, int KS, const uint8_t *wq, cons
     if (a.head_out && (FP8 || KS != 3 || cop != 32 || a.Cin % 32 != 0 || a.out_f32)) return hipErrorInvalidValue;
     if (a.in2 && (a.in_mask || a.Cin1 <= 0 || a.Cin1 >= a.Cin || a.Cin1 % 8 != 0)) return hipErrorInvalidValue;
     // the upsampling input is read by the halo kernel only
-    if (a.up_in && (FP8 || KS != 3 || !a.in2 || a.Cin1 % 32 != 0 || a.Cin % 32 != 0 || a.out_f32 || a.in_mask ||
+    if (a.up_in && (KS != 3 || !a.in2 || a.Cin1 % 32 != 0 || a.Cin % 32 != 0 || a.out_f32 || a.in_mask ||
                     a.H % 2 || a.W % 2))
         return hipErrorInvalidValue;
     const unsigned gx = (unsigned)((a.W + kHaloCols - 1) / kHaloCols);
@@ -1263,32 +1284,35 @@ static hipError_t launch_conv(const ConvArgs &a, int KS, const uint8_t *wq, cons
         hipLaunchKernelGGL(k_conv_c8, dim3(gx, gy, (unsigned)a.B), dim3(256), 0, s, a);
         return hipGetLastError();
     }
-    // bf16 3x3 layers with Cin a multiple of 32: direct convolution from halo
-    // tiles (32 output channels per 4 waves, or 64 per 8 waves)
-    const bool halo = !FP8 && KS == 3 && a.Cin % 32 == 0 && (!a.in2 || a.Cin1 % 32 == 0) && !a.out_f32 &&
-                      (cop == 32 || cop % 64 == 0) && (int64_t)a.B * (cop == 32 ? 1 : cop / 64) <= 65535;
+    // 3x3 layers with Cin a multiple of 32: direct convolution from halo tiles
+    // (32 output channels per 8 waves and 8 rows, or 64 per 8 waves and 4
+    // rows; FP8 for the latter)
+    const bool halo = KS == 3 && a.Cin % 32 == 0 && (!a.in2 || a.Cin1 % 32 == 0) && !a.out_f32 &&
+                      (FP8 ? cop % 64 == 0 && !a.in_mask : (cop == 32 || cop % 64 == 0)) &&
+                      (int64_t)a.B * (cop == 32 ? 1 : cop / 64) <= 65535;
     if (halo && cop == 32) {
-        // 8 rows x 64 pixels x 32 channels per workgroup of 8 waves
         const dim3 grid(gx, (unsigned)((a.H + 7) / 8), (unsigned)a.B);
         if (a.head_out) {
             if (a.in_mask || a.Cout != 32 || a.up_in) return hipErrorInvalidValue;
-            hipLaunchKernelGGL((k_conv_halo<32, 8, false, true, false>), grid, dim3(512), 0, s, a);
+            hipLaunchKernelGGL((k_conv_halo<32, 8, false, true, false, false>), grid, dim3(512), 0, s, a, wq, sw, sa);
         } else if (a.in_mask) {
-            hipLaunchKernelGGL((k_conv_halo<32, 8, true, false, false>), grid, dim3(512), 0, s, a);
+            hipLaunchKernelGGL((k_conv_halo<32, 8, true, false, false, false>), grid, dim3(512), 0, s, a, wq, sw, sa);
         } else if (a.up_in) {
-            hipLaunchKernelGGL((k_conv_halo<32, 8, false, false, true>), grid, dim3(512), 0, s, a);
+            hipLaunchKernelGGL((k_conv_halo<32, 8, false, false, true, false>), grid, dim3(512), 0, s, a, wq, sw, sa);
         } else {
-            hipLaunchKernelGGL((k_conv_halo<32, 8, false, false, false>), grid, dim3(512), 0, s, a);
+            hipLaunchKernelGGL((k_conv_halo<32, 8, false, false, false, false>), grid, dim3(512), 0, s, a, wq, sw, sa);
         }
         return hipGetLastError();
     }
     if (a.head_out) return hipErrorInvalidValue;
     if (halo) {
-        // 4 rows x 64 pixels x 64 channels per workgroup of 8 waves
         const dim3 grid(gx, (unsigned)((a.H + 3) / 4), (unsigned)(a.B * (cop / 64)));
-        if (a.in_mask) hipLaunchKernelGGL((k_conv_halo<64, 4, true, false, false>), grid, dim3(512), 0, s, a);
-        else if (a.up_in) hipLaunchKernelGGL((k_conv_halo<64, 4, false, false, true>), grid, dim3(512), 0, s, a);
-        else hipLaunchKernelGGL((k_conv_halo<64, 4, false, false, false>), grid, dim3(512), 0, s, a);
+        if (a.in_mask)
+            hipLaunchKernelGGL((k_conv_halo<64, 4, true, false, false, false>), grid, dim3(512), 0, s, a, wq, sw, sa);
+        else if (a.up_in)
+            hipLaunchKernelGGL((k_conv_halo<64, 4, false, false, true, FP8>), grid, dim3(512), 0, s, a, wq, sw, sa);
+        else
+            hipLaunchKernelGGL((k_conv_halo<64, 4, false, false, false, FP8>), grid, dim3(512), 0, s, a, wq, sw, sa);
         return hipGetLastError();
     }
     if (a.up_in) return hipErrorInvalidValue;
