@@ -103,6 +103,21 @@ def test_unit_cube_full_parity():
     assert_same(g, o)
 
 
+@pytest.mark.parametrize("znear", [1e-39, 0.1])
+def test_both_division_paths(znear):
+    """The render divides by the depth through a correctly rounded reciprocal
+    when the fp32 cull range lies in [2^-124, 2^125) (znear 0.1), by IEEE
+    division otherwise (a denormal znear): both bit-exact."""
+    announce(f"unit cube 200003 points 301x207, LDS render, znear={znear}")
+    sc = scenes.unit_cube(n=200003, seed=5, W=301, H=207)
+    cam = scenes.Camera(eye=(1.7, 1.5, 1.3), target=(0.5, 0.5, 0.5), znear=znear)
+    kw = scene_args(sc)
+    g = gpu_frame(sc.x, sc.y, sc.z, sc.attrs, cam, sc.W, sc.H, variant=3, **kw)
+    o = oracle_frame(sc.x, sc.y, sc.z, sc.attrs, cam, sc.W, sc.H, **kw)
+    assert (o["keys"] != EMPTY).mean() > 0.1
+    assert_same(g, o)
+
+
 @pytest.mark.parametrize("n", [0, 1, 3, 4, 5, 1023, 4097, 65537, 300001])
 def test_ragged_sizes(n):
     announce(f"ragged n={n} 97x61")
