@@ -273,29 +273,38 @@ __global__ __launch_bounds__(kT) void k_radix_hist(const unsigned long long *key
     hist[(uint64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
 }
 
+// One LSD pass: each workgroup moves its kScanTile elements to the offsets
+// the histogram scan gave its digits, in element order (a stable sort).  Wave
+// w ranks the contiguous sub-range [w, w + 1) * kScanTile / 4 of the block,
+// 64 elements per round: an element's rank is the number of equal digits in
+// the wave's earlier rounds (a running per-wave count in LDS, updated by the
+// first lane of each digit group: a wave's LDS operations complete in order,
+// so no barrier is needed) plus the equal digits at lower lanes of its round
+// (ballot match on the 8 digit bits).  The per-wave counts are then combined
+// into block offsets, the block is reordered in LDS, and written out with
+// consecutive threads on consecutive destinations.
 __global__ __launch_bounds__(kT) void k_radix_scatter(const unsigned long long *kin, const uint32_t *vin,
                                                       unsigned long long *kout, uint32_t *vout, const uint32_t *count,
                                                       uint64_t cap, int shift, const uint32_t *offs, uint32_t nblk)
 {
+    constexpr int NW = kT / 64;
+    constexpr int PER_WAVE = kScanTile / NW;
     __shared__ unsigned long long skey[kScanTile];
     __shared__ uint32_t sval[kScanTile];
-    __shared__ uint32_t wcnt[kT / 64][256];  // (round << 8) | count, so stale rounds read as 0
-    __shared__ uint32_t woff[kT / 64][256];
-    __shared__ uint32_t run[256];
+    __shared__ uint32_t wcnt[NW][256];  // running digit counts of each wave, then each wave's offset
     __shared__ uint32_t bstart[256];
-    __shared__ uint32_t lds4[kT / 64];
+    __shared__ uint32_t lds4[NW];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const uint64_t N = min((uint64_t)*count, cap);
     const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
     if (base >= N) return;  // uniform for the workgroup
-    run[threadIdx.x] = 0;
 #pragma unroll
-    for (int w = 0; w < kT / 64; ++w) wcnt[w][threadIdx.x] = 0xFFFFFFFFu;
+    for (int w = 0; w < NW; ++w) wcnt[w][threadIdx.x] = 0u;
     unsigned long long k[kScanItems];
     uint32_t v[kScanItems], rank[kScanItems], dig[kScanItems];
 #pragma unroll
     for (int r = 0; r < kScanItems; ++r) {
-        const uint64_t e = base + (uint64_t)r * kT + threadIdx.x;
+        const uint64_t e = base + (uint64_t)wid * PER_WAVE + (uint64_t)r * 64 + lane;
         const bool ok = e < N;
         k[r] = ok ? kin[e] : 0ull;
         v[r] = ok ? vin[e] : 0u;
@@ -303,7 +312,7 @@ __global__ __launch_bounds__(kT) void k_radix_scatter(const unsigned long long *
     }
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     __syncthreads();
-    // rank every element among equal digits in block order (round, wave, lane)
+    uint32_t *cnt = wcnt[wid];
 #pragma unroll
     for (int r = 0; r < kScanItems; ++r) {
         const uint32_t d = dig[r];
@@ -314,30 +323,29 @@ __global__ __launch_bounds__(kT) void k_radix_scatter(const unsigned long long *
             m &= ((d >> b) & 1u) ? bb : ~bb;
         }
         const uint32_t inwave = (uint32_t)__popcll(m & below);
-        if (d < 256u && inwave == 0) wcnt[wid][d] = ((uint32_t)r << 8) | (uint32_t)__popcll(m);
-        __syncthreads();
-        {
-            uint32_t acc = run[threadIdx.x];
-#pragma unroll
-            for (int w = 0; w < kT / 64; ++w) {
-                const uint32_t c = wcnt[w][threadIdx.x];
-                woff[w][threadIdx.x] = acc;
-                acc += (c >> 8) == (uint32_t)r ? (c & 255u) : 0u;
-            }
-            run[threadIdx.x] = acc;
-        }
-        __syncthreads();
-        rank[r] = d < 256u ? woff[wid][d] + inwave : 0u;
+        const uint32_t before = d < 256u ? cnt[d] : 0u;
+        rank[r] = before + inwave;
+        // the group's first lane advances the count after every lane has read it
+        __builtin_amdgcn_wave_barrier();
+        if (d < 256u && inwave == 0) cnt[d] = before + (uint32_t)__popcll(m);
+        __builtin_amdgcn_wave_barrier();
     }
-    // block-local start of every digit
+    __syncthreads();
+    // per digit (thread = digit): offsets of the waves, and the digit's total
+    uint32_t tot = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        const uint32_t c = wcnt[w][threadIdx.x];
+        wcnt[w][threadIdx.x] = tot;
+        tot += c;
+    }
     uint32_t total;
-    const uint32_t ex = block_excl_scan(run[threadIdx.x], lds4, &total);
-    bstart[threadIdx.x] = ex;
+    bstart[threadIdx.x] = block_excl_scan(tot, lds4, &total);
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kScanItems; ++r) {
         if (dig[r] < 256u) {
-            const uint32_t pos = bstart[dig[r]] + rank[r];
+            const uint32_t pos = bstart[dig[r]] + cnt[dig[r]] + rank[r];
             if (pos < (uint32_t)kScanTile) {
                 skey[pos] = k[r];
                 sval[pos] = v[r];
