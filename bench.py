@@ -131,6 +131,25 @@ def frame_section(torch, log_fn, frames=12, train_views=400, train_steps=200):
     _, train_s = train.train(w, feats[:ntr], targets[:ntr], train_steps, batch=16, lr=1e-3, lam_tv=1e-3,
                              log=log_fn, log_every=100)
     val = train.evaluate(w, feats[ntr:], targets[ntr:])
+    # training step throughput: 10 timed steps on a fixed batch of 16 views
+    # (a separate, freshly initialised parameter set, so the trained one is
+    # untouched); FLOPs counted as 3 x forward (forward, input gradients,
+    # weight gradients)
+    tw = narvis.NetWeights(train.init_blob(1))
+    tws = torch.empty(narvis.narvis_train_workspace_size(16, 512, 512), dtype=torch.uint8, device="cuda")
+    tl = torch.empty(1, dtype=torch.float32, device="cuda")
+    fb, tb = feats[:16].contiguous(), targets[:16].contiguous()
+    for _ in range(2):
+        narvis.narvis_train_step(tw, fb, tb, 16, 512, 512, 1e-3, 1e-3, tl, tws)
+    te0, te1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    te0.record()
+    for _ in range(10):
+        narvis.narvis_train_step(tw, fb, tb, 16, 512, 512, 1e-3, 1e-3, tl, tws)
+    te1.record()
+    torch.cuda.synchronize()
+    train_step_ms = te0.elapsed_time(te1) / 10
+    tw.close()
+    del tws, fb, tb
     # FP8: static activation scales calibrated on 4 training views
     cal_ws = torch.empty(narvis.narvis_train_workspace_size(4, 512, 512), dtype=torch.uint8, device="cuda")
     narvis.narvis_weights_calibrate_fp8(w, feats[:4].contiguous(), 4, 512, 512, cal_ws)
@@ -186,6 +205,8 @@ def frame_section(torch, log_fn, frames=12, train_views=400, train_steps=200):
             "psnr_db": round(m(p_net), 3), "ssim": round(m(s_net), 4),
             "psnr_raster_only_db": round(m(p_ras), 3), "ssim_raster_only": round(m(s_ras), 4),
             "val_512_psnr_db": round(val[0], 3), "val_512_psnr_raster_only_db": round(val[1], 3),
+            "train_step_ms_b16_512": round(train_step_ms, 3),
+            "train_tflops": round(3 * 327360.0 * 512 * 512 * 16 / (train_step_ms / 1e3) / 1e12, 1),
             "net_tflops": round(net_gflop / net_ms, 2), "net_gflop_per_frame": round(net_gflop, 1),
             "net_fp8_ms": round(m(t_n8), 4), "frame_fp8_ms": round(raster_ms + m(t_n8), 4),
             "psnr_fp8_db": round(m(p_net8), 3)}
