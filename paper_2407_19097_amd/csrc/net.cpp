@@ -42,6 +42,13 @@ const LayerDef kLayers[] = {
 constexpr int kNumLayers = sizeof(kLayers) / sizeof(kLayers[0]);
 enum { E1A, E1B, E2A, E2B, E3A, E3B, E4A, E4B, D3A, D3B, D2A, D2B, D1A, D1B, HEAD };
 
+// resolution level a layer runs at (0 full, 1 half, 2 quarter, 3 eighth)
+int layer_level(int l)
+{
+    static const int level[] = {0, 0, 1, 1, 2, 2, 3, 3, 2, 2, 1, 1, 0, 0, 0};
+    return level[l];
+}
+
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
 uint64_t align256(uint64_t v) { return (v + 255) & ~uint64_t(255); }
 
@@ -78,6 +85,20 @@ int64_t param_count()
     int64_t n = 0;
     for (const LayerDef &d : kLayers) n += (int64_t)d.cout * d.cin * d.ks * d.ks + d.cout;
     return n;
+}
+
+// Split-K of a layer's weight gradient over the P pixels of a batch: enough
+// splits for about 2048 workgroups (64 x 128 output tiles), at most 1024, each
+// split a multiple of 64 pixels.  Returns the number of splits, *per the
+// pixels per split.
+int wgrad_splits(int rows, int kpad, int64_t P, int64_t *per)
+{
+    const int tiles = ((kpad + 127) / 128) * ((rows + 63) / 64);
+    int64_t splits = std::min<int64_t>(1024, std::max<int64_t>(1, (2048 + tiles - 1) / tiles));
+    int64_t pp = (P + splits - 1) / splits;
+    pp = (pp + 63) / 64 * 64;
+    *per = pp;
+    return (int)((P + pp - 1) / pp);
 }
 
 // Workspace plan for a batch of B images of H x W (multiples of 8).
@@ -155,12 +176,16 @@ Plan make_plan(int B, int H, int W, bool train)
         p.g_pool1 = bf(p.P[1], 32);
         p.g_e1b = bf(p.P[0], 32);
         p.g_e1a = bf(p.P[0], 32);
-        // split-K partials for the weight gradients: at most kMaxSplits splits
+        // split-K partials for the weight gradients (the largest layer need)
         int64_t pf = 0, bfl = 0;
-        for (const LayerDef &d : kLayers) {
+        for (int l = 0; l < kNumLayers; ++l) {
+            const LayerDef &d = kLayers[l];
             const int rows = round_up(d.cout, 16), kpad = round_up(d.ks * d.ks * d.cin, 32);
-            pf = std::max<int64_t>(pf, (int64_t)64 * rows * kpad);
-            bfl = std::max<int64_t>(bfl, (int64_t)64 * rows);
+            const int level = layer_level(l);
+            int64_t per;
+            const int splits = wgrad_splits(rows, kpad, p.P[level], &per);
+            pf = std::max<int64_t>(pf, (int64_t)splits * rows * kpad);
+            bfl = std::max<int64_t>(bfl, (int64_t)splits * rows);
         }
         p.part_floats = pf;
         p.bpart_floats = bfl;
@@ -349,11 +374,8 @@ hipError_t layer_backward(const LayerBuf &l, const __bf16 *dy, int dy_stride, in
     a.H = H;
     a.W = W;
     const int64_t P = (int64_t)B * H * W;
-    const int tiles = ((l.kpad + 63) / 64) * ((l.rows + 63) / 64);
-    int splits = (int)std::min<int64_t>(64, std::max<int64_t>(1, 2048 / tiles));
-    int64_t per = (P + splits - 1) / splits;
-    per = (per + 31) / 32 * 32;
-    splits = (int)((P + per - 1) / per);
+    int64_t per;
+    const int splits = wgrad_splits(l.rows, l.kpad, P, &per);
     a.splits = splits;
     a.pix_per_split = per;
     a.part = reinterpret_cast<float *>(ws + p.part);

@@ -62,7 +62,7 @@ struct WgradArgs {
     int Cin, KS, Cout, Cout_pad, Kpad;
     int B, H, W;
     int splits;
-    int64_t pix_per_split;             // multiple of 32
+    int64_t pix_per_split;             // multiple of 64
     float *part;                       // [splits][Cout_pad][Kpad]
     float *bpart;                      // [splits][Cout_pad]
 };

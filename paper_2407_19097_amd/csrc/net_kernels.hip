@@ -938,95 +938,142 @@ __global__ __launch_bounds__(256) void k_pool2_bwd_add(SliceArgs s)
 // operand is 8 consecutive pixels of one row.
 // ---------------------------------------------------------------------------
 
-constexpr int kWgPix = 32;  // pixels per LDS chunk (= MFMA K)
+constexpr int kWgPix = 64;  // pixels per LDS chunk (two MFMA K steps)
 
+// LDS rows of 64 pixels (128 bytes) for one channel / im2col column; the 16-byte
+// octets of pixels are XOR-swizzled by row so that the transposing 8-byte
+// stores (rows 8 group + j) and the 16-byte fragment reads (16 consecutive
+// rows) spread over the banks.  Returns the element offset of pixel quad q.
+__device__ __forceinline__ int wg_at(int row, int q)
+{
+    const int f = (row ^ (row >> 3)) & 7;
+    return row * kWgPix + (((q >> 1) ^ f) << 3) + ((q & 1) << 2);
+}
+
+// dW tile of 64 output channels x 128 im2col columns per workgroup, over the
+// pixel range of its split; wave (wm, wn) computes channels 32 wm.. x
+// columns 64 wn.. (2 x 4 fragments), the pixels being the MFMA's K.
 __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a)
 {
-    __shared__ __bf16 sdy[64][kWgPix + 8];   // [co][pixel], padded row
-    __shared__ __bf16 sx[64][kWgPix + 8];    // [k][pixel]
+    __shared__ __attribute__((aligned(16))) __bf16 sdy[64 * kWgPix];   // [co][pixel]
+    __shared__ __attribute__((aligned(16))) __bf16 sx[128 * kWgPix];   // [k][pixel]
+    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, r = lane & 15;
+    const int wm = wave & 1, wn = wave >> 1;
     const int co0 = blockIdx.y * 64;
-    const int k0 = blockIdx.x * 64;
+    const int k0 = blockIdx.x * 128;
     const int64_t P = (int64_t)a.B * a.H * a.W;
-    const int64_t chunk_per_split = a.pix_per_split;
-    const int64_t pbeg = (int64_t)blockIdx.z * chunk_per_split;
-    const int64_t pend = min(P, pbeg + chunk_per_split);
+    const int64_t pbeg = (int64_t)blockIdx.z * a.pix_per_split;
+    const int64_t pend = min(P, pbeg + a.pix_per_split);
     const int K = a.KS * a.KS * a.Cin;
-    // wave w computes co rows [16 (w), +16) x all 64 k columns (4 fragments)
-    f32x4 acc[4];
+    const int hw = a.H * a.W;  // B * H * W < 2^31
+    // staging roles: dy by threads 0..127 (pixel quad, group of 8 channels),
+    // the im2col columns by all 256 (pixel quad, group of 8 columns)
+    const int qd = threadIdx.x >> 3, cg = threadIdx.x & 7;
+    const int qx = threadIdx.x >> 4, kg = threadIdx.x & 15;
+    const int kk = k0 + kg * 8;
+    int tap = 0, ci = 0, ty = 0, tx = 0;
+    if (kk < K) {
+        tap = kk / a.Cin;
+        ci = kk - tap * a.Cin;
+        ty = a.KS == 3 ? tap / 3 - 1 : 0;
+        tx = a.KS == 3 ? tap % 3 - 1 : 0;
+    }
+    const bool second = a.x2 && ci >= a.xCin1;
+    const __bf16 *xsrc = second ? a.x2 + a.x2_off + (ci - a.xCin1) : a.x + a.x_off + ci;
+    const int xstride = second ? a.x2_stride : a.x_stride;
+    f32x4 acc[2][4];
 #pragma unroll
-    for (int f = 0; f < 4; ++f) acc[f] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int f = 0; f < 4; ++f) acc[i][f] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     float bsum = 0.0f;
     for (int64_t pc = pbeg; pc < pend; pc += kWgPix) {
-        // stage dy: 32 pixels x 64 channels, thread -> (pixel, group of 8 channels)
-        {
-            const int px = threadIdx.x >> 3, cg = threadIdx.x & 7;
-            const int64_t p = pc + px;
-            bf16x8 v = zero8();
+        if (threadIdx.x < 128) {
             const int c = co0 + cg * 8;
-            if (p < pend && c < a.Cout) {
-                v = load8(a.dy + p * a.dy_stride + a.dy_off + c);
-                if (a.mask) {
-                    const bf16x8 m = load8(a.mask + p * a.mask_stride + a.mask_off + c);
+            bf16x8 v[4];
 #pragma unroll
-                    for (int j = 0; j < 8; ++j)
-                        if (!((float)m[j] > 0.0f)) v[j] = (__bf16)0.0f;
+            for (int e = 0; e < 4; ++e) {
+                const int64_t p = pc + 4 * qd + e;
+                v[e] = zero8();
+                if (p < pend && c < a.Cout) {
+                    v[e] = load8(a.dy + p * a.dy_stride + a.dy_off + c);
+                    if (a.mask) {
+                        const bf16x8 m = load8(a.mask + p * a.mask_stride + a.mask_off + c);
+#pragma unroll
+                        for (int j = 0; j < 8; ++j)
+                            if (!((float)m[j] > 0.0f)) v[e][j] = (__bf16)0.0f;
+                    }
                 }
             }
 #pragma unroll
-            for (int j = 0; j < 8; ++j) sdy[cg * 8 + j][px] = v[j];
+            for (int j = 0; j < 8; ++j)
+                *reinterpret_cast<bf16x4 *>(&sdy[wg_at(cg * 8 + j, qd)]) = bf16x4{v[0][j], v[1][j], v[2][j], v[3][j]};
         }
-        // stage im2col: 32 pixels x 64 k, thread -> (pixel, group of 8 k)
         {
-            const int px = threadIdx.x >> 3, kg = threadIdx.x & 7;
-            const int64_t p = pc + px;
-            const int kk = k0 + kg * 8;
-            bf16x8 v = zero8();
-            if (p < pend && kk < K) {
-                const int tap = kk / a.Cin, ci = kk - tap * a.Cin;
-                const int dy = a.KS == 3 ? tap / 3 - 1 : 0, dx = a.KS == 3 ? tap % 3 - 1 : 0;
-                const int64_t hw = (int64_t)a.H * a.W;
-                const int64_t b = p / hw, rem = p - b * hw;
-                const int y = (int)(rem / a.W) + dy, x = (int)(rem % a.W) + dx;
-                if (y >= 0 && y < a.H && x >= 0 && x < a.W)
-                    {
-                        const int64_t q = (b * a.H + y) * a.W + x;
-                        v = load8(a.x2 && ci >= a.xCin1 ? a.x2 + q * a.x2_stride + a.x2_off + (ci - a.xCin1)
-                                                        : a.x + q * a.x_stride + a.x_off + ci);
+            bf16x8 v[4];
+            const int64_t p0 = pc + 4 * qx;
+            int b = (int)(p0 / hw);
+            const int rem = (int)(p0 - (int64_t)b * hw);
+            int y = rem / a.W;
+            int x = rem - y * a.W;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                v[e] = zero8();
+                const int y2 = y + ty, x2 = x + tx;
+                if (kk < K && p0 + e < pend && y2 >= 0 && y2 < a.H && x2 >= 0 && x2 < a.W)
+                    v[e] = load8(xsrc + (((int64_t)b * a.H + y2) * a.W + x2) * xstride);
+                if (++x == a.W) {  // next pixel (W >= 8, so at most one wrap in a quad)
+                    x = 0;
+                    if (++y == a.H) {
+                        y = 0;
+                        ++b;
                     }
+                }
             }
 #pragma unroll
-            for (int j = 0; j < 8; ++j) sx[kg * 8 + j][px] = v[j];
+            for (int j = 0; j < 8; ++j)
+                *reinterpret_cast<bf16x4 *>(&sx[wg_at(kg * 8 + j, qx)]) = bf16x4{v[0][j], v[1][j], v[2][j], v[3][j]};
         }
         __syncthreads();
-        // A = dy^T rows co (16 per wave), B = im2col columns k; K = 32 pixels
-        bf16x8 av;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) av[j] = sdy[wave * 16 + r][8 * g + j];
+        for (int st = 0; st < kWgPix / 32; ++st) {
+            // fragment lane (g, r): row r of the fragment, pixels 32 st + 8 g .. + 7
+            const int q = 8 * st + 2 * g;
+            bf16x8 av[2], bv[4];
 #pragma unroll
-        for (int f = 0; f < 4; ++f) {
-            bf16x8 bv;
+            for (int i = 0; i < 2; ++i) av[i] = *reinterpret_cast<const bf16x8 *>(&sdy[wg_at(32 * wm + 16 * i + r, q)]);
 #pragma unroll
-            for (int j = 0; j < 8; ++j) bv[j] = sx[f * 16 + r][8 * g + j];
-            acc[f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[f], 0, 0, 0);
+            for (int f = 0; f < 4; ++f) bv[f] = *reinterpret_cast<const bf16x8 *>(&sx[wg_at(64 * wn + 16 * f + r, q)]);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int f = 0; f < 4; ++f)
+                    acc[i][f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[f], acc[i][f], 0, 0, 0);
         }
         if (blockIdx.x == 0 && threadIdx.x < 64) {
-#pragma unroll 8
-            for (int j = 0; j < kWgPix; ++j) bsum = bsum + (float)sdy[threadIdx.x][j];
+#pragma unroll
+            for (int o = 0; o < 8; ++o) {
+                const bf16x8 t = *reinterpret_cast<const bf16x8 *>(&sdy[threadIdx.x * kWgPix + 8 * o]);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) bsum = bsum + (float)t[j];
+            }
         }
         __syncthreads();
     }
     // partial results: part[split][co][k] (fp32), reduced in split order later
     float *out = a.part + (int64_t)blockIdx.z * a.Cout_pad * a.Kpad;
 #pragma unroll
-    for (int f = 0; f < 4; ++f)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int co = co0 + wave * 16 + 4 * g + e;
-            const int k = k0 + f * 16 + r;
-            if (co < a.Cout_pad && k < a.Kpad) out[(int64_t)co * a.Kpad + k] = acc[f][e];
-        }
+        for (int f = 0; f < 4; ++f)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int co = co0 + 32 * wm + 16 * i + 4 * g + e;
+                const int k = k0 + 64 * wn + 16 * f + r;
+                if (co < a.Cout_pad && k < a.Kpad) out[(int64_t)co * a.Kpad + k] = acc[i][f][e];
+            }
     if (blockIdx.x == 0 && threadIdx.x < 64 && co0 + threadIdx.x < a.Cout_pad)
         a.bpart[(int64_t)blockIdx.z * a.Cout_pad + co0 + threadIdx.x] = bsum;
 }
@@ -1288,12 +1335,13 @@ static hipError_t launch_conv(const ConvArgs &a, int KS, const uint8_t *wq, cons
     // (32 output channels per 8 waves and 8 rows, or 64 per 8 waves and 4
     // rows; FP8 for the latter)
     const bool halo = KS == 3 && a.Cin % 32 == 0 && (!a.in2 || a.Cin1 % 32 == 0) && !a.out_f32 &&
-                      (FP8 ? cop % 64 == 0 && !a.in_mask : (cop == 32 || cop % 64 == 0)) &&
-                      (int64_t)a.B * (cop == 32 ? 1 : cop / 64) <= 65535;
-    if (halo && cop == 32) {
-        const dim3 grid(gx, (unsigned)((a.H + 7) / 8), (unsigned)a.B);
+                      (FP8 ? cop % 64 == 0 && !a.in_mask : cop % 32 == 0) &&
+                      (int64_t)a.B * (cop % 64 ? cop / 32 : cop / 64) <= 65535;
+    if (halo && cop % 64) {
+        // tiles of 32 output channels (cop = 32, or 96 for an input gradient)
+        const dim3 grid(gx, (unsigned)((a.H + 7) / 8), (unsigned)(a.B * (cop / 32)));
         if (a.head_out) {
-            if (a.in_mask || a.Cout != 32 || a.up_in) return hipErrorInvalidValue;
+            if (a.in_mask || a.Cout != 32 || cop != 32 || a.up_in) return hipErrorInvalidValue;
             hipLaunchKernelGGL((k_conv_halo<32, 8, false, true, false, false>), grid, dim3(512), 0, s, a, wq, sw, sa);
         } else if (a.in_mask) {
             hipLaunchKernelGGL((k_conv_halo<32, 8, true, false, false, false>), grid, dim3(512), 0, s, a, wq, sw, sa);
@@ -1407,7 +1455,7 @@ hipError_t pool2_bwd_add(const SliceArgs &a, hipStream_t s)
 
 hipError_t wgrad(const WgradArgs &a, float *dw, float *db, hipStream_t s)
 {
-    dim3 grid((unsigned)((a.Kpad + 63) / 64), (unsigned)((a.Cout_pad + 63) / 64), (unsigned)a.splits);
+    dim3 grid((unsigned)((a.Kpad + 127) / 128), (unsigned)((a.Cout_pad + 63) / 64), (unsigned)a.splits);
     hipLaunchKernelGGL(k_wgrad, grid, dim3(256), 0, s, a);
     const int64_t nw = (int64_t)a.Cout_pad * a.Kpad;
     hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblocks(nw > a.Cout_pad ? nw : a.Cout_pad)), dim3(256), 0, s, a.part,
