@@ -1078,20 +1078,34 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a)
         a.bpart[(int64_t)blockIdx.z * a.Cout_pad + co0 + threadIdx.x] = bsum;
 }
 
-// sum the split partials in split order (deterministic)
+// sum the split partials (deterministic): 16 lanes per output element, lane
+// j summing splits j, j + 16, ... in order, then the 16 lane sums added in
+// lane order; one workgroup covers 16 consecutive outputs (threads 16 j + o),
+// so a wave reads 16 consecutive outputs of 4 splits at a time
+constexpr int kRedLanes = 16;
+
 __global__ __launch_bounds__(256) void k_wgrad_reduce(const float *part, const float *bpart, int splits,
                                                       int64_t nw, int nb, float *dw, float *db)
 {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < nw) {
-        float s = 0.0f;
-        for (int z = 0; z < splits; ++z) s = s + part[(int64_t)z * nw + i];
-        dw[i] = s;
-    }
-    if (i < nb) {
-        float s = 0.0f;
-        for (int z = 0; z < splits; ++z) s = s + bpart[(int64_t)z * nb + i];
-        db[i] = s;
+    __shared__ float sw[256], sb[256];
+    const int j = threadIdx.x / 16, o = threadIdx.x % 16;
+    const int64_t i = (int64_t)blockIdx.x * 16 + o;
+    float w = 0.0f, bsum = 0.0f;
+    if (i < nw)
+        for (int z = j; z < splits; z += kRedLanes) w = w + part[(int64_t)z * nw + i];
+    if (i < nb)
+        for (int z = j; z < splits; z += kRedLanes) bsum = bsum + bpart[(int64_t)z * nb + i];
+    sw[threadIdx.x] = w;
+    sb[threadIdx.x] = bsum;
+    __syncthreads();
+    if (j == 0) {
+        float t = 0.0f, u = 0.0f;
+        for (int k = 0; k < kRedLanes; ++k) {
+            t = t + sw[16 * k + o];
+            u = u + sb[16 * k + o];
+        }
+        if (i < nw) dw[i] = t;
+        if (i < nb) db[i] = u;
     }
 }
 
@@ -1458,8 +1472,9 @@ hipError_t wgrad(const WgradArgs &a, float *dw, float *db, hipStream_t s)
     dim3 grid((unsigned)((a.Kpad + 127) / 128), (unsigned)((a.Cout_pad + 63) / 64), (unsigned)a.splits);
     hipLaunchKernelGGL(k_wgrad, grid, dim3(256), 0, s, a);
     const int64_t nw = (int64_t)a.Cout_pad * a.Kpad;
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblocks(nw > a.Cout_pad ? nw : a.Cout_pad)), dim3(256), 0, s, a.part,
-                       a.bpart, a.splits, nw, a.Cout_pad, dw, db);
+    const int64_t nout = nw > a.Cout_pad ? nw : a.Cout_pad;
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblocks(nout, 16)), dim3(256), 0, s, a.part, a.bpart, a.splits,
+                       nw, a.Cout_pad, dw, db);
     return hipGetLastError();
 }
 
