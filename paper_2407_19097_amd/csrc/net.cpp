@@ -88,12 +88,13 @@ int64_t param_count()
 }
 
 // Split-K of a layer's weight gradient over the P pixels of a batch: enough
-// splits for about 2048 workgroups (64 x 128 output tiles), at most 1024, each
+// splits for about 2048 workgroups (64 x 128 output tiles, 32 x 256 for
+// layers with at most 32 output channels), at most 1024, each
 // split a multiple of 64 pixels.  Returns the number of splits, *per the
 // pixels per split.
 int wgrad_splits(int rows, int kpad, int64_t P, int64_t *per)
 {
-    const int tiles = ((kpad + 127) / 128) * ((rows + 63) / 64);
+    const int tiles = rows <= 32 ? (kpad + 255) / 256 : ((kpad + 127) / 128) * ((rows + 63) / 64);
     int64_t splits = std::min<int64_t>(1024, std::max<int64_t>(1, (2048 + tiles - 1) / tiles));
     int64_t pp = (P + splits - 1) / splits;
     pp = (pp + 63) / 64 * 64;

@@ -950,39 +950,54 @@ __device__ __forceinline__ int wg_at(int row, int q)
     return row * kWgPix + (((q >> 1) ^ f) << 3) + ((q & 1) << 2);
 }
 
-// dW tile of 64 output channels x 128 im2col columns per workgroup, over the
-// pixel range of its split; wave (wm, wn) computes channels 32 wm.. x
-// columns 64 wn.. (2 x 4 fragments), the pixels being the MFMA's K.
+// dW tile of TCO output channels x TK im2col columns per workgroup (64 x 128,
+// or 32 x 256 for layers with 32 output channels), over the pixel range of
+// its split; wave (wm, wn) computes channels 32 wm.. x columns 64 wn.. (2 x 4
+// fragments), the pixels being the MFMA's K.
+template <int TCO>
 __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a)
 {
-    __shared__ __attribute__((aligned(16))) __bf16 sdy[64 * kWgPix];   // [co][pixel]
-    __shared__ __attribute__((aligned(16))) __bf16 sx[128 * kWgPix];   // [k][pixel]
+    constexpr int TK = 8192 / TCO;        // 128 or 256 columns
+    constexpr int NWM = TCO / 32;         // waves along the channels
+    __shared__ __attribute__((aligned(16))) __bf16 sdy[TCO * kWgPix];   // [co][pixel]
+    __shared__ __attribute__((aligned(16))) __bf16 sx[TK * kWgPix];     // [k][pixel]
     typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, r = lane & 15;
-    const int wm = wave & 1, wn = wave >> 1;
-    const int co0 = blockIdx.y * 64;
-    const int k0 = blockIdx.x * 128;
+    const int wm = wave % NWM, wn = wave / NWM;
+    const int co0 = blockIdx.y * TCO;
+    const int k0 = blockIdx.x * TK;
     const int64_t P = (int64_t)a.B * a.H * a.W;
     const int64_t pbeg = (int64_t)blockIdx.z * a.pix_per_split;
     const int64_t pend = min(P, pbeg + a.pix_per_split);
     const int K = a.KS * a.KS * a.Cin;
     const int hw = a.H * a.W;  // B * H * W < 2^31
-    // staging roles: dy by threads 0..127 (pixel quad, group of 8 channels),
-    // the im2col columns by all 256 (pixel quad, group of 8 columns)
-    const int qd = threadIdx.x >> 3, cg = threadIdx.x & 7;
-    const int qx = threadIdx.x >> 4, kg = threadIdx.x & 15;
-    const int kk = k0 + kg * 8;
-    int tap = 0, ci = 0, ty = 0, tx = 0;
-    if (kk < K) {
-        tap = kk / a.Cin;
-        ci = kk - tap * a.Cin;
-        ty = a.KS == 3 ? tap / 3 - 1 : 0;
-        tx = a.KS == 3 ? tap % 3 - 1 : 0;
+    // staging roles: dy by threads 0 .. 2 TCO - 1 (pixel quad, group of 8
+    // channels), the im2col columns by all 256 threads, TK / 128 groups of 8
+    // columns each (pixel quad, column group)
+    constexpr int XG = TK / 128;
+    const int qd = threadIdx.x / (TCO / 8), cg = threadIdx.x % (TCO / 8);
+    const int qx = threadIdx.x >> 4;
+    int kg[XG], ty[XG], tx[XG], xstride[XG];
+    bool kin[XG];
+    const __bf16 *xsrc[XG];
+#pragma unroll
+    for (int h = 0; h < XG; ++h) {
+        kg[h] = (threadIdx.x & 15) + 16 * h;
+        const int kk = k0 + kg[h] * 8;
+        int tap = 0, ci = 0;
+        ty[h] = tx[h] = 0;
+        kin[h] = kk < K;
+        if (kin[h]) {
+            tap = kk / a.Cin;
+            ci = kk - tap * a.Cin;
+            ty[h] = a.KS == 3 ? tap / 3 - 1 : 0;
+            tx[h] = a.KS == 3 ? tap % 3 - 1 : 0;
+        }
+        const bool second = a.x2 && ci >= a.xCin1;
+        xsrc[h] = second ? a.x2 + a.x2_off + (ci - a.xCin1) : a.x + a.x_off + ci;
+        xstride[h] = second ? a.x2_stride : a.x_stride;
     }
-    const bool second = a.x2 && ci >= a.xCin1;
-    const __bf16 *xsrc = second ? a.x2 + a.x2_off + (ci - a.xCin1) : a.x + a.x_off + ci;
-    const int xstride = second ? a.x2_stride : a.x_stride;
     f32x4 acc[2][4];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -990,7 +1005,7 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a)
         for (int f = 0; f < 4; ++f) acc[i][f] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     float bsum = 0.0f;
     for (int64_t pc = pbeg; pc < pend; pc += kWgPix) {
-        if (threadIdx.x < 128) {
+        if (threadIdx.x < 2 * TCO) {
             const int c = co0 + cg * 8;
             bf16x8 v[4];
 #pragma unroll
@@ -1011,7 +1026,8 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a)
             for (int j = 0; j < 8; ++j)
                 *reinterpret_cast<bf16x4 *>(&sdy[wg_at(cg * 8 + j, qd)]) = bf16x4{v[0][j], v[1][j], v[2][j], v[3][j]};
         }
-        {
+#pragma unroll
+        for (int h = 0; h < XG; ++h) {
             bf16x8 v[4];
             const int64_t p0 = pc + 4 * qx;
             int b = (int)(p0 / hw);
@@ -1021,9 +1037,9 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 v[e] = zero8();
-                const int y2 = y + ty, x2 = x + tx;
-                if (kk < K && p0 + e < pend && y2 >= 0 && y2 < a.H && x2 >= 0 && x2 < a.W)
-                    v[e] = load8(xsrc + (((int64_t)b * a.H + y2) * a.W + x2) * xstride);
+                const int y2 = y + ty[h], x2 = x + tx[h];
+                if (kin[h] && p0 + e < pend && y2 >= 0 && y2 < a.H && x2 >= 0 && x2 < a.W)
+                    v[e] = load8(xsrc[h] + (((int64_t)b * a.H + y2) * a.W + x2) * xstride[h]);
                 if (++x == a.W) {  // next pixel (W >= 8, so at most one wrap in a quad)
                     x = 0;
                     if (++y == a.H) {
@@ -1034,7 +1050,8 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a)
             }
 #pragma unroll
             for (int j = 0; j < 8; ++j)
-                *reinterpret_cast<bf16x4 *>(&sx[wg_at(kg * 8 + j, qx)]) = bf16x4{v[0][j], v[1][j], v[2][j], v[3][j]};
+                *reinterpret_cast<bf16x4 *>(&sx[wg_at(kg[h] * 8 + j, qx)]) =
+                    bf16x4{v[0][j], v[1][j], v[2][j], v[3][j]};
         }
         __syncthreads();
 #pragma unroll
@@ -1052,7 +1069,7 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a)
                 for (int f = 0; f < 4; ++f)
                     acc[i][f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[f], acc[i][f], 0, 0, 0);
         }
-        if (blockIdx.x == 0 && threadIdx.x < 64) {
+        if (blockIdx.x == 0 && threadIdx.x < TCO) {
 #pragma unroll
             for (int o = 0; o < 8; ++o) {
                 const bf16x8 t = *reinterpret_cast<const bf16x8 *>(&sdy[threadIdx.x * kWgPix + 8 * o]);
@@ -1074,7 +1091,7 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a)
                 const int k = k0 + 64 * wn + 16 * f + r;
                 if (co < a.Cout_pad && k < a.Kpad) out[(int64_t)co * a.Kpad + k] = acc[i][f][e];
             }
-    if (blockIdx.x == 0 && threadIdx.x < 64 && co0 + threadIdx.x < a.Cout_pad)
+    if (blockIdx.x == 0 && threadIdx.x < TCO && co0 + threadIdx.x < a.Cout_pad)
         a.bpart[(int64_t)blockIdx.z * a.Cout_pad + co0 + threadIdx.x] = bsum;
 }
 
@@ -1469,8 +1486,13 @@ hipError_t pool2_bwd_add(const SliceArgs &a, hipStream_t s)
 
 hipError_t wgrad(const WgradArgs &a, float *dw, float *db, hipStream_t s)
 {
-    dim3 grid((unsigned)((a.Kpad + 127) / 128), (unsigned)((a.Cout_pad + 63) / 64), (unsigned)a.splits);
-    hipLaunchKernelGGL(k_wgrad, grid, dim3(256), 0, s, a);
+    if (a.Cout_pad <= 32) {
+        dim3 grid((unsigned)((a.Kpad + 255) / 256), 1u, (unsigned)a.splits);
+        hipLaunchKernelGGL(k_wgrad<32>, grid, dim3(256), 0, s, a);
+    } else {
+        dim3 grid((unsigned)((a.Kpad + 127) / 128), (unsigned)((a.Cout_pad + 63) / 64), (unsigned)a.splits);
+        hipLaunchKernelGGL(k_wgrad<64>, grid, dim3(256), 0, s, a);
+    }
     const int64_t nw = (int64_t)a.Cout_pad * a.Kpad;
     const int64_t nout = nw > a.Cout_pad ? nw : a.Cout_pad;
     hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblocks(nout, 16)), dim3(256), 0, s, a.part, a.bpart, a.splits,
