@@ -262,7 +262,7 @@ def main():
         narvis.narvis_raster_clear(g.keys, W, H, stream)
         if ev is not None:
             ev[0].record(stream)
-        narvis.narvis_raster_render(pts, n, vp, nf, ff, W, H, g.keys, stream=stream)
+        narvis.narvis_raster_render(pts, n, vp, nf, ff, W, H, g.keys, bounds=g.bounds, stream=stream)
         if ev is not None:
             ev[1].record(stream)
         narvis.narvis_raster_resolve(pts, sc.attrs, n, vp, W, H, g, stream=stream)
@@ -331,7 +331,9 @@ def main():
                    "covered_fraction_frame0": round(covered, 4)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
-                     "kernel": "render (k_render_lds)", "avg_launch_ms": round(render_avg, 4),
+                     "kernel": "render stage: k_render_lds (every 8th chunk of 2048 points), k_tile_bounds, "
+                               "k_render_cull (the other chunks against the bounds)",
+                     "avg_launch_ms": round(render_avg, 4),
                      "algorithmic_bytes_per_launch": alg_bytes},
         "stream_copy_GBps": round(copy_gbps, 1),
     }

@@ -45,6 +45,8 @@ typedef enum { NARVIS_U8 = 0, NARVIS_U16 = 1, NARVIS_F16 = 2, NARVIS_F32 = 3 } n
 
 #define NARVIS_MAX_ATTRS 8
 #define NARVIS_KEY_EMPTY 0xFFFFFFFFFFFFFFFFull
+/* Screen tiles (at most) of the bounded render. */
+#define NARVIS_TILE_BOUNDS_MAX 8192
 
 /* Point positions, structure of arrays: x[n], y[n], z[n] float32, device. */
 typedef struct {
@@ -98,7 +100,12 @@ typedef struct {
  *                         of normalised device coordinates along v
  *                         (v'x, v'y), then theta = atan2(v'y, v'x)/pi and
  *                         |v'|; 0 for an empty pixel.
- *   lut    float[256][3] device table for rgb. */
+ *   lut    float[256][3] device table for rgb.
+ *   bounds  optional device scratch of bounds_bytes >=
+ *           narvis_raster_bounds_bytes(W, H) bytes (2-byte aligned, contents
+ *           overwritten): when given, narvis_rasterize renders in the bounded
+ *           mode (see narvis_raster_opts); NULL renders in one pass.  The
+ *           keys are the same either way. */
 typedef struct {
     uint64_t *keys;
     float *depth;
@@ -110,6 +117,8 @@ typedef struct {
     float lut_min;
     float lut_inv_range;
     int32_t vel_attr;
+    void *bounds;
+    size_t bounds_bytes;
 } narvis_gbuffer;
 
 /* Render-stage strategy.  Every variant produces the same key buffer; they
@@ -123,10 +132,28 @@ typedef enum {
                                   touched pixel (scalar path: as EARLYZ)     */
 } narvis_render_variant;
 
+/* Bounded render (LDS variant on 16-byte aligned coordinates, when bounds
+ * are given, n >= 4096 and W, H < 2^24): the points are taken in chunks of
+ * 2048; every 8th chunk is rendered first.  Then, with d(p) the depth bits of
+ * the smallest key pixel p holds so far (0xFFFFFFFF if none), the scratch
+ * receives
+ *   uint16 tile[NARVIS_TILE_BOUNDS_MAX]: for screen tiles of 2^s x 2^s
+ *          pixels (the smallest s >= 3 giving at most NARVIS_TILE_BOUNDS_MAX
+ *          tiles, row-major), the largest d(p) >> 16 over the tile,
+ *   uint16 pixel[H][W]: d(p) >> 16,
+ * and the other chunks are rendered, a point being dropped when
+ * (bits(w) >> 16) exceeds the bound of its tile or of its pixel.  Keys only
+ * decrease, so the pixel's key is already smaller than such a point's: the
+ * result is the single-pass result, bit for bit.  This is the paper's early
+ * z-test (Sec. 3.2), taken against a compact copy of the depth buffer. */
 typedef struct {
     int32_t variant;      /* narvis_render_variant                           */
     int32_t grid_blocks;  /* 0 = automatic, otherwise the number of
                              workgroups (a grid-stride loop covers all points) */
+    void *bounds;         /* NULL, or device scratch of bounds_bytes >=
+                             narvis_raster_bounds_bytes(W, H) bytes (2-byte
+                             aligned, contents overwritten): bounded render */
+    size_t bounds_bytes;
 } narvis_raster_opts;
 
 /* Colour of a point in the splat renderer. */
@@ -158,6 +185,10 @@ const char *narvis_status_string(narvis_status s);
  * 0 < znear < zfar. */
 narvis_status narvis_camera_matrix(const narvis_camera *cam, int32_t W, int32_t H,
                                    float vp_rowmajor[16], float *near_f, float *far_f);
+
+/* Bytes of the bounded render's scratch for a W x H image:
+ * 2 (NARVIS_TILE_BOUNDS_MAX + W H); 0 for invalid W, H. */
+size_t narvis_raster_bounds_bytes(int32_t W, int32_t H);
 
 /* Fill keys[W*H] with NARVIS_KEY_EMPTY. */
 narvis_status narvis_raster_clear(uint64_t *keys, int32_t W, int32_t H, void *stream);

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libnarvis.so")
 
 MAX_ATTRS = 8
 KEY_EMPTY = 0xFFFFFFFFFFFFFFFF
+TILE_BOUNDS_MAX = 8192
 
 STATUS = {0: "NARVIS_OK", -1: "NARVIS_ERR_INVALID_ARG", -2: "NARVIS_ERR_OUT_OF_MEMORY",
           -3: "NARVIS_ERR_DEVICE", -4: "NARVIS_ERR_UNSUPPORTED", -5: "NARVIS_ERR_WORKSPACE"}
@@ -46,11 +47,12 @@ class GBuffer(ctypes.Structure):
     _fields_ = [("keys", ctypes.c_void_p), ("depth", ctypes.c_void_p), ("attr", ctypes.c_void_p),
                 ("rgb", ctypes.c_void_p), ("vel2d", ctypes.c_void_p), ("lut", ctypes.c_void_p),
                 ("lut_attr", ctypes.c_int32), ("lut_min", ctypes.c_float), ("lut_inv_range", ctypes.c_float),
-                ("vel_attr", ctypes.c_int32)]
+                ("vel_attr", ctypes.c_int32), ("bounds", ctypes.c_void_p), ("bounds_bytes", ctypes.c_size_t)]
 
 
 class RasterOpts(ctypes.Structure):
-    _fields_ = [("variant", ctypes.c_int32), ("grid_blocks", ctypes.c_int32)]
+    _fields_ = [("variant", ctypes.c_int32), ("grid_blocks", ctypes.c_int32), ("bounds", ctypes.c_void_p),
+                ("bounds_bytes", ctypes.c_size_t)]
 
 
 class SplatParams(ctypes.Structure):
@@ -68,6 +70,7 @@ SIGNATURES = {
     "narvis_camera_matrix": (ctypes.c_int, [ctypes.POINTER(Camera), ctypes.c_int32, ctypes.c_int32, _F16,
                                             ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
     "narvis_raster_clear": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P]),
+    "narvis_raster_bounds_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
     "narvis_raster_render": (ctypes.c_int, [ctypes.POINTER(Points), ctypes.c_uint64, _F16, ctypes.c_float,
                                             ctypes.c_float, ctypes.c_int32, ctypes.c_int32, _P,
                                             ctypes.POINTER(RasterOpts), _P]),

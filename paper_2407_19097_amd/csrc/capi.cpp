@@ -119,6 +119,12 @@ extern "C" narvis_status narvis_raster_clear(uint64_t *keys, int32_t W, int32_t 
     return from_hip(launch_clear(keys, (int64_t)W * H, static_cast<hipStream_t>(stream)));
 }
 
+extern "C" size_t narvis_raster_bounds_bytes(int32_t W, int32_t H)
+{
+    if (!image_ok(W, H)) return 0;
+    return 2 * ((size_t)NARVIS_TILE_BOUNDS_MAX + (size_t)W * (size_t)H);
+}
+
 extern "C" narvis_status narvis_raster_render(const narvis_points *pts, uint64_t n, const float vp[16],
                                               float near_f, float far_f, int32_t W, int32_t H, uint64_t *keys,
                                               const narvis_raster_opts *opts, void *stream)
@@ -128,13 +134,16 @@ extern "C" narvis_status narvis_raster_render(const narvis_points *pts, uint64_t
     if (reinterpret_cast<uintptr_t>(keys) & 7u) return NARVIS_ERR_INVALID_ARG;
     int32_t variant = opts ? opts->variant : NARVIS_RENDER_AUTO;
     int32_t grid = opts ? opts->grid_blocks : 0;
+    void *bounds = opts ? opts->bounds : nullptr;
     if (variant < NARVIS_RENDER_AUTO || variant > NARVIS_RENDER_LDS || grid < 0) return NARVIS_ERR_INVALID_ARG;
+    if (reinterpret_cast<uintptr_t>(bounds) & 1u) return NARVIS_ERR_INVALID_ARG;
+    if (bounds && opts->bounds_bytes < narvis_raster_bounds_bytes(W, H)) return NARVIS_ERR_WORKSPACE;
     if (n > 0 && ((reinterpret_cast<uintptr_t>(pts->x) | reinterpret_cast<uintptr_t>(pts->y) |
                    reinterpret_cast<uintptr_t>(pts->z)) & 3u))
         return NARVIS_ERR_INVALID_ARG;
     const Proj P = make_proj(vp, near_f, far_f, W, H);
     return from_hip(launch_render(n ? pts->x : nullptr, n ? pts->y : nullptr, n ? pts->z : nullptr, n, P, keys,
-                                  variant, grid, static_cast<hipStream_t>(stream)));
+                                  variant, grid, static_cast<uint16_t *>(bounds), static_cast<hipStream_t>(stream)));
 }
 
 extern "C" narvis_status narvis_raster_resolve(const narvis_points *pts, const narvis_attrs *attrs, uint64_t n,
@@ -180,13 +189,15 @@ extern "C" narvis_status narvis_rasterize(const narvis_points *pts, const narvis
     if (n > 0 && ((reinterpret_cast<uintptr_t>(pts->x) | reinterpret_cast<uintptr_t>(pts->y) |
                    reinterpret_cast<uintptr_t>(pts->z)) & 3u))
         return NARVIS_ERR_INVALID_ARG;
-    if (reinterpret_cast<uintptr_t>(gbuf->keys) & 7u) return NARVIS_ERR_INVALID_ARG;
+    if ((reinterpret_cast<uintptr_t>(gbuf->keys) & 7u) || (reinterpret_cast<uintptr_t>(gbuf->bounds) & 1u))
+        return NARVIS_ERR_INVALID_ARG;
+    if (gbuf->bounds && gbuf->bounds_bytes < narvis_raster_bounds_bytes(W, H)) return NARVIS_ERR_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     st = from_hip(launch_clear(gbuf->keys, (int64_t)W * H, s));
     if (st != NARVIS_OK) return st;
     const Proj P = make_proj(vp, near_f, far_f, W, H);
     st = from_hip(launch_render(n ? pts->x : nullptr, n ? pts->y : nullptr, n ? pts->z : nullptr, n, P,
-                                gbuf->keys, NARVIS_RENDER_AUTO, 0, s));
+                                gbuf->keys, NARVIS_RENDER_AUTO, 0, static_cast<uint16_t *>(gbuf->bounds), s));
     if (st != NARVIS_OK) return st;
     return from_hip(launch_resolve(n ? pts->x : nullptr, n ? pts->y : nullptr, n ? pts->z : nullptr, n, P, pack,
                                    *gbuf, s));

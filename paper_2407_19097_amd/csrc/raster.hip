@@ -52,7 +52,8 @@ __device__ __forceinline__ float div_rcp(float a, float w, float y)
 // coordinates); valid when every kept depth is a normal float with exponent
 // in [-124, 124], which the host checks from the near/far bounds.
 template <bool RCP = false>
-__device__ __forceinline__ bool project(const Proj &P, float x, float y, float z, uint32_t &pix, float &w)
+__device__ __forceinline__ bool project(const Proj &P, float x, float y, float z, uint32_t &ix, uint32_t &iy,
+                                       float &w)
 {
     float cx = P.m00 * x;
     cx = cx + P.m01 * y;
@@ -83,11 +84,27 @@ __device__ __forceinline__ bool project(const Proj &P, float x, float y, float z
     float sy = ny * 0.5f;
     sy = 0.5f - sy;
     sy = sy * P.Hf;
-    const bool ok = (ww >= P.near_f) & (ww <= P.far_f) & (sx >= 0.0f) & (sx < P.Wf) & (sy >= 0.0f) & (sy < P.Hf);
+    // 0 <= sx < W as one unsigned comparison of bit patterns: sx is never -0
+    // (u + 0.5 and 0.5 - u are never -0 in round to nearest, and scaling by
+    // W >= 1 cannot flush a nonzero value to zero), non-negative floats order
+    // like their bits, and every negative value or NaN has a pattern above
+    // that of the positive finite W.  Likewise for sy.
+    const bool ok = (ww >= P.near_f) & (ww <= P.far_f) & (__float_as_uint(sx) < __float_as_uint(P.Wf)) &
+                    (__float_as_uint(sy) < __float_as_uint(P.Hf));
     // clamped before the conversion; equal to sx, sy whenever ok
     const float xs = fminf(fmaxf(sx, 0.0f), P.Wf), ys = fminf(fmaxf(sy, 0.0f), P.Hf);
-    pix = (uint32_t)(int32_t)ys * (uint32_t)P.W + (uint32_t)(int32_t)xs;
+    ix = (uint32_t)(int32_t)xs;
+    iy = (uint32_t)(int32_t)ys;
     w = ww;
+    return ok;
+}
+
+template <bool RCP = false>
+__device__ __forceinline__ bool project(const Proj &P, float x, float y, float z, uint32_t &pix, float &w)
+{
+    uint32_t ix, iy;
+    const bool ok = project<RCP>(P, x, y, z, ix, iy, w);
+    pix = iy * (uint32_t)P.W + ix;
     return ok;
 }
 
@@ -250,23 +267,65 @@ __device__ __forceinline__ void global_merge(unsigned long long *__restrict__ ke
         if (hit[t] && key[t] < cur[t]) __hip_atomic_fetch_min(keys + pix[t], key[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Which chunks of kChunk points a launch renders: the multiples of `mul`,
+// without those that are multiples of mul * excl when excl >= 2.  Virtual
+// chunk v of the launch is real chunk mul v (excl = 0), or mul times the v-th
+// integer that is not a multiple of excl.  `tail`: this launch also renders
+// the last n % 4 points.
+struct ChunkSel {
+    uint32_t mul, excl;
+    uint64_t nv;  // virtual chunks of this launch
+    uint32_t tail;
+};
+
+__device__ __forceinline__ uint64_t real_chunk(const ChunkSel &c, uint64_t v)
+{
+    return (uint64_t)c.mul * (c.excl ? v + v / (c.excl - 1) + 1 : v);
+}
+
+// Screen tiles of 2^shift x 2^shift pixels, tiles_x per row, one depth bound
+// per tile (the high 16 bits of the largest depth bits held by a pixel of the
+// tile) and one per pixel (the high 16 bits of its depth bits), both taken by
+// k_tile_bounds.
+constexpr int kMaxTiles = 8192;
+
+struct TileGrid {
+    const uint16_t *bounds;
+    const uint16_t *pixb;
+    uint32_t shift, tiles_x, ntiles;
+};
+
+__device__ __forceinline__ void render_tail(const float *X, const float *Y, const float *Z, uint64_t n,
+                                            const Proj &P, unsigned long long *keys, const ChunkSel &sel)
+{
+    const uint64_t nq = n >> 2;
+    if (sel.tail && blockIdx.x == 0 && threadIdx.x < (n & 3)) {
+        const uint64_t i = (nq << 2) + threadIdx.x;
+        uint32_t pix;
+        float w;
+        if (project(P, X[i], Y[i], Z[i], pix, w)) merge<NARVIS_RENDER_EARLYZ>(keys, pix, w, (uint32_t)i);
+    }
+}
+
 // (4 waves per SIMD: the compiler keeps it within 128 registers)
 template <bool RCP>
 __global__ __launch_bounds__(kBlock, 4) void k_render_lds(const float *__restrict__ X, const float *__restrict__ Y,
                                                         const float *__restrict__ Z, uint64_t n, Proj P,
-                                                        unsigned long long *__restrict__ keys, ChunkOrder order)
+                                                        unsigned long long *__restrict__ keys, ChunkOrder order,
+                                                        ChunkSel sel)
 {
     __shared__ unsigned long long best[kSlots];
     __shared__ uint32_t pixof[kChunk];
     for (int s = threadIdx.x; s < kSlots; s += kBlock) best[s] = NARVIS_KEY_EMPTY;
     const uint64_t nq = n >> 2;
     const uint64_t lb = logical_block(order);
-    const uint64_t stride = (uint64_t)gridDim.x * kBlock * kQuadsPerThread;
+    constexpr uint64_t kQuads = (uint64_t)kBlock * kQuadsPerThread;  // quads per chunk
     const uint32_t npx = (uint32_t)P.W * (uint32_t)P.H;
     const uint32_t spread = (uint32_t)((lb * 2654435761ull) % (uint64_t)npx);
     __syncthreads();
     // uniform trip count for the whole workgroup: the barriers below need it
-    for (uint64_t start = lb * kBlock * kQuadsPerThread; start < nq; start += stride) {
+    for (uint64_t v = lb; v < sel.nv; v += gridDim.x) {
+        const uint64_t start = real_chunk(sel, v) * kQuads;
         const uint32_t first = (uint32_t)(start << 2);  // index of the chunk's first point (mod 2^32)
         f32x4 xs[kQuadsPerThread], ys[kQuadsPerThread], zs[kQuadsPerThread];
 #pragma unroll
@@ -324,12 +383,133 @@ __global__ __launch_bounds__(kBlock, 4) void k_render_lds(const float *__restric
         global_merge<kPts>(keys, pix, key, hit, spread);
         __syncthreads();
     }
-    // the last n % 4 points
-    if (blockIdx.x == 0 && threadIdx.x < (n & 3)) {
-        const uint64_t i = (nq << 2) + threadIdx.x;
-        uint32_t pix;
-        float w;
-        if (project(P, X[i], Y[i], Z[i], pix, w)) merge<NARVIS_RENDER_EARLYZ>(keys, pix, w, (uint32_t)i);
+    render_tail(X, Y, Z, n, P, keys, sel);
+}
+
+// Bounded render of the chunks `sel` picks, after some chunks have been
+// rendered and k_tile_bounds has taken the bounds.  Keys only decrease, so a
+// point deeper than its bound cannot win its pixel: each point is tested
+// against its tile's bound (LDS), the survivors against their pixel's bound
+// (a 16-bit global read, two bytes per pixel, mostly cache-resident), and
+// what is left goes to the atomic minimum.  No LDS table and no barrier in
+// the loop: the waves stream independently.
+// Key address with a 32-bit byte offset when the image has fewer than 2^29
+// pixels (the load and atomic then take a scalar base and one offset register).
+template <bool OFF32>
+__device__ __forceinline__ unsigned long long *key_at(unsigned long long *keys, uint32_t pix)
+{
+    if (OFF32) return reinterpret_cast<unsigned long long *>(reinterpret_cast<char *>(keys) + (pix << 3));
+    return keys + pix;
+}
+
+// quads per thread and workgroup size: one chunk of kChunk points per
+// workgroup iteration
+constexpr int kCullQpt = 2;
+constexpr int kCullBlock = kChunk / 4 / kCullQpt;
+constexpr int kCullPts = 4 * kCullQpt;
+
+template <bool RCP, bool OFF32>
+__global__ __launch_bounds__(kCullBlock) void k_render_cull(const float *__restrict__ X, const float *__restrict__ Y,
+                                                        const float *__restrict__ Z, uint64_t n, Proj P,
+                                                        unsigned long long *__restrict__ keys, ChunkOrder order,
+                                                        ChunkSel sel, TileGrid tg)
+{
+    __shared__ uint16_t tb[kMaxTiles];
+    for (uint32_t s = threadIdx.x; s < tg.ntiles; s += kCullBlock) tb[s] = tg.bounds[s];
+    const uint64_t nq = n >> 2;
+    const uint64_t lb = logical_block(order);
+    constexpr uint64_t kQuads = (uint64_t)kCullBlock * kCullQpt;
+    const uint32_t npx = (uint32_t)P.W * (uint32_t)P.H;
+    const uint32_t spread = (uint32_t)((lb * 2654435761ull) % (uint64_t)npx);
+    __syncthreads();
+    for (uint64_t v = lb; v < sel.nv; v += gridDim.x) {
+        const uint64_t start = real_chunk(sel, v) * kQuads;
+        const uint32_t first = (uint32_t)(start << 2);
+        f32x4 xs[kCullQpt], ys[kCullQpt], zs[kCullQpt];
+#pragma unroll
+        for (int k = 0; k < kCullQpt; ++k) {
+            const uint64_t q = start + threadIdx.x + (uint64_t)k * kCullBlock;
+            if (q < nq) {
+                xs[k] = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(X) + q);
+                ys[k] = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(Y) + q);
+                zs[k] = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(Z) + q);
+            }
+        }
+        uint32_t pix[kCullPts];
+        unsigned long long key[kCullPts];
+        bool hit[kCullPts];
+#pragma unroll
+        for (int k = 0; k < kCullQpt; ++k) {
+            const uint32_t lq = threadIdx.x + (uint32_t)k * kCullBlock;
+            const bool live = start + lq < nq;
+            const float px[4] = {xs[k].x, xs[k].y, xs[k].z, xs[k].w};
+            const float py[4] = {ys[k].x, ys[k].y, ys[k].z, ys[k].w};
+            const float pz[4] = {zs[k].x, zs[k].y, zs[k].z, zs[k].w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int t = k * 4 + j;
+                float w = 0.0f;
+                uint32_t ix = 0, iy = 0;
+                bool h = project<RCP>(P, px[j], py[j], pz[j], ix, iy, w) & live;
+                const uint32_t tile = h ? __umul24(iy >> tg.shift, tg.tiles_x) + (ix >> tg.shift) : 0u;
+                hit[t] = h & ((__float_as_uint(w) >> 16) <= (uint32_t)tb[tile]);
+                pix[t] = __umul24(iy, (uint32_t)P.W) + ix;
+                key[t] = ((unsigned long long)__float_as_uint(w) << 32) | (first + lq * 4 + (uint32_t)j);
+            }
+        }
+        // pixel bounds of the survivors (a read no lane of the wave needs is
+        // skipped; a lane without a survivor reads the wave's shared pixel so
+        // that its request merges), then the atomics
+        bool any[kCullPts];
+        uint32_t pb[kCullPts];
+#pragma unroll
+        for (int t = 0; t < kCullPts; ++t) {
+            any[t] = __ballot(hit[t]) != 0;
+            pb[t] = 0;
+        }
+#pragma unroll
+        for (int t = 0; t < kCullPts; ++t)
+            if (any[t]) pb[t] = tg.pixb[hit[t] ? pix[t] : spread];
+#pragma unroll
+        for (int t = 0; t < kCullPts; ++t) hit[t] = hit[t] && (uint32_t)(key[t] >> 48) <= pb[t];
+#pragma unroll
+        for (int t = 0; t < kCullPts; ++t)
+            if (hit[t])
+                __hip_atomic_fetch_min(key_at<OFF32>(keys, pix[t]), key[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    render_tail(X, Y, Z, n, P, keys, sel);
+}
+
+// Depth bounds after the first levels: per pixel the high 16 bits of its
+// depth bits, per screen tile the largest of those over the tile's pixels (an
+// empty pixel counts as depth bits 0xFFFFFFFF, bound 0xFFFF, which culls
+// nothing).  A point with (bits(w) >> 16) > bound has bits(w) > the depth
+// bits of the pixel (every pixel of the tile).  One workgroup per tile.
+__global__ __launch_bounds__(kBlock) void k_tile_bounds(const unsigned long long *__restrict__ keys, int32_t W,
+                                                        int32_t H, uint32_t shift, uint32_t tiles_x,
+                                                        uint16_t *__restrict__ bounds, uint16_t *__restrict__ pixb)
+{
+    __shared__ uint32_t red[kBlock / 64];
+    const uint32_t t = blockIdx.x;
+    const uint32_t x0 = (t % tiles_x) << shift, y0 = (t / tiles_x) << shift;
+    const uint32_t side = 1u << shift;
+    uint32_t m = 0;
+    for (uint32_t i = threadIdx.x; i < side * side; i += kBlock) {
+        const uint32_t x = x0 + (i & (side - 1)), y = y0 + (i >> shift);
+        if (x < (uint32_t)W && y < (uint32_t)H) {
+            const size_t p = (size_t)y * (uint32_t)W + x;
+            const uint32_t d = (uint32_t)(keys[p] >> 32);
+            pixb[p] = (uint16_t)(d >> 16);
+            m = max(m, d);
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < kBlock / 64; ++k) m = max(m, red[k]);
+        bounds[t] = (uint16_t)(m >> 16);
     }
 }
 
@@ -498,8 +678,15 @@ uint32_t coprime_stride(uint32_t per)
 
 }  // namespace
 
+// Levels of the bounded render: the chunks that are multiples of 8 first
+// (single-pass kernel), then all the others, culled against the tile bounds
+// the first level left (more levels are supported: each later level is
+// culled against the bounds of everything before it).
+constexpr uint32_t kLevels[] = {8, 1};
+constexpr int kNumLevels = sizeof(kLevels) / sizeof(kLevels[0]);
+
 hipError_t launch_render(const float *x, const float *y, const float *z, uint64_t n, const Proj &P,
-                         uint64_t *keys, int32_t variant, int32_t grid_blocks, hipStream_t s)
+                         uint64_t *keys, int32_t variant, int32_t grid_blocks, uint16_t *bounds, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     const DeviceInfo dev = device_info();
@@ -507,24 +694,77 @@ hipError_t launch_render(const float *x, const float *y, const float *z, uint64_
     const bool vec = ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y) |
                        reinterpret_cast<uintptr_t>(z)) & 15u) == 0;
     const uint64_t per_block = vec ? (uint64_t)kBlock * kQuadsPerThread * 4 : (uint64_t)kBlock;
-    uint64_t blocks = grid_blocks > 0 ? (uint64_t)grid_blocks : (n + per_block - 1) / per_block;
-    if (blocks > (1u << 22)) blocks = 1u << 22;  // grid-stride covers the rest
-    // a multiple of the XCD count keeps the block renumbering a bijection
-    blocks = (blocks + xcds - 1) / xcds * xcds;
-    ChunkOrder order;
-    order.xcds = xcds;
-    order.per = (uint32_t)(blocks / xcds);
-    order.stride = coprime_stride(order.per);
+    // grid size as a multiple of the XCD count (keeps the block renumbering a
+    // bijection), at most 2^22 workgroups (grid-stride loops cover the rest)
+    auto grid_of = [&](uint64_t want) {
+        uint64_t blocks = want < 1 ? 1 : want;
+        if (blocks > (1u << 22)) blocks = 1u << 22;
+        return (blocks + xcds - 1) / xcds * xcds;
+    };
+    auto order_of = [&](uint64_t blocks) {
+        ChunkOrder order;
+        order.xcds = xcds;
+        order.per = (uint32_t)(blocks / xcds);
+        order.stride = coprime_stride(order.per);
+        return order;
+    };
+    uint64_t blocks = grid_of(grid_blocks > 0 ? (uint64_t)grid_blocks : (n + per_block - 1) / per_block);
+    ChunkOrder order = order_of(blocks);
     auto *k = reinterpret_cast<unsigned long long *>(keys);
     if (variant == NARVIS_RENDER_AUTO) variant = vec ? NARVIS_RENDER_LDS : NARVIS_RENDER_EARLYZ;
     if (variant == NARVIS_RENDER_LDS && !vec) variant = NARVIS_RENDER_EARLYZ;
     if (vec && variant == NARVIS_RENDER_LDS) {
         // kept depths lie in [near_f, far_f]: the reciprocal path needs them in
         // the range where rcp_rn is exact
-        if (P.near_f >= 0x1p-124f && P.far_f < 0x1p125f)
-            hipLaunchKernelGGL(k_render_lds<true>, dim3((unsigned)blocks), dim3(kBlock), 0, s, x, y, z, n, P, k, order);
-        else
-            hipLaunchKernelGGL(k_render_lds<false>, dim3((unsigned)blocks), dim3(kBlock), 0, s, x, y, z, n, P, k, order);
+        const bool rcp = P.near_f >= 0x1p-124f && P.far_f < 0x1p125f;
+        constexpr uint64_t kChunkQuads = (uint64_t)kBlock * kQuadsPerThread;
+        const uint64_t nchunks = ((n >> 2) + kChunkQuads - 1) / kChunkQuads;
+        auto lds = [&](const ChunkSel &sel, uint64_t nblocks) {
+            const ChunkOrder o = order_of(nblocks);
+            if (rcp)
+                hipLaunchKernelGGL(k_render_lds<true>, dim3((unsigned)nblocks), dim3(kBlock), 0, s, x, y, z, n, P, k,
+                                   o, sel);
+            else
+                hipLaunchKernelGGL(k_render_lds<false>, dim3((unsigned)nblocks), dim3(kBlock), 0, s, x, y, z, n, P, k,
+                                   o, sel);
+        };
+        // bounded render for at least two chunks (24-bit pixel arithmetic)
+        if (bounds && n >= 4096 && P.W < (1 << 24) && P.H < (1 << 24)) {
+            TileGrid tg{bounds, bounds + kMaxTiles, 3u, 0u, 0u};
+            while (true) {
+                tg.tiles_x = ((uint32_t)P.W + (1u << tg.shift) - 1) >> tg.shift;
+                tg.ntiles = tg.tiles_x * (((uint32_t)P.H + (1u << tg.shift) - 1) >> tg.shift);
+                if (tg.ntiles <= (uint32_t)kMaxTiles) break;
+                ++tg.shift;
+            }
+            auto ceil_div = [](uint64_t a, uint64_t b) { return (a + b - 1) / b; };
+            for (int lv = 0; lv < kNumLevels; ++lv) {
+                ChunkSel sel;
+                sel.mul = kLevels[lv];
+                sel.excl = lv ? kLevels[lv - 1] / kLevels[lv] : 0u;
+                sel.nv = ceil_div(nchunks, sel.mul) - (lv ? ceil_div(nchunks, kLevels[lv - 1]) : 0u);
+                sel.tail = lv == 0;
+                if (lv == 0) {
+                    lds(sel, grid_of(sel.nv));
+                } else {
+                    hipLaunchKernelGGL(k_tile_bounds, dim3(tg.ntiles), dim3(kBlock), 0, s, k, P.W, P.H, tg.shift,
+                                       tg.tiles_x, bounds, bounds + kMaxTiles);
+                    if (sel.nv == 0) continue;
+                    // a resident grid: each workgroup loads the bounds once
+                    const uint64_t resident = (uint64_t)dev.cus * (2048 / kCullBlock);
+                    const uint64_t nb = grid_of(grid_blocks > 0 ? (uint64_t)grid_blocks
+                                                                : (sel.nv < resident ? sel.nv : resident));
+                    const ChunkOrder o = order_of(nb);
+                    const bool off32 = (uint64_t)P.W * (uint64_t)P.H < (1ull << 29);
+                    auto kern = rcp ? (off32 ? k_render_cull<true, true> : k_render_cull<true, false>)
+                                    : (off32 ? k_render_cull<false, true> : k_render_cull<false, false>);
+                    hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(kCullBlock), 0, s, x, y, z, n, P, k, o, sel, tg);
+                }
+            }
+        } else {
+            ChunkSel all{1u, 0u, nchunks, 1u};
+            lds(all, blocks);
+        }
     } else if (vec) {
         if (variant == NARVIS_RENDER_GLOBAL)
             hipLaunchKernelGGL(k_render_vec<NARVIS_RENDER_GLOBAL>, dim3((unsigned)blocks), dim3(kBlock), 0, s,

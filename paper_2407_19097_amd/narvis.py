@@ -13,7 +13,7 @@ from typing import Optional, Sequence
 import numpy as np
 
 from . import _lib
-from ._lib import KEY_EMPTY, NarvisError  # noqa: F401
+from ._lib import KEY_EMPTY, TILE_BOUNDS_MAX, NarvisError  # noqa: F401
 
 RENDER_AUTO, RENDER_GLOBAL, RENDER_EARLYZ, RENDER_LDS = 0, 1, 2, 3
 
@@ -88,9 +88,10 @@ class GBuffer:
     lut_min: float = 0.0
     lut_inv_range: float = 1.0
     vel_attr: int = -1
+    bounds: object = None         # uint8 [narvis_raster_bounds_bytes(W, H)] scratch of the bounded render
 
     @staticmethod
-    def allocate(W: int, H: int, nattr: int = 0, depth=True, rgb=False, vel2d=False, device="cuda"):
+    def allocate(W: int, H: int, nattr: int = 0, depth=True, rgb=False, vel2d=False, bounded=True, device="cuda"):
         import torch
         npx = W * H
         e = lambda *s: torch.empty(*s, device=device, dtype=torch.float32)
@@ -98,12 +99,14 @@ class GBuffer:
                        depth=e(npx) if depth else None,
                        attr=e(nattr, npx) if nattr else None,
                        rgb=e(3, npx) if rgb else None,
-                       vel2d=e(4, npx) if vel2d else None)
+                       vel2d=e(4, npx) if vel2d else None,
+                       bounds=raster_bounds(W, H, device) if bounded else None)
 
     def struct(self) -> _lib.GBuffer:
         return _lib.GBuffer(_ptr(self.keys), _ptr(self.depth), _ptr(self.attr), _ptr(self.rgb), _ptr(self.vel2d),
                             _ptr(self.lut), int(self.lut_attr), float(self.lut_min), float(self.lut_inv_range),
-                            int(self.vel_attr))
+                            int(self.vel_attr), _ptr(self.bounds),
+                            0 if self.bounds is None else int(self.bounds.numel() * self.bounds.element_size()))
 
 
 def narvis_status_string(status: int) -> str:
@@ -130,10 +133,21 @@ def narvis_raster_clear(keys, W: int, H: int, stream=None) -> None:
     _lib.check(_lib.load().narvis_raster_clear(_ptr(keys), W, H, _stream_ptr(stream)), "narvis_raster_clear")
 
 
+def narvis_raster_bounds_bytes(W: int, H: int) -> int:
+    return int(_lib.load().narvis_raster_bounds_bytes(W, H))
+
+
+def raster_bounds(W: int, H: int, device="cuda"):
+    """Scratch tensor for the bounded render of a W x H image."""
+    import torch
+    return torch.empty(narvis_raster_bounds_bytes(W, H), device=device, dtype=torch.uint8)
+
+
 def narvis_raster_render(points, n: int, vp, near_f, far_f, W: int, H: int, keys, variant: int = RENDER_AUTO,
-                         grid_blocks: int = 0, stream=None) -> None:
+                         grid_blocks: int = 0, bounds=None, stream=None) -> None:
     p = points_struct(points)
-    o = _lib.RasterOpts(int(variant), int(grid_blocks))
+    nb = 0 if bounds is None else int(bounds.numel() * bounds.element_size())
+    o = _lib.RasterOpts(int(variant), int(grid_blocks), _ptr(bounds), nb)
     _lib.check(_lib.load().narvis_raster_render(ctypes.byref(p), int(n), _vp(vp), float(near_f), float(far_f), W, H,
                                                 _ptr(keys), ctypes.byref(o), _stream_ptr(stream)),
                "narvis_raster_render")

@@ -99,6 +99,12 @@ def test_invalid_arguments_rejected_before_any_launch():
     bad_opts = _lib.RasterOpts(7, 0)
     assert L.narvis_raster_render(ctypes.byref(pts), 10, vp, 0.1, 10.0, 8, 8, fake, ctypes.byref(bad_opts),
                                   None) == -1
+    # bounded render: misaligned or undersized scratch
+    odd = _lib.RasterOpts(3, 0, fake + 1, 1 << 20)
+    assert L.narvis_raster_render(ctypes.byref(pts), 10, vp, 0.1, 10.0, 8, 8, fake, ctypes.byref(odd), None) == -1
+    small = _lib.RasterOpts(3, 0, fake, L.narvis_raster_bounds_bytes(8, 8) - 2)
+    assert L.narvis_raster_render(ctypes.byref(pts), 10, vp, 0.1, 10.0, 8, 8, fake, ctypes.byref(small),
+                                  None) == -5
     nan_vp = (ctypes.c_float * 16)(*([float("nan")] * 16))
     assert L.narvis_raster_render(ctypes.byref(pts), 10, nan_vp, 0.1, 10.0, 8, 8, fake, None, None) == -1
     mis = _lib.Points(fake + 2, fake, fake)
@@ -123,6 +129,15 @@ def test_invalid_arguments_rejected_before_any_launch():
     cam = narvis.camera_struct(scenes.Camera(eye=(1, 1, 1), target=(1, 1, 1)))
     assert L.narvis_rasterize(ctypes.byref(pts), ctypes.byref(a), 10, ctypes.byref(cam), 8, 8, ctypes.byref(g),
                               None) == -1
+
+
+def test_raster_bounds_bytes():
+    """Scratch of the bounded render: 8192 tile bounds and one per pixel, 16 bits each."""
+    L = _lib.load()
+    assert L.narvis_raster_bounds_bytes(1920, 1080) == 2 * (8192 + 1920 * 1080)
+    assert L.narvis_raster_bounds_bytes(1, 1) == 2 * 8193
+    assert L.narvis_raster_bounds_bytes(0, 8) == 0
+    assert L.narvis_raster_bounds_bytes(1 << 16, 1 << 16) == 0
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):

@@ -40,8 +40,9 @@ def ulp_diff(a, b):
 
 
 def gpu_frame(x, y, z, attrs, cam, W, H, lut=None, lut_attr=-1, lut_min=0.0, lut_inv=1.0, vel_attr=-1,
-              variant=0, grid_blocks=0, xyz_dev=None, attrs_dev=None):
-    """Clear + render + resolve through the C ABI; returns numpy planes."""
+              variant=0, grid_blocks=0, xyz_dev=None, attrs_dev=None, bounded=False):
+    """Clear + render + resolve through the C ABI; returns numpy planes
+    (and the tile bounds of the bounded render when it is asked for)."""
     n = int(x.shape[0])
     vp, nf, ff = narvis.narvis_camera_matrix(cam, W, H)
     X, Y, Z = xyz_dev if xyz_dev is not None else (dev(x), dev(y), dev(z))
@@ -52,9 +53,12 @@ def gpu_frame(x, y, z, attrs, cam, W, H, lut=None, lut_attr=-1, lut_min=0.0, lut
         g.lut_attr, g.lut_min, g.lut_inv_range = lut_attr, lut_min, lut_inv
     g.vel_attr = vel_attr
     narvis.narvis_raster_clear(g.keys, W, H)
-    narvis.narvis_raster_render((X, Y, Z), n, vp, nf, ff, W, H, g.keys, variant=variant, grid_blocks=grid_blocks)
+    narvis.narvis_raster_render((X, Y, Z), n, vp, nf, ff, W, H, g.keys, variant=variant, grid_blocks=grid_blocks,
+                                bounds=g.bounds if bounded else None)
     narvis.narvis_raster_resolve((X, Y, Z), A, n, vp, W, H, g)
     out = {"keys": host(g.keys).view(np.uint64), "depth": host(g.depth)}
+    if bounded:
+        out["bounds"] = host(g.bounds).view(np.uint16)
     if g.attr is not None:
         out["attrs"] = host(g.attr)
     if g.rgb is not None:
@@ -139,6 +143,64 @@ def test_variants_and_launch_geometry(variant, grid):
     cam = scenes.Camera(eye=(1.8, 1.5, 1.3), target=(0.5, 0.5, 0.5))
     g = gpu_frame(sc.x, sc.y, sc.z, sc.attrs, cam, sc.W, sc.H, variant=variant, grid_blocks=grid)
     o = oracle_frame(sc.x, sc.y, sc.z, sc.attrs, cam, sc.W, sc.H)
+    assert_same(g, o)
+
+
+def expected_bounds(x, y, z, cam, W, H):
+    """Bounds the bounded render must leave behind, from the oracle: the keys
+    of its first level (points of every 8th chunk of 2048, plus the last n % 4
+    points; the others are made NaN so that the indices stay put), then per
+    tile of 2^s x 2^s pixels (smallest s >= 3 with at most 8192 tiles) the
+    largest depth bits over the tile's pixels, and per pixel its depth bits,
+    each shifted down by 16.  Returns (tile bounds, pixel bounds)."""
+    n = len(x)
+    i = np.arange(n)
+    sample = ((i // 2048) % 8 == 0) | (i >= 4 * (n // 4))
+    xs = np.where(sample, x, np.float32(np.nan)).astype(np.float32)
+    M, near, far = ocam.clip_matrix(cam, W, H)
+    keys = orast.render(xs, y, z, M, near, far, W, H)
+    s = 3
+    while -(-W >> s) * -(-H >> s) > 8192:
+        s += 1
+    tx, ty = -(-W >> s), -(-H >> s)
+    depth = np.full((ty << s, tx << s), 0, np.uint64)
+    depth[:H, :W] = (keys >> np.uint64(32)).reshape(H, W)
+    tiles = depth.reshape(ty, 1 << s, tx, 1 << s).max(axis=(1, 3)).reshape(-1)
+    return (tiles >> np.uint64(16)).astype(np.uint16), (keys >> np.uint64(48)).astype(np.uint16)
+
+
+@pytest.mark.parametrize("n,W,H,grid", [(4096, 64, 48, 0), (4099, 97, 61, 0), (65537, 32, 24, 1),
+                                        (300001, 97, 61, 7), (300001, 301, 207, 0),
+                                        (1 << 20, 160, 120, 0), (1 << 20, 1920, 1080, 100)])
+def test_bounded_render(n, W, H, grid):
+    """Bounded two-pass render (sample chunks, tile bounds, the rest culled
+    against them): keys and planes bit-exact, and the bounds exactly those
+    of the oracle's sample pass."""
+    announce(f"bounded render n={n} {W}x{H} grid_blocks={grid}")
+    sc = scenes.unit_cube(n=n, seed=n % 97 + W, W=W, H=H)
+    cam = scenes.Camera(eye=(1.7, 1.5, 1.3), target=(0.5, 0.5, 0.5))
+    kw = scene_args(sc)
+    g = gpu_frame(sc.x, sc.y, sc.z, sc.attrs, cam, W, H, variant=3, grid_blocks=grid, bounded=True, **kw)
+    o = oracle_frame(sc.x, sc.y, sc.z, sc.attrs, cam, W, H, **kw)
+    assert_same(g, o)
+    exp, exp_pix = expected_bounds(sc.x, sc.y, sc.z, cam, W, H)
+    np.testing.assert_array_equal(g["bounds"][:len(exp)], exp)
+    np.testing.assert_array_equal(g["bounds"][8192:8192 + W * H], exp_pix)
+    if n >= 20 * W * H:
+        assert (exp < 0xFFFF).mean() > 0.1  # dense enough that the culling is exercised
+
+
+def test_bounded_render_descending_depth_one_pixel():
+    """Every later point closer than all earlier ones, all in one pixel: the
+    bounds cull nothing that could win."""
+    announce("bounded render, 1M points in one pixel, descending depth")
+    n = 1 << 20
+    cam = scenes.Camera(eye=(0, 0, 0), target=(0, 0, -1), up=(0, 1, 0))
+    z = -np.linspace(5.0, 1.0, n, dtype=np.float32)
+    x = np.full(n, 0.001, np.float32)
+    y = np.full(n, 0.001, np.float32)
+    g = gpu_frame(x, y, z, [], cam, 16, 16, variant=3, bounded=True)
+    o = oracle_frame(x, y, z, [], cam, 16, 16)
     assert_same(g, o)
 
 
