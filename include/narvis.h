@@ -140,11 +140,11 @@ typedef enum {
  *   uint16 tile[NARVIS_TILE_BOUNDS_MAX]: for screen tiles of 2^s x 2^s
  *          pixels (the smallest s >= 3 giving at most NARVIS_TILE_BOUNDS_MAX
  *          tiles, row-major), the largest d(p) >> 16 over the tile,
- *   uint16 pixel[H][W]: d(p) >> 16,
+ *   uint32 pixel[H][W]: d(p)  (from byte 2 NARVIS_TILE_BOUNDS_MAX),
  * and the other chunks are rendered, a point being dropped when
- * (bits(w) >> 16) exceeds the bound of its tile or of its pixel.  Keys only
- * decrease, so the pixel's key is already smaller than such a point's: the
- * result is the single-pass result, bit for bit.  This is the paper's early
+ * (bits(w) >> 16) exceeds the bound of its tile or bits(w) that of its pixel.
+ * Keys only decrease, so the pixel's key is already smaller than such a
+ * point's: the result is the single-pass result, bit for bit.  This is the paper's early
  * z-test (Sec. 3.2), taken against a compact copy of the depth buffer. */
 typedef struct {
     int32_t variant;      /* narvis_render_variant                           */
@@ -187,7 +187,7 @@ narvis_status narvis_camera_matrix(const narvis_camera *cam, int32_t W, int32_t 
                                    float vp_rowmajor[16], float *near_f, float *far_f);
 
 /* Bytes of the bounded render's scratch for a W x H image:
- * 2 (NARVIS_TILE_BOUNDS_MAX + W H); 0 for invalid W, H. */
+ * 2 NARVIS_TILE_BOUNDS_MAX + 4 W H; 0 for invalid W, H. */
 size_t narvis_raster_bounds_bytes(int32_t W, int32_t H);
 
 /* Fill keys[W*H] with NARVIS_KEY_EMPTY. */

@@ -122,7 +122,7 @@ extern "C" narvis_status narvis_raster_clear(uint64_t *keys, int32_t W, int32_t 
 extern "C" size_t narvis_raster_bounds_bytes(int32_t W, int32_t H)
 {
     if (!image_ok(W, H)) return 0;
-    return 2 * ((size_t)NARVIS_TILE_BOUNDS_MAX + (size_t)W * (size_t)H);
+    return 2 * (size_t)NARVIS_TILE_BOUNDS_MAX + 4 * (size_t)W * (size_t)H;
 }
 
 extern "C" narvis_status narvis_raster_render(const narvis_points *pts, uint64_t n, const float vp[16],

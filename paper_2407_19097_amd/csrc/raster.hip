@@ -285,13 +285,12 @@ __device__ __forceinline__ uint64_t real_chunk(const ChunkSel &c, uint64_t v)
 
 // Screen tiles of 2^shift x 2^shift pixels, tiles_x per row, one depth bound
 // per tile (the high 16 bits of the largest depth bits held by a pixel of the
-// tile) and one per pixel (the high 16 bits of its depth bits), both taken by
-// k_tile_bounds.
+// tile) and one per pixel (its depth bits), both taken by k_tile_bounds.
 constexpr int kMaxTiles = 8192;
 
 struct TileGrid {
     const uint16_t *bounds;
-    const uint16_t *pixb;
+    const uint32_t *pixb;
     uint32_t shift, tiles_x, ntiles;
 };
 
@@ -386,13 +385,6 @@ __global__ __launch_bounds__(kBlock, 4) void k_render_lds(const float *__restric
     render_tail(X, Y, Z, n, P, keys, sel);
 }
 
-// Bounded render of the chunks `sel` picks, after some chunks have been
-// rendered and k_tile_bounds has taken the bounds.  Keys only decrease, so a
-// point deeper than its bound cannot win its pixel: each point is tested
-// against its tile's bound (LDS), the survivors against their pixel's bound
-// (a 16-bit global read, two bytes per pixel, mostly cache-resident), and
-// what is left goes to the atomic minimum.  No LDS table and no barrier in
-// the loop: the waves stream independently.
 // Key address with a 32-bit byte offset when the image has fewer than 2^29
 // pixels (the load and atomic then take a scalar base and one offset register).
 template <bool OFF32>
@@ -402,12 +394,20 @@ __device__ __forceinline__ unsigned long long *key_at(unsigned long long *keys, 
     return keys + pix;
 }
 
-// quads per thread and workgroup size: one chunk of kChunk points per
-// workgroup iteration
+// quads per thread and workgroup size of the cull pass: one chunk of kChunk
+// points per workgroup iteration
 constexpr int kCullQpt = 2;
 constexpr int kCullBlock = kChunk / 4 / kCullQpt;
 constexpr int kCullPts = 4 * kCullQpt;
 
+// Bounded render of the chunks `sel` picks, after some chunks have been
+// rendered and k_tile_bounds has taken the bounds.  Keys only decrease, so a
+// point deeper than its bound cannot win its pixel: each point is tested
+// against its tile's bound (LDS), the survivors against their pixel's bound
+// (a 32-bit global read; the 16 high bits would pass every point of a
+// surface, whose depths at one pixel agree to a few ulps), and what is left
+// goes to the atomic minimum.  No LDS table and no barrier in the loop: the
+// waves stream independently.
 template <bool RCP, bool OFF32>
 __global__ __launch_bounds__(kCullBlock) void k_render_cull(const float *__restrict__ X, const float *__restrict__ Y,
                                                         const float *__restrict__ Z, uint64_t n, Proj P,
@@ -456,6 +456,16 @@ __global__ __launch_bounds__(kCullBlock) void k_render_cull(const float *__restr
                 pix[t] = __umul24(iy, (uint32_t)P.W) + ix;
                 key[t] = ((unsigned long long)__float_as_uint(w) << 32) | (first + lq * 4 + (uint32_t)j);
             }
+            // consecutive points on one pixel (a surface sampled finer than
+            // the pixels): the last of a run carries the run's smallest key
+#pragma unroll
+            for (int j = 1; j < 4; ++j) {
+                const int t = k * 4 + j;
+                if (hit[t - 1] && hit[t] && pix[t - 1] == pix[t]) {
+                    key[t] = key[t - 1] < key[t] ? key[t - 1] : key[t];
+                    hit[t - 1] = false;
+                }
+            }
         }
         // pixel bounds of the survivors (a read no lane of the wave needs is
         // skipped; a lane without a survivor reads the wave's shared pixel so
@@ -471,7 +481,7 @@ __global__ __launch_bounds__(kCullBlock) void k_render_cull(const float *__restr
         for (int t = 0; t < kCullPts; ++t)
             if (any[t]) pb[t] = tg.pixb[hit[t] ? pix[t] : spread];
 #pragma unroll
-        for (int t = 0; t < kCullPts; ++t) hit[t] = hit[t] && (uint32_t)(key[t] >> 48) <= pb[t];
+        for (int t = 0; t < kCullPts; ++t) hit[t] = hit[t] && (uint32_t)(key[t] >> 32) <= pb[t];
 #pragma unroll
         for (int t = 0; t < kCullPts; ++t)
             if (hit[t])
@@ -480,14 +490,14 @@ __global__ __launch_bounds__(kCullBlock) void k_render_cull(const float *__restr
     render_tail(X, Y, Z, n, P, keys, sel);
 }
 
-// Depth bounds after the first levels: per pixel the high 16 bits of its
-// depth bits, per screen tile the largest of those over the tile's pixels (an
-// empty pixel counts as depth bits 0xFFFFFFFF, bound 0xFFFF, which culls
-// nothing).  A point with (bits(w) >> 16) > bound has bits(w) > the depth
-// bits of the pixel (every pixel of the tile).  One workgroup per tile.
+// Depth bounds after the first levels: per pixel its depth bits, per screen
+// tile the high 16 bits of the largest of those over the tile's pixels (an
+// empty pixel counts as depth bits 0xFFFFFFFF, tile bound 0xFFFF, which culls
+// nothing).  A point with bits(w) > the pixel bound, or (bits(w) >> 16) > the
+// tile bound, is deeper than the key of its pixel.  One workgroup per tile.
 __global__ __launch_bounds__(kBlock) void k_tile_bounds(const unsigned long long *__restrict__ keys, int32_t W,
                                                         int32_t H, uint32_t shift, uint32_t tiles_x,
-                                                        uint16_t *__restrict__ bounds, uint16_t *__restrict__ pixb)
+                                                        uint16_t *__restrict__ bounds, uint32_t *__restrict__ pixb)
 {
     __shared__ uint32_t red[kBlock / 64];
     const uint32_t t = blockIdx.x;
@@ -499,7 +509,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_bounds(const unsigned long long
         if (x < (uint32_t)W && y < (uint32_t)H) {
             const size_t p = (size_t)y * (uint32_t)W + x;
             const uint32_t d = (uint32_t)(keys[p] >> 32);
-            pixb[p] = (uint16_t)(d >> 16);
+            pixb[p] = d;
             m = max(m, d);
         }
     }
@@ -730,7 +740,8 @@ hipError_t launch_render(const float *x, const float *y, const float *z, uint64_
         };
         // bounded render for at least two chunks (24-bit pixel arithmetic)
         if (bounds && n >= 4096 && P.W < (1 << 24) && P.H < (1 << 24)) {
-            TileGrid tg{bounds, bounds + kMaxTiles, 3u, 0u, 0u};
+            uint32_t *pixb = reinterpret_cast<uint32_t *>(bounds + kMaxTiles);
+            TileGrid tg{bounds, pixb, 3u, 0u, 0u};
             while (true) {
                 tg.tiles_x = ((uint32_t)P.W + (1u << tg.shift) - 1) >> tg.shift;
                 tg.ntiles = tg.tiles_x * (((uint32_t)P.H + (1u << tg.shift) - 1) >> tg.shift);
@@ -748,7 +759,7 @@ hipError_t launch_render(const float *x, const float *y, const float *z, uint64_
                     lds(sel, grid_of(sel.nv));
                 } else {
                     hipLaunchKernelGGL(k_tile_bounds, dim3(tg.ntiles), dim3(kBlock), 0, s, k, P.W, P.H, tg.shift,
-                                       tg.tiles_x, bounds, bounds + kMaxTiles);
+                                       tg.tiles_x, bounds, pixb);
                     if (sel.nv == 0) continue;
                     // a resident grid: each workgroup loads the bounds once
                     const uint64_t resident = (uint64_t)dev.cus * (2048 / kCullBlock);

@@ -132,10 +132,10 @@ def test_invalid_arguments_rejected_before_any_launch():
 
 
 def test_raster_bounds_bytes():
-    """Scratch of the bounded render: 8192 tile bounds and one per pixel, 16 bits each."""
+    """Scratch of the bounded render: 8192 16-bit tile bounds, one 32-bit bound per pixel."""
     L = _lib.load()
-    assert L.narvis_raster_bounds_bytes(1920, 1080) == 2 * (8192 + 1920 * 1080)
-    assert L.narvis_raster_bounds_bytes(1, 1) == 2 * 8193
+    assert L.narvis_raster_bounds_bytes(1920, 1080) == 2 * 8192 + 4 * 1920 * 1080
+    assert L.narvis_raster_bounds_bytes(1, 1) == 2 * 8192 + 4
     assert L.narvis_raster_bounds_bytes(0, 8) == 0
     assert L.narvis_raster_bounds_bytes(1 << 16, 1 << 16) == 0
 

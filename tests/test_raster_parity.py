@@ -151,8 +151,8 @@ def expected_bounds(x, y, z, cam, W, H):
     of its first level (points of every 8th chunk of 2048, plus the last n % 4
     points; the others are made NaN so that the indices stay put), then per
     tile of 2^s x 2^s pixels (smallest s >= 3 with at most 8192 tiles) the
-    largest depth bits over the tile's pixels, and per pixel its depth bits,
-    each shifted down by 16.  Returns (tile bounds, pixel bounds)."""
+    largest depth bits over the tile's pixels shifted down by 16, and per
+    pixel its depth bits.  Returns (tile bounds, pixel bounds)."""
     n = len(x)
     i = np.arange(n)
     sample = ((i // 2048) % 8 == 0) | (i >= 4 * (n // 4))
@@ -166,7 +166,7 @@ def expected_bounds(x, y, z, cam, W, H):
     depth = np.full((ty << s, tx << s), 0, np.uint64)
     depth[:H, :W] = (keys >> np.uint64(32)).reshape(H, W)
     tiles = depth.reshape(ty, 1 << s, tx, 1 << s).max(axis=(1, 3)).reshape(-1)
-    return (tiles >> np.uint64(16)).astype(np.uint16), (keys >> np.uint64(48)).astype(np.uint16)
+    return (tiles >> np.uint64(16)).astype(np.uint16), (keys >> np.uint64(32)).astype(np.uint32)
 
 
 @pytest.mark.parametrize("n,W,H,grid", [(4096, 64, 48, 0), (4099, 97, 61, 0), (65537, 32, 24, 1),
@@ -185,7 +185,7 @@ def test_bounded_render(n, W, H, grid):
     assert_same(g, o)
     exp, exp_pix = expected_bounds(sc.x, sc.y, sc.z, cam, W, H)
     np.testing.assert_array_equal(g["bounds"][:len(exp)], exp)
-    np.testing.assert_array_equal(g["bounds"][8192:8192 + W * H], exp_pix)
+    np.testing.assert_array_equal(g["bounds"][8192:].view(np.uint32)[:W * H], exp_pix)
     if n >= 20 * W * H:
         assert (exp < 0xFFFF).mean() > 0.1  # dense enough that the culling is exercised
 
