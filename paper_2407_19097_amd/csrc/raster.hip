@@ -422,19 +422,24 @@ __global__ __launch_bounds__(kCullBlock) void k_render_cull(const float *__restr
     const uint32_t npx = (uint32_t)P.W * (uint32_t)P.H;
     const uint32_t spread = (uint32_t)((lb * 2654435761ull) % (uint64_t)npx);
     __syncthreads();
+    f32x4 xs[kCullQpt], ys[kCullQpt], zs[kCullQpt];
+    // every quad index is clamped into the array so that each fetch issues
+    // the same six loads (the extra quads are not live)
+    auto fetch = [&](uint64_t v) {
+        const uint64_t st = real_chunk(sel, v) * kQuads;
+#pragma unroll
+        for (int k = 0; k < kCullQpt; ++k) {
+            uint64_t q = st + threadIdx.x + (uint64_t)k * kCullBlock;
+            q = q < nq ? q : nq - 1;
+            xs[k] = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(X) + q);
+            ys[k] = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(Y) + q);
+            zs[k] = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(Z) + q);
+        }
+    };
+    if (lb < sel.nv && nq > 0) fetch(lb);
     for (uint64_t v = lb; v < sel.nv; v += gridDim.x) {
         const uint64_t start = real_chunk(sel, v) * kQuads;
         const uint32_t first = (uint32_t)(start << 2);
-        f32x4 xs[kCullQpt], ys[kCullQpt], zs[kCullQpt];
-#pragma unroll
-        for (int k = 0; k < kCullQpt; ++k) {
-            const uint64_t q = start + threadIdx.x + (uint64_t)k * kCullBlock;
-            if (q < nq) {
-                xs[k] = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(X) + q);
-                ys[k] = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(Y) + q);
-                zs[k] = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(Z) + q);
-            }
-        }
         uint32_t pix[kCullPts];
         unsigned long long key[kCullPts];
         bool hit[kCullPts];
@@ -467,19 +472,15 @@ __global__ __launch_bounds__(kCullBlock) void k_render_cull(const float *__restr
                 }
             }
         }
-        // pixel bounds of the survivors (a read no lane of the wave needs is
-        // skipped; a lane without a survivor reads the wave's shared pixel so
-        // that its request merges), then the atomics
-        bool any[kCullPts];
+        // pixel bounds of the survivors (a lane without a survivor reads the
+        // wave's shared pixel, so its request merges), then the atomics
         uint32_t pb[kCullPts];
 #pragma unroll
-        for (int t = 0; t < kCullPts; ++t) {
-            any[t] = __ballot(hit[t]) != 0;
-            pb[t] = 0;
-        }
-#pragma unroll
-        for (int t = 0; t < kCullPts; ++t)
-            if (any[t]) pb[t] = tg.pixb[hit[t] ? pix[t] : spread];
+        for (int t = 0; t < kCullPts; ++t) pb[t] = tg.pixb[hit[t] ? pix[t] : spread];
+        // the next chunk's points are loaded while the bounds come back (both
+        // load sequences have a fixed length, so the wait for the bounds
+        // leaves the six point loads in flight)
+        fetch(v + gridDim.x < sel.nv ? v + gridDim.x : v);
 #pragma unroll
         for (int t = 0; t < kCullPts; ++t) hit[t] = hit[t] && (uint32_t)(key[t] >> 32) <= pb[t];
 #pragma unroll
