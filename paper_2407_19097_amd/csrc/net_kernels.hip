@@ -1004,31 +1004,26 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a)
 #pragma unroll
         for (int f = 0; f < 4; ++f) acc[i][f] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     float bsum = 0.0f;
-    for (int64_t pc = pbeg; pc < pend; pc += kWgPix) {
+    // the chunk's loads land in registers (dy, its mask and the im2col
+    // columns) and go to LDS at the top of the next iteration, so the loads of
+    // chunk c + 1 are in flight during the MFMAs of chunk c
+    bf16x8 dv[4], dm[4], xv[XG][4];
+    auto gload = [&](int64_t pc) {
         if (threadIdx.x < 2 * TCO) {
             const int c = co0 + cg * 8;
-            bf16x8 v[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int64_t p = pc + 4 * qd + e;
-                v[e] = zero8();
+                dv[e] = zero8();
+                dm[e] = zero8();
                 if (p < pend && c < a.Cout) {
-                    v[e] = load8(a.dy + p * a.dy_stride + a.dy_off + c);
-                    if (a.mask) {
-                        const bf16x8 m = load8(a.mask + p * a.mask_stride + a.mask_off + c);
-#pragma unroll
-                        for (int j = 0; j < 8; ++j)
-                            if (!((float)m[j] > 0.0f)) v[e][j] = (__bf16)0.0f;
-                    }
+                    dv[e] = load8(a.dy + p * a.dy_stride + a.dy_off + c);
+                    if (a.mask) dm[e] = load8(a.mask + p * a.mask_stride + a.mask_off + c);
                 }
             }
-#pragma unroll
-            for (int j = 0; j < 8; ++j)
-                *reinterpret_cast<bf16x4 *>(&sdy[wg_at(cg * 8 + j, qd)]) = bf16x4{v[0][j], v[1][j], v[2][j], v[3][j]};
         }
 #pragma unroll
         for (int h = 0; h < XG; ++h) {
-            bf16x8 v[4];
             const int64_t p0 = pc + 4 * qx;
             int b = (int)(p0 / hw);
             const int rem = (int)(p0 - (int64_t)b * hw);
@@ -1036,10 +1031,10 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a)
             int x = rem - y * a.W;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                v[e] = zero8();
+                xv[h][e] = zero8();
                 const int y2 = y + ty[h], x2 = x + tx[h];
                 if (kin[h] && p0 + e < pend && y2 >= 0 && y2 < a.H && x2 >= 0 && x2 < a.W)
-                    v[e] = load8(xsrc[h] + (((int64_t)b * a.H + y2) * a.W + x2) * xstride[h]);
+                    xv[h][e] = load8(xsrc[h] + (((int64_t)b * a.H + y2) * a.W + x2) * xstride[h]);
                 if (++x == a.W) {  // next pixel (W >= 8, so at most one wrap in a quad)
                     x = 0;
                     if (++y == a.H) {
@@ -1048,12 +1043,34 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a)
                     }
                 }
             }
+        }
+    };
+    auto lstore = [&]() {
+        if (threadIdx.x < 2 * TCO) {
+            if (a.mask) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+#pragma unroll
+                    for (int j = 0; j < 8; ++j)
+                        if (!((float)dm[e][j] > 0.0f)) dv[e][j] = (__bf16)0.0f;
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                *reinterpret_cast<bf16x4 *>(&sdy[wg_at(cg * 8 + j, qd)]) =
+                    bf16x4{dv[0][j], dv[1][j], dv[2][j], dv[3][j]};
+        }
+#pragma unroll
+        for (int h = 0; h < XG; ++h)
 #pragma unroll
             for (int j = 0; j < 8; ++j)
                 *reinterpret_cast<bf16x4 *>(&sx[wg_at(kg[h] * 8 + j, qx)]) =
-                    bf16x4{v[0][j], v[1][j], v[2][j], v[3][j]};
-        }
+                    bf16x4{xv[h][0][j], xv[h][1][j], xv[h][2][j], xv[h][3][j]};
+    };
+    if (pbeg < pend) gload(pbeg);
+    for (int64_t pc = pbeg; pc < pend; pc += kWgPix) {
+        lstore();
         __syncthreads();
+        if (pc + kWgPix < pend) gload(pc + kWgPix);
 #pragma unroll
         for (int st = 0; st < kWgPix / 32; ++st) {
             // fragment lane (g, r): row r of the fragment, pixels 32 st + 8 g .. + 7
