@@ -107,16 +107,18 @@ def test_unit_cube_full_parity():
     assert_same(g, o)
 
 
+@pytest.mark.parametrize("bounded", [False, True])
 @pytest.mark.parametrize("znear", [1e-39, 0.1])
-def test_both_division_paths(znear):
+def test_both_division_paths(znear, bounded):
     """The render divides by the depth through a correctly rounded reciprocal
     when the fp32 cull range lies in [2^-124, 2^125) (znear 0.1), by IEEE
-    division otherwise (a denormal znear): both bit-exact."""
-    announce(f"unit cube 200003 points 301x207, LDS render, znear={znear}")
+    division otherwise (a denormal znear): both bit-exact, single-pass and
+    bounded."""
+    announce(f"unit cube 200003 points 301x207, LDS render, znear={znear}, bounded={bounded}")
     sc = scenes.unit_cube(n=200003, seed=5, W=301, H=207)
     cam = scenes.Camera(eye=(1.7, 1.5, 1.3), target=(0.5, 0.5, 0.5), znear=znear)
     kw = scene_args(sc)
-    g = gpu_frame(sc.x, sc.y, sc.z, sc.attrs, cam, sc.W, sc.H, variant=3, **kw)
+    g = gpu_frame(sc.x, sc.y, sc.z, sc.attrs, cam, sc.W, sc.H, variant=3, bounded=bounded, **kw)
     o = oracle_frame(sc.x, sc.y, sc.z, sc.attrs, cam, sc.W, sc.H, **kw)
     assert (o["keys"] != EMPTY).mean() > 0.1
     assert_same(g, o)
@@ -188,6 +190,37 @@ def test_bounded_render(n, W, H, grid):
     np.testing.assert_array_equal(g["bounds"][8192:].view(np.uint32)[:W * H], exp_pix)
     if n >= 20 * W * H:
         assert (exp < 0xFFFF).mean() > 0.1  # dense enough that the culling is exercised
+
+
+def test_bounded_render_merges_into_existing_keys():
+    """Keys are merged into what the buffer holds: the bounded render of all
+    the points onto a buffer that already holds the first half's keys (its
+    bounds then start from those keys) gives the keys of all the points."""
+    announce("bounded render onto the first half's keys, 1M points 160x120")
+    n, W, H = 1 << 20, 160, 120
+    sc = scenes.unit_cube(n=n, seed=31, W=W, H=H)
+    cam = scenes.Camera(eye=(1.7, 1.5, 1.3), target=(0.5, 0.5, 0.5))
+    vp, nf, ff = narvis.narvis_camera_matrix(cam, W, H)
+    X, Y, Z = dev(sc.x), dev(sc.y), dev(sc.z)
+    keys = torch.empty(W * H, dtype=torch.int64, device="cuda")
+    bounds = narvis.raster_bounds(W, H)
+    h = n // 2
+    narvis.narvis_raster_clear(keys, W, H)
+    narvis.narvis_raster_render((X[:h], Y[:h], Z[:h]), h, vp, nf, ff, W, H, keys, variant=3, bounds=bounds)
+    part = host(keys).view(np.uint64).copy()
+    narvis.narvis_raster_clear(keys, W, H)
+    narvis.narvis_raster_render((X, Y, Z), n, vp, nf, ff, W, H, keys, variant=3, bounds=bounds)
+    full = host(keys).view(np.uint64).copy()
+    # onto the first half's keys
+    keys.copy_(torch.from_numpy(part.view(np.int64)).cuda())
+    narvis.narvis_raster_render((X, Y, Z), n, vp, nf, ff, W, H, keys, variant=3, bounds=bounds)
+    merged = host(keys).view(np.uint64)
+    M, near, far = ocam.clip_matrix(cam, W, H)
+    okeys = orast.render(sc.x, sc.y, sc.z, M, near, far, W, H)
+    np.testing.assert_array_equal(full, okeys)
+    np.testing.assert_array_equal(merged, okeys)
+    ohalf = orast.render(sc.x[:h], sc.y[:h], sc.z[:h], M, near, far, W, H)
+    np.testing.assert_array_equal(part, ohalf)
 
 
 def test_bounded_render_descending_depth_one_pixel():
