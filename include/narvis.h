@@ -102,7 +102,7 @@ typedef struct {
  *                         |v'|; 0 for an empty pixel.
  *   lut    float[256][3] device table for rgb.
  *   bounds  optional device scratch of bounds_bytes >=
- *           narvis_raster_bounds_bytes(W, H) bytes (2-byte aligned, contents
+ *           narvis_raster_bounds_bytes(W, H) bytes (4-byte aligned, contents
  *           overwritten): when given, narvis_rasterize renders in the bounded
  *           mode (see narvis_raster_opts); NULL renders in one pass.  The
  *           keys are the same either way. */
@@ -151,7 +151,7 @@ typedef struct {
     int32_t grid_blocks;  /* 0 = automatic, otherwise the number of
                              workgroups (a grid-stride loop covers all points) */
     void *bounds;         /* NULL, or device scratch of bounds_bytes >=
-                             narvis_raster_bounds_bytes(W, H) bytes (2-byte
+                             narvis_raster_bounds_bytes(W, H) bytes (4-byte
                              aligned, contents overwritten): bounded render */
     size_t bounds_bytes;
 } narvis_raster_opts;

@@ -136,7 +136,7 @@ extern "C" narvis_status narvis_raster_render(const narvis_points *pts, uint64_t
     int32_t grid = opts ? opts->grid_blocks : 0;
     void *bounds = opts ? opts->bounds : nullptr;
     if (variant < NARVIS_RENDER_AUTO || variant > NARVIS_RENDER_LDS || grid < 0) return NARVIS_ERR_INVALID_ARG;
-    if (reinterpret_cast<uintptr_t>(bounds) & 1u) return NARVIS_ERR_INVALID_ARG;
+    if (reinterpret_cast<uintptr_t>(bounds) & 3u) return NARVIS_ERR_INVALID_ARG;
     if (bounds && opts->bounds_bytes < narvis_raster_bounds_bytes(W, H)) return NARVIS_ERR_WORKSPACE;
     if (n > 0 && ((reinterpret_cast<uintptr_t>(pts->x) | reinterpret_cast<uintptr_t>(pts->y) |
                    reinterpret_cast<uintptr_t>(pts->z)) & 3u))
@@ -189,7 +189,7 @@ extern "C" narvis_status narvis_rasterize(const narvis_points *pts, const narvis
     if (n > 0 && ((reinterpret_cast<uintptr_t>(pts->x) | reinterpret_cast<uintptr_t>(pts->y) |
                    reinterpret_cast<uintptr_t>(pts->z)) & 3u))
         return NARVIS_ERR_INVALID_ARG;
-    if ((reinterpret_cast<uintptr_t>(gbuf->keys) & 7u) || (reinterpret_cast<uintptr_t>(gbuf->bounds) & 1u))
+    if ((reinterpret_cast<uintptr_t>(gbuf->keys) & 7u) || (reinterpret_cast<uintptr_t>(gbuf->bounds) & 3u))
         return NARVIS_ERR_INVALID_ARG;
     if (gbuf->bounds && gbuf->bounds_bytes < narvis_raster_bounds_bytes(W, H)) return NARVIS_ERR_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);

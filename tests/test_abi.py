@@ -100,8 +100,10 @@ def test_invalid_arguments_rejected_before_any_launch():
     assert L.narvis_raster_render(ctypes.byref(pts), 10, vp, 0.1, 10.0, 8, 8, fake, ctypes.byref(bad_opts),
                                   None) == -1
     # bounded render: misaligned or undersized scratch
-    odd = _lib.RasterOpts(3, 0, fake + 1, 1 << 20)
-    assert L.narvis_raster_render(ctypes.byref(pts), 10, vp, 0.1, 10.0, 8, 8, fake, ctypes.byref(odd), None) == -1
+    for off in (1, 2):  # the pixel bounds are 32-bit words
+        odd = _lib.RasterOpts(3, 0, fake + off, 1 << 20)
+        assert L.narvis_raster_render(ctypes.byref(pts), 10, vp, 0.1, 10.0, 8, 8, fake, ctypes.byref(odd),
+                                      None) == -1
     small = _lib.RasterOpts(3, 0, fake, L.narvis_raster_bounds_bytes(8, 8) - 2)
     assert L.narvis_raster_render(ctypes.byref(pts), 10, vp, 0.1, 10.0, 8, 8, fake, ctypes.byref(small),
                                   None) == -5
