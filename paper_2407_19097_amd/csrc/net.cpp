@@ -240,6 +240,15 @@ ConvArgs with_skip(ConvArgs a, const __bf16 *skip, int skip_stride, int cin1)
     return a;
 }
 
+// The layer also writes the 2x2 average pool of its output (stride = Cout).
+ConvArgs with_pool(ConvArgs a, __bf16 *pooled)
+{
+    a.pool_out = pooled;
+    a.pool_stride = a.Cout;
+    a.pool_off = 0;
+    return a;
+}
+
 SliceArgs slice(const __bf16 *in, int is, int io, __bf16 *out, int os, int oo, int C, int B, int H, int W)
 {
     SliceArgs s{};
@@ -283,14 +292,16 @@ hipError_t forward(const narvis_weights *w, const float *feat_planes, char *ws, 
     const LayerBuf *L = w->L;
     TRY(features(feat_planes, c.b(p.feat), B, H, W, s));
     TRY(run_conv(w, E1A, conv_args(L[E1A], c.b(p.feat), 8, 0, c.b(p.e1a), 32, 0, B, H, W), fp8, s));
-    TRY(run_conv(w, E1B, conv_args(L[E1B], c.b(p.e1a), 32, 0, c.b(p.sk1), 32, 0, B, H, W), fp8, s));
-    TRY(pool2(slice(c.b(p.sk1), 32, 0, c.b(p.pool1), 32, 0, 32, B, H, W), s));
+    // the second layer of each encoder level also writes the pooled input of
+    // the next level
+    TRY(run_conv(w, E1B, with_pool(conv_args(L[E1B], c.b(p.e1a), 32, 0, c.b(p.sk1), 32, 0, B, H, W), c.b(p.pool1)),
+                 fp8, s));
     TRY(run_conv(w, E2A, conv_args(L[E2A], c.b(p.pool1), 32, 0, c.b(p.e2a), 64, 0, B, H1, W1), fp8, s));
-    TRY(run_conv(w, E2B, conv_args(L[E2B], c.b(p.e2a), 64, 0, c.b(p.sk2), 64, 0, B, H1, W1), fp8, s));
-    TRY(pool2(slice(c.b(p.sk2), 64, 0, c.b(p.pool2), 64, 0, 64, B, H1, W1), s));
+    TRY(run_conv(w, E2B, with_pool(conv_args(L[E2B], c.b(p.e2a), 64, 0, c.b(p.sk2), 64, 0, B, H1, W1), c.b(p.pool2)),
+                 fp8, s));
     TRY(run_conv(w, E3A, conv_args(L[E3A], c.b(p.pool2), 64, 0, c.b(p.e3a), 128, 0, B, H2, W2), fp8, s));
-    TRY(run_conv(w, E3B, conv_args(L[E3B], c.b(p.e3a), 128, 0, c.b(p.sk3), 128, 0, B, H2, W2), fp8, s));
-    TRY(pool2(slice(c.b(p.sk3), 128, 0, c.b(p.pool3), 128, 0, 128, B, H2, W2), s));
+    TRY(run_conv(w, E3B,
+                 with_pool(conv_args(L[E3B], c.b(p.e3a), 128, 0, c.b(p.sk3), 128, 0, B, H2, W2), c.b(p.pool3)), fp8, s));
     TRY(run_conv(w, E4A, conv_args(L[E4A], c.b(p.pool3), 128, 0, c.b(p.e4a), 256, 0, B, H3, W3), fp8, s));
     TRY(run_conv(w, E4B, conv_args(L[E4B], c.b(p.e4a), 256, 0, c.b(p.e4b), 256, 0, B, H3, W3), fp8, s));
     // A decoder layer's input is [2x upsample of the layer below | skip].  In

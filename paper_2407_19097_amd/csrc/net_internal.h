@@ -37,6 +37,10 @@ struct ConvArgs {
     int head_kpad;
     const float *head_b;
     float *head_out;
+    // optional fused 2x2 average pooling of the (bf16-rounded) output, NHWC
+    // slice at H/2 x W/2 (halo kernel, H and W even)
+    __bf16 *pool_out;
+    int pool_stride, pool_off;         // multiples of 4
 };
 
 // Pooling / upsampling / gradient-sum kernels over channel slices (C multiple of 8).
@@ -73,7 +77,6 @@ hipError_t quant_weights(const float *master, int Cout, int Cin, int KS, int row
                          hipStream_t s);
 hipError_t absmax_bf16(const __bf16 *x, int64_t n, unsigned int *out, hipStream_t s);
 hipError_t features(const float *in, __bf16 *out, int B, int H, int W, hipStream_t s);
-hipError_t pool2(const SliceArgs &a, hipStream_t s);
 hipError_t upsample2(const SliceArgs &a, hipStream_t s);
 hipError_t upsample2_bwd(const SliceArgs &a, hipStream_t s);
 hipError_t pool2_bwd_add(const SliceArgs &a, hipStream_t s);

@@ -463,6 +463,8 @@ __global__ __launch_bounds__(64 * ROWS * CO / 32, 4) void k_conv_halo(ConvArgs a
                                                                       float sa)
 {
     static_assert(!FP8 || (!MASK && !HEAD), "FP8 runs inference layers without the fused head");
+    static_assert(ROWS % 2 == 0 && (CO / 32) * (ROWS / 2) * 8 * 64 * 8 <= 9 * CO * 32 * (FP8 ? 1 : 2),
+                  "room in the weights' LDS for the pooled rows");
     typedef ConvOps<FP8> Ops;
     // LDS holds bf16, or e4m3 for FP8 (activations converted on the way in)
     constexpr int EB = FP8 ? 1 : 2;
@@ -671,7 +673,16 @@ __global__ __launch_bounds__(64 * ROWS * CO / 32, 4) void k_conv_halo(ConvArgs a
         }
         return;
     }
-    if (y >= a.H) return;
+    // Fused 2x2 average pooling (pool_out): the odd row of each pair leaves
+    // its rounded outputs in the weights' LDS, the even row adds them to its
+    // own and its right neighbour's in the standalone kernel's order.  Every
+    // wave reaches both barriers (the pooling flag is uniform).
+    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+    const bool pool = a.pool_out != nullptr;
+    bf16x4 *const pl = reinterpret_cast<bf16x4 *>(ws);  // [(wch, row pair, i, f)][lane]
+    const int pslot = (wch * (ROWS / 2) + (wrow >> 1)) * 8;
+    if (pool) __syncthreads();  // every wave is done with the tiles
+    bf16x4 own[2][4];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
         const int cb = co0 + 32 * wch + 16 * i + 4 * g;
@@ -684,17 +695,49 @@ __global__ __launch_bounds__(64 * ROWS * CO / 32, 4) void k_conv_halo(ConvArgs a
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
             const int x = x0 + 16 * f + r;
-            if (x >= a.W || cb >= a.Cout) continue;
-            const int64_t p = ((int64_t)b * a.H + y) * a.W + x;
-            typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-            bf16x4 w4;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 float t = FP8 ? acc[i][f][e] * scale[e] + bias[e] : acc[i][f][e] + bias[e];
                 if (a.relu) t = fmaxf(t, 0.0f);
-                w4[e] = (__bf16)t;
+                own[i][f][e] = (__bf16)t;
             }
-            *reinterpret_cast<bf16x4 *>(a.out + p * a.out_stride + a.out_off + cb) = w4;
+            if (pool && (wrow & 1)) pl[(pslot + 4 * i + f) * 64 + lane] = own[i][f];
+            if (y >= a.H || x >= a.W || cb >= a.Cout) continue;
+            const int64_t p = ((int64_t)b * a.H + y) * a.W + x;
+            *reinterpret_cast<bf16x4 *>(a.out + p * a.out_stride + a.out_off + cb) = own[i][f];
+        }
+    }
+    if (!pool) return;
+    __syncthreads();
+    if (wrow & 1) return;
+    const int Wo = a.W / 2;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int cb = co0 + 32 * wch + 16 * i + 4 * g;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            // the right neighbour's output (lane r ^ 1), as two 32-bit words
+            typedef int int2v __attribute__((ext_vector_type(2)));
+            int2v mine = __builtin_bit_cast(int2v, own[i][f]), theirs;
+            theirs[0] = __shfl_xor(mine[0], 1);
+            theirs[1] = __shfl_xor(mine[1], 1);
+            const bf16x4 right = __builtin_bit_cast(bf16x4, theirs);
+            const int x = x0 + 16 * f + r;
+            if ((r & 1) || y >= a.H || x >= a.W || cb >= a.Cout) continue;
+            const bf16x4 below = pl[(pslot + 4 * i + f) * 64 + lane];
+            const bf16x4 below_right = pl[(pslot + 4 * i + f) * 64 + lane + 1];
+            bf16x4 o;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                float t = 0.0f;
+                t = t + (float)own[i][f][e];
+                t = t + (float)right[e];
+                t = t + (float)below[e];
+                t = t + (float)below_right[e];
+                o[e] = (__bf16)(t * 0.25f);
+            }
+            const int64_t q = ((int64_t)b * (a.H / 2) + y / 2) * Wo + x / 2;
+            *reinterpret_cast<bf16x4 *>(a.pool_out + q * a.pool_stride + a.pool_off + cb) = o;
         }
     }
 }
@@ -805,34 +848,11 @@ __global__ __launch_bounds__(256) void k_features(const float *in, __bf16 *out, 
     *reinterpret_cast<bf16x8 *>(out + p * 8) = v;
 }
 
-// Pooling and upsampling: blockIdx.y walks output rows (b, y) (uniform, so
-// the row arithmetic is scalar), x and the 8-channel group come from the
-// thread index within the row.
-
-// 2x2 average pooling: one thread per (output pixel, group of 8 channels)
-__global__ __launch_bounds__(256) void k_pool2(SliceArgs s)
-{
-    const int groups = s.C / 8;
-    const int Wo = s.W / 2;
-    const int t = blockIdx.x * 256 + threadIdx.x;
-    if (t >= Wo * groups) return;
-    const int x = t / groups, c8 = t - x * groups;
-    const int64_t rows = (int64_t)s.B * (s.H / 2);
-    for (int64_t ro = blockIdx.y; ro < rows; ro += gridDim.y) {
-        float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
-        for (int d = 0; d < 4; ++d) {
-            const int64_t q = (2 * ro + (d >> 1)) * s.W + 2 * x + (d & 1);  // input row 2 ro + dy of the same image
-            const bf16x8 v = load8(s.in + q * s.in_stride + s.in_off + c8 * 8);
-#pragma unroll
-            for (int j = 0; j < 8; ++j) acc[j] = acc[j] + (float)v[j];
-        }
-        bf16x8 o;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) o[j] = (__bf16)(acc[j] * 0.25f);
-        *reinterpret_cast<bf16x8 *>(s.out + (ro * Wo + x) * s.out_stride + s.out_off + c8 * 8) = o;
-    }
-}
+// Upsampling (and its adjoint, and the pooling adjoint below): blockIdx.y
+// walks output rows (b, y) (uniform, so the row arithmetic is scalar), x and
+// the 8-channel group come from the thread index within the row.  The 2x2
+// average pooling itself is fused into the convolution that produces its
+// input (k_conv_halo, pool_out).
 
 // 2x bilinear upsample, in: [B][H][W] slice, out: [B][2H][2W] slice
 __global__ __launch_bounds__(256) void k_upsample2(SliceArgs s)
@@ -1374,6 +1394,12 @@ static hipError_t launch_conv(const ConvArgs &a, int KS, const uint8_t *wq, cons
         return hipErrorInvalidValue;
     const unsigned gx = (unsigned)((a.W + kHaloCols - 1) / kHaloCols);
     const unsigned gy = (unsigned)((a.H + kHaloRows - 1) / kHaloRows);
+    // the fused pooling is the halo kernel's
+    const bool halo_ok = KS == 3 && a.Cin % 32 == 0 && (!a.in2 || a.Cin1 % 32 == 0) && !a.out_f32 &&
+                         (FP8 ? cop % 64 == 0 && !a.in_mask : cop % 32 == 0) &&
+                         (int64_t)a.B * (cop % 64 ? cop / 32 : cop / 64) <= 65535;
+    if (a.pool_out && (!halo_ok || a.head_out || a.H % 2 || a.W % 2 || a.pool_stride % 4 || a.pool_off % 4))
+        return hipErrorInvalidValue;
     // first layer (8 input channels, 32 output channels)
     if (!FP8 && KS == 3 && cop == 32 && a.Cin == 8 && a.Kpad == 96 && !a.in_mask && !a.in2 && !a.out_f32) {
         hipLaunchKernelGGL(k_conv_c8, dim3(gx, gy, (unsigned)a.B), dim3(256), 0, s, a);
@@ -1382,9 +1408,7 @@ static hipError_t launch_conv(const ConvArgs &a, int KS, const uint8_t *wq, cons
     // 3x3 layers with Cin a multiple of 32: direct convolution from halo tiles
     // (32 output channels per 8 waves and 8 rows, or 64 per 8 waves and 4
     // rows; FP8 for the latter)
-    const bool halo = KS == 3 && a.Cin % 32 == 0 && (!a.in2 || a.Cin1 % 32 == 0) && !a.out_f32 &&
-                      (FP8 ? cop % 64 == 0 && !a.in_mask : cop % 32 == 0) &&
-                      (int64_t)a.B * (cop % 64 ? cop / 32 : cop / 64) <= 65535;
+    const bool halo = halo_ok;
     if (halo && cop % 64) {
         // tiles of 32 output channels (cop = 32, or 96 for an input gradient)
         const dim3 grid(gx, (unsigned)((a.H + 7) / 8), (unsigned)(a.B * (cop / 32)));
@@ -1471,13 +1495,6 @@ hipError_t features(const float *in, __bf16 *out, int B, int H, int W, hipStream
 static dim3 row_grid(int64_t row_items, int64_t rows)
 {
     return dim3(nblocks(row_items), (unsigned)std::min<int64_t>(rows, 65535));
-}
-
-hipError_t pool2(const SliceArgs &a, hipStream_t s)
-{
-    if ((int64_t)a.B * a.H * a.W == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pool2, row_grid((int64_t)(a.W / 2) * (a.C / 8), (int64_t)a.B * (a.H / 2)), dim3(256), 0, s, a);
-    return hipGetLastError();
 }
 
 hipError_t upsample2(const SliceArgs &a, hipStream_t s)
