@@ -165,32 +165,42 @@ def frame_section(torch, log_fn, frames=12, train_views=400, train_steps=200):
     t_r, t_n, t_s, p_net, p_ras, s_net, s_ras = [], [], [], [], [], [], []
     t_n8, p_net8 = [], []
     img8 = torch.empty_like(img)
-    for rep, k in enumerate([picks[0]] + picks):  # first pass warms up
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        return e0, e1
+
+    bf16 = lambda out: narvis.narvis_postprocess(w, feat, 1, W, H, out, ws, stream=stream)
+    fp8 = lambda out: narvis.narvis_postprocess(w, feat, 1, W, H, out, ws, precision=narvis.PRECISION_FP8,
+                                                stream=stream)
+    # the frame loop as a viewer runs it (G-buffer, network, next frame), once
+    # with the BF16 and once with the FP8 network; the first frame warms up
+    for net, t_net in ((bf16, t_n), (fp8, t_n8)):
+        evs = []
+        for k in [picks[0]] + picks:
+            evs.append((timed(lambda: r.gbuffer(sc.cameras[k], feat[0])), timed(lambda: net(img))))
+        torch.cuda.synchronize()
+        for (g0, g1), (n0, n1) in evs[1:]:
+            if net is bf16:
+                t_r.append(g0.elapsed_time(g1))
+            t_net.append(n0.elapsed_time(n1))
+    # quality against the splat, and the splat's own time
+    for rep, k in enumerate([picks[0]] + picks):
         cam = sc.cameras[k]
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
-        # G-buffer, BF16 network, FP8 network (each network right after the
-        # G-buffer it reads, in the same cache state), then the splat
-        ev[0].record(stream)
         r.gbuffer(cam, feat[0])
-        ev[1].record(stream)
-        narvis.narvis_postprocess(w, feat, 1, W, H, img, ws, stream=stream)
-        ev[2].record(stream)
-        r.gbuffer(cam, feat[0])
-        ev[3].record(stream)
-        narvis.narvis_postprocess(w, feat, 1, W, H, img8, ws, precision=narvis.PRECISION_FP8, stream=stream)
-        ev[4].record(stream)
-        r.splat(cam, tgt)
-        ev[5].record(stream)
+        bf16(img)
+        fp8(img8)
+        sp = timed(lambda: r.splat(cam, tgt))
         torch.cuda.synchronize()
         if rep == 0:
             continue
-        t_n8.append(ev[3].elapsed_time(ev[4]))
-        p_net8.append(metrics.psnr(img8.clamp(0.0, 1.0), tgt.view(1, 3, H, W)).item())
-        t_r.append(ev[0].elapsed_time(ev[1]))
-        t_n.append(ev[1].elapsed_time(ev[2]))
-        t_s.append(ev[4].elapsed_time(ev[5]))
-        y = img.clamp(0.0, 1.0)
+        t_s.append(sp[0].elapsed_time(sp[1]))
         t3 = tgt.view(1, 3, H, W)
+        y = img.clamp(0.0, 1.0)
+        p_net8.append(metrics.psnr(img8.clamp(0.0, 1.0), t3).item())
         p_net.append(metrics.psnr(y, t3).item())
         p_ras.append(metrics.psnr(feat[:, 0:3].view(1, 3, H, W), t3).item())
         s_net.append(metrics.ssim(y, t3).item())
