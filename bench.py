@@ -326,6 +326,28 @@ def main():
     copy_gbps = 5 * 2 * a.numel() * 4 / (e0.elapsed_time(e1) / 1e3) / 1e9
     del a, b
 
+    # rate of random 64-bit atomic minima into a W x H buffer of int64 keys
+    # (torch's scatter_reduce 'amin': one device-scope atomic per element), for
+    # context beside the render's own atomics; the same kernel's L2 atomic
+    # counter calibrates those counts
+    m = 1 << 26
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(7)
+    idx = torch.randint(0, W * H, (m,), device=dev, generator=gen)
+    val = torch.randint(0, 1 << 62, (m,), device=dev, generator=gen)
+    buf = torch.full((W * H,), (1 << 63) - 1, dtype=torch.int64, device=dev)
+    buf.scatter_reduce_(0, idx, val, reduce="amin")
+    atomic_ms = []
+    for _ in range(3):
+        buf.fill_((1 << 63) - 1)
+        e0.record(stream)
+        buf.scatter_reduce_(0, idx, val, reduce="amin")
+        e1.record(stream)
+        torch.cuda.synchronize()
+        atomic_ms.append(e0.elapsed_time(e1))
+    atomic_rate = m / (float(np.median(atomic_ms)) / 1e3)
+    del idx, val, buf
+
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -350,6 +372,7 @@ def main():
                      "avg_launch_ms": round(render_avg, 4),
                      "algorithmic_bytes_per_launch": alg_bytes},
         "stream_copy_GBps": round(copy_gbps, 1),
+        "atomic_min_u64_random_Gops": round(atomic_rate / 1e9, 3),
     }
     if sc.name == "terrain" and W * H >= 3840 * 2160 and g.attr is not None and g.attr.shape[0] >= 3:
         # end-to-end 4K frame: the raster step above + the BF16 network on its
