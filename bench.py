@@ -311,6 +311,18 @@ def main():
     step(0)
     torch.cuda.synchronize()
     covered = float((g.keys != -1).float().mean().item())
+    # fraction of the points inside the first frame's view volume (the rest
+    # fail the frustum test), from plain torch arithmetic, for context
+    m0 = [float(v) for v in mats[0][0]]
+    visible = 0
+    for s0 in range(0, n, 1 << 26):
+        px, py, pz = sc.x[s0:s0 + (1 << 26)], sc.y[s0:s0 + (1 << 26)], sc.z[s0:s0 + (1 << 26)]
+        w = ((px * m0[12] + py * m0[13]) + pz * m0[14]) + m0[15]
+        sx = ((((px * m0[0] + py * m0[1]) + pz * m0[2]) + m0[3]) / w * 0.5 + 0.5) * W
+        sy = (0.5 - (((px * m0[4] + py * m0[5]) + pz * m0[6]) + m0[7]) / w * 0.5) * H
+        ok = (w >= float(mats[0][1])) & (w <= float(mats[0][2])) & (sx >= 0) & (sx < W) & (sy >= 0) & (sy < H)
+        visible += int(ok.sum().item())
+        del px, py, pz, w, sx, sy, ok
 
     # bandwidth of a plain streaming kernel (read 2 GiB, write 2 GiB), for
     # context and as the known-size reference for the HBM byte counters
@@ -364,7 +376,8 @@ def main():
         "config": {"workload": desc, "points": n, "W": W, "H": H, "frames": len(cams),
                    "planes": ["keys", "depth"] + [f"attr:{nm}" for nm in sc.attr_names]
                    + (["rgb"] if sc.lut_attr >= 0 else []) + (["vel2d"] if sc.vel_attr >= 0 else []),
-                   "covered_fraction_frame0": round(covered, 4)},
+                   "covered_fraction_frame0": round(covered, 4),
+                   "visible_point_fraction_frame0": round(visible / n, 4)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                      "kernel": "render stage: k_render_lds (every 8th chunk of 2048 points), k_tile_bounds, "
