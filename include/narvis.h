@@ -145,7 +145,15 @@ typedef enum {
  * (bits(w) >> 16) exceeds the bound of its tile or bits(w) that of its pixel.
  * Keys only decrease, so the pixel's key is already smaller than such a
  * point's: the result is the single-pass result, bit for bit.  This is the paper's early
- * z-test (Sec. 3.2), taken against a compact copy of the depth buffer. */
+ * z-test (Sec. 3.2), taken against a compact copy of the depth buffer.
+ *
+ * Hinted bounded render (hint_keys given, with bounds): before the first
+ * chunks, every key of the hint buffer that is not empty and whose index
+ * (low 32 bits) is below n names a point, which is rendered like any other.
+ * In a viewer loop the previous frame's keys name points near the front of
+ * the next frame, so the bounds are tighter and fewer points reach the
+ * atomics.  Whatever the hint holds, the result is the same bit for bit.
+ * Ignored when the bounded render does not apply (see above). */
 typedef struct {
     int32_t variant;      /* narvis_render_variant                           */
     int32_t grid_blocks;  /* 0 = automatic, otherwise the number of
@@ -154,6 +162,10 @@ typedef struct {
                              narvis_raster_bounds_bytes(W, H) bytes (4-byte
                              aligned, contents overwritten): bounded render */
     size_t bounds_bytes;
+    const void *hint_keys; /* NULL, or (with bounds) a device key buffer
+                             uint64[H][W] of an earlier render, 8-byte
+                             aligned, read only, overlapping neither `keys`
+                             nor the scratch: hinted bounded render     */
 } narvis_raster_opts;
 
 /* Colour of a point in the splat renderer. */

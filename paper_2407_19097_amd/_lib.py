@@ -52,7 +52,7 @@ class GBuffer(ctypes.Structure):
 
 class RasterOpts(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("grid_blocks", ctypes.c_int32), ("bounds", ctypes.c_void_p),
-                ("bounds_bytes", ctypes.c_size_t)]
+                ("bounds_bytes", ctypes.c_size_t), ("hint_keys", ctypes.c_void_p)]
 
 
 class SplatParams(ctypes.Structure):

@@ -138,12 +138,20 @@ extern "C" narvis_status narvis_raster_render(const narvis_points *pts, uint64_t
     if (variant < NARVIS_RENDER_AUTO || variant > NARVIS_RENDER_LDS || grid < 0) return NARVIS_ERR_INVALID_ARG;
     if (reinterpret_cast<uintptr_t>(bounds) & 3u) return NARVIS_ERR_INVALID_ARG;
     if (bounds && opts->bounds_bytes < narvis_raster_bounds_bytes(W, H)) return NARVIS_ERR_WORKSPACE;
+    // the hint is read while keys and the scratch are written: no overlap
+    const uint64_t *hint = opts ? static_cast<const uint64_t *>(opts->hint_keys) : nullptr;
+    if (hint) {
+        const uintptr_t h0 = reinterpret_cast<uintptr_t>(hint), h1 = h0 + 8 * (uintptr_t)W * (uintptr_t)H;
+        const uintptr_t k0 = reinterpret_cast<uintptr_t>(keys), k1 = k0 + 8 * (uintptr_t)W * (uintptr_t)H;
+        const uintptr_t b0 = reinterpret_cast<uintptr_t>(bounds), b1 = b0 + opts->bounds_bytes;
+        if (!bounds || (h0 & 7u) || (h0 < k1 && k0 < h1) || (h0 < b1 && b0 < h1)) return NARVIS_ERR_INVALID_ARG;
+    }
     if (n > 0 && ((reinterpret_cast<uintptr_t>(pts->x) | reinterpret_cast<uintptr_t>(pts->y) |
                    reinterpret_cast<uintptr_t>(pts->z)) & 3u))
         return NARVIS_ERR_INVALID_ARG;
     const Proj P = make_proj(vp, near_f, far_f, W, H);
     return from_hip(launch_render(n ? pts->x : nullptr, n ? pts->y : nullptr, n ? pts->z : nullptr, n, P, keys,
-                                  variant, grid, static_cast<uint16_t *>(bounds), static_cast<hipStream_t>(stream)));
+                                  variant, grid, static_cast<uint16_t *>(bounds), hint, static_cast<hipStream_t>(stream)));
 }
 
 extern "C" narvis_status narvis_raster_resolve(const narvis_points *pts, const narvis_attrs *attrs, uint64_t n,
@@ -197,7 +205,7 @@ extern "C" narvis_status narvis_rasterize(const narvis_points *pts, const narvis
     if (st != NARVIS_OK) return st;
     const Proj P = make_proj(vp, near_f, far_f, W, H);
     st = from_hip(launch_render(n ? pts->x : nullptr, n ? pts->y : nullptr, n ? pts->z : nullptr, n, P,
-                                gbuf->keys, NARVIS_RENDER_AUTO, 0, static_cast<uint16_t *>(gbuf->bounds), s));
+                                gbuf->keys, NARVIS_RENDER_AUTO, 0, static_cast<uint16_t *>(gbuf->bounds), nullptr, s));
     if (st != NARVIS_OK) return st;
     return from_hip(launch_resolve(n ? pts->x : nullptr, n ? pts->y : nullptr, n ? pts->z : nullptr, n, P, pack,
                                    *gbuf, s));

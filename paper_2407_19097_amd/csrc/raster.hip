@@ -491,6 +491,28 @@ __global__ __launch_bounds__(kCullBlock) void k_render_cull(const float *__restr
     render_tail(X, Y, Z, n, P, keys, sel);
 }
 
+// First level of a hinted bounded render: every pixel of an earlier key
+// buffer (the previous frame of a viewer loop) names the point that won it;
+// those points, rendered first, leave depths near the front of this frame
+// too, so the bounds taken after the sample are tighter and fewer points of
+// the later levels reach the atomics.  Any hint gives the exact result: the
+// hinted points are points of this cloud and merge like any other (an empty
+// key or an index >= n is skipped).
+__global__ __launch_bounds__(kBlock) void k_hint_render(const unsigned long long *__restrict__ hint, uint32_t npx,
+                                                        const float *__restrict__ X, const float *__restrict__ Y,
+                                                        const float *__restrict__ Z, uint64_t n, Proj P,
+                                                        unsigned long long *__restrict__ keys)
+{
+    const uint32_t q = blockIdx.x * kBlock + threadIdx.x;
+    if (q >= npx) return;
+    const unsigned long long h = hint[q];
+    const uint32_t i = (uint32_t)h;
+    if (h == NARVIS_KEY_EMPTY || (uint64_t)i >= n) return;
+    uint32_t pix;
+    float w;
+    if (project(P, X[i], Y[i], Z[i], pix, w)) merge<NARVIS_RENDER_EARLYZ>(keys, pix, w, i);
+}
+
 // Depth bounds after the first levels: per pixel its depth bits, per screen
 // tile the high 16 bits of the largest of those over the tile's pixels (an
 // empty pixel counts as depth bits 0xFFFFFFFF, tile bound 0xFFFF, which culls
@@ -697,7 +719,8 @@ constexpr uint32_t kLevels[] = {8, 1};
 constexpr int kNumLevels = sizeof(kLevels) / sizeof(kLevels[0]);
 
 hipError_t launch_render(const float *x, const float *y, const float *z, uint64_t n, const Proj &P,
-                         uint64_t *keys, int32_t variant, int32_t grid_blocks, uint16_t *bounds, hipStream_t s)
+                         uint64_t *keys, int32_t variant, int32_t grid_blocks, uint16_t *bounds, const uint64_t *hint,
+                         hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     const DeviceInfo dev = device_info();
@@ -750,6 +773,11 @@ hipError_t launch_render(const float *x, const float *y, const float *z, uint64_
                 ++tg.shift;
             }
             auto ceil_div = [](uint64_t a, uint64_t b) { return (a + b - 1) / b; };
+            if (hint) {
+                const uint32_t npx = (uint32_t)P.W * (uint32_t)P.H;
+                hipLaunchKernelGGL(k_hint_render, dim3((npx + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
+                                   reinterpret_cast<const unsigned long long *>(hint), npx, x, y, z, n, P, k);
+            }
             for (int lv = 0; lv < kNumLevels; ++lv) {
                 ChunkSel sel;
                 sel.mul = kLevels[lv];

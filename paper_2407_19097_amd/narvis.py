@@ -144,10 +144,10 @@ def raster_bounds(W: int, H: int, device="cuda"):
 
 
 def narvis_raster_render(points, n: int, vp, near_f, far_f, W: int, H: int, keys, variant: int = RENDER_AUTO,
-                         grid_blocks: int = 0, bounds=None, stream=None) -> None:
+                         grid_blocks: int = 0, bounds=None, hint_keys=None, stream=None) -> None:
     p = points_struct(points)
     nb = 0 if bounds is None else int(bounds.numel() * bounds.element_size())
-    o = _lib.RasterOpts(int(variant), int(grid_blocks), _ptr(bounds), nb)
+    o = _lib.RasterOpts(int(variant), int(grid_blocks), _ptr(bounds), nb, _ptr(hint_keys))
     _lib.check(_lib.load().narvis_raster_render(ctypes.byref(p), int(n), _vp(vp), float(near_f), float(far_f), W, H,
                                                 _ptr(keys), ctypes.byref(o), _stream_ptr(stream)),
                "narvis_raster_render")

@@ -107,6 +107,18 @@ def test_invalid_arguments_rejected_before_any_launch():
     small = _lib.RasterOpts(3, 0, fake, L.narvis_raster_bounds_bytes(8, 8) - 2)
     assert L.narvis_raster_render(ctypes.byref(pts), 10, vp, 0.1, 10.0, 8, 8, fake, ctypes.byref(small),
                                   None) == -5
+    # hinted render: a hint needs the scratch, 8-byte alignment and no
+    # overlap with the keys or the scratch
+    keys, scratch, hint = fake, 0x20000, 0x40000
+    nb = L.narvis_raster_bounds_bytes(8, 8)
+    for o in (_lib.RasterOpts(3, 0, None, 0, hint),           # hint without a scratch
+              _lib.RasterOpts(3, 0, scratch, nb, hint + 4),    # misaligned hint
+              _lib.RasterOpts(3, 0, scratch, nb, keys),        # the key buffer itself
+              _lib.RasterOpts(3, 0, scratch, nb, keys + 8 * 63),  # its last key
+              _lib.RasterOpts(3, 0, scratch, nb, keys - 8 * 63),  # ends on its first key
+              _lib.RasterOpts(3, 0, scratch, nb, scratch + 16)):  # inside the scratch
+        assert L.narvis_raster_render(ctypes.byref(pts), 10, vp, 0.1, 10.0, 8, 8, keys, ctypes.byref(o),
+                                      None) == -1
     nan_vp = (ctypes.c_float * 16)(*([float("nan")] * 16))
     assert L.narvis_raster_render(ctypes.byref(pts), 10, nan_vp, 0.1, 10.0, 8, 8, fake, None, None) == -1
     mis = _lib.Points(fake + 2, fake, fake)

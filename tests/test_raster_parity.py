@@ -192,6 +192,40 @@ def test_bounded_render(n, W, H, grid):
         assert (exp < 0xFFFF).mean() > 0.1  # dense enough that the culling is exercised
 
 
+def test_hinted_bounded_render():
+    """The hinted render equals the oracle whatever the hint holds: the keys
+    of another camera's frame (the viewer-loop use), the frame's own keys,
+    random keys with indices past n, and an empty buffer; the hint is read
+    only."""
+    announce("hinted bounded render, 1M points + ragged tail, 200x150")
+    n, W, H = (1 << 20) + 1234 + 3, 200, 150
+    sc = scenes.unit_cube(n=n, seed=41, W=W, H=H)
+    cams = [scenes.Camera(eye=(1.9, 1.4, 1.2), target=(0.5, 0.5, 0.5)),
+            scenes.Camera(eye=(1.7, 1.7, 1.1), target=(0.5, 0.5, 0.45))]
+    X, Y, Z = dev(sc.x), dev(sc.y), dev(sc.z)
+    bounds = narvis.raster_bounds(W, H)
+    keys = torch.empty(W * H, dtype=torch.int64, device="cuda")
+    okeys = []
+    for cam in cams:
+        M, near, far = ocam.clip_matrix(cam, W, H)
+        okeys.append(orast.render(sc.x, sc.y, sc.z, M, near, far, W, H))
+    rng = np.random.default_rng(5)
+    junk = rng.integers(0, (1 << 63) - 1, size=W * H, dtype=np.int64)
+    junk[::3] = -1                                              # empty keys
+    junk[1::3] = (junk[1::3] & ~0xFFFFFFFF) | (n + 7)           # indices past n
+    hints = {"other camera": torch.from_numpy(okeys[0].view(np.int64)).cuda(),
+             "own frame": torch.from_numpy(okeys[1].view(np.int64)).cuda(),
+             "random": torch.from_numpy(junk).cuda(),
+             "empty": torch.full((W * H,), -1, dtype=torch.int64, device="cuda")}
+    vp, nf, ff = narvis.narvis_camera_matrix(cams[1], W, H)
+    for name, hint in hints.items():
+        before = hint.clone()
+        narvis.narvis_raster_clear(keys, W, H)
+        narvis.narvis_raster_render((X, Y, Z), n, vp, nf, ff, W, H, keys, variant=3, bounds=bounds, hint_keys=hint)
+        np.testing.assert_array_equal(host(keys).view(np.uint64), okeys[1], err_msg=name)
+        assert torch.equal(hint, before), name
+
+
 def test_bounded_render_merges_into_existing_keys():
     """Keys are merged into what the buffer holds: the bounded render of all
     the points onto a buffer that already holds the first half's keys (its
