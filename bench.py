@@ -238,6 +238,8 @@ def main():
     ap.add_argument("--frame-only", action="store_true",
                     help="run only the 1080p frame section (for profiling the network kernels)")
     ap.add_argument("--train-steps", type=int, default=200, help="Adam steps of the frame section's training")
+    ap.add_argument("--no-hinted", action="store_true",
+                    help="skip the viewer loop with the previous frame's keys as hint (for profiling the plain stage)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the rasterizer runs on a single device "
@@ -310,39 +312,46 @@ def main():
     # the same frames as a viewer loop that hands each render the previous
     # frame's keys as the hint of the bounded render (two key buffers in turn;
     # the result is the same bit for bit, checked on the last frame)
-    log("viewer loop with the previous frame's keys as hint")
-    bufs = [g.keys, torch.empty_like(g.keys)]
+    def viewer_loop_hinted():
+        log("viewer loop with the previous frame's keys as hint")
+        bufs = [g.keys, torch.empty_like(g.keys)]
 
-    def hinted_step(k, ev=None):
-        vp, nf, ff = narvis.narvis_camera_matrix(cams[k % len(cams)], W, H)
-        g.keys = bufs[k % 2]
+        def hinted_step(k, ev=None):
+            vp, nf, ff = narvis.narvis_camera_matrix(cams[k % len(cams)], W, H)
+            g.keys = bufs[k % 2]
+            narvis.narvis_raster_clear(g.keys, W, H, stream)
+            if ev is not None:
+                ev[0].record(stream)
+            narvis.narvis_raster_render(pts, n, vp, nf, ff, W, H, g.keys, bounds=g.bounds,
+                                        hint_keys=bufs[(k + 1) % 2] if k > 0 else None, stream=stream)
+            if ev is not None:
+                ev[1].record(stream)
+            narvis.narvis_raster_resolve(pts, sc.attrs, n, vp, W, H, g, stream=stream)
+
+        for k in range(args.warmup):
+            hinted_step(k)
+        hevs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        start.record(stream)
+        for k in range(args.steps):
+            hinted_step(args.warmup + k, hevs[k])
+        stop.record(stream)
+        torch.cuda.synchronize()
+        hinted_total = start.elapsed_time(stop)
+        hinted_render = float(np.mean([a.elapsed_time(b) for a, b in hevs]))
+        last = g.keys.clone()
+        g.keys = bufs[0]
+        vp, nf, ff = narvis.narvis_camera_matrix(cams[(args.warmup + args.steps - 1) % len(cams)], W, H)
         narvis.narvis_raster_clear(g.keys, W, H, stream)
-        if ev is not None:
-            ev[0].record(stream)
-        narvis.narvis_raster_render(pts, n, vp, nf, ff, W, H, g.keys, bounds=g.bounds,
-                                    hint_keys=bufs[(k + 1) % 2] if k > 0 else None, stream=stream)
-        if ev is not None:
-            ev[1].record(stream)
-        narvis.narvis_raster_resolve(pts, sc.attrs, n, vp, W, H, g, stream=stream)
+        narvis.narvis_raster_render(pts, n, vp, nf, ff, W, H, g.keys, bounds=g.bounds, stream=stream)
+        hinted_same = bool(torch.equal(g.keys, last))
+        del bufs, last
+        return {"value": round(n * args.steps / (hinted_total / 1e3) / 1e9, 3), "unit": "Gpoints/s",
+                "ms_per_step": round(hinted_total / args.steps, 4), "render_stage_ms": round(hinted_render, 4),
+                "hint": "previous frame's keys (hinted bounded render)",
+                "same_keys_as_unhinted_last_frame": hinted_same}
 
-    for k in range(args.warmup):
-        hinted_step(k)
-    hevs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    start.record(stream)
-    for k in range(args.steps):
-        hinted_step(args.warmup + k, hevs[k])
-    stop.record(stream)
-    torch.cuda.synchronize()
-    hinted_total = start.elapsed_time(stop)
-    hinted_render = float(np.mean([a.elapsed_time(b) for a, b in hevs]))
-    last = g.keys.clone()
-    g.keys = bufs[0]
-    vp, nf, ff = narvis.narvis_camera_matrix(cams[(args.warmup + args.steps - 1) % len(cams)], W, H)
-    narvis.narvis_raster_clear(g.keys, W, H, stream)
-    narvis.narvis_raster_render(pts, n, vp, nf, ff, W, H, g.keys, bounds=g.bounds, stream=stream)
-    hinted_same = bool(torch.equal(g.keys, last))
-    del bufs, last
+    hinted = None if args.no_hinted else viewer_loop_hinted()
 
     # coverage of the first frame, for context
     step(0)
@@ -423,12 +432,9 @@ def main():
                      "algorithmic_bytes_per_launch": alg_bytes},
         "stream_copy_GBps": round(copy_gbps, 1),
         "atomic_min_u64_random_Gops": round(atomic_rate / 1e9, 3),
-        "viewer_loop_hinted": {"value": round(n * args.steps / (hinted_total / 1e3) / 1e9, 3), "unit": "Gpoints/s",
-                               "ms_per_step": round(hinted_total / args.steps, 4),
-                               "render_stage_ms": round(hinted_render, 4),
-                               "hint": "previous frame's keys (hinted bounded render)",
-                               "same_keys_as_unhinted_last_frame": hinted_same},
     }
+    if hinted is not None:
+        out["viewer_loop_hinted"] = hinted
     if sc.name == "terrain" and W * H >= 3840 * 2160 and g.attr is not None and g.attr.shape[0] >= 3:
         # end-to-end 4K frame: the raster step above + the BF16 network on its
         # G-buffer (RGB from the resolved RGBA planes, depth, no velocity);
