@@ -105,7 +105,10 @@ typedef struct {
  *           narvis_raster_bounds_bytes(W, H) bytes (4-byte aligned, contents
  *           overwritten): when given, narvis_rasterize renders in the bounded
  *           mode (see narvis_raster_opts); NULL renders in one pass.  The
- *           keys are the same either way. */
+ *           keys are the same either way.
+ *   hint_keys  optional (with bounds) earlier key buffer uint64[H][W], as
+ *           narvis_raster_opts.hint_keys: 8-byte aligned, read only,
+ *           overlapping neither keys nor the scratch. */
 typedef struct {
     uint64_t *keys;
     float *depth;
@@ -119,6 +122,7 @@ typedef struct {
     int32_t vel_attr;
     void *bounds;
     size_t bounds_bytes;
+    const void *hint_keys;
 } narvis_gbuffer;
 
 /* Render-stage strategy.  Every variant produces the same key buffer; they

@@ -47,7 +47,8 @@ class GBuffer(ctypes.Structure):
     _fields_ = [("keys", ctypes.c_void_p), ("depth", ctypes.c_void_p), ("attr", ctypes.c_void_p),
                 ("rgb", ctypes.c_void_p), ("vel2d", ctypes.c_void_p), ("lut", ctypes.c_void_p),
                 ("lut_attr", ctypes.c_int32), ("lut_min", ctypes.c_float), ("lut_inv_range", ctypes.c_float),
-                ("vel_attr", ctypes.c_int32), ("bounds", ctypes.c_void_p), ("bounds_bytes", ctypes.c_size_t)]
+                ("vel_attr", ctypes.c_int32), ("bounds", ctypes.c_void_p), ("bounds_bytes", ctypes.c_size_t),
+                ("hint_keys", ctypes.c_void_p)]
 
 
 class RasterOpts(ctypes.Structure):

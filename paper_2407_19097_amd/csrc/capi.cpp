@@ -119,6 +119,17 @@ extern "C" narvis_status narvis_raster_clear(uint64_t *keys, int32_t W, int32_t 
     return from_hip(launch_clear(keys, (int64_t)W * H, static_cast<hipStream_t>(stream)));
 }
 
+// a hint needs the bounded render's scratch, 8-byte alignment, and no
+// overlap with the keys or the scratch (it is read while they are written)
+static bool hint_ok(const void *hint, const void *keys, const void *bounds, size_t bounds_bytes, int32_t W, int32_t H)
+{
+    if (!hint) return true;
+    const uintptr_t h0 = reinterpret_cast<uintptr_t>(hint), h1 = h0 + 8 * (uintptr_t)W * (uintptr_t)H;
+    const uintptr_t k0 = reinterpret_cast<uintptr_t>(keys), k1 = k0 + 8 * (uintptr_t)W * (uintptr_t)H;
+    const uintptr_t b0 = reinterpret_cast<uintptr_t>(bounds), b1 = b0 + bounds_bytes;
+    return bounds && !(h0 & 7u) && !(h0 < k1 && k0 < h1) && !(h0 < b1 && b0 < h1);
+}
+
 extern "C" size_t narvis_raster_bounds_bytes(int32_t W, int32_t H)
 {
     if (!image_ok(W, H)) return 0;
@@ -138,14 +149,8 @@ extern "C" narvis_status narvis_raster_render(const narvis_points *pts, uint64_t
     if (variant < NARVIS_RENDER_AUTO || variant > NARVIS_RENDER_LDS || grid < 0) return NARVIS_ERR_INVALID_ARG;
     if (reinterpret_cast<uintptr_t>(bounds) & 3u) return NARVIS_ERR_INVALID_ARG;
     if (bounds && opts->bounds_bytes < narvis_raster_bounds_bytes(W, H)) return NARVIS_ERR_WORKSPACE;
-    // the hint is read while keys and the scratch are written: no overlap
     const uint64_t *hint = opts ? static_cast<const uint64_t *>(opts->hint_keys) : nullptr;
-    if (hint) {
-        const uintptr_t h0 = reinterpret_cast<uintptr_t>(hint), h1 = h0 + 8 * (uintptr_t)W * (uintptr_t)H;
-        const uintptr_t k0 = reinterpret_cast<uintptr_t>(keys), k1 = k0 + 8 * (uintptr_t)W * (uintptr_t)H;
-        const uintptr_t b0 = reinterpret_cast<uintptr_t>(bounds), b1 = b0 + opts->bounds_bytes;
-        if (!bounds || (h0 & 7u) || (h0 < k1 && k0 < h1) || (h0 < b1 && b0 < h1)) return NARVIS_ERR_INVALID_ARG;
-    }
+    if (!hint_ok(hint, keys, bounds, bounds ? opts->bounds_bytes : 0, W, H)) return NARVIS_ERR_INVALID_ARG;
     if (n > 0 && ((reinterpret_cast<uintptr_t>(pts->x) | reinterpret_cast<uintptr_t>(pts->y) |
                    reinterpret_cast<uintptr_t>(pts->z)) & 3u))
         return NARVIS_ERR_INVALID_ARG;
@@ -200,12 +205,14 @@ extern "C" narvis_status narvis_rasterize(const narvis_points *pts, const narvis
     if ((reinterpret_cast<uintptr_t>(gbuf->keys) & 7u) || (reinterpret_cast<uintptr_t>(gbuf->bounds) & 3u))
         return NARVIS_ERR_INVALID_ARG;
     if (gbuf->bounds && gbuf->bounds_bytes < narvis_raster_bounds_bytes(W, H)) return NARVIS_ERR_WORKSPACE;
+    if (!hint_ok(gbuf->hint_keys, gbuf->keys, gbuf->bounds, gbuf->bounds_bytes, W, H)) return NARVIS_ERR_INVALID_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);
     st = from_hip(launch_clear(gbuf->keys, (int64_t)W * H, s));
     if (st != NARVIS_OK) return st;
     const Proj P = make_proj(vp, near_f, far_f, W, H);
     st = from_hip(launch_render(n ? pts->x : nullptr, n ? pts->y : nullptr, n ? pts->z : nullptr, n, P,
-                                gbuf->keys, NARVIS_RENDER_AUTO, 0, static_cast<uint16_t *>(gbuf->bounds), nullptr, s));
+                                gbuf->keys, NARVIS_RENDER_AUTO, 0, static_cast<uint16_t *>(gbuf->bounds),
+                                static_cast<const uint64_t *>(gbuf->hint_keys), s));
     if (st != NARVIS_OK) return st;
     return from_hip(launch_resolve(n ? pts->x : nullptr, n ? pts->y : nullptr, n ? pts->z : nullptr, n, P, pack,
                                    *gbuf, s));

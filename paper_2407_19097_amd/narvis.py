@@ -89,6 +89,7 @@ class GBuffer:
     lut_inv_range: float = 1.0
     vel_attr: int = -1
     bounds: object = None         # uint8 [narvis_raster_bounds_bytes(W, H)] scratch of the bounded render
+    hint: object = None           # int64 [H*W] keys of an earlier render (hinted bounded render)
 
     @staticmethod
     def allocate(W: int, H: int, nattr: int = 0, depth=True, rgb=False, vel2d=False, bounded=True, device="cuda"):
@@ -106,7 +107,8 @@ class GBuffer:
         return _lib.GBuffer(_ptr(self.keys), _ptr(self.depth), _ptr(self.attr), _ptr(self.rgb), _ptr(self.vel2d),
                             _ptr(self.lut), int(self.lut_attr), float(self.lut_min), float(self.lut_inv_range),
                             int(self.vel_attr), _ptr(self.bounds),
-                            0 if self.bounds is None else int(self.bounds.numel() * self.bounds.element_size()))
+                            0 if self.bounds is None else int(self.bounds.numel() * self.bounds.element_size()),
+                            _ptr(self.hint))
 
 
 def narvis_status_string(status: int) -> str:

@@ -43,18 +43,30 @@ class Renderer:
         self.sc, self.W, self.H = sc, W, H
         self.lut = torch.from_numpy(scenes.colour_lut()).to(device)
         self.inv = float(np.float32(1.0 / (sc.lut_max - sc.lut_min)))
-        self.keys = torch.empty(W * H, dtype=torch.int64, device=device)
+        # two key buffers in turn, so that a frame can take the previous
+        # frame's keys as the hint of its bounded render
+        self.key_bufs = [torch.empty(W * H, dtype=torch.int64, device=device) for _ in range(2)]
+        self.frame = 0
+        self.bounds = narvis.raster_bounds(W, H, device)
         self.params = narvis.SplatParams(sigma_px=sigma, opacity=1.0, color_mode=narvis.COLOR_LUT,
                                          color_attr=sc.lut_attr, lut=self.lut, lut_min=sc.lut_min,
                                          lut_inv_range=self.inv)
         self.ws = torch.empty(max(1, narvis.narvis_splat_workspace_size(sc.n, W, H, self.params)), dtype=torch.uint8,
                               device=device)
 
-    def gbuffer(self, cam, out):
-        """out: float32 [8, H*W] view (r, g, b, depth, v'x, v'y, theta, |v'|)."""
+    @property
+    def keys(self):
+        return self.key_bufs[self.frame % 2]
+
+    def gbuffer(self, cam, out, hint=False):
+        """out: float32 [8, H*W] view (r, g, b, depth, v'x, v'y, theta, |v'|).
+        hint: the previous gbuffer() call's keys seed the bounded render (a
+        viewer loop; the planes are the same either way)."""
+        self.frame += 1
         g = narvis.GBuffer(keys=self.keys, depth=out[3], rgb=out[0:3], vel2d=out[4:8], lut=self.lut,
                            lut_attr=self.sc.lut_attr, lut_min=self.sc.lut_min, lut_inv_range=self.inv,
-                           vel_attr=self.sc.vel_attr)
+                           vel_attr=self.sc.vel_attr, bounds=self.bounds,
+                           hint=self.key_bufs[(self.frame + 1) % 2] if hint else None)
         narvis.narvis_rasterize((self.sc.x, self.sc.y, self.sc.z), self.sc.attrs, self.sc.n, cam, self.W, self.H, g)
 
     def splat(self, cam, out):

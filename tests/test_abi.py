@@ -143,6 +143,13 @@ def test_invalid_arguments_rejected_before_any_launch():
     cam = narvis.camera_struct(scenes.Camera(eye=(1, 1, 1), target=(1, 1, 1)))
     assert L.narvis_rasterize(ctypes.byref(pts), ctypes.byref(a), 10, ctypes.byref(cam), 8, 8, ctypes.byref(g),
                               None) == -1
+    # whole frame with a hint: without a scratch, misaligned, or over the keys
+    good_cam = narvis.camera_struct(scenes.Camera(eye=(2, 2, 2), target=(0, 0, 0)))
+    nb = L.narvis_raster_bounds_bytes(8, 8)
+    for hint, scratch in ((0x40000, None), (0x40004, 0x20000), (fake + 8, 0x20000)):
+        gh = _lib.GBuffer(fake, 0, 0, 0, 0, 0, 0, 0.0, 1.0, -1, scratch, nb if scratch else 0, hint)
+        assert L.narvis_rasterize(ctypes.byref(pts), ctypes.byref(a), 10, ctypes.byref(good_cam), 8, 8,
+                                  ctypes.byref(gh), None) == -1
 
 
 def test_raster_bounds_bytes():

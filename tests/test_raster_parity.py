@@ -366,3 +366,25 @@ def test_rasterize_whole_frame_entry_point():
            "rgb": host(g.rgb), "vel2d": host(g.vel2d)}
     o = oracle_frame(sc.x, sc.y, sc.z, sc.attrs, sc.cameras[0], sc.W, sc.H, **kw)
     assert_same(got, o)
+
+
+def test_rasterize_with_previous_frame_hint():
+    announce("narvis_rasterize of a second camera with the first frame's keys as hint")
+    sc = scenes.unit_cube(n=300000, seed=13, W=256, H=192)
+    kw = scene_args(sc)
+    X, Y, Z = dev(sc.x), dev(sc.y), dev(sc.z)
+    A = [dev(a) for a in sc.attrs]
+    cam2 = scenes.Camera(eye=(1.9, 2.2, 1.7), target=(0.45, 0.5, 0.5))
+    frames = []
+    for k, cam in enumerate((sc.cameras[0], cam2)):
+        g = narvis.GBuffer.allocate(sc.W, sc.H, nattr=4, rgb=True, vel2d=True)
+        g.lut = dev(kw["lut"])
+        g.lut_attr, g.lut_min, g.lut_inv_range, g.vel_attr = 3, 0.0, float(kw["lut_inv"]), 0
+        g.hint = frames[-1].keys if frames else None
+        narvis.narvis_rasterize((X, Y, Z), A, sc.n, cam, sc.W, sc.H, g)
+        frames.append(g)
+    g = frames[1]
+    got = {"keys": host(g.keys).view(np.uint64), "depth": host(g.depth), "attrs": host(g.attr),
+           "rgb": host(g.rgb), "vel2d": host(g.vel2d)}
+    o = oracle_frame(sc.x, sc.y, sc.z, sc.attrs, cam2, sc.W, sc.H, **kw)
+    assert_same(got, o)
