@@ -351,7 +351,8 @@ def main():
                 "hint": "previous frame's keys (hinted bounded render)",
                 "same_keys_as_unhinted_last_frame": hinted_same}
 
-    hinted = None if args.no_hinted else viewer_loop_hinted()
+    # (a moving camera only: with one view the hint would be the answer itself)
+    hinted = None if args.no_hinted or len(cams) < 2 else viewer_loop_hinted()
 
     # coverage of the first frame, for context
     step(0)
