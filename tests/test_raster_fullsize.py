@@ -19,7 +19,9 @@ def announce(msg):
     print(f"\n[case] {msg}", flush=True)
 
 
-def run_pair(sc, cams, with_planes=True):
+def run_pair(sc, cams, with_planes=True, hinted=False):
+    """hinted: each frame after the first gets the previous frame's keys as
+    the hint of its bounded render (a viewer loop)."""
     n, W, H = sc.n, sc.W, sc.H
     t0 = time.time()
     xh, yh, zh = (t.cpu().numpy() for t in (sc.x, sc.y, sc.z))
@@ -30,8 +32,10 @@ def run_pair(sc, cams, with_planes=True):
     inv = np.float32(1.0 / (sc.lut_max - sc.lut_min))
     lut = scenes.colour_lut()
     with_planes = with_planes and sc.lut_attr >= 0
+    prev = None
     for cam in cams:
         g = narvis.GBuffer.allocate(W, H, nattr=len(sc.attrs), rgb=with_planes, vel2d=with_planes and sc.vel_attr >= 0)
+        g.hint = prev if hinted else None
         if with_planes:
             g.lut = torch.from_numpy(lut).cuda()
             g.lut_attr, g.lut_min, g.lut_inv_range, g.vel_attr = sc.lut_attr, sc.lut_min, float(inv), sc.vel_attr
@@ -56,6 +60,7 @@ def run_pair(sc, cams, with_planes=True):
                 np.testing.assert_array_equal(v[c].view(np.uint32), o["vel2d"][c].view(np.uint32))
             d = np.abs(v[2].view(np.int32).astype(np.int64) - o["vel2d"][2].view(np.int32).astype(np.int64))
             assert d.max() <= 4
+        prev = g.keys
         del g
 
 
@@ -63,12 +68,16 @@ def test_vector_field_50m_full():
     announce("vector field 500x500x200 = 50M points, 1920x1080, orbit frames 0, 17, 45")
     sc = scenes.vector_field(device="cuda")
     run_pair(sc, [sc.cameras[0], sc.cameras[17], sc.cameras[45]])
+    announce("vector field, orbit frames 17, 18, 19 with the previous frame's keys as hint")
+    run_pair(sc, [sc.cameras[17], sc.cameras[18], sc.cameras[19]], hinted=True)
 
 
 def test_trajectories_350m_full():
     announce("trajectories 3.5M particles x 100 steps = 350M points, 1920x1080, fly-through frame 60 + overview")
     sc = scenes.trajectories(device="cuda")
     run_pair(sc, [sc.cameras[60], sc.cameras[-1]], with_planes=True)
+    announce("trajectories, fly-through frames 30, 31 with the previous frame's keys as hint")
+    run_pair(sc, [sc.cameras[30], sc.cameras[31]], with_planes=False, hinted=True)
 
 
 def test_terrain_1b_full_and_quarter():
