@@ -82,6 +82,12 @@ typedef struct {
     double zfar;
 } narvis_camera;
 
+/* Colour of a point: the G-buffer's rgb plane and the splat renderer. */
+typedef enum {
+    NARVIS_COLOR_LUT = 0,   /* lut[q] of one attribute (transfer function)     */
+    NARVIS_COLOR_RGB8 = 1   /* three uint8 attributes times fp32(1/255)        */
+} narvis_color_mode;
+
 /* Output planes of the resolve stage.  `keys` is required; every other plane
  * pointer may be NULL to skip it.
  *   keys   uint64[H][W]   per pixel: (fp32 depth bits << 32) | point index of
@@ -92,9 +98,14 @@ typedef struct {
  *                         fp32 (integers by value, fp16 widened; a half NaN
  *                         becomes the quiet fp32 NaN with the same sign and
  *                         payload), 0 for an empty pixel.
- *   rgb    float[3][H][W] transfer-function colour lut[q] of attribute
- *                         lut_attr, q = floor((s - lut_min) * lut_inv_range * 256)
- *                         clamped to [0,255] (NaN -> 0); 0 for an empty pixel.
+ *   rgb    float[3][H][W] colour of the winner, 0 for an empty pixel; with
+ *                         rgb_mode NARVIS_COLOR_LUT the transfer-function
+ *                         colour lut[q] of attribute lut_attr,
+ *                         q = floor((s - lut_min) * lut_inv_range * 256)
+ *                         clamped to [0,255] (NaN -> 0); with
+ *                         NARVIS_COLOR_RGB8 the uint8 attributes lut_attr,
+ *                         lut_attr+1, lut_attr+2 times fp32(1/255) (each
+ *                         product rounded once), as the splat colours them.
  *   vel2d  float[4][H][W] Vel2D of Sec. 4.5.3 from attributes vel_attr,
  *                         vel_attr+1, vel_attr+2 (vx, vy, vz): the derivative
  *                         of normalised device coordinates along v
@@ -108,7 +119,11 @@ typedef struct {
  *           keys are the same either way.
  *   hint_keys  optional (with bounds) earlier key buffer uint64[H][W], as
  *           narvis_raster_opts.hint_keys: 8-byte aligned, read only,
- *           overlapping neither keys nor the scratch. */
+ *           overlapping neither keys nor the scratch.
+ *   rgb_mode  narvis_color_mode of the rgb plane (0 = LUT).
+ * The depth, rgb and vel2d planes may be slices of one [8][H][W] tensor in
+ * the order r, g, b, depth, v'x, v'y, theta, |v'|: that is the network input
+ * narvis_postprocess reads. */
 typedef struct {
     uint64_t *keys;
     float *depth;
@@ -123,6 +138,7 @@ typedef struct {
     void *bounds;
     size_t bounds_bytes;
     const void *hint_keys;
+    int32_t rgb_mode;
 } narvis_gbuffer;
 
 /* Render-stage strategy.  Every variant produces the same key buffer; they
@@ -171,13 +187,6 @@ typedef struct {
                              aligned, read only, overlapping neither `keys`
                              nor the scratch: hinted bounded render     */
 } narvis_raster_opts;
-
-/* Colour of a point in the splat renderer. */
-typedef enum {
-    NARVIS_COLOR_LUT = 0,   /* lut[q] of attribute color_attr, binned like the
-                               G-buffer rgb plane                              */
-    NARVIS_COLOR_RGB8 = 1   /* attributes color_attr..color_attr+2 (uint8) / 255 */
-} narvis_color_mode;
 
 /* Parameters of the Gaussian splat renderer. */
 typedef struct {
@@ -363,6 +372,26 @@ narvis_status narvis_train_step(narvis_weights *w, const float *feat, const floa
 narvis_status narvis_train_gradients(narvis_weights *w, const float *feat, const float *target, int32_t B, int32_t W,
                                      int32_t H, float lam_tv, float *grad_out, float *loss_out, void *ws,
                                      size_t ws_bytes, void *stream);
+
+/* Where the training calls keep one tensor of the forward and backward
+ * passes inside their workspace (for B images of W x H), so that a caller
+ * can inspect it after narvis_train_step / narvis_train_gradients returned
+ * (tests feed each layer's stored input, output and upstream gradient to a
+ * reference and compare element by element).  Host only.
+ * name: "feat" (network input, depth inverted), the layer outputs "e1a",
+ * "sk1" (= e1b), "e2a", "sk2", "e3a", "sk3", "e4a", "e4b", "d3a", "d3b",
+ * "d2a", "d2b", "d1a", "d1b", the pooled "pool1".."pool3", the upsampled
+ * "up3", "up2", "up1", the head output "out", and the gradients "gy" (of the
+ * loss with respect to "out"), "g_<layer>" (with respect to that layer's
+ * output), "g_cat1".."g_cat3" (with respect to a decoder layer's
+ * concatenated input [upsampled, skip]) and "g_pool1".."g_pool3".
+ * *offset: byte offset in the workspace; *channels, *height, *width: the
+ * tensor's shape per image; *dtype 0: bfloat16 NHWC [B][height][width][channels]
+ * ("gy" holds 8 channels, the last 5 zero), 1: fp32 planar
+ * [B][channels][height][width].  INVALID_ARG for an unknown name or invalid
+ * dimensions. */
+narvis_status narvis_train_tensor(int32_t B, int32_t W, int32_t H, const char *name, size_t *offset,
+                                  int32_t *channels, int32_t *height, int32_t *width, int32_t *dtype);
 
 #ifdef __cplusplus
 }

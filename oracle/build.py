@@ -6,7 +6,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["raster_ref.c", "splat_ref.c"]
+SOURCES = ["raster_ref.c", "raster_mt.c", "splat_ref.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 
 
@@ -14,7 +14,7 @@ def build(verbose: bool = False) -> str:
     srcs = [os.path.join(HERE, s) for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
     tmp = LIB + ".tmp"
     cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-msse2", "-mfpmath=sse",
-           "-fPIC", "-shared", "-std=c11", "-Wall", "-o", tmp] + srcs + ["-lm"]
+           "-fPIC", "-shared", "-std=c11", "-Wall", "-pthread", "-o", tmp] + srcs + ["-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

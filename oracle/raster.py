@@ -30,13 +30,16 @@ def lib():
                                     ctypes.c_int32, ctypes.c_int32, P]
         L.oracle_render_range.argtypes = [P, P, P, ctypes.c_uint64, ctypes.c_uint64, P, ctypes.c_float,
                                           ctypes.c_float, ctypes.c_int32, ctypes.c_int32, P]
+        L.oracle_render_mt.argtypes = [P, P, P, ctypes.c_uint64, P, ctypes.c_float, ctypes.c_float,
+                                       ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int]
+        L.oracle_render_mt.restype = ctypes.c_int
         L.oracle_project_point.argtypes = [P, ctypes.c_float, ctypes.c_float, ctypes.c_int32, ctypes.c_int32,
                                            ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                            ctypes.POINTER(ctypes.c_float)]
         L.oracle_project_point.restype = ctypes.c_int64
         L.oracle_resolve.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, P, P, P, P, ctypes.c_int32,
                                      P, P, P, P, ctypes.c_int32, ctypes.c_float, ctypes.c_float,
-                                     P, ctypes.c_int32]
+                                     P, ctypes.c_int32, ctypes.c_int32]
         _lib = L
     return _lib
 
@@ -54,6 +57,20 @@ def render(x, y, z, M, near, far, W, H):
     M, pm = _f32(M)
     keys = np.empty(W * H, dtype=np.uint64)
     lib().oracle_render(px, py, pz, x.shape[0], pm, float(near), float(far), W, H, keys.ctypes.data)
+    return keys
+
+
+def render_mt(x, y, z, M, near, far, W, H, threads):
+    """render() on `threads` host threads (private key buffers merged by
+    elementwise minimum: the same keys)."""
+    x, px = _f32(x)
+    y, py = _f32(y)
+    z, pz = _f32(z)
+    M, pm = _f32(M)
+    keys = np.empty(W * H, dtype=np.uint64)
+    if lib().oracle_render_mt(px, py, pz, x.shape[0], pm, float(near), float(far), W, H, keys.ctypes.data,
+                              int(threads)) != 0:
+        raise MemoryError("oracle_render_mt: no memory or threads")
     return keys
 
 
@@ -88,8 +105,9 @@ def _attr_array(attrs):
 
 
 def resolve(keys, W, H, x, y, z, M, attrs, want_depth=True, want_attrs=True,
-            lut=None, lut_attr=-1, lut_min=0.0, lut_inv_range=1.0, vel_attr=-1):
-    """Returns dict with depth [H*W], attrs [C][H*W], rgb [3][H*W], vel2d [4][H*W] as requested."""
+            lut=None, lut_attr=-1, lut_min=0.0, lut_inv_range=1.0, vel_attr=-1, rgb_mode=0):
+    """Returns dict with depth [H*W], attrs [C][H*W], rgb [3][H*W], vel2d [4][H*W] as requested
+    (rgb: lut given, or rgb_mode 1 = three uint8 attributes from lut_attr, scaled by 1/255)."""
     keys = np.ascontiguousarray(keys, dtype=np.uint64)
     x, px = _f32(x)
     y, py = _f32(y)
@@ -100,13 +118,13 @@ def resolve(keys, W, H, x, y, z, M, attrs, want_depth=True, want_attrs=True,
     out = {}
     depth = np.empty(npx, np.float32) if want_depth else None
     chan = np.empty((len(attrs), npx), np.float32) if (want_attrs and attrs) else None
-    rgb = np.empty((3, npx), np.float32) if lut is not None else None
+    rgb = np.empty((3, npx), np.float32) if (lut is not None or rgb_mode == 1) else None
     vel = np.empty((4, npx), np.float32) if vel_attr >= 0 else None
     lutc = np.ascontiguousarray(lut, dtype=np.float32).reshape(-1) if lut is not None else None
     ptr = lambda a: None if a is None else a.ctypes.data
     lib().oracle_resolve(keys.ctypes.data, W, H, px, py, pz, pm, ctypes.cast(arr, ctypes.c_void_p),
                          len(attrs), ptr(depth), ptr(chan), ptr(rgb), ptr(lutc), lut_attr,
-                         float(lut_min), float(lut_inv_range), ptr(vel), vel_attr)
+                         float(lut_min), float(lut_inv_range), ptr(vel), vel_attr, int(rgb_mode))
     if depth is not None:
         out["depth"] = depth
     if chan is not None:

@@ -161,7 +161,9 @@ static float attr_value(const oracle_attr *a, uint64_t i)
 /* Resolve stage plus optional derived channels.
  *   depth  [H*W]        or NULL
  *   chan   [nattr][H*W] or NULL   raw attributes of the winner
- *   rgb    [3][H*W]     or NULL   lut[q][c] with q the 256-bin index of attribute lut_attr
+ *   rgb    [3][H*W]     or NULL   rgb_mode 0: lut[q][c] with q the 256-bin index of attribute
+ *                                 lut_attr; rgb_mode 1: attribute lut_attr + c (uint8) times
+ *                                 the fp32 value of 1/255
  *   vel2d  [4][H*W]     or NULL   (v'x, v'y, theta/pi, |v'|) from attributes vel_attr..+2
  */
 void oracle_resolve(const uint64_t *keys, int32_t W, int32_t H,
@@ -169,7 +171,7 @@ void oracle_resolve(const uint64_t *keys, int32_t W, int32_t H,
                     const oracle_attr *attrs, int32_t nattr,
                     float *depth, float *chan,
                     float *rgb, const float *lut, int32_t lut_attr, float lut_min, float lut_inv_range,
-                    float *vel2d, int32_t vel_attr)
+                    float *vel2d, int32_t vel_attr, int32_t rgb_mode)
 {
     const int64_t npx = (int64_t)W * (int64_t)H;
     const float pi_f = 3.14159265358979323846f;
@@ -181,7 +183,11 @@ void oracle_resolve(const uint64_t *keys, int32_t W, int32_t H,
         if (chan)
             for (int32_t c = 0; c < nattr; ++c)
                 chan[(int64_t)c * npx + p] = empty ? 0.0f : attr_value(&attrs[c], i);
-        if (rgb) {
+        if (rgb && rgb_mode == 1) {
+            const float inv255 = 1.0f / 255.0f;
+            for (int c = 0; c < 3; ++c)
+                rgb[(int64_t)c * npx + p] = empty ? 0.0f : attr_value(&attrs[lut_attr + c], i) * inv255;
+        } else if (rgb) {
             int q = 0;
             if (!empty) {
                 float t = attr_value(&attrs[lut_attr], i) - lut_min;

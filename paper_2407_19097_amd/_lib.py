@@ -48,7 +48,7 @@ class GBuffer(ctypes.Structure):
                 ("rgb", ctypes.c_void_p), ("vel2d", ctypes.c_void_p), ("lut", ctypes.c_void_p),
                 ("lut_attr", ctypes.c_int32), ("lut_min", ctypes.c_float), ("lut_inv_range", ctypes.c_float),
                 ("vel_attr", ctypes.c_int32), ("bounds", ctypes.c_void_p), ("bounds_bytes", ctypes.c_size_t),
-                ("hint_keys", ctypes.c_void_p)]
+                ("hint_keys", ctypes.c_void_p), ("rgb_mode", ctypes.c_int32)]
 
 
 class RasterOpts(ctypes.Structure):
@@ -102,6 +102,10 @@ SIGNATURES = {
                                          ctypes.c_float, ctypes.c_float, _P, _P, ctypes.c_size_t, _P]),
     "narvis_train_gradients": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                               ctypes.c_float, _P, _P, _P, ctypes.c_size_t, _P]),
+    "narvis_train_tensor": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_char_p,
+                                           ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_int32),
+                                           ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                           ctypes.POINTER(ctypes.c_int32)]),
 }
 
 _lib = None

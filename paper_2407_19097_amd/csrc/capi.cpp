@@ -98,6 +98,18 @@ bool pack_attrs(const narvis_attrs *attrs, uint64_t n, AttrPack &out)
 
 narvis_status from_hip(hipError_t e) { return e == hipSuccess ? NARVIS_OK : NARVIS_ERR_DEVICE; }
 
+// the rgb plane's colour source: a table over one attribute, or three uint8
+// attributes
+bool rgb_ok(const narvis_gbuffer &g, const AttrPack &pack)
+{
+    if (!g.rgb) return true;
+    if (g.rgb_mode == NARVIS_COLOR_LUT) return g.lut && g.lut_attr >= 0 && g.lut_attr < pack.count;
+    if (g.rgb_mode != NARVIS_COLOR_RGB8 || g.lut_attr < 0 || g.lut_attr + 2 >= pack.count) return false;
+    for (int c = 0; c < 3; ++c)
+        if (pack.a[g.lut_attr + c].dtype != NARVIS_U8) return false;
+    return true;
+}
+
 }  // namespace
 
 extern "C" const char *narvis_status_string(narvis_status s)
@@ -168,7 +180,7 @@ extern "C" narvis_status narvis_raster_resolve(const narvis_points *pts, const n
     AttrPack pack;
     if (!pack_attrs(attrs, n, pack)) return NARVIS_ERR_INVALID_ARG;
     if (gbuf->attr && pack.count == 0) return NARVIS_ERR_INVALID_ARG;
-    if (gbuf->rgb && (!gbuf->lut || gbuf->lut_attr < 0 || gbuf->lut_attr >= pack.count)) return NARVIS_ERR_INVALID_ARG;
+    if (!rgb_ok(*gbuf, pack)) return NARVIS_ERR_INVALID_ARG;
     if (gbuf->vel2d) {
         if (gbuf->vel_attr < 0 || gbuf->vel_attr + 2 >= pack.count) return NARVIS_ERR_INVALID_ARG;
         if (!points_ok(pts, n) || !vp) return NARVIS_ERR_INVALID_ARG;
@@ -197,7 +209,7 @@ extern "C" narvis_status narvis_rasterize(const narvis_points *pts, const narvis
     if (!matrix_ok(vp, near_f, far_f)) return NARVIS_ERR_INVALID_ARG;
     // validate the resolve arguments before enqueuing anything
     if (gbuf->attr && pack.count == 0) return NARVIS_ERR_INVALID_ARG;
-    if (gbuf->rgb && (!gbuf->lut || gbuf->lut_attr < 0 || gbuf->lut_attr >= pack.count)) return NARVIS_ERR_INVALID_ARG;
+    if (!rgb_ok(*gbuf, pack)) return NARVIS_ERR_INVALID_ARG;
     if (gbuf->vel2d && (gbuf->vel_attr < 0 || gbuf->vel_attr + 2 >= pack.count)) return NARVIS_ERR_INVALID_ARG;
     if (n > 0 && ((reinterpret_cast<uintptr_t>(pts->x) | reinterpret_cast<uintptr_t>(pts->y) |
                    reinterpret_cast<uintptr_t>(pts->z)) & 3u))

@@ -680,6 +680,55 @@ extern "C" narvis_status narvis_train_step(narvis_weights *w, const float *feat,
     return st(e);
 }
 
+namespace {
+
+// Named tensors of the training workspace: {name, plan member, level,
+// channels}; level -1 marks the fp32 planar output.
+struct NamedTensor {
+    const char *name;
+    uint64_t Plan::*off;
+    int level, ch;
+};
+
+const NamedTensor kTensors[] = {
+    {"feat", &Plan::feat, 0, 8},      {"e1a", &Plan::e1a, 0, 32},       {"sk1", &Plan::sk1, 0, 32},
+    {"pool1", &Plan::pool1, 1, 32},   {"e2a", &Plan::e2a, 1, 64},       {"sk2", &Plan::sk2, 1, 64},
+    {"pool2", &Plan::pool2, 2, 64},   {"e3a", &Plan::e3a, 2, 128},      {"sk3", &Plan::sk3, 2, 128},
+    {"pool3", &Plan::pool3, 3, 128},  {"e4a", &Plan::e4a, 3, 256},      {"e4b", &Plan::e4b, 3, 256},
+    {"up3", &Plan::up3, 2, 256},      {"d3a", &Plan::d3a, 2, 128},      {"d3b", &Plan::d3b, 2, 128},
+    {"up2", &Plan::up2, 1, 128},      {"d2a", &Plan::d2a, 1, 64},       {"d2b", &Plan::d2b, 1, 64},
+    {"up1", &Plan::up1, 0, 64},       {"d1a", &Plan::d1a, 0, 32},       {"d1b", &Plan::d1b, 0, 32},
+    {"out", &Plan::out, -1, 3},       {"gy", &Plan::gy, 0, 8},          {"g_d1b", &Plan::g_d1b, 0, 32},
+    {"g_d1a", &Plan::g_d1a, 0, 32},   {"g_cat1", &Plan::g_cat1, 0, 96}, {"g_d2b", &Plan::g_d2b, 1, 64},
+    {"g_d2a", &Plan::g_d2a, 1, 64},   {"g_cat2", &Plan::g_cat2, 1, 192}, {"g_d3b", &Plan::g_d3b, 2, 128},
+    {"g_d3a", &Plan::g_d3a, 2, 128},  {"g_cat3", &Plan::g_cat3, 2, 384}, {"g_e4b", &Plan::g_e4b, 3, 256},
+    {"g_e4a", &Plan::g_e4a, 3, 256},  {"g_pool3", &Plan::g_pool3, 3, 128}, {"g_e3b", &Plan::g_e3b, 2, 128},
+    {"g_e3a", &Plan::g_e3a, 2, 128},  {"g_pool2", &Plan::g_pool2, 2, 64}, {"g_e2b", &Plan::g_e2b, 1, 64},
+    {"g_e2a", &Plan::g_e2a, 1, 64},   {"g_pool1", &Plan::g_pool1, 1, 32}, {"g_e1b", &Plan::g_e1b, 0, 32},
+    {"g_e1a", &Plan::g_e1a, 0, 32},
+};
+
+}  // namespace
+
+extern "C" narvis_status narvis_train_tensor(int32_t B, int32_t W, int32_t H, const char *name, size_t *offset,
+                                             int32_t *channels, int32_t *height, int32_t *width, int32_t *dtype)
+{
+    if (!name || !offset || !channels || !height || !width || !dtype || !dims_ok(B, W, H))
+        return NARVIS_ERR_INVALID_ARG;
+    const Plan p = make_plan(B, H, W, true);
+    for (const NamedTensor &t : kTensors) {
+        if (std::strcmp(t.name, name) != 0) continue;
+        const int lv = t.level < 0 ? 0 : t.level;
+        *offset = (size_t)(p.*(t.off));
+        *channels = t.ch;
+        *height = H >> lv;
+        *width = W >> lv;
+        *dtype = t.level < 0 ? 1 : 0;
+        return NARVIS_OK;
+    }
+    return NARVIS_ERR_INVALID_ARG;
+}
+
 extern "C" narvis_status narvis_weights_calibrate_fp8(narvis_weights *w, const float *feat, int32_t B, int32_t W,
                                                       int32_t H, void *ws, size_t ws_bytes, void *stream)
 {

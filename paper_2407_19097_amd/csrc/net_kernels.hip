@@ -1169,19 +1169,16 @@ __global__ __launch_bounds__(256) void k_wgrad_reduce(const float *part, const f
 // 3..7 zero) for the head's backward; per-block partial sums of the loss.
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_loss(const float *y, const float *t, int B, int H, int W, float lam,
-                                              __bf16 *grad, float *partial)
+// The scales are computed on the host: c_all = 1/(3P), c_mse = 2/(3P),
+// c_hx = lam/(3B H (W-1)) and c_hy = lam/(3B (H-1) W) (0 when that difference
+// does not exist).
+__global__ __launch_bounds__(256) void k_loss(const float *y, const float *t, int B, int H, int W, float c_all,
+                                              float c_mse, float c_hx, float c_hy, __bf16 *grad, float *partial)
 {
     __shared__ float red[256];
     const int64_t hw = (int64_t)H * W;
     const int64_t P = (int64_t)B * hw;
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const double n_all = 3.0 * (double)P;
-    const double n_hx = 3.0 * (double)B * H * (W - 1);
-    const double n_hy = 3.0 * (double)B * (H - 1) * W;
-    const float c_mse = (float)(2.0 / n_all);
-    const float c_hx = W > 1 ? (float)((double)lam / n_hx) : 0.0f;
-    const float c_hy = H > 1 ? (float)((double)lam / n_hy) : 0.0f;
     float l = 0.0f;
     bf16x8 go = zero8();
     if (p < P) {
@@ -1191,7 +1188,7 @@ __global__ __launch_bounds__(256) void k_loss(const float *y, const float *t, in
             const float *yc = y + (b * 3 + c) * hw;
             const float d = yc[pix] - t[(b * 3 + c) * hw + pix];
             float gsum = c_mse * d;
-            l = l + d * d * (float)(1.0 / n_all);
+            l = l + d * d * c_all;
             if (xx + 1 < W) {
                 const float h = yc[pix + 1] - yc[pix];
                 l = l + fabsf(h) * c_hx;
@@ -1539,7 +1536,14 @@ hipError_t loss(const float *y, const float *t, int B, int H, int W, float lam, 
 {
     const int64_t P = (int64_t)B * H * W;
     const unsigned nb = nblocks(P);
-    hipLaunchKernelGGL(k_loss, dim3(nb), dim3(256), 0, s, y, t, B, H, W, lam, grad, partial);
+    const double n_all = 3.0 * (double)P;
+    const double n_hx = 3.0 * (double)B * H * (W - 1);
+    const double n_hy = 3.0 * (double)B * (H - 1) * W;
+    const float c_all = (float)(1.0 / n_all);
+    const float c_mse = (float)(2.0 / n_all);
+    const float c_hx = W > 1 ? (float)((double)lam / n_hx) : 0.0f;
+    const float c_hy = H > 1 ? (float)((double)lam / n_hy) : 0.0f;
+    hipLaunchKernelGGL(k_loss, dim3(nb), dim3(256), 0, s, y, t, B, H, W, c_all, c_mse, c_hx, c_hy, grad, partial);
     hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, partial, (int64_t)nb, out);
     return hipGetLastError();
 }

@@ -595,7 +595,7 @@ struct ResolveArgs {
     const float *X, *Y, *Z;
     float *depth, *attr, *rgb, *vel;
     const float *lut;
-    int32_t lut_attr, vel_attr;
+    int32_t lut_attr, vel_attr, rgb_mode;
     float lut_min, lut_inv;
     int64_t npx;
     uint64_t n;
@@ -616,7 +616,12 @@ __global__ __launch_bounds__(kBlock) void k_resolve(ResolveArgs R, AttrPack A, P
     }
     if (R.rgb) {
         float r = 0.0f, g = 0.0f, b = 0.0f;
-        if (!empty) {
+        if (!empty && R.rgb_mode == NARVIS_COLOR_RGB8) {
+            const float s = 1.0f / 255.0f;
+            r = load_attr(A.a[R.lut_attr], i) * s;
+            g = load_attr(A.a[R.lut_attr + 1], i) * s;
+            b = load_attr(A.a[R.lut_attr + 2], i) * s;
+        } else if (!empty) {
             float t = load_attr(A.a[R.lut_attr], i) - R.lut_min;
             t = t * R.lut_inv;
             t = t * 256.0f;
@@ -839,6 +844,7 @@ hipError_t launch_resolve(const float *x, const float *y, const float *z, uint64
     R.lut = g.lut;
     R.lut_attr = g.lut_attr;
     R.vel_attr = g.vel_attr;
+    R.rgb_mode = g.rgb_mode;
     R.lut_min = g.lut_min;
     R.lut_inv = g.lut_inv_range;
     R.npx = (int64_t)P.W * P.H;

@@ -1,37 +1,46 @@
 """Image-quality metrics used to judge the post-process against the splat
-renderer (the paper reports PSNR and SSIM, Sec. 4.1).
+renderer (the paper reports PSNR and SSIM, Sec. 4.1, without defining its
+variants).
 
-PSNR = 10 log10(1 / MSE) for images in [0, 1], over all channels.
+PSNR = 10 log10(1 / MSE) for images in [0, 1], over all channels (+inf for
+identical images).
 SSIM after Wang et al. (2004): 11 x 11 Gaussian window with sigma 1.5,
 K1 = 0.01, K2 = 0.03, dynamic range 1, computed per channel on the valid
-region and averaged.  Batched torch tensors [N, 3, H, W] in, one value per
-image out.
+region (no padding) and averaged over pixels and channels.
+
+Batched torch tensors [N, C, H, W] in, one value per image out.  Both run in
+fp32 on the tensors' own device (evaluation only, not part of the hot path);
+images are clamped to [0, 1] first, as they would be displayed.
 """
 from __future__ import annotations
 
 import math
 
 
+def _prep(a):
+    return a.float().clamp(0.0, 1.0)
+
+
 def psnr(a, b):
-    d = (a.double() - b.double()) ** 2
-    mse = d.flatten(1).mean(dim=1)
-    return 10.0 * (1.0 / mse.clamp_min(1e-20)).log10()
+    import torch
+    d = _prep(a) - _prep(b)
+    mse = (d * d).flatten(1).mean(dim=1)
+    inf = torch.full_like(mse, math.inf)
+    return torch.where(mse > 0, 10.0 * torch.log10(1.0 / mse.clamp_min(1e-30)), inf)
 
 
-def _gauss(torch, device):
-    x = torch.arange(11, dtype=torch.float64, device=device) - 5.0
-    g = torch.exp(-(x * x) / (2.0 * 1.5 * 1.5))
-    g = g / g.sum()
-    return g
+def gaussian_window(torch, device, size=11, sigma=1.5):
+    x = torch.arange(size, dtype=torch.float32, device=device) - (size - 1) / 2.0
+    g = torch.exp(-(x * x) / (2.0 * sigma * sigma))
+    return g / g.sum()
 
 
 def ssim(a, b):
     import torch
     import torch.nn.functional as F
-    a = a.double()
-    b = b.double()
+    a, b = _prep(a), _prep(b)
     n, c, h, w = a.shape
-    g = _gauss(torch, a.device)
+    g = gaussian_window(torch, a.device)
     kx = g.view(1, 1, 1, 11).repeat(c, 1, 1, 1)
     ky = g.view(1, 1, 11, 1).repeat(c, 1, 1, 1)
 

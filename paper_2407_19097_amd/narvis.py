@@ -90,6 +90,7 @@ class GBuffer:
     vel_attr: int = -1
     bounds: object = None         # uint8 [narvis_raster_bounds_bytes(W, H)] scratch of the bounded render
     hint: object = None           # int64 [H*W] keys of an earlier render (hinted bounded render)
+    rgb_mode: int = 0             # COLOR_LUT or COLOR_RGB8 (three uint8 attributes from lut_attr)
 
     @staticmethod
     def allocate(W: int, H: int, nattr: int = 0, depth=True, rgb=False, vel2d=False, bounded=True, device="cuda"):
@@ -108,7 +109,7 @@ class GBuffer:
                             _ptr(self.lut), int(self.lut_attr), float(self.lut_min), float(self.lut_inv_range),
                             int(self.vel_attr), _ptr(self.bounds),
                             0 if self.bounds is None else int(self.bounds.numel() * self.bounds.element_size()),
-                            _ptr(self.hint))
+                            _ptr(self.hint), int(self.rgb_mode))
 
 
 def narvis_status_string(status: int) -> str:
@@ -289,3 +290,13 @@ def narvis_weights_calibrate_fp8(weights: NetWeights, feat, B: int, W: int, H: i
     nbytes = workspace.numel() * workspace.element_size()
     _lib.check(_lib.load().narvis_weights_calibrate_fp8(weights.handle, _ptr(feat), B, W, H, _ptr(workspace), nbytes,
                                                         _stream_ptr(stream)), "narvis_weights_calibrate_fp8")
+
+
+def narvis_train_tensor(B: int, W: int, H: int, name: str):
+    """(byte offset, channels, height, width, dtype) of a named tensor in the
+    training workspace; dtype 0 = bfloat16 NHWC, 1 = fp32 planar."""
+    off, c, h, w, dt = ctypes.c_size_t(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _lib.check(_lib.load().narvis_train_tensor(B, W, H, name.encode(), ctypes.byref(off), ctypes.byref(c),
+                                               ctypes.byref(h), ctypes.byref(w), ctypes.byref(dt)),
+               "narvis_train_tensor")
+    return int(off.value), int(c.value), int(h.value), int(w.value), int(dt.value)

@@ -144,6 +144,35 @@ def train(weights: narvis.NetWeights, feats, targets, steps: int, batch=16, lr=1
     return losses, time.time() - t0
 
 
+C2_CENTRE = (0.5, 0.5, 0.2)
+C2_DIAG = math.sqrt(1.0 + 1.0 + 0.4 * 0.4)
+
+
+def c4_views(n: int = 2000, seed: int = 4) -> List[scenes.Camera]:
+    """Hemisphere views of the vector-field volume (radius 0.75 x the box
+    diagonal around the box centre); the last 10 % are held out."""
+    return hemisphere_views(n, C2_CENTRE, 0.75 * C2_DIAG, seed=seed)
+
+
+def train_c4(sc: scenes.Scene, views: int = 2000, steps: int = 2500, res: int = 512, seed: int = 0, log=print):
+    """Train the post-process on the 9:1 training split of `views` hemisphere
+    views of `sc` at res x res (G-buffer input, splat target), Adam lr 1e-3,
+    batch 16, lam_tv 1e-3.  Returns (weights, 16 training views' inputs for
+    FP8 calibration, the held-out cameras, training seconds, loss log)."""
+    import torch
+    cams = c4_views(views)
+    ntr = int(0.9 * views)
+    r = Renderer(sc, res, res)
+    feats, targets = render_dataset(r, cams[:ntr], log=log)
+    w = narvis.NetWeights(init_blob(seed))
+    losses, secs = train(w, feats, targets, steps, batch=16, lr=1e-3, lam_tv=1e-3, seed=seed, log=log,
+                         log_every=500)
+    cal = feats[:16].clone()
+    del feats, targets, r
+    torch.cuda.empty_cache()
+    return w, cal, cams[ntr:], secs, losses
+
+
 def evaluate(weights: narvis.NetWeights, feats, targets, chunk=8):
     """(psnr of the network output, psnr of the raster's RGB planes alone, ssim net, ssim raster) vs targets."""
     import torch
@@ -154,7 +183,7 @@ def evaluate(weights: narvis.NetWeights, feats, targets, chunk=8):
     for i in range(0, n, chunk):
         b = min(chunk, n - i)
         narvis.narvis_postprocess(weights, feats[i:i + b].contiguous(), b, W, H, out, ws)
-        y = out[:b].clamp(0.0, 1.0)
+        y = out[:b]
         t = targets[i:i + b]
         p_net.append(metrics.psnr(y, t))
         p_ras.append(metrics.psnr(feats[i:i + b, 0:3], t))

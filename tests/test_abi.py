@@ -194,3 +194,57 @@ def test_splat_host_logic():
     assert L.narvis_splat_workspace_size(1 << 30, 64, 64, ctypes.byref(p)) == 0
     bad = _lib.SplatParams(0.0, 1.0, 0, 0, 0x1000, 0.0, 1.0)
     assert L.narvis_splat_workspace_size(1000, 64, 64, ctypes.byref(bad)) == 0
+
+
+def test_device_code_has_no_fp64_instructions(tmp_path):
+    """FP64 runs only on the host (the camera composition): the gfx950 code
+    object of the built library holds no double-precision VALU instruction."""
+    import shutil
+    import subprocess
+    objdump = "/opt/rocm/llvm/bin/llvm-objdump"
+    if not os.path.exists(objdump):
+        pytest.skip("llvm-objdump not available")
+    lib = os.path.join(ROOT, "paper_2407_19097_amd", "libnarvis.so")
+    if not os.path.exists(lib):
+        pytest.skip("library not built")
+    local = tmp_path / "libnarvis.so"
+    shutil.copy(lib, local)
+    # extracts every offload bundle next to the copy
+    subprocess.run([objdump, "--offloading", str(local)], check=True, capture_output=True)
+    objs = sorted(str(p) for p in tmp_path.iterdir() if p.name.endswith("gfx950"))
+    assert objs, "no gfx950 code object in the library"
+    f64 = re.compile(r"\bv_[a-z0-9_]*_f64\b")
+    for o in objs:
+        dis = subprocess.run([objdump, "-d", o], check=True, capture_output=True, text=True).stdout
+        assert "k_" in dis
+        hits = [ln.strip() for ln in dis.splitlines() if f64.search(ln)]
+        assert not hits, hits[:5]
+
+
+TRAIN_TENSORS = ["feat", "e1a", "sk1", "pool1", "e2a", "sk2", "pool2", "e3a", "sk3", "pool3", "e4a", "e4b",
+                 "up3", "d3a", "d3b", "up2", "d2a", "d2b", "up1", "d1a", "d1b", "out", "gy", "g_d1b", "g_d1a",
+                 "g_cat1", "g_d2b", "g_d2a", "g_cat2", "g_d3b", "g_d3a", "g_cat3", "g_e4b", "g_e4a", "g_pool3",
+                 "g_e3b", "g_e3a", "g_pool2", "g_e2b", "g_e2a", "g_pool1", "g_e1b", "g_e1a"]
+
+
+@pytest.mark.parametrize("B,H,W", [(2, 32, 48), (1, 40, 24), (16, 512, 512)])
+def test_train_tensor_layout(B, H, W):
+    """Every named training tensor lies inside the workspace, no two overlap,
+    and the shapes follow the network's levels."""
+    ws = narvis.narvis_train_workspace_size(B, W, H)
+    spans = []
+    for name in TRAIN_TENSORS:
+        off, c, h, w, dt = narvis.narvis_train_tensor(B, W, H, name)
+        nbytes = B * c * h * w * (4 if dt == 1 else 2)
+        assert off % 256 == 0 and off + nbytes <= ws, name
+        assert (h, w) in [(H >> lv, W >> lv) for lv in range(4)]
+        spans.append((off, off + nbytes, name))
+    spans.sort()
+    for (a0, a1, na), (b0, b1, nb) in zip(spans, spans[1:]):
+        assert a1 <= b0, (na, nb)
+    assert narvis.narvis_train_tensor(B, W, H, "out")[1:] == (3, H, W, 1)
+    assert narvis.narvis_train_tensor(B, W, H, "g_cat3")[1:] == (384, H // 4, W // 4, 0)
+    with pytest.raises(narvis.NarvisError):
+        narvis.narvis_train_tensor(B, W, H, "nope")
+    with pytest.raises(narvis.NarvisError):
+        narvis.narvis_train_tensor(B, W + 1, H, "feat")

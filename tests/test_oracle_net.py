@@ -153,3 +153,42 @@ def test_psnr():
     a = np.zeros((3, 4, 4))
     assert onet.psnr(a, a) == float("inf")
     assert onet.psnr(a, a + 0.1) == pytest.approx(20.0)
+
+
+def test_features_hand_computed_fixture():
+    """features(): a 2 x 2 image computed by hand (tests/golden/features_2x2.txt):
+    depth d > 0 becomes 1/d, an empty pixel (d = 0) gives 0, the other seven
+    planes are unchanged."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "features_2x2.txt")
+    rows = {"in": [], "out": []}
+    for line in open(path):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        kind, _name, *vals = line.split()
+        rows[kind].append([float(v) for v in vals])
+    x = np.array(rows["in"]).reshape(1, 8, 2, 2)
+    want = np.array(rows["out"]).reshape(1, 8, 2, 2)
+    np.testing.assert_array_equal(onet.features(x), want)
+    # the input array itself is left untouched
+    assert x[0, 3, 0, 0] == 2.0
+
+
+def test_crop_forward_equals_full_forward():
+    """The crop procedure the 1920 x 1080 parity test relies on: a tile's
+    outputs computed on a crop with the margin equal the full-image outputs
+    (narrow layers: the reach of an output depends on the depth only), at
+    the border and inside; a margin far below the reach does not."""
+    import netcheck
+    rng = np.random.default_rng(5)
+    table = onet.layer_table(widths=(4, 4, 4, 8), in_ch=8, out_ch=3)
+    P = onet.init_params(rng, table)
+    P = {k: (w, rng.standard_normal(b.shape) * 0.1) for k, (w, b) in P.items()}
+    x = rng.random((1, 8, 240, 304))
+    full, _ = onet.forward(P, x)
+    for (y0, y1, x0, x1) in [(0, 32, 0, 48), (104, 136, 128, 176), (208, 240, 264, 304)]:
+        tile = netcheck.crop_forward(P, x, y0, y1, x0, x1)
+        np.testing.assert_allclose(tile, full[:, :, y0:y1, x0:x1], rtol=0, atol=1e-12)
+    short = netcheck.crop_forward(P, x, 104, 136, 128, 176, margin=16)
+    assert np.abs(short - full[:, :, 104:136, 128:176]).max() > 1e-6

@@ -368,3 +368,49 @@ def test_lut_binning():
     for p in range(W):
         q = want_q[int(idx[p])]
         np.testing.assert_array_equal(out["rgb"][:, p], lut[q])
+
+
+def test_resolve_rgb8_colour_is_value_over_255():
+    """RGB8 colour mode: each of the three uint8 attributes of the winner
+    becomes (nearly) its value / 255: within one fp32 rounding of the exact
+    quotient, 0 stays 0, and the ramp is monotone; empty pixels are 0."""
+    W, H = 4, 4
+    M, near, far = ocam.clip_matrix(scenes.Camera(eye=(0, 0, 0), target=(0, 0, -1), up=(0, 1, 0),
+                                                  fovy_deg=90.0), W, H)
+    vals = np.arange(256, dtype=np.uint8)
+    # one point per pixel of the top-left 2x2 block is enough to check the
+    # mapping; every value goes through the resolve on its own pixel
+    got = np.empty((3, 256), np.float64)
+    for start in range(0, 256, 4):
+        v = vals[start:start + 4]
+        x = np.array([-0.75, -0.25, -0.75, -0.25], np.float32)
+        y = np.array([0.75, 0.75, 0.25, 0.25], np.float32)
+        z = np.full(4, -1.0, np.float32)
+        keys = orast.render(x, y, z, M, near, far, W, H)
+        r, g, b = v.copy(), v[::-1].copy(), np.full(4, 255 - start // 4, np.uint8)
+        out = orast.resolve(keys, W, H, x, y, z, M, [r, g, b], rgb_mode=1, lut_attr=0)
+        rgb = out["rgb"].reshape(3, H, W)
+        assert (out["rgb"][:, keys == orast.EMPTY] == 0).all()
+        got[0, start:start + 4] = [rgb[0, 0, 0], rgb[0, 0, 1], rgb[0, 1, 0], rgb[0, 1, 1]]
+        np.testing.assert_array_equal(rgb[1, :2, :2].ravel(), rgb[0, :2, :2].ravel()[::-1])
+        assert np.all(rgb[2, :2, :2] == rgb[2, 0, 0])
+    exact = vals / 255.0
+    assert got[0, 0] == 0.0
+    assert np.all(np.abs(got[0] - exact) <= 2.0 ** -23 * exact + 1e-45)
+    assert np.all(np.diff(got[0]) > 0)
+
+
+@pytest.mark.parametrize("threads", [1, 2, 3, 8, 13])
+def test_multithreaded_oracle_is_bit_identical(threads):
+    """The all-cores form (private key buffers merged by elementwise minimum)
+    returns the single-threaded keys bit for bit, also with ties and shared
+    pixels across the threads' ranges."""
+    sc = scenes.unit_cube(n=200_003, seed=9, W=97, H=61)
+    q = np.float32(1 / 64)
+    x, y, z = ((np.floor(a / q) * q).astype(np.float32) for a in (sc.x, sc.y, sc.z))
+    cam = scenes.Camera(eye=(1.6, 1.4, 1.2), target=(0.5, 0.5, 0.5))
+    M, near, far = ocam.clip_matrix(cam, sc.W, sc.H)
+    want = orast.render(x, y, z, M, near, far, sc.W, sc.H)
+    got = orast.render_mt(x, y, z, M, near, far, sc.W, sc.H, threads)
+    assert (want != orast.EMPTY).sum() > 1000
+    np.testing.assert_array_equal(got, want)

@@ -388,3 +388,30 @@ def test_rasterize_with_previous_frame_hint():
            "rgb": host(g.rgb), "vel2d": host(g.vel2d)}
     o = oracle_frame(sc.x, sc.y, sc.z, sc.attrs, cam2, sc.W, sc.H, **kw)
     assert_same(got, o)
+
+
+def test_rgb8_colour_into_network_input_slices():
+    """Terrain colours (AoS RGBA uint8) resolved in the RGB8 colour mode
+    straight into the network's input tensor: rgb and depth are slices of one
+    [8][H][W] buffer, bit-exact against the oracle; the velocity slices a
+    scene without velocity leaves alone stay as the caller set them."""
+    announce("terrain 90000 points 160x96, RGB8 rgb + depth into an [8][H][W] input")
+    sc = scenes.terrain(device="cpu", grid=256, lattice=300, n=90000, W=160, H=96)
+    x, y, z = (t.numpy() for t in (sc.x, sc.y, sc.z))
+    rgba = sc.extra["rgba"].numpy()
+    W, H, cam = sc.W, sc.H, sc.cameras[0]
+    RGBA = dev(rgba)
+    A = [RGBA[:, c] for c in range(4)]
+    feat = torch.zeros((8, W * H), dtype=torch.float32, device="cuda")
+    g = narvis.GBuffer(keys=torch.empty(W * H, dtype=torch.int64, device="cuda"), depth=feat[3], rgb=feat[0:3],
+                       lut_attr=0, rgb_mode=narvis.COLOR_RGB8, bounds=narvis.raster_bounds(W, H, "cuda"))
+    narvis.narvis_rasterize((dev(x), dev(y), dev(z)), A, x.shape[0], cam, W, H, g)
+    got = host(feat)
+    M, near, far = ocam.clip_matrix(cam, W, H)
+    okeys = orast.render(x, y, z, M, near, far, W, H)
+    o = orast.resolve(okeys, W, H, x, y, z, M, [rgba[:, c].copy() for c in range(4)], rgb_mode=1, lut_attr=0)
+    assert (okeys != EMPTY).mean() > 0.3
+    np.testing.assert_array_equal(host(g.keys).view(np.uint64), okeys)
+    np.testing.assert_array_equal(got[0:3].view(np.uint32), o["rgb"].view(np.uint32))
+    np.testing.assert_array_equal(got[3].view(np.uint32), o["depth"].view(np.uint32))
+    assert (got[4:8] == 0).all()
