@@ -136,7 +136,7 @@ def conv_backward(dy, cols, Wt, xshape):
     k = Wt.shape[2]
     dy2 = dy.reshape(N, co, H * Wd)
     Wm = Wt.reshape(co, -1)
-    dW = np.einsum("nop,nkp->ok", dy2, cols).reshape(Wt.shape)
+    dW = np.matmul(dy2, cols.transpose(0, 2, 1)).sum(axis=0).reshape(Wt.shape)
     db = dy2.sum(axis=(0, 2))
     dcols = np.matmul(Wm.T, dy2)
     dx = _col2im3(dcols, xshape) if k == 3 else dcols.reshape(xshape)
@@ -170,15 +170,17 @@ def upsample_matrix(n):
 
 
 def upsample2(x):
+    """y[n, c] = Uh @ x[n, c] @ Uw^T (rows, then columns interpolated)."""
     N, C, H, W = x.shape
     Uh, Uw = upsample_matrix(H), upsample_matrix(W)
-    return np.einsum("ah,nchw,bw->ncab", Uh, x, Uw)
+    return np.matmul(Uh, np.matmul(x, Uw.T))
 
 
 def upsample2_backward(dy):
+    """Adjoint of upsample2: dx[n, c] = Uh^T @ dy[n, c] @ Uw."""
     N, C, H2, W2 = dy.shape
     Uh, Uw = upsample_matrix(H2 // 2), upsample_matrix(W2 // 2)
-    return np.einsum("ah,ncab,bw->nchw", Uh, dy, Uw)
+    return np.matmul(Uh.T, np.matmul(dy, Uw))
 
 
 # ---------------------------------------------------------------------------
