@@ -121,6 +121,18 @@ typedef enum {
  *           narvis_raster_opts.hint_keys: 8-byte aligned, read only,
  *           overlapping neither keys nor the scratch.
  *   rgb_mode  narvis_color_mode of the rgb plane (0 = LUT).
+ *   glyph   optional uint8[n] glyph mask (original point order; nonzero =
+ *           glyph point) for the glyph-priority render of narvis_rasterize:
+ *           see narvis_raster_opts.glyph.
+ *   radius  float[H][W] projected splat radius of the winner in pixels
+ *           (Sec. 3.2: the rasterizer computes the projected point radius;
+ *           Sec. 4.2: the world radius is the mean distance to the four
+ *           nearest neighbours, narvis_knn_radius):
+ *           (r * radius_focal_px) / depth with r = fp32 attribute
+ *           radius_attr of the winner (each product rounded once); 0 for an
+ *           empty pixel.  narvis_rasterize sets radius_focal_px itself
+ *           (narvis_camera_focal_px); narvis_raster_resolve takes it from
+ *           the struct.
  * The depth, rgb and vel2d planes may be slices of one [8][H][W] tensor in
  * the order r, g, b, depth, v'x, v'y, theta, |v'|: that is the network input
  * narvis_postprocess reads. */
@@ -139,6 +151,10 @@ typedef struct {
     size_t bounds_bytes;
     const void *hint_keys;
     int32_t rgb_mode;
+    const uint8_t *glyph;
+    float *radius;
+    int32_t radius_attr;
+    float radius_focal_px;
 } narvis_gbuffer;
 
 /* Render-stage strategy.  Every variant produces the same key buffer; they
@@ -186,6 +202,17 @@ typedef struct {
                              uint64[H][W] of an earlier render, 8-byte
                              aligned, read only, overlapping neither `keys`
                              nor the scratch: hinted bounded render     */
+    const uint8_t *glyph;  /* NULL, or a device uint8[n] glyph mask:
+                             glyph-priority render (VisGlyph, Sec. 4.3
+                             "Glyph Stylization Support": the frontmost glyph
+                             point of a pixel is kept and non-glyph points in
+                             front of it are ignored).  A pixel that a point
+                             with glyph[i] != 0 reaches keeps the nearest such
+                             point; any other pixel keeps the nearest point.
+                             The key of a point with glyph[i] == 0 has bit 63
+                             set ((bits(w) | 2^31) << 32 | i), so the minimum
+                             key is the answer; the resolve's depth drops
+                             that bit.  Not with narvis_raster_render_layout. */
 } narvis_raster_opts;
 
 /* Parameters of the Gaussian splat renderer. */
@@ -210,6 +237,12 @@ const char *narvis_status_string(narvis_status s);
  * 0 < znear < zfar. */
 narvis_status narvis_camera_matrix(const narvis_camera *cam, int32_t W, int32_t H,
                                    float vp_rowmajor[16], float *near_f, float *far_f);
+
+/* Focal length in pixels of `cam` for an image H pixels high:
+ * (H / 2) / tan(fovy / 2), composed in FP64 on the host and rounded once to
+ * fp32 (the scale of narvis_gbuffer.radius).  Host only.  INVALID_ARG as
+ * narvis_camera_matrix. */
+narvis_status narvis_camera_focal_px(const narvis_camera *cam, int32_t H, float *focal_px);
 
 /* Bytes of the bounded render's scratch for a W x H image:
  * 2 NARVIS_TILE_BOUNDS_MAX + 4 W H; 0 for invalid W, H. */
@@ -246,6 +279,106 @@ narvis_status narvis_raster_resolve(const narvis_points *pts, const narvis_attrs
 narvis_status narvis_rasterize(const narvis_points *pts, const narvis_attrs *attrs, uint64_t n,
                                const narvis_camera *cam, int32_t W, int32_t H,
                                narvis_gbuffer *gbuf, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Spatial layout (Morton order + per-batch boxes) for the batch-culled
+ * render.  The compute rasterizer that the paper's rasterizer extends keeps
+ * its points sorted along a Morton (Z-order) curve (Sec. 3.2; Sec. 4.3 names
+ * its Morton-ordered data); a batch of consecutive points is then a compact
+ * piece of space, and its bounding box lets the render skip the whole batch
+ * when it lies outside the view volume or behind the depths already drawn.
+ * The keys are those of the original order, bit for bit: every key carries
+ * the point's original index, so ties still go to the lowest original index.
+ * ------------------------------------------------------------------------ */
+
+/* Points per batch of a layout (one box each). */
+#define NARVIS_LAYOUT_BATCH 2048
+
+/* A layout of n points, caller-owned device memory (16-byte aligned):
+ *   x, y, z  float[n]       coordinates in layout order;
+ *   index    uint32[n]      original index of each point (a permutation);
+ *   boxes    float[nb][8]   per batch b of points [2048 b, 2048 (b+1)) the
+ *                           box of its points with finite coordinates:
+ *                           xmin, ymin, zmin, 0, xmax, ymax, zmax, 0
+ *                           (+inf ... -inf when it has none),
+ *                           nb = narvis_layout_batches(n).
+ * Order (narvis_layout_build): the stable sort by the 30-bit Morton code of
+ * each point's cell in a 1024^3 grid over the box [lo, hi] of all points
+ * with finite coordinates: per axis t = (a - lo) * (1024 / (hi - lo)) in fp32
+ * (each operation rounded; scale 0 when hi == lo), cell 0 if not t > 0, 1023
+ * if t >= 1023, else floor(t); bit k of the x, y, z cells goes to bit 3k,
+ * 3k + 1, 3k + 2 of the code; a point with a non-finite coordinate gets code
+ * 2^30.  Equal codes keep the original order. */
+typedef struct {
+    float *x;
+    float *y;
+    float *z;
+    uint32_t *index;
+    float *boxes;
+} narvis_layout;
+
+/* Number of batches (boxes) of a layout of n points: ceil(n / 2048). */
+uint64_t narvis_layout_batches(uint64_t n);
+
+/* Device workspace bytes of narvis_layout_build for n points (24 n bytes
+ * and a little more); 0 for n >= 2^32. */
+size_t narvis_layout_workspace_size(uint64_t n);
+
+/* Build the layout of the n points `pts` (original order, device, any
+ * alignment) into `out` (see narvis_layout; every array 16-byte aligned and
+ * disjoint from the input).  n < 2^32.  INVALID_ARG on bad arguments,
+ * WORKSPACE if ws_bytes is too small.  Asynchronous on `stream`. */
+narvis_status narvis_layout_build(const narvis_points *pts, uint64_t n, const narvis_layout *out, void *ws,
+                                  size_t ws_bytes, void *stream);
+
+/* Render stage over a layout: the same keys as narvis_raster_render over
+ * the points in their original order (each key's low word is the original
+ * index), with whole batches skipped when their box cannot hold a kept
+ * point.  opts: variant AUTO or LDS only, bounds as for narvis_raster_render
+ * (then batches are also skipped when their box's nearest depth exceeds
+ * every tile bound under its screen rectangle); hint_keys must be NULL.
+ * n < 2^32.  INVALID_ARG otherwise. */
+narvis_status narvis_raster_render_layout(const narvis_layout *L, uint64_t n, const float vp_rowmajor[16],
+                                          float near_f, float far_f, int32_t W, int32_t H, uint64_t *keys,
+                                          const narvis_raster_opts *opts, void *stream);
+
+/* Whole frame over a layout: camera matrix, clear, batch-culled render
+ * (bounded when gbuf->bounds is given; gbuf->hint_keys must be NULL), and
+ * the resolve of narvis_rasterize, which gathers the winners' attributes by
+ * their original index from `attrs` (original order).  `pts` (original
+ * order) is needed only for the vel2d planes and may be NULL otherwise. */
+narvis_status narvis_rasterize_layout(const narvis_layout *L, const narvis_points *pts, const narvis_attrs *attrs,
+                                      uint64_t n, const narvis_camera *cam, int32_t W, int32_t H,
+                                      narvis_gbuffer *gbuf, void *stream);
+
+/* ------------------------------------------------------------------------
+ * World splat radius of every point: the mean distance to its four nearest
+ * neighbours (Sec. 4.2, the hole-filling splat radius of the terrain), the
+ * attribute that narvis_gbuffer.radius projects per pixel.  In fp32, each
+ * operation rounded in the order written:
+ *   d(i, j) = sqrt(((x_j - x_i)^2 + (y_j - y_i)^2) + (z_j - z_i)^2),
+ *   r_i = (((d1 + d2) + d3) + d4) * 0.25 with d1 <= d2 <= d3 <= d4 the four
+ *   smallest d(i, j) over the other points j with finite coordinates
+ *   (duplicates of i count, at distance 0); with m < 4 such points the m
+ *   smallest are summed the same way and divided by m; r_i = 0 when m = 0
+ *   or when a coordinate of i is not finite.
+ * Exact for every point: a uniform grid (cell size chosen from the cloud's
+ * box and measured cell occupancy) settles most points within a few rings
+ * of cells, and the others are found by a scan of all points.
+ * ------------------------------------------------------------------------ */
+
+/* Device workspace bytes of narvis_knn_radius for n points (about 28 n +
+ * 12 * 2^ceil(log2(2 n)) bytes); 0 for n >= 2^32. */
+size_t narvis_knn_radius_workspace_size(uint64_t n);
+
+/* radius: float[n] device, written for every point.  pts: original order,
+ * 4-byte aligned.  n < 2^32.  Synchronises `stream` (the grid is sized on
+ * the host from the cloud's box and occupancy, read back during the call).
+ * *cell_out (optional, host): the grid's cell edge; *unresolved_out
+ * (optional, host): the points settled by the full scan.  INVALID_ARG on bad
+ * arguments, WORKSPACE if ws_bytes is too small, DEVICE on a runtime error. */
+narvis_status narvis_knn_radius(const narvis_points *pts, uint64_t n, float *radius, void *ws, size_t ws_bytes,
+                                float *cell_out, uint32_t *unresolved_out, void *stream);
 
 /* Bytes of device workspace narvis_splat needs for n points at W x H
  * (0 if the arguments are invalid).  The size grows linearly with n: point

@@ -96,6 +96,29 @@ void oracle_render(const float *x, const float *y, const float *z, uint64_t n,
     }
 }
 
+/* Glyph-priority render (the paper's VisGlyph, Sec. 4.3 "Glyph Stylization
+ * Support": the frontmost glyph point is rendered and non-glyph points in
+ * front of it are ignored).  Reading: a pixel that some glyph point reaches
+ * keeps the nearest glyph point; a pixel that no glyph point reaches keeps
+ * the nearest point, as in the plain render.  glyph[i] != 0 marks glyph
+ * points.  The ranking (not a glyph, depth, index) is packed in the key by
+ * setting bit 63 for non-glyph points: depth bits never use bit 31 (w > 0). */
+void oracle_render_glyph(const float *x, const float *y, const float *z, uint64_t n,
+                         const float *M, float near_f, float far_f, int32_t W, int32_t H,
+                         const uint8_t *glyph, uint64_t *keys)
+{
+    const int64_t npx = (int64_t)W * (int64_t)H;
+    for (int64_t p = 0; p < npx; ++p) keys[p] = ORACLE_EMPTY;
+    for (uint64_t i = 0; i < n; ++i) {
+        int64_t p;
+        float w, cx, cy;
+        if (!project(M, near_f, far_f, W, H, x[i], y[i], z[i], &p, &w, &cx, &cy)) continue;
+        uint64_t rank = glyph[i] ? 0u : 1u;
+        uint64_t key = (rank << 63) | ((uint64_t)bits_of(w) << 32) | (uint64_t)(uint32_t)i;
+        if (key < keys[p]) keys[p] = key;
+    }
+}
+
 /* The same render restricted to points [i0, i1), merging into an existing key
  * buffer (used to time bounded samples; min is order-free, so rendering a
  * range into a buffer that already holds other ranges gives the same result). */
@@ -158,6 +181,28 @@ static float attr_value(const oracle_attr *a, uint64_t i)
     }
 }
 
+/* Projected splat radius of each pixel's winner (Sec. 3.2: MACR computes
+ * the projected point radius; Sec. 4.2: the world radius is the mean distance
+ * to the four nearest neighbours): radius_px = (r * focal_px) / depth, with r
+ * the winner's world radius (fp32 attribute), focal_px = (H / 2) / tan(fovy / 2)
+ * and depth the winner's w; 0 for an empty pixel. */
+void oracle_resolve_radius(const uint64_t *keys, int32_t W, int32_t H, const float *r_world, float focal_px,
+                           float *out)
+{
+    const int64_t npx = (int64_t)W * (int64_t)H;
+    for (int64_t p = 0; p < npx; ++p) {
+        uint64_t k = keys[p];
+        if (k == ORACLE_EMPTY) {
+            out[p] = 0.0f;
+            continue;
+        }
+        float w = float_of((uint32_t)(k >> 32) & 0x7FFFFFFFu);
+        float r = r_world[k & 0xFFFFFFFFull];
+        float t = r * focal_px;
+        out[p] = t / w;
+    }
+}
+
 /* Resolve stage plus optional derived channels.
  *   depth  [H*W]        or NULL
  *   chan   [nattr][H*W] or NULL   raw attributes of the winner
@@ -179,7 +224,7 @@ void oracle_resolve(const uint64_t *keys, int32_t W, int32_t H,
         uint64_t k = keys[p];
         int empty = (k == ORACLE_EMPTY);
         uint64_t i = k & 0xFFFFFFFFull;
-        if (depth) depth[p] = empty ? 0.0f : float_of((uint32_t)(k >> 32));
+        if (depth) depth[p] = empty ? 0.0f : float_of((uint32_t)(k >> 32) & 0x7FFFFFFFu);
         if (chan)
             for (int32_t c = 0; c < nattr; ++c)
                 chan[(int64_t)c * npx + p] = empty ? 0.0f : attr_value(&attrs[c], i);

@@ -48,18 +48,24 @@ class GBuffer(ctypes.Structure):
                 ("rgb", ctypes.c_void_p), ("vel2d", ctypes.c_void_p), ("lut", ctypes.c_void_p),
                 ("lut_attr", ctypes.c_int32), ("lut_min", ctypes.c_float), ("lut_inv_range", ctypes.c_float),
                 ("vel_attr", ctypes.c_int32), ("bounds", ctypes.c_void_p), ("bounds_bytes", ctypes.c_size_t),
-                ("hint_keys", ctypes.c_void_p), ("rgb_mode", ctypes.c_int32)]
+                ("hint_keys", ctypes.c_void_p), ("rgb_mode", ctypes.c_int32), ("glyph", ctypes.c_void_p),
+                ("radius", ctypes.c_void_p), ("radius_attr", ctypes.c_int32), ("radius_focal_px", ctypes.c_float)]
 
 
 class RasterOpts(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("grid_blocks", ctypes.c_int32), ("bounds", ctypes.c_void_p),
-                ("bounds_bytes", ctypes.c_size_t), ("hint_keys", ctypes.c_void_p)]
+                ("bounds_bytes", ctypes.c_size_t), ("hint_keys", ctypes.c_void_p), ("glyph", ctypes.c_void_p)]
 
 
 class SplatParams(ctypes.Structure):
     _fields_ = [("sigma_px", ctypes.c_float), ("opacity", ctypes.c_float), ("color_mode", ctypes.c_int32),
                 ("color_attr", ctypes.c_int32), ("lut", ctypes.c_void_p), ("lut_min", ctypes.c_float),
                 ("lut_inv_range", ctypes.c_float)]
+
+
+class Layout(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p), ("index", ctypes.c_void_p),
+                ("boxes", ctypes.c_void_p)]
 
 
 _P = ctypes.c_void_p
@@ -70,6 +76,7 @@ SIGNATURES = {
     "narvis_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "narvis_camera_matrix": (ctypes.c_int, [ctypes.POINTER(Camera), ctypes.c_int32, ctypes.c_int32, _F16,
                                             ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
+    "narvis_camera_focal_px": (ctypes.c_int, [ctypes.POINTER(Camera), ctypes.c_int32, ctypes.POINTER(ctypes.c_float)]),
     "narvis_raster_clear": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P]),
     "narvis_raster_bounds_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
     "narvis_raster_render": (ctypes.c_int, [ctypes.POINTER(Points), ctypes.c_uint64, _F16, ctypes.c_float,
@@ -80,6 +87,19 @@ SIGNATURES = {
     "narvis_rasterize": (ctypes.c_int, [ctypes.POINTER(Points), ctypes.POINTER(Attrs), ctypes.c_uint64,
                                         ctypes.POINTER(Camera), ctypes.c_int32, ctypes.c_int32,
                                         ctypes.POINTER(GBuffer), _P]),
+    "narvis_knn_radius_workspace_size": (ctypes.c_size_t, [ctypes.c_uint64]),
+    "narvis_knn_radius": (ctypes.c_int, [ctypes.POINTER(Points), ctypes.c_uint64, _P, _P, ctypes.c_size_t,
+                                         ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_uint32), _P]),
+    "narvis_layout_batches": (ctypes.c_uint64, [ctypes.c_uint64]),
+    "narvis_layout_workspace_size": (ctypes.c_size_t, [ctypes.c_uint64]),
+    "narvis_layout_build": (ctypes.c_int, [ctypes.POINTER(Points), ctypes.c_uint64, ctypes.POINTER(Layout), _P,
+                                           ctypes.c_size_t, _P]),
+    "narvis_raster_render_layout": (ctypes.c_int, [ctypes.POINTER(Layout), ctypes.c_uint64, _F16, ctypes.c_float,
+                                                   ctypes.c_float, ctypes.c_int32, ctypes.c_int32, _P,
+                                                   ctypes.POINTER(RasterOpts), _P]),
+    "narvis_rasterize_layout": (ctypes.c_int, [ctypes.POINTER(Layout), ctypes.POINTER(Points), ctypes.POINTER(Attrs),
+                                               ctypes.c_uint64, ctypes.POINTER(Camera), ctypes.c_int32,
+                                               ctypes.c_int32, ctypes.POINTER(GBuffer), _P]),
     "narvis_splat_workspace_size": (ctypes.c_size_t, [ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32,
                                                        ctypes.POINTER(SplatParams)]),
     "narvis_splat": (ctypes.c_int, [ctypes.POINTER(Points), ctypes.POINTER(Attrs), ctypes.c_uint64,

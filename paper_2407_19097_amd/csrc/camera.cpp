@@ -69,3 +69,13 @@ extern "C" narvis_status narvis_camera_matrix(const narvis_camera *cam, int32_t 
     if (far_f) *far_f = (float)fa;
     return NARVIS_OK;
 }
+
+extern "C" narvis_status narvis_camera_focal_px(const narvis_camera *cam, int32_t H, float *focal_px)
+{
+    if (!cam || !focal_px || H < 1) return NARVIS_ERR_INVALID_ARG;
+    if (!(cam->fovy_deg > 0.0 && cam->fovy_deg < 180.0)) return NARVIS_ERR_INVALID_ARG;
+    const double kPi = 3.14159265358979323846;
+    const double t = std::tan(cam->fovy_deg * (kPi / 180.0) / 2.0);
+    *focal_px = (float)((double)H * 0.5 / t);
+    return NARVIS_OK;
+}

@@ -133,6 +133,13 @@ extern "C" narvis_status narvis_raster_clear(uint64_t *keys, int32_t W, int32_t 
 
 // a hint needs the bounded render's scratch, 8-byte alignment, and no
 // overlap with the keys or the scratch (it is read while they are written)
+// the radius plane reads attribute radius_attr with a finite focal length
+static bool radius_ok(const narvis_gbuffer &g, const AttrPack &pack)
+{
+    if (!g.radius) return true;
+    return g.radius_attr >= 0 && g.radius_attr < pack.count;
+}
+
 static bool hint_ok(const void *hint, const void *keys, const void *bounds, size_t bounds_bytes, int32_t W, int32_t H)
 {
     if (!hint) return true;
@@ -166,9 +173,11 @@ extern "C" narvis_status narvis_raster_render(const narvis_points *pts, uint64_t
     if (n > 0 && ((reinterpret_cast<uintptr_t>(pts->x) | reinterpret_cast<uintptr_t>(pts->y) |
                    reinterpret_cast<uintptr_t>(pts->z)) & 3u))
         return NARVIS_ERR_INVALID_ARG;
+    const uint8_t *glyph = (opts && n > 0) ? opts->glyph : nullptr;
     const Proj P = make_proj(vp, near_f, far_f, W, H);
     return from_hip(launch_render(n ? pts->x : nullptr, n ? pts->y : nullptr, n ? pts->z : nullptr, n, P, keys,
-                                  variant, grid, static_cast<uint16_t *>(bounds), hint, static_cast<hipStream_t>(stream)));
+                                  variant, grid, static_cast<uint16_t *>(bounds), hint, static_cast<hipStream_t>(stream),
+                                  LayoutArgs{nullptr, nullptr, glyph}));
 }
 
 extern "C" narvis_status narvis_raster_resolve(const narvis_points *pts, const narvis_attrs *attrs, uint64_t n,
@@ -180,7 +189,8 @@ extern "C" narvis_status narvis_raster_resolve(const narvis_points *pts, const n
     AttrPack pack;
     if (!pack_attrs(attrs, n, pack)) return NARVIS_ERR_INVALID_ARG;
     if (gbuf->attr && pack.count == 0) return NARVIS_ERR_INVALID_ARG;
-    if (!rgb_ok(*gbuf, pack)) return NARVIS_ERR_INVALID_ARG;
+    if (!rgb_ok(*gbuf, pack) || !radius_ok(*gbuf, pack)) return NARVIS_ERR_INVALID_ARG;
+    if (gbuf->radius && !std::isfinite(gbuf->radius_focal_px)) return NARVIS_ERR_INVALID_ARG;
     if (gbuf->vel2d) {
         if (gbuf->vel_attr < 0 || gbuf->vel_attr + 2 >= pack.count) return NARVIS_ERR_INVALID_ARG;
         if (!points_ok(pts, n) || !vp) return NARVIS_ERR_INVALID_ARG;
@@ -196,9 +206,12 @@ extern "C" narvis_status narvis_raster_resolve(const narvis_points *pts, const n
                                    static_cast<hipStream_t>(stream)));
 }
 
-extern "C" narvis_status narvis_rasterize(const narvis_points *pts, const narvis_attrs *attrs, uint64_t n,
-                                          const narvis_camera *cam, int32_t W, int32_t H, narvis_gbuffer *gbuf,
-                                          void *stream)
+namespace {
+
+// Whole frame with the bounds scratch `bounds` (NULL: single pass).
+narvis_status rasterize_frame(const narvis_points *pts, const narvis_attrs *attrs, uint64_t n,
+                              const narvis_camera *cam, int32_t W, int32_t H, const narvis_gbuffer *gbuf,
+                              void *bounds, size_t bounds_bytes, void *stream)
 {
     float vp[16], near_f = 0.0f, far_f = 0.0f;
     narvis_status st = narvis_camera_matrix(cam, W, H, vp, &near_f, &far_f);
@@ -209,25 +222,176 @@ extern "C" narvis_status narvis_rasterize(const narvis_points *pts, const narvis
     if (!matrix_ok(vp, near_f, far_f)) return NARVIS_ERR_INVALID_ARG;
     // validate the resolve arguments before enqueuing anything
     if (gbuf->attr && pack.count == 0) return NARVIS_ERR_INVALID_ARG;
-    if (!rgb_ok(*gbuf, pack)) return NARVIS_ERR_INVALID_ARG;
+    if (!rgb_ok(*gbuf, pack) || !radius_ok(*gbuf, pack)) return NARVIS_ERR_INVALID_ARG;
     if (gbuf->vel2d && (gbuf->vel_attr < 0 || gbuf->vel_attr + 2 >= pack.count)) return NARVIS_ERR_INVALID_ARG;
+    narvis_gbuffer g = *gbuf;
+    if (g.radius && narvis_camera_focal_px(cam, H, &g.radius_focal_px) != NARVIS_OK) return NARVIS_ERR_INVALID_ARG;
     if (n > 0 && ((reinterpret_cast<uintptr_t>(pts->x) | reinterpret_cast<uintptr_t>(pts->y) |
                    reinterpret_cast<uintptr_t>(pts->z)) & 3u))
         return NARVIS_ERR_INVALID_ARG;
-    if ((reinterpret_cast<uintptr_t>(gbuf->keys) & 7u) || (reinterpret_cast<uintptr_t>(gbuf->bounds) & 3u))
+    if ((reinterpret_cast<uintptr_t>(gbuf->keys) & 7u) || (reinterpret_cast<uintptr_t>(bounds) & 3u))
         return NARVIS_ERR_INVALID_ARG;
-    if (gbuf->bounds && gbuf->bounds_bytes < narvis_raster_bounds_bytes(W, H)) return NARVIS_ERR_WORKSPACE;
-    if (!hint_ok(gbuf->hint_keys, gbuf->keys, gbuf->bounds, gbuf->bounds_bytes, W, H)) return NARVIS_ERR_INVALID_ARG;
+    if (bounds && bounds_bytes < narvis_raster_bounds_bytes(W, H)) return NARVIS_ERR_WORKSPACE;
+    if (!hint_ok(gbuf->hint_keys, gbuf->keys, bounds, bounds_bytes, W, H)) return NARVIS_ERR_INVALID_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);
     st = from_hip(launch_clear(gbuf->keys, (int64_t)W * H, s));
     if (st != NARVIS_OK) return st;
     const Proj P = make_proj(vp, near_f, far_f, W, H);
     st = from_hip(launch_render(n ? pts->x : nullptr, n ? pts->y : nullptr, n ? pts->z : nullptr, n, P,
-                                gbuf->keys, NARVIS_RENDER_AUTO, 0, static_cast<uint16_t *>(gbuf->bounds),
-                                static_cast<const uint64_t *>(gbuf->hint_keys), s));
+                                gbuf->keys, NARVIS_RENDER_AUTO, 0, static_cast<uint16_t *>(bounds),
+                                static_cast<const uint64_t *>(gbuf->hint_keys), s,
+                                LayoutArgs{nullptr, nullptr, n ? gbuf->glyph : nullptr}));
     if (st != NARVIS_OK) return st;
-    return from_hip(launch_resolve(n ? pts->x : nullptr, n ? pts->y : nullptr, n ? pts->z : nullptr, n, P, pack,
-                                   *gbuf, s));
+    return from_hip(launch_resolve(n ? pts->x : nullptr, n ? pts->y : nullptr, n ? pts->z : nullptr, n, P, pack, g,
+                                   s));
+}
+
+}  // namespace
+
+extern "C" narvis_status narvis_rasterize(const narvis_points *pts, const narvis_attrs *attrs, uint64_t n,
+                                          const narvis_camera *cam, int32_t W, int32_t H, narvis_gbuffer *gbuf,
+                                          void *stream)
+{
+    if (!gbuf) return NARVIS_ERR_INVALID_ARG;
+    return rasterize_frame(pts, attrs, n, cam, W, H, gbuf, gbuf->bounds, gbuf->bounds_bytes, stream);
+}
+
+// ---------------------------------------------------------------------------
+// spatial layout
+// ---------------------------------------------------------------------------
+
+extern "C" uint64_t narvis_layout_batches(uint64_t n) { return (n + NARVIS_LAYOUT_BATCH - 1) / NARVIS_LAYOUT_BATCH; }
+
+extern "C" size_t narvis_layout_workspace_size(uint64_t n)
+{
+    if (n >= (uint64_t(1) << 32)) return 0;
+    return (size_t)layout_workspace(n).bytes;
+}
+
+namespace {
+
+bool aligned16(const void *p) { return !(reinterpret_cast<uintptr_t>(p) & 15u); }
+
+// a layout of n points: every array given and 16-byte aligned
+bool layout_ok(const narvis_layout *L, uint64_t n)
+{
+    if (!L || n >= (uint64_t(1) << 32)) return false;
+    if (n == 0) return true;
+    return L->x && L->y && L->z && L->index && L->boxes && aligned16(L->x) && aligned16(L->y) && aligned16(L->z) &&
+           aligned16(L->index) && aligned16(L->boxes);
+}
+
+}  // namespace
+
+extern "C" narvis_status narvis_layout_build(const narvis_points *pts, uint64_t n, const narvis_layout *out, void *ws,
+                                             size_t ws_bytes, void *stream)
+{
+    if (!points_ok(pts, n) || !layout_ok(out, n)) return NARVIS_ERR_INVALID_ARG;
+    if (n > 0 && ((reinterpret_cast<uintptr_t>(pts->x) | reinterpret_cast<uintptr_t>(pts->y) |
+                   reinterpret_cast<uintptr_t>(pts->z)) & 3u))
+        return NARVIS_ERR_INVALID_ARG;
+    if (!ws || ws_bytes < narvis_layout_workspace_size(n)) return NARVIS_ERR_WORKSPACE;
+    if (n == 0) return NARVIS_OK;
+    // the outputs must not overlap the inputs (the gather reads them)
+    const uintptr_t in[3] = {reinterpret_cast<uintptr_t>(pts->x), reinterpret_cast<uintptr_t>(pts->y),
+                             reinterpret_cast<uintptr_t>(pts->z)};
+    const uintptr_t o[3] = {reinterpret_cast<uintptr_t>(out->x), reinterpret_cast<uintptr_t>(out->y),
+                            reinterpret_cast<uintptr_t>(out->z)};
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            if (o[a] < in[b] + 4 * n && in[b] < o[a] + 4 * n) return NARVIS_ERR_INVALID_ARG;
+    return from_hip(launch_layout(pts->x, pts->y, pts->z, n, out->x, out->y, out->z, out->index, out->boxes, ws,
+                                  static_cast<hipStream_t>(stream)));
+}
+
+extern "C" size_t narvis_knn_radius_workspace_size(uint64_t n)
+{
+    if (n >= (uint64_t(1) << 32)) return 0;
+    return (size_t)knn_workspace(n).bytes;
+}
+
+extern "C" narvis_status narvis_knn_radius(const narvis_points *pts, uint64_t n, float *radius, void *ws,
+                                           size_t ws_bytes, float *cell_out, uint32_t *unresolved_out, void *stream)
+{
+    if (!points_ok(pts, n) || n >= (uint64_t(1) << 32) || (n > 0 && !radius)) return NARVIS_ERR_INVALID_ARG;
+    if (n > 0 && ((reinterpret_cast<uintptr_t>(pts->x) | reinterpret_cast<uintptr_t>(pts->y) |
+                   reinterpret_cast<uintptr_t>(pts->z) | reinterpret_cast<uintptr_t>(radius)) & 3u))
+        return NARVIS_ERR_INVALID_ARG;
+    if (!ws || ws_bytes < narvis_knn_radius_workspace_size(n) || (reinterpret_cast<uintptr_t>(ws) & 255u))
+        return NARVIS_ERR_WORKSPACE;
+    KnnStats st{};
+    const narvis_status r = from_hip(launch_knn(n ? pts->x : nullptr, n ? pts->y : nullptr, n ? pts->z : nullptr, n,
+                                                radius, ws, static_cast<hipStream_t>(stream), &st));
+    if (r != NARVIS_OK) return r;
+    if (cell_out) *cell_out = st.cell;
+    if (unresolved_out) *unresolved_out = st.unresolved;
+    return NARVIS_OK;
+}
+
+namespace {
+
+LayoutArgs layout_args(const narvis_layout *L, uint64_t n)
+{
+    return LayoutArgs{n ? L->index : nullptr, n ? reinterpret_cast<const float4 *>(L->boxes) : nullptr, nullptr};
+}
+
+}  // namespace
+
+extern "C" narvis_status narvis_raster_render_layout(const narvis_layout *L, uint64_t n, const float vp[16],
+                                                     float near_f, float far_f, int32_t W, int32_t H, uint64_t *keys,
+                                                     const narvis_raster_opts *opts, void *stream)
+{
+    if (!keys || !image_ok(W, H) || !layout_ok(L, n) || !matrix_ok(vp, near_f, far_f)) return NARVIS_ERR_INVALID_ARG;
+    if (reinterpret_cast<uintptr_t>(keys) & 7u) return NARVIS_ERR_INVALID_ARG;
+    const int32_t variant = opts ? opts->variant : NARVIS_RENDER_AUTO;
+    const int32_t grid = opts ? opts->grid_blocks : 0;
+    void *bounds = opts ? opts->bounds : nullptr;
+    if ((variant != NARVIS_RENDER_AUTO && variant != NARVIS_RENDER_LDS) || grid < 0) return NARVIS_ERR_INVALID_ARG;
+    if (opts && (opts->hint_keys || opts->glyph)) return NARVIS_ERR_INVALID_ARG;
+    if (reinterpret_cast<uintptr_t>(bounds) & 3u) return NARVIS_ERR_INVALID_ARG;
+    if (bounds && opts->bounds_bytes < narvis_raster_bounds_bytes(W, H)) return NARVIS_ERR_WORKSPACE;
+    const Proj P = make_proj(vp, near_f, far_f, W, H);
+    return from_hip(launch_render(n ? L->x : nullptr, n ? L->y : nullptr, n ? L->z : nullptr, n, P, keys,
+                                  NARVIS_RENDER_LDS, grid, static_cast<uint16_t *>(bounds), nullptr,
+                                  static_cast<hipStream_t>(stream), layout_args(L, n)));
+}
+
+extern "C" narvis_status narvis_rasterize_layout(const narvis_layout *L, const narvis_points *pts,
+                                                 const narvis_attrs *attrs, uint64_t n, const narvis_camera *cam,
+                                                 int32_t W, int32_t H, narvis_gbuffer *gbuf, void *stream)
+{
+    float vp[16], near_f = 0.0f, far_f = 0.0f;
+    narvis_status st = narvis_camera_matrix(cam, W, H, vp, &near_f, &far_f);
+    if (st != NARVIS_OK) return st;
+    if (!gbuf || !gbuf->keys || !image_ok(W, H) || !layout_ok(L, n)) return NARVIS_ERR_INVALID_ARG;
+    if (gbuf->hint_keys || gbuf->glyph) return NARVIS_ERR_INVALID_ARG;
+    AttrPack pack;
+    if (!pack_attrs(attrs, n, pack)) return NARVIS_ERR_INVALID_ARG;
+    if (!matrix_ok(vp, near_f, far_f)) return NARVIS_ERR_INVALID_ARG;
+    if (gbuf->attr && pack.count == 0) return NARVIS_ERR_INVALID_ARG;
+    if (!rgb_ok(*gbuf, pack) || !radius_ok(*gbuf, pack)) return NARVIS_ERR_INVALID_ARG;
+    narvis_gbuffer g = *gbuf;
+    if (g.radius && narvis_camera_focal_px(cam, H, &g.radius_focal_px) != NARVIS_OK) return NARVIS_ERR_INVALID_ARG;
+    if (gbuf->vel2d) {
+        if (gbuf->vel_attr < 0 || gbuf->vel_attr + 2 >= pack.count || !points_ok(pts, n)) return NARVIS_ERR_INVALID_ARG;
+        if (n > 0 && ((reinterpret_cast<uintptr_t>(pts->x) | reinterpret_cast<uintptr_t>(pts->y) |
+                       reinterpret_cast<uintptr_t>(pts->z)) & 3u))
+            return NARVIS_ERR_INVALID_ARG;
+    }
+    if ((reinterpret_cast<uintptr_t>(gbuf->keys) & 7u) || (reinterpret_cast<uintptr_t>(gbuf->bounds) & 3u))
+        return NARVIS_ERR_INVALID_ARG;
+    if (gbuf->bounds && gbuf->bounds_bytes < narvis_raster_bounds_bytes(W, H)) return NARVIS_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    st = from_hip(launch_clear(gbuf->keys, (int64_t)W * H, s));
+    if (st != NARVIS_OK) return st;
+    const Proj P = make_proj(vp, near_f, far_f, W, H);
+    st = from_hip(launch_render(n ? L->x : nullptr, n ? L->y : nullptr, n ? L->z : nullptr, n, P, gbuf->keys,
+                                NARVIS_RENDER_LDS, 0, static_cast<uint16_t *>(gbuf->bounds), nullptr, s,
+                                layout_args(L, n)));
+    if (st != NARVIS_OK) return st;
+    const bool need_pts = gbuf->vel2d != nullptr && n > 0;
+    return from_hip(launch_resolve(need_pts ? pts->x : nullptr, need_pts ? pts->y : nullptr,
+                                   need_pts ? pts->z : nullptr, n, P, pack, g, s));
 }
 
 namespace {

@@ -40,10 +40,38 @@ struct DeviceInfo {
 };
 DeviceInfo device_info();
 
+// Workspace carve-up of the nearest-neighbour radius (size query and launcher).
+struct KnnWorkspace {
+    uint64_t slots;  // hash table slots (a power of two >= 2 n)
+    uint64_t off_bb, off_count, off_sum, off_ka, off_kb, off_va, off_vb, off_hist, off_sums, off_hkey, off_hval,
+        off_unres;
+    uint64_t bytes;
+};
+struct KnnStats {
+    float cell, occupancy;
+    uint64_t finite;
+    uint32_t unresolved;
+};
+KnnWorkspace knn_workspace(uint64_t n);
+hipError_t launch_knn(const float *x, const float *y, const float *z, uint64_t n, float *radius, void *ws,
+                      hipStream_t s, KnnStats *stats);
+
+// Extra per-point streams of the render.  Layout: the points are in layout
+// order, ix gives the original index of each point and box one box per batch
+// of NARVIS_LAYOUT_BATCH points (two float4: minima, maxima); ix == nullptr:
+// original order.  glyph: one byte per point (nonzero = glyph point) for the
+// glyph-priority render, or nullptr.  A layout and a glyph mask are not
+// combined.
+struct LayoutArgs {
+    const uint32_t *ix;
+    const float4 *box;
+    const uint8_t *glyph;
+};
+
 hipError_t launch_clear(uint64_t *keys, int64_t npx, hipStream_t s);
 hipError_t launch_render(const float *x, const float *y, const float *z, uint64_t n, const Proj &P,
                          uint64_t *keys, int32_t variant, int32_t grid_blocks, uint16_t *bounds, const uint64_t *hint,
-                         hipStream_t s);
+                         hipStream_t s, const LayoutArgs &lay = LayoutArgs{nullptr, nullptr, nullptr});
 hipError_t launch_resolve(const float *x, const float *y, const float *z, uint64_t n, const Proj &P,
                           const AttrPack &attrs, const narvis_gbuffer &g, hipStream_t s);
 
@@ -57,5 +85,25 @@ struct SplatLayout {
 SplatLayout splat_layout(uint64_t n, int32_t W, int32_t H, float sigma);
 hipError_t launch_splat(const float *x, const float *y, const float *z, uint64_t n, const Proj &P, const AttrPack &A,
                         const narvis_splat_params &prm, float *img, void *ws, hipStream_t s);
+
+// Workspace carve-up of the layout build (shared by the size query and the
+// launcher).
+struct LayoutWorkspace {
+    uint64_t off_bb, off_count, off_ka, off_kb, off_va, off_vb, off_hist, off_sums;
+    uint64_t bytes;
+};
+LayoutWorkspace layout_workspace(uint64_t n);
+hipError_t launch_layout(const float *x, const float *y, const float *z, uint64_t n, float *xs, float *ys, float *zs,
+                         uint32_t *ix, float *box, void *ws, hipStream_t s);
+
+// Stable LSD radix sort (8-bit digits) of the first min(*count, cap) (key,
+// value) pairs by the low key_bits bits of the keys, ping-ponging between
+// (ka, va) and (kb, vb); *in_b tells where the result ends.  hist and sums
+// hold radix_sort_hist_len(cap) and radix_sort_sums_len(cap) uint32.
+hipError_t launch_radix_sort(unsigned long long *ka, uint32_t *va, unsigned long long *kb, uint32_t *vb,
+                             const uint32_t *count, uint64_t cap, int key_bits, uint32_t *hist, uint32_t *sums,
+                             hipStream_t s, bool *in_b);
+uint64_t radix_sort_hist_len(uint64_t cap);
+uint64_t radix_sort_sums_len(uint64_t cap);
 
 }  // namespace narvis

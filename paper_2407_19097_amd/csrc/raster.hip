@@ -15,6 +15,10 @@
 // final G-buffers"): one thread per pixel gathers the winner's attributes.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+#include <type_traits>
+#include <vector>
+
 #include "internal.h"
 
 #pragma clang fp contract(off)
@@ -24,6 +28,7 @@ namespace narvis {
 namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kBlock = 256;
 constexpr int kQuadsPerThread = 2;
@@ -108,10 +113,21 @@ __device__ __forceinline__ bool project(const Proj &P, float x, float y, float z
     return ok;
 }
 
-template <int VARIANT>
-__device__ __forceinline__ void merge(unsigned long long *keys, uint32_t pix, float w, uint32_t idx)
+// Glyph-priority render (VisGlyph): a point that is not a glyph point
+// carries bit 31 in the high word of its key, so any glyph point reaching a
+// pixel beats every non-glyph point there (depth bits never use bit 31: the
+// kept depths are positive).
+constexpr uint32_t kNotGlyph = 0x80000000u;
+
+__device__ __forceinline__ uint32_t glyph_rank(const uint8_t *glyph, uint64_t i)
 {
-    const unsigned long long key = ((unsigned long long)__float_as_uint(w) << 32) | idx;
+    return glyph ? (glyph[i] ? 0u : kNotGlyph) : 0u;
+}
+
+template <int VARIANT>
+__device__ __forceinline__ void merge(unsigned long long *keys, uint32_t pix, float w, uint32_t idx, uint32_t rank = 0)
+{
+    const unsigned long long key = ((unsigned long long)(__float_as_uint(w) | rank) << 32) | idx;
     if (VARIANT == NARVIS_RENDER_EARLYZ) {
         if (key >= keys[pix]) return;
     }
@@ -143,7 +159,8 @@ __device__ __forceinline__ uint64_t logical_block(const ChunkOrder &o)
 template <int VARIANT>
 __global__ __launch_bounds__(kBlock) void k_render_vec(const float *__restrict__ X, const float *__restrict__ Y,
                                                         const float *__restrict__ Z, uint64_t n, Proj P,
-                                                        unsigned long long *__restrict__ keys, ChunkOrder order)
+                                                        unsigned long long *__restrict__ keys, ChunkOrder order,
+                                                        const uint8_t *__restrict__ glyph)
 {
     const uint64_t nq = n >> 2;
     const uint64_t lb = logical_block(order);
@@ -181,7 +198,8 @@ __global__ __launch_bounds__(kBlock) void k_render_vec(const float *__restrict__
                 uint32_t pp = 0;
                 hit[k * 4 + j] = live && project(P, px[j], py[j], pz[j], pp, w);
                 pix[k * 4 + j] = pp;
-                key[k * 4 + j] = ((unsigned long long)__float_as_uint(w) << 32) | (i0 + (uint32_t)j);
+                const uint32_t rank = (live && glyph) ? glyph_rank(glyph, (q << 2) + j) : 0u;
+                key[k * 4 + j] = ((unsigned long long)(__float_as_uint(w) | rank) << 32) | (i0 + (uint32_t)j);
             }
         }
         if (VARIANT == NARVIS_RENDER_EARLYZ) {
@@ -212,7 +230,7 @@ __global__ __launch_bounds__(kBlock) void k_render_vec(const float *__restrict__
         const uint64_t i = (nq << 2) + threadIdx.x;
         uint32_t pix;
         float w;
-        if (project(P, X[i], Y[i], Z[i], pix, w)) merge<VARIANT>(keys, pix, w, (uint32_t)i);
+        if (project(P, X[i], Y[i], Z[i], pix, w)) merge<VARIANT>(keys, pix, w, (uint32_t)i, glyph_rank(glyph, i));
     }
 }
 
@@ -294,27 +312,138 @@ struct TileGrid {
     uint32_t shift, tiles_x, ntiles;
 };
 
+__device__ __forceinline__ float wave_min(float v)
+{
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v = fminf(v, __shfl_xor(v, d));
+    return v;
+}
+
+__device__ __forceinline__ float wave_max(float v)
+{
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v = fmaxf(v, __shfl_xor(v, d));
+    return v;
+}
+
+// Whole-batch cull of the layout render (every lane of the wave must call it
+// with the same box; every lane returns the same answer, so a workgroup whose
+// waves all call it stays uniform).  The eight corners of the batch's box are
+// projected with the points' own arithmetic.  A point of the box has clip
+// values within the corners' hull widened by the rounding of both
+// evaluations (four rounded operations each: below 2^-21 of the row's sum of
+// magnitudes S); the test widens by 2^-20 S.  Lane l takes corner (l & 31) >> 2
+// and margin signs l & 3; min/max over the wave give the depth range and, when
+// every depth is positive, the range of cx/w and cy/w (a ratio of affine
+// functions takes its extremes at the hull's vertices; rounding is monotone),
+// hence the screen rectangle.  True when no point of the box can be kept:
+// its depth range misses [near, far], its rectangle misses the image, or
+// (OCCL) its nearest depth exceeds the tile bound of every tile that the
+// rectangle, one pixel wider on each side, touches.  A box without a finite
+// point (+inf/-inf) is culled: non-finite points never pass the cull.
+template <bool OCCL>
+__device__ __forceinline__ bool batch_culled(const Proj &P, float4 lo, float4 hi, const uint16_t *tb, uint32_t shift,
+                                             uint32_t tiles_x)
+{
+    if (!(lo.x <= hi.x)) return true;
+    const uint32_t lane = threadIdx.x & 31, c = lane >> 2, sg = lane & 3;
+    const float x = (c & 1) ? hi.x : lo.x, y = (c & 2) ? hi.y : lo.y, z = (c & 4) ? hi.z : lo.z;
+    const float ax = fmaxf(fabsf(lo.x), fabsf(hi.x)), ay = fmaxf(fabsf(lo.y), fabsf(hi.y)),
+                az = fmaxf(fabsf(lo.z), fabsf(hi.z));
+    float cx = P.m00 * x;
+    cx = cx + P.m01 * y;
+    cx = cx + P.m02 * z;
+    cx = cx + P.m03;
+    float cy = P.m10 * x;
+    cy = cy + P.m11 * y;
+    cy = cy + P.m12 * z;
+    cy = cy + P.m13;
+    float w = P.m30 * x;
+    w = w + P.m31 * y;
+    w = w + P.m32 * z;
+    w = w + P.m33;
+    float sx = fabsf(P.m00) * ax;
+    sx = sx + fabsf(P.m01) * ay;
+    sx = sx + fabsf(P.m02) * az;
+    sx = sx + fabsf(P.m03);
+    float sy = fabsf(P.m10) * ax;
+    sy = sy + fabsf(P.m11) * ay;
+    sy = sy + fabsf(P.m12) * az;
+    sy = sy + fabsf(P.m13);
+    float sw = fabsf(P.m30) * ax;
+    sw = sw + fabsf(P.m31) * ay;
+    sw = sw + fabsf(P.m32) * az;
+    sw = sw + fabsf(P.m33);
+    const float mx = sx * 0x1p-20f, my = sy * 0x1p-20f, mw = sw * 0x1p-20f;
+    const float wlo = wave_min(w - mw), whi = wave_max(w + mw);
+    if (whi < P.near_f || wlo > P.far_f) return true;
+    if (!(wlo > 0.0f)) return false;  // the box reaches behind the eye: no rectangle
+    const float wv = (sg & 2) ? w + mw : w - mw;
+    const float nx = ((sg & 1) ? cx + mx : cx - mx) / wv;
+    const float ny = ((sg & 1) ? cy + my : cy - my) / wv;
+    const float nxlo = wave_min(nx), nxhi = wave_max(nx), nylo = wave_min(ny), nyhi = wave_max(ny);
+    float sxlo = nxlo * 0.5f;
+    sxlo = sxlo + 0.5f;
+    sxlo = sxlo * P.Wf;
+    float sxhi = nxhi * 0.5f;
+    sxhi = sxhi + 0.5f;
+    sxhi = sxhi * P.Wf;
+    float sylo = nyhi * 0.5f;
+    sylo = 0.5f - sylo;
+    sylo = sylo * P.Hf;
+    float syhi = nylo * 0.5f;
+    syhi = 0.5f - syhi;
+    syhi = syhi * P.Hf;
+    if (sxhi < 0.0f || sxlo >= P.Wf || syhi < 0.0f || sylo >= P.Hf) return true;
+    if (!OCCL) return false;
+    const uint32_t ix0 = (uint32_t)fmaxf(floorf(sxlo) - 1.0f, 0.0f);
+    const uint32_t ix1 = (uint32_t)fminf(floorf(sxhi) + 1.0f, P.Wf - 1.0f);
+    const uint32_t iy0 = (uint32_t)fmaxf(floorf(sylo) - 1.0f, 0.0f);
+    const uint32_t iy1 = (uint32_t)fminf(floorf(syhi) + 1.0f, P.Hf - 1.0f);
+    const uint32_t tx0 = ix0 >> shift, tx1 = ix1 >> shift, ty0 = iy0 >> shift, ty1 = iy1 >> shift;
+    if (tx1 < tx0 || ty1 < ty0) return false;
+    const uint32_t ntx = tx1 - tx0 + 1, nt = ntx * (ty1 - ty0 + 1);
+    if (nt > 1024) return false;
+    // kept points have depth >= max(lowest depth, near), positive: their bit
+    // patterns order like the depths
+    const uint32_t dlo = __float_as_uint(fmaxf(wlo, P.near_f)) >> 16;
+    uint32_t m = 0;
+    for (uint32_t t = threadIdx.x & 63; t < nt; t += 64) m = max(m, (uint32_t)tb[(ty0 + t / ntx) * tiles_x + tx0 + t % ntx]);
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, d));
+    return dlo > m;
+}
+
 __device__ __forceinline__ void render_tail(const float *X, const float *Y, const float *Z, uint64_t n,
-                                            const Proj &P, unsigned long long *keys, const ChunkSel &sel)
+                                            const Proj &P, unsigned long long *keys, const ChunkSel &sel,
+                                            const uint32_t *ix = nullptr, const uint8_t *glyph = nullptr)
 {
     const uint64_t nq = n >> 2;
     if (sel.tail && blockIdx.x == 0 && threadIdx.x < (n & 3)) {
         const uint64_t i = (nq << 2) + threadIdx.x;
         uint32_t pix;
         float w;
-        if (project(P, X[i], Y[i], Z[i], pix, w)) merge<NARVIS_RENDER_EARLYZ>(keys, pix, w, (uint32_t)i);
+        if (project(P, X[i], Y[i], Z[i], pix, w))
+            merge<NARVIS_RENDER_EARLYZ>(keys, pix, w, ix ? ix[i] : (uint32_t)i, glyph_rank(glyph, i));
     }
 }
 
 // (4 waves per SIMD: the compiler keeps it within 128 registers)
-template <bool RCP>
+// MODE 1 (layout): the points are in layout order; key indices come from the
+// index stream, and a chunk (= one batch) outside the view volume is skipped
+// whole.  The slot winner's pixel is then recorded by the winner itself (its
+// key is unique) instead of being looked up from its position in the chunk.
+// MODE 2 (glyph priority): the glyph mask, one byte per point, sets the rank
+// bit of non-glyph points' keys.
+template <bool RCP, int MODE>
 __global__ __launch_bounds__(kBlock, 4) void k_render_lds(const float *__restrict__ X, const float *__restrict__ Y,
                                                         const float *__restrict__ Z, uint64_t n, Proj P,
                                                         unsigned long long *__restrict__ keys, ChunkOrder order,
-                                                        ChunkSel sel)
+                                                        ChunkSel sel, LayoutArgs lay)
 {
+    constexpr bool IX = MODE == 1, GLYPH = MODE == 2;
     __shared__ unsigned long long best[kSlots];
-    __shared__ uint32_t pixof[kChunk];
+    __shared__ uint32_t pixof[kChunk];  // IX: pixel of each slot's winner
     for (int s = threadIdx.x; s < kSlots; s += kBlock) best[s] = NARVIS_KEY_EMPTY;
     const uint64_t nq = n >> 2;
     const uint64_t lb = logical_block(order);
@@ -324,16 +453,23 @@ __global__ __launch_bounds__(kBlock, 4) void k_render_lds(const float *__restric
     __syncthreads();
     // uniform trip count for the whole workgroup: the barriers below need it
     for (uint64_t v = lb; v < sel.nv; v += gridDim.x) {
-        const uint64_t start = real_chunk(sel, v) * kQuads;
+        const uint64_t chunk = real_chunk(sel, v);
+        const uint64_t start = chunk * kQuads;
         const uint32_t first = (uint32_t)(start << 2);  // index of the chunk's first point (mod 2^32)
+        if (IX && batch_culled<false>(P, lay.box[2 * chunk], lay.box[2 * chunk + 1], nullptr, 0, 0)) continue;
         f32x4 xs[kQuadsPerThread], ys[kQuadsPerThread], zs[kQuadsPerThread];
+        u32x4 is[kQuadsPerThread];
+        uint32_t gq[kQuadsPerThread];
 #pragma unroll
         for (int k = 0; k < kQuadsPerThread; ++k) {
             const uint64_t q = start + threadIdx.x + (uint64_t)k * kBlock;
+            gq[k] = 0xFFFFFFFFu;
             if (q < nq) {
                 xs[k] = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(X) + q);
                 ys[k] = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(Y) + q);
                 zs[k] = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(Z) + q);
+                if (IX) is[k] = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(lay.ix) + q);
+                if (GLYPH) gq[k] = __builtin_nontemporal_load(reinterpret_cast<const uint32_t *>(lay.glyph) + q);
             }
         }
         uint32_t pix[kPts];
@@ -346,6 +482,13 @@ __global__ __launch_bounds__(kBlock, 4) void k_render_lds(const float *__restric
             const float px[4] = {xs[k].x, xs[k].y, xs[k].z, xs[k].w};
             const float py[4] = {ys[k].x, ys[k].y, ys[k].z, ys[k].w};
             const float pz[4] = {zs[k].x, zs[k].y, zs[k].z, zs[k].w};
+            uint32_t pi[4] = {first + lq * 4, first + lq * 4 + 1, first + lq * 4 + 2, first + lq * 4 + 3};
+            if (IX) {
+                pi[0] = is[k].x;
+                pi[1] = is[k].y;
+                pi[2] = is[k].z;
+                pi[3] = is[k].w;
+            }
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int t = k * 4 + j;
@@ -353,8 +496,9 @@ __global__ __launch_bounds__(kBlock, 4) void k_render_lds(const float *__restric
                 uint32_t pp = 0;
                 hit[t] = project<RCP>(P, px[j], py[j], pz[j], pp, w) & live;
                 pix[t] = pp;
-                key[t] = ((unsigned long long)__float_as_uint(w) << 32) | (first + lq * 4 + (uint32_t)j);
-                pixof[lq * 4 + j] = hit[t] ? pp : kNoPixel;
+                const uint32_t rank = (GLYPH && ((gq[k] >> (8 * j)) & 0xFFu) == 0u) ? kNotGlyph : 0u;
+                key[t] = ((unsigned long long)(__float_as_uint(w) | rank) << 32) | pi[j];
+                if (!IX) pixof[lq * 4 + j] = hit[t] ? pp : kNoPixel;
                 if (hit[t]) atomicMin(&best[pp & (kSlots - 1)], key[t]);
             }
         }
@@ -363,8 +507,19 @@ __global__ __launch_bounds__(kBlock, 4) void k_render_lds(const float *__restric
         unsigned long long won[kPts];
 #pragma unroll
         for (int t = 0; t < kPts; ++t) won[t] = best[pix[t] & (kSlots - 1)];
+        if (IX) {
+            // the winner (unique key) records its pixel for its slot
 #pragma unroll
-        for (int t = 0; t < kPts; ++t) hit[t] = hit[t] && pixof[((uint32_t)won[t] - first) & (kChunk - 1)] != pix[t];
+            for (int t = 0; t < kPts; ++t)
+                if (hit[t] && won[t] == key[t]) pixof[pix[t] & (kSlots - 1)] = pix[t];
+            __syncthreads();
+#pragma unroll
+            for (int t = 0; t < kPts; ++t) hit[t] = hit[t] && pixof[pix[t] & (kSlots - 1)] != pix[t];
+        } else {
+#pragma unroll
+            for (int t = 0; t < kPts; ++t)
+                hit[t] = hit[t] && pixof[((uint32_t)won[t] - first) & (kChunk - 1)] != pix[t];
+        }
         // my slots' winners
         uint32_t fpix[kPer];
         unsigned long long fkey[kPer];
@@ -373,7 +528,10 @@ __global__ __launch_bounds__(kBlock, 4) void k_render_lds(const float *__restric
         for (int t = 0; t < kPer; ++t) {
             fkey[t] = best[threadIdx.x + t * kBlock];
             fhit[t] = fkey[t] != NARVIS_KEY_EMPTY;
-            fpix[t] = fhit[t] ? pixof[((uint32_t)fkey[t] - first) & (kChunk - 1)] : 0u;
+            if (IX)
+                fpix[t] = fhit[t] ? pixof[threadIdx.x + t * kBlock] : 0u;
+            else
+                fpix[t] = fhit[t] ? pixof[((uint32_t)fkey[t] - first) & (kChunk - 1)] : 0u;
         }
         __syncthreads();
 #pragma unroll
@@ -382,7 +540,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_render_lds(const float *__restric
         global_merge<kPts>(keys, pix, key, hit, spread);
         __syncthreads();
     }
-    render_tail(X, Y, Z, n, P, keys, sel);
+    render_tail(X, Y, Z, n, P, keys, sel, lay.ix, lay.glyph);
 }
 
 // Key address with a 32-bit byte offset when the image has fewer than 2^29
@@ -408,12 +566,19 @@ constexpr int kCullPts = 4 * kCullQpt;
 // surface, whose depths at one pixel agree to a few ulps), and what is left
 // goes to the atomic minimum.  No LDS table and no barrier in the loop: the
 // waves stream independently.
-template <bool RCP, bool OFF32>
+// MODE 1 (layout): the points are in layout order (key indices from the
+// index stream, read only for the points that reach the atomic), and a chunk
+// (= one batch) whose box is outside the view volume or behind the tile
+// bounds is skipped whole, before its points are loaded.  MODE 2 (glyph
+// priority): the rank bit of non-glyph points takes part in every bound test
+// and key, exactly like a depth bit above all others.
+template <bool RCP, bool OFF32, int MODE>
 __global__ __launch_bounds__(kCullBlock) void k_render_cull(const float *__restrict__ X, const float *__restrict__ Y,
                                                         const float *__restrict__ Z, uint64_t n, Proj P,
                                                         unsigned long long *__restrict__ keys, ChunkOrder order,
-                                                        ChunkSel sel, TileGrid tg)
+                                                        ChunkSel sel, TileGrid tg, LayoutArgs lay)
 {
+    constexpr bool IX = MODE == 1, GLYPH = MODE == 2;
     __shared__ uint16_t tb[kMaxTiles];
     for (uint32_t s = threadIdx.x; s < tg.ntiles; s += kCullBlock) tb[s] = tg.bounds[s];
     const uint64_t nq = n >> 2;
@@ -423,6 +588,7 @@ __global__ __launch_bounds__(kCullBlock) void k_render_cull(const float *__restr
     const uint32_t spread = (uint32_t)((lb * 2654435761ull) % (uint64_t)npx);
     __syncthreads();
     f32x4 xs[kCullQpt], ys[kCullQpt], zs[kCullQpt];
+    uint32_t gq[kCullQpt];
     // every quad index is clamped into the array so that each fetch issues
     // the same six loads (the extra quads are not live)
     auto fetch = [&](uint64_t v) {
@@ -434,10 +600,24 @@ __global__ __launch_bounds__(kCullBlock) void k_render_cull(const float *__restr
             xs[k] = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(X) + q);
             ys[k] = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(Y) + q);
             zs[k] = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(Z) + q);
+            if (GLYPH) gq[k] = __builtin_nontemporal_load(reinterpret_cast<const uint32_t *>(lay.glyph) + q);
         }
     };
-    if (lb < sel.nv && nq > 0) fetch(lb);
-    for (uint64_t v = lb; v < sel.nv; v += gridDim.x) {
+    // the first chunk at or after v (in steps of the grid) that is not culled
+    // whole (wave-uniform; without a layout every chunk is rendered)
+    auto visible = [&](uint64_t v) {
+        if (IX) {
+            while (v < sel.nv) {
+                const uint64_t c = real_chunk(sel, v);
+                if (!batch_culled<true>(P, lay.box[2 * c], lay.box[2 * c + 1], tb, tg.shift, tg.tiles_x)) break;
+                v += gridDim.x;
+            }
+        }
+        return v;
+    };
+    uint64_t v = visible(lb);
+    if (v < sel.nv && nq > 0) fetch(v);
+    while (v < sel.nv) {
         const uint64_t start = real_chunk(sel, v) * kQuads;
         const uint32_t first = (uint32_t)(start << 2);
         uint32_t pix[kCullPts];
@@ -456,22 +636,29 @@ __global__ __launch_bounds__(kCullBlock) void k_render_cull(const float *__restr
                 float w = 0.0f;
                 uint32_t ix = 0, iy = 0;
                 bool h = project<RCP>(P, px[j], py[j], pz[j], ix, iy, w) & live;
+                const uint32_t hw = __float_as_uint(w) | ((GLYPH && ((gq[k] >> (8 * j)) & 0xFFu) == 0u) ? kNotGlyph : 0u);
                 const uint32_t tile = h ? __umul24(iy >> tg.shift, tg.tiles_x) + (ix >> tg.shift) : 0u;
-                hit[t] = h & ((__float_as_uint(w) >> 16) <= (uint32_t)tb[tile]);
+                hit[t] = h & ((hw >> 16) <= (uint32_t)tb[tile]);
                 pix[t] = __umul24(iy, (uint32_t)P.W) + ix;
-                key[t] = ((unsigned long long)__float_as_uint(w) << 32) | (first + lq * 4 + (uint32_t)j);
+                // IX: the low word holds the point's position until the atomic
+                key[t] = ((unsigned long long)hw << 32) | (first + lq * 4 + (uint32_t)j);
             }
             // consecutive points on one pixel (a surface sampled finer than
             // the pixels): the last of a run carries the run's smallest key
+            // (IX: only across different depths, where the index cannot matter)
 #pragma unroll
             for (int j = 1; j < 4; ++j) {
                 const int t = k * 4 + j;
                 if (hit[t - 1] && hit[t] && pix[t - 1] == pix[t]) {
+                    if (IX && (key[t - 1] >> 32) == (key[t] >> 32)) continue;
                     key[t] = key[t - 1] < key[t] ? key[t - 1] : key[t];
                     hit[t - 1] = false;
                 }
             }
         }
+        // the next chunk to render (its box test runs before the bound reads,
+        // which would otherwise have to complete first)
+        const uint64_t vn = visible(v + gridDim.x);
         // pixel bounds of the survivors (a lane without a survivor reads the
         // wave's shared pixel, so its request merges), then the atomics
         uint32_t pb[kCullPts];
@@ -480,15 +667,21 @@ __global__ __launch_bounds__(kCullBlock) void k_render_cull(const float *__restr
         // the next chunk's points are loaded while the bounds come back (both
         // load sequences have a fixed length, so the wait for the bounds
         // leaves the six point loads in flight)
-        fetch(v + gridDim.x < sel.nv ? v + gridDim.x : v);
+        fetch(vn < sel.nv ? vn : v);
 #pragma unroll
         for (int t = 0; t < kCullPts; ++t) hit[t] = hit[t] && (uint32_t)(key[t] >> 32) <= pb[t];
+        if (IX) {
+#pragma unroll
+            for (int t = 0; t < kCullPts; ++t)
+                if (hit[t]) key[t] = (key[t] & 0xFFFFFFFF00000000ull) | lay.ix[(uint32_t)key[t]];
+        }
 #pragma unroll
         for (int t = 0; t < kCullPts; ++t)
             if (hit[t])
                 __hip_atomic_fetch_min(key_at<OFF32>(keys, pix[t]), key[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        v = vn;
     }
-    render_tail(X, Y, Z, n, P, keys, sel);
+    render_tail(X, Y, Z, n, P, keys, sel, lay.ix, lay.glyph);
 }
 
 // First level of a hinted bounded render: every pixel of an earlier key
@@ -501,7 +694,8 @@ __global__ __launch_bounds__(kCullBlock) void k_render_cull(const float *__restr
 __global__ __launch_bounds__(kBlock) void k_hint_render(const unsigned long long *__restrict__ hint, uint32_t npx,
                                                         const float *__restrict__ X, const float *__restrict__ Y,
                                                         const float *__restrict__ Z, uint64_t n, Proj P,
-                                                        unsigned long long *__restrict__ keys)
+                                                        unsigned long long *__restrict__ keys,
+                                                        const uint8_t *__restrict__ glyph)
 {
     const uint32_t q = blockIdx.x * kBlock + threadIdx.x;
     if (q >= npx) return;
@@ -510,7 +704,7 @@ __global__ __launch_bounds__(kBlock) void k_hint_render(const unsigned long long
     if (h == NARVIS_KEY_EMPTY || (uint64_t)i >= n) return;
     uint32_t pix;
     float w;
-    if (project(P, X[i], Y[i], Z[i], pix, w)) merge<NARVIS_RENDER_EARLYZ>(keys, pix, w, i);
+    if (project(P, X[i], Y[i], Z[i], pix, w)) merge<NARVIS_RENDER_EARLYZ>(keys, pix, w, i, glyph_rank(glyph, i));
 }
 
 // Depth bounds after the first levels: per pixel its depth bits, per screen
@@ -549,13 +743,14 @@ __global__ __launch_bounds__(kBlock) void k_tile_bounds(const unsigned long long
 template <int VARIANT>
 __global__ __launch_bounds__(kBlock) void k_render_scalar(const float *__restrict__ X, const float *__restrict__ Y,
                                                            const float *__restrict__ Z, uint64_t n, Proj P,
-                                                           unsigned long long *__restrict__ keys, ChunkOrder order)
+                                                           unsigned long long *__restrict__ keys, ChunkOrder order,
+                                                           const uint8_t *__restrict__ glyph)
 {
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     for (uint64_t i = logical_block(order) * kBlock + threadIdx.x; i < n; i += stride) {
         uint32_t pix;
         float w;
-        if (project(P, X[i], Y[i], Z[i], pix, w)) merge<VARIANT>(keys, pix, w, (uint32_t)i);
+        if (project(P, X[i], Y[i], Z[i], pix, w)) merge<VARIANT>(keys, pix, w, (uint32_t)i, glyph_rank(glyph, i));
     }
 }
 
@@ -593,10 +788,10 @@ __device__ __forceinline__ float load_attr(const AttrArg &a, uint32_t i)
 struct ResolveArgs {
     const unsigned long long *keys;
     const float *X, *Y, *Z;
-    float *depth, *attr, *rgb, *vel;
+    float *depth, *attr, *rgb, *vel, *radius;
     const float *lut;
-    int32_t lut_attr, vel_attr, rgb_mode;
-    float lut_min, lut_inv;
+    int32_t lut_attr, vel_attr, rgb_mode, radius_attr;
+    float lut_min, lut_inv, focal;
     int64_t npx;
     uint64_t n;
 };
@@ -610,7 +805,17 @@ __global__ __launch_bounds__(kBlock) void k_resolve(ResolveArgs R, AttrPack A, P
     // render; it resolves as empty instead of reading out of bounds
     const bool empty = (k == NARVIS_KEY_EMPTY) || (uint64_t)(uint32_t)k >= R.n;
     const uint32_t i = (uint32_t)k;
-    if (R.depth) R.depth[p] = empty ? 0.0f : __uint_as_float((uint32_t)(k >> 32));
+    const float depth = __uint_as_float((uint32_t)(k >> 32) & ~kNotGlyph);
+    if (R.depth) R.depth[p] = empty ? 0.0f : depth;
+    // projected splat radius: the winner's world radius at its depth, in pixels
+    if (R.radius) {
+        float rp = 0.0f;
+        if (!empty) {
+            rp = load_attr(A.a[R.radius_attr], i) * R.focal;
+            rp = rp / depth;
+        }
+        R.radius[p] = rp;
+    }
     if (R.attr) {
         for (int c = 0; c < A.count; ++c) R.attr[c * R.npx + p] = empty ? 0.0f : load_attr(A.a[c], i);
     }
@@ -725,7 +930,7 @@ constexpr int kNumLevels = sizeof(kLevels) / sizeof(kLevels[0]);
 
 hipError_t launch_render(const float *x, const float *y, const float *z, uint64_t n, const Proj &P,
                          uint64_t *keys, int32_t variant, int32_t grid_blocks, uint16_t *bounds, const uint64_t *hint,
-                         hipStream_t s)
+                         hipStream_t s, const LayoutArgs &lay)
 {
     if (n == 0) return hipSuccess;
     const DeviceInfo dev = device_info();
@@ -752,20 +957,27 @@ hipError_t launch_render(const float *x, const float *y, const float *z, uint64_
     auto *k = reinterpret_cast<unsigned long long *>(keys);
     if (variant == NARVIS_RENDER_AUTO) variant = vec ? NARVIS_RENDER_LDS : NARVIS_RENDER_EARLYZ;
     if (variant == NARVIS_RENDER_LDS && !vec) variant = NARVIS_RENDER_EARLYZ;
+    // a layout is rendered by the LDS and cull kernels only (16-byte aligned
+    // arrays; the C ABI checks this before any launch), and never with a
+    // glyph mask; the LDS and cull kernels read the mask four bytes at a time
+    if (lay.ix && (lay.glyph || !(vec && variant == NARVIS_RENDER_LDS && !(reinterpret_cast<uintptr_t>(lay.ix) & 15u))))
+        return hipErrorInvalidValue;
+    if (lay.glyph && vec && variant == NARVIS_RENDER_LDS && (reinterpret_cast<uintptr_t>(lay.glyph) & 3u))
+        variant = NARVIS_RENDER_EARLYZ;
     if (vec && variant == NARVIS_RENDER_LDS) {
         // kept depths lie in [near_f, far_f]: the reciprocal path needs them in
         // the range where rcp_rn is exact
         const bool rcp = P.near_f >= 0x1p-124f && P.far_f < 0x1p125f;
         constexpr uint64_t kChunkQuads = (uint64_t)kBlock * kQuadsPerThread;
         const uint64_t nchunks = ((n >> 2) + kChunkQuads - 1) / kChunkQuads;
+        const bool ix = lay.ix != nullptr;
+        const int mode = ix ? 1 : (lay.glyph ? 2 : 0);
         auto lds = [&](const ChunkSel &sel, uint64_t nblocks) {
             const ChunkOrder o = order_of(nblocks);
-            if (rcp)
-                hipLaunchKernelGGL(k_render_lds<true>, dim3((unsigned)nblocks), dim3(kBlock), 0, s, x, y, z, n, P, k,
-                                   o, sel);
-            else
-                hipLaunchKernelGGL(k_render_lds<false>, dim3((unsigned)nblocks), dim3(kBlock), 0, s, x, y, z, n, P, k,
-                                   o, sel);
+            auto kern = rcp ? (mode == 1 ? k_render_lds<true, 1> : mode == 2 ? k_render_lds<true, 2> : k_render_lds<true, 0>)
+                            : (mode == 1 ? k_render_lds<false, 1>
+                                         : mode == 2 ? k_render_lds<false, 2> : k_render_lds<false, 0>);
+            hipLaunchKernelGGL(kern, dim3((unsigned)nblocks), dim3(kBlock), 0, s, x, y, z, n, P, k, o, sel, lay);
         };
         // bounded render for at least two chunks (24-bit pixel arithmetic)
         if (bounds && n >= 4096 && P.W < (1 << 24) && P.H < (1 << 24)) {
@@ -778,10 +990,11 @@ hipError_t launch_render(const float *x, const float *y, const float *z, uint64_
                 ++tg.shift;
             }
             auto ceil_div = [](uint64_t a, uint64_t b) { return (a + b - 1) / b; };
-            if (hint) {
+            if (hint && !ix) {
                 const uint32_t npx = (uint32_t)P.W * (uint32_t)P.H;
                 hipLaunchKernelGGL(k_hint_render, dim3((npx + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
-                                   reinterpret_cast<const unsigned long long *>(hint), npx, x, y, z, n, P, k);
+                                   reinterpret_cast<const unsigned long long *>(hint), npx, x, y, z, n, P, k,
+                                   lay.glyph);
             }
             for (int lv = 0; lv < kNumLevels; ++lv) {
                 ChunkSel sel;
@@ -801,9 +1014,16 @@ hipError_t launch_render(const float *x, const float *y, const float *z, uint64_
                                                                 : (sel.nv < resident ? sel.nv : resident));
                     const ChunkOrder o = order_of(nb);
                     const bool off32 = (uint64_t)P.W * (uint64_t)P.H < (1ull << 29);
-                    auto kern = rcp ? (off32 ? k_render_cull<true, true> : k_render_cull<true, false>)
-                                    : (off32 ? k_render_cull<false, true> : k_render_cull<false, false>);
-                    hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(kCullBlock), 0, s, x, y, z, n, P, k, o, sel, tg);
+                    auto pick = [&](auto m) {
+                        constexpr int M = decltype(m)::value;
+                        return rcp ? (off32 ? k_render_cull<true, true, M> : k_render_cull<true, false, M>)
+                                   : (off32 ? k_render_cull<false, true, M> : k_render_cull<false, false, M>);
+                    };
+                    auto kern = mode == 1 ? pick(std::integral_constant<int, 1>{})
+                                          : mode == 2 ? pick(std::integral_constant<int, 2>{})
+                                                      : pick(std::integral_constant<int, 0>{});
+                    hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(kCullBlock), 0, s, x, y, z, n, P, k, o, sel, tg,
+                                       lay);
                 }
             }
         } else {
@@ -813,17 +1033,17 @@ hipError_t launch_render(const float *x, const float *y, const float *z, uint64_
     } else if (vec) {
         if (variant == NARVIS_RENDER_GLOBAL)
             hipLaunchKernelGGL(k_render_vec<NARVIS_RENDER_GLOBAL>, dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                               x, y, z, n, P, k, order);
+                               x, y, z, n, P, k, order, lay.glyph);
         else
             hipLaunchKernelGGL(k_render_vec<NARVIS_RENDER_EARLYZ>, dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                               x, y, z, n, P, k, order);
+                               x, y, z, n, P, k, order, lay.glyph);
     } else {
         if (variant == NARVIS_RENDER_GLOBAL)
             hipLaunchKernelGGL(k_render_scalar<NARVIS_RENDER_GLOBAL>, dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                               x, y, z, n, P, k, order);
+                               x, y, z, n, P, k, order, lay.glyph);
         else
             hipLaunchKernelGGL(k_render_scalar<NARVIS_RENDER_EARLYZ>, dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                               x, y, z, n, P, k, order);
+                               x, y, z, n, P, k, order, lay.glyph);
     }
     return hipGetLastError();
 }
@@ -841,6 +1061,9 @@ hipError_t launch_resolve(const float *x, const float *y, const float *z, uint64
     R.attr = g.attr;
     R.rgb = g.rgb;
     R.vel = g.vel2d;
+    R.radius = g.radius;
+    R.radius_attr = g.radius_attr;
+    R.focal = g.radius_focal_px;
     R.lut = g.lut;
     R.lut_attr = g.lut_attr;
     R.vel_attr = g.vel_attr;

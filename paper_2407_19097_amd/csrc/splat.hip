@@ -506,6 +506,36 @@ static hipError_t scan_excl(const uint32_t *in, uint32_t *out, uint64_t len, uin
     return hipGetLastError();
 }
 
+hipError_t launch_radix_sort(unsigned long long *ka, uint32_t *va, unsigned long long *kb, uint32_t *vb,
+                             const uint32_t *count, uint64_t cap, int key_bits, uint32_t *hist, uint32_t *sums,
+                             hipStream_t s, bool *in_b)
+{
+    const uint64_t nblk64 = (cap + kScanTile - 1) / kScanTile;
+    const uint32_t nblk = (uint32_t)(nblk64 ? nblk64 : 1);
+    bool b = false;
+    for (int shift = 0; shift < key_bits; shift += 8) {
+        hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kT), 0, s, b ? kb : ka, count, cap, shift, hist, nblk);
+        const hipError_t e = scan_excl(hist, hist, (uint64_t)nblk * 256, sums, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(kT), 0, s, b ? kb : ka, b ? vb : va, b ? ka : kb,
+                           b ? va : vb, count, cap, shift, hist, nblk);
+        b = !b;
+    }
+    *in_b = b;
+    return hipGetLastError();
+}
+
+uint64_t radix_sort_hist_len(uint64_t cap)
+{
+    const uint64_t nblk = (cap + kScanTile - 1) / kScanTile;
+    return (nblk ? nblk : 1) * 256;
+}
+
+uint64_t radix_sort_sums_len(uint64_t cap)
+{
+    return (radix_sort_hist_len(cap) + kScanTile - 1) / kScanTile;
+}
+
 hipError_t launch_splat(const float *x, const float *y, const float *z, uint64_t n, const Proj &P, const AttrPack &A,
                         const narvis_splat_params &prm, float *img, void *ws, hipStream_t s)
 {

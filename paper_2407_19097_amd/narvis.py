@@ -91,6 +91,10 @@ class GBuffer:
     bounds: object = None         # uint8 [narvis_raster_bounds_bytes(W, H)] scratch of the bounded render
     hint: object = None           # int64 [H*W] keys of an earlier render (hinted bounded render)
     rgb_mode: int = 0             # COLOR_LUT or COLOR_RGB8 (three uint8 attributes from lut_attr)
+    glyph: object = None          # uint8 [n] glyph mask (glyph-priority render), original point order
+    radius: object = None         # float32 [H*W] projected splat radius in pixels
+    radius_attr: int = -1         # attribute holding the world radius
+    radius_focal_px: float = 0.0  # only read by narvis_raster_resolve (narvis_rasterize sets it)
 
     @staticmethod
     def allocate(W: int, H: int, nattr: int = 0, depth=True, rgb=False, vel2d=False, bounded=True, device="cuda"):
@@ -109,7 +113,8 @@ class GBuffer:
                             _ptr(self.lut), int(self.lut_attr), float(self.lut_min), float(self.lut_inv_range),
                             int(self.vel_attr), _ptr(self.bounds),
                             0 if self.bounds is None else int(self.bounds.numel() * self.bounds.element_size()),
-                            _ptr(self.hint), int(self.rgb_mode))
+                            _ptr(self.hint), int(self.rgb_mode), _ptr(self.glyph), _ptr(self.radius),
+                            int(self.radius_attr), float(self.radius_focal_px))
 
 
 def narvis_status_string(status: int) -> str:
@@ -125,6 +130,13 @@ def narvis_camera_matrix(camera, W: int, H: int):
     _lib.check(L.narvis_camera_matrix(ctypes.byref(c), W, H, vp, ctypes.byref(nf), ctypes.byref(ff)),
                "narvis_camera_matrix")
     return np.frombuffer(vp, dtype=np.float32).copy(), np.float32(nf.value), np.float32(ff.value)
+
+
+def narvis_camera_focal_px(camera, H: int) -> float:
+    c = camera_struct(camera)
+    f = ctypes.c_float()
+    _lib.check(_lib.load().narvis_camera_focal_px(ctypes.byref(c), H, ctypes.byref(f)), "narvis_camera_focal_px")
+    return float(f.value)
 
 
 def _vp(vp) -> ctypes.Array:
@@ -147,10 +159,10 @@ def raster_bounds(W: int, H: int, device="cuda"):
 
 
 def narvis_raster_render(points, n: int, vp, near_f, far_f, W: int, H: int, keys, variant: int = RENDER_AUTO,
-                         grid_blocks: int = 0, bounds=None, hint_keys=None, stream=None) -> None:
+                         grid_blocks: int = 0, bounds=None, hint_keys=None, glyph=None, stream=None) -> None:
     p = points_struct(points)
     nb = 0 if bounds is None else int(bounds.numel() * bounds.element_size())
-    o = _lib.RasterOpts(int(variant), int(grid_blocks), _ptr(bounds), nb, _ptr(hint_keys))
+    o = _lib.RasterOpts(int(variant), int(grid_blocks), _ptr(bounds), nb, _ptr(hint_keys), _ptr(glyph))
     _lib.check(_lib.load().narvis_raster_render(ctypes.byref(p), int(n), _vp(vp), float(near_f), float(far_f), W, H,
                                                 _ptr(keys), ctypes.byref(o), _stream_ptr(stream)),
                "narvis_raster_render")
@@ -171,6 +183,91 @@ def narvis_rasterize(points, attrs, n: int, camera, W: int, H: int, gbuf: GBuffe
     g = gbuf.struct()
     _lib.check(_lib.load().narvis_rasterize(ctypes.byref(p), ctypes.byref(a), int(n), ctypes.byref(c), W, H,
                                             ctypes.byref(g), _stream_ptr(stream)), "narvis_rasterize")
+
+
+LAYOUT_BATCH = 2048
+
+
+class Layout:
+    """Morton layout of a point cloud in caller-owned device tensors: x, y, z
+    float32 [n] in layout order, index uint32 (as int32) [n] original index,
+    boxes float32 [nbatch][8]."""
+
+    def __init__(self, n: int, device="cuda"):
+        import torch
+        self.n = int(n)
+        nb = int(_lib.load().narvis_layout_batches(self.n))
+        e = lambda m: torch.empty(max(m, 4), dtype=torch.float32, device=device)
+        self.x, self.y, self.z = e(self.n), e(self.n), e(self.n)
+        self.index = torch.empty(max(self.n, 4), dtype=torch.int32, device=device)
+        self.boxes = torch.empty((max(nb, 1), 8), dtype=torch.float32, device=device)
+
+    def struct(self) -> _lib.Layout:
+        return _lib.Layout(_ptr(self.x), _ptr(self.y), _ptr(self.z), _ptr(self.index), _ptr(self.boxes))
+
+
+def narvis_knn_radius_workspace_size(n: int) -> int:
+    return int(_lib.load().narvis_knn_radius_workspace_size(int(n)))
+
+
+def narvis_knn_radius(points, n: int, radius, workspace=None, stream=None):
+    """World splat radius (mean distance to the four nearest neighbours) of
+    every point into radius (float32 [n] device tensor).  Returns (cell edge,
+    points settled by the full scan).  Synchronises the stream."""
+    import torch
+    p = points_struct(points)
+    ws = workspace if workspace is not None else torch.empty(max(256, narvis_knn_radius_workspace_size(n)),
+                                                              dtype=torch.uint8, device=radius.device)
+    cell, unres = ctypes.c_float(), ctypes.c_uint32()
+    _lib.check(_lib.load().narvis_knn_radius(ctypes.byref(p), int(n), _ptr(radius), _ptr(ws),
+                                             ws.numel() * ws.element_size(), ctypes.byref(cell), ctypes.byref(unres),
+                                             _stream_ptr(stream)), "narvis_knn_radius")
+    return float(cell.value), int(unres.value)
+
+
+def narvis_layout_workspace_size(n: int) -> int:
+    return int(_lib.load().narvis_layout_workspace_size(int(n)))
+
+
+def narvis_layout_build(points, n: int, layout: Layout, workspace, stream=None) -> None:
+    p = points_struct(points)
+    L = layout.struct()
+    nbytes = workspace.numel() * workspace.element_size()
+    _lib.check(_lib.load().narvis_layout_build(ctypes.byref(p), int(n), ctypes.byref(L), _ptr(workspace), nbytes,
+                                               _stream_ptr(stream)), "narvis_layout_build")
+
+
+def build_layout(points, n: int, device="cuda") -> Layout:
+    """Allocate a Layout and build it (the workspace is freed afterwards)."""
+    import torch
+    L = Layout(n, device)
+    ws = torch.empty(max(1, narvis_layout_workspace_size(n)), dtype=torch.uint8, device=device)
+    narvis_layout_build(points, n, L, ws)
+    del ws
+    return L
+
+
+def narvis_raster_render_layout(layout: Layout, n: int, vp, near_f, far_f, W: int, H: int, keys, grid_blocks: int = 0,
+                                bounds=None, stream=None) -> None:
+    L = layout.struct()
+    nb = 0 if bounds is None else int(bounds.numel() * bounds.element_size())
+    o = _lib.RasterOpts(RENDER_AUTO, int(grid_blocks), _ptr(bounds), nb, None, None)
+    _lib.check(_lib.load().narvis_raster_render_layout(ctypes.byref(L), int(n), _vp(vp), float(near_f), float(far_f),
+                                                       W, H, _ptr(keys), ctypes.byref(o), _stream_ptr(stream)),
+               "narvis_raster_render_layout")
+
+
+def narvis_rasterize_layout(layout: Layout, points, attrs, n: int, camera, W: int, H: int, gbuf: GBuffer,
+                            stream=None) -> None:
+    """points: the original-order coordinates (only read for vel2d; may be None otherwise)."""
+    L = layout.struct()
+    p = points_struct(points) if points is not None else _lib.Points()
+    a = attrs_struct(attrs or [])
+    c = camera_struct(camera)
+    g = gbuf.struct()
+    _lib.check(_lib.load().narvis_rasterize_layout(ctypes.byref(L), ctypes.byref(p), ctypes.byref(a), int(n),
+                                                   ctypes.byref(c), W, H, ctypes.byref(g), _stream_ptr(stream)),
+               "narvis_rasterize_layout")
 
 
 COLOR_LUT, COLOR_RGB8 = 0, 1
