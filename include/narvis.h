@@ -380,6 +380,33 @@ size_t narvis_knn_radius_workspace_size(uint64_t n);
 narvis_status narvis_knn_radius(const narvis_points *pts, uint64_t n, float *radius, void *ws, size_t ws_bytes,
                                 float *cell_out, uint32_t *unresolved_out, void *stream);
 
+/* Largest image (in pixels) of narvis_rasterize_static, and the bytes of
+ * its static device scratch: narvis_raster_bounds_bytes of that image
+ * (3840 x 2160 = 8,294,400 pixels: 33,193,984 bytes per device). */
+#define NARVIS_STATIC_MAX_PIXELS (3840u * 2160u)
+#define NARVIS_STATIC_SCRATCH_BYTES (2u * NARVIS_TILE_BOUNDS_MAX + 4u * NARVIS_STATIC_MAX_PIXELS)
+
+/* Allocation-free whole frame, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Computes exactly what narvis_rasterize computes in the
+ * bounded mode, with the bounds scratch taken from a static device array of
+ * NARVIS_STATIC_SCRATCH_BYTES bytes owned by the library instead of
+ * gbuf->bounds: each device that the library runs on holds its copy from
+ * the library's load until the process ends.  Allocates nothing (no
+ * hipMalloc, hipFree or allocating library call); the first call on a
+ * device looks the array's address up once.
+ *   gbuf->bounds must be NULL (INVALID_ARG otherwise); gbuf->hint_keys is
+ *   honoured as in narvis_rasterize.  W * H > NARVIS_STATIC_MAX_PIXELS:
+ *   NARVIS_ERR_WORKSPACE, nothing enqueued.  Other errors as narvis_rasterize.
+ * Every call on one device shares that device's scratch, and the scratch
+ * keeps the last call's contents (each call overwrites every byte it reads,
+ * so nothing carries over): calls that can overlap in time on one device
+ * (unordered streams, several host threads) race and must be serialised by
+ * the caller. */
+narvis_status narvis_rasterize_static(const narvis_points *pts, const narvis_attrs *attrs, uint64_t n,
+                                      const narvis_camera *cam, int32_t W, int32_t H, narvis_gbuffer *gbuf,
+                                      void *stream);
+
 /* Bytes of device workspace narvis_splat needs for n points at W x H
  * (0 if the arguments are invalid).  The size grows linearly with n: point
  * records, tile counts, two ping-pong copies of the (key, index) pairs (at

@@ -90,6 +90,9 @@ SIGNATURES = {
     "narvis_knn_radius_workspace_size": (ctypes.c_size_t, [ctypes.c_uint64]),
     "narvis_knn_radius": (ctypes.c_int, [ctypes.POINTER(Points), ctypes.c_uint64, _P, _P, ctypes.c_size_t,
                                          ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_uint32), _P]),
+    "narvis_rasterize_static": (ctypes.c_int, [ctypes.POINTER(Points), ctypes.POINTER(Attrs), ctypes.c_uint64,
+                                               ctypes.POINTER(Camera), ctypes.c_int32, ctypes.c_int32,
+                                               ctypes.POINTER(GBuffer), _P]),
     "narvis_layout_batches": (ctypes.c_uint64, [ctypes.c_uint64]),
     "narvis_layout_workspace_size": (ctypes.c_size_t, [ctypes.c_uint64]),
     "narvis_layout_build": (ctypes.c_int, [ctypes.POINTER(Points), ctypes.c_uint64, ctypes.POINTER(Layout), _P,

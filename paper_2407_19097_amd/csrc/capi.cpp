@@ -256,6 +256,19 @@ extern "C" narvis_status narvis_rasterize(const narvis_points *pts, const narvis
     return rasterize_frame(pts, attrs, n, cam, W, H, gbuf, gbuf->bounds, gbuf->bounds_bytes, stream);
 }
 
+extern "C" narvis_status narvis_rasterize_static(const narvis_points *pts, const narvis_attrs *attrs, uint64_t n,
+                                                 const narvis_camera *cam, int32_t W, int32_t H,
+                                                 narvis_gbuffer *gbuf, void *stream)
+{
+    if (!gbuf || gbuf->bounds) return NARVIS_ERR_INVALID_ARG;
+    if (!image_ok(W, H)) return NARVIS_ERR_INVALID_ARG;
+    if ((uint64_t)W * (uint64_t)H > (uint64_t)NARVIS_STATIC_MAX_PIXELS) return NARVIS_ERR_WORKSPACE;
+    void *scratch = nullptr;
+    const narvis_status st = from_hip(static_scratch(&scratch));
+    if (st != NARVIS_OK) return st;
+    return rasterize_frame(pts, attrs, n, cam, W, H, gbuf, scratch, NARVIS_STATIC_SCRATCH_BYTES, stream);
+}
+
 // ---------------------------------------------------------------------------
 // spatial layout
 // ---------------------------------------------------------------------------

@@ -72,6 +72,9 @@ hipError_t launch_clear(uint64_t *keys, int64_t npx, hipStream_t s);
 hipError_t launch_render(const float *x, const float *y, const float *z, uint64_t n, const Proj &P,
                          uint64_t *keys, int32_t variant, int32_t grid_blocks, uint16_t *bounds, const uint64_t *hint,
                          hipStream_t s, const LayoutArgs &lay = LayoutArgs{nullptr, nullptr, nullptr});
+// Device address of this device's static scratch of
+// NARVIS_STATIC_SCRATCH_BYTES bytes (resolved on the first call per device).
+hipError_t static_scratch(void **ptr);
 hipError_t launch_resolve(const float *x, const float *y, const float *z, uint64_t n, const Proj &P,
                           const AttrPack &attrs, const narvis_gbuffer &g, hipStream_t s);
 

@@ -889,6 +889,33 @@ Proj make_proj(const float vp[16], float near_f, float far_f, int32_t W, int32_t
     return P;
 }
 
+// Scratch of the allocation-free whole-frame call: the bounded render's tile
+// and pixel bounds for images of up to NARVIS_STATIC_MAX_PIXELS pixels.  Each
+// device holds its own copy from the library's load until the process ends.
+// Host code never passes this name to a kernel (on the host it is only a
+// stand-in): static_scratch() resolves the device address once per device.
+static __device__ __align__(256) unsigned char scratch[NARVIS_STATIC_SCRATCH_BYTES];
+
+hipError_t static_scratch(void **ptr)
+{
+    static std::mutex mu;
+    static std::vector<void *> addr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(mu);
+    if ((int)addr.size() <= dev) addr.resize(dev + 1, nullptr);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
+}
+
 hipError_t launch_clear(uint64_t *keys, int64_t npx, hipStream_t s)
 {
     const int64_t blocks = (npx + kBlock - 1) / kBlock;

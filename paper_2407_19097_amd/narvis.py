@@ -185,6 +185,18 @@ def narvis_rasterize(points, attrs, n: int, camera, W: int, H: int, gbuf: GBuffe
                                             ctypes.byref(g), _stream_ptr(stream)), "narvis_rasterize")
 
 
+def narvis_rasterize_static(points, attrs, n: int, camera, W: int, H: int, gbuf: GBuffer, stream=None) -> None:
+    """Whole frame without any allocation: the bounds scratch is the library's
+    static device array (gbuf.bounds must be None)."""
+    p = points_struct(points)
+    a = attrs_struct(attrs or [])
+    c = camera_struct(camera)
+    g = gbuf.struct()
+    _lib.check(_lib.load().narvis_rasterize_static(ctypes.byref(p), ctypes.byref(a), int(n), ctypes.byref(c), W, H,
+                                                   ctypes.byref(g), _stream_ptr(stream)), "narvis_rasterize_static")
+
+
+STATIC_MAX_PIXELS = 3840 * 2160
 LAYOUT_BATCH = 2048
 
 
