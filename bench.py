@@ -175,6 +175,8 @@ def frame_section(torch, log_fn, frames=12, train_views=2000, train_steps=2500):
     # FP8: static activation scales calibrated on 16 training views
     cal_ws = torch.empty(narvis.narvis_train_workspace_size(16, 512, 512), dtype=torch.uint8, device="cuda")
     narvis.narvis_weights_calibrate_fp8(w, fb, 16, 512, 512, cal_ws)
+    names = ["e1a", "e1b", "e2a", "e2b", "e3a", "e3b", "e4a", "e4b", "d3a", "d3b", "d2a", "d2b", "d1a", "d1b", "head"]
+    fp8_layers = [nm for i, nm in enumerate(names) if (narvis.narvis_weights_fp8_layers(w) >> i) & 1]
     del cal, fb, cal_ws
     W, H = 1920, 1080
     r = train.Renderer(sc, W, H)
@@ -228,6 +230,27 @@ def frame_section(torch, log_fn, frames=12, train_views=2000, train_steps=2500):
         s_net.append(metrics.ssim(y, t3).item())
         s_ras.append(metrics.ssim(feat[:, 0:3].view(1, 3, H, W), t3).item())
     pairs = narvis.narvis_splat_pair_count(r.ws, sc.n, W, H, r.params)  # of the last frame
+    # the anisotropic target (Gaussians elongated along the velocity, s = 300,
+    # the paper's stretch for its hurricane vector field) of the first frame
+    del r
+    torch.cuda.empty_cache()
+    lut_t = torch.from_numpy(scenes.colour_lut()).cuda()
+    inv = float(np.float32(1.0 / (sc.lut_max - sc.lut_min)))
+    ap = narvis.SplatParams(sigma_px=1.5, opacity=1.0, color_mode=narvis.COLOR_LUT, color_attr=sc.lut_attr, lut=lut_t,
+                            lut_min=sc.lut_min, lut_inv_range=inv, aniso=1, vel_attr=sc.vel_attr, stretch=300.0,
+                            max_pairs=1)
+    aws = torch.empty(narvis.narvis_splat_workspace_size(sc.n, W, H, ap), dtype=torch.uint8, device="cuda")
+    cam0 = sc.cameras[picks[0]]
+    apairs = narvis.narvis_splat_count_pairs((sc.x, sc.y, sc.z), sc.attrs, sc.n, cam0, W, H, ap, aws)
+    del aws
+    ap.max_pairs = apairs
+    aws = torch.empty(narvis.narvis_splat_workspace_size(sc.n, W, H, ap), dtype=torch.uint8, device="cuda")
+    aimg = lambda: narvis.narvis_splat((sc.x, sc.y, sc.z), sc.attrs, sc.n, cam0, W, H, tgt, ap, aws, stream=stream)
+    aimg()
+    ta = [timed(aimg) for _ in range(3)]
+    torch.cuda.synchronize()
+    aniso_ms = float(np.mean([a.elapsed_time(b) for a, b in ta]))
+    del aws
     w.close()
     m = lambda xs: float(np.mean(xs))
     raster_ms, net_ms, splat_ms = m(t_r), m(t_n), m(t_s)
@@ -245,7 +268,9 @@ def frame_section(torch, log_fn, frames=12, train_views=2000, train_steps=2500):
             "train_tflops": round(3 * 327360.0 * 512 * 512 * 16 / (train_step_ms / 1e3) / 1e12, 1),
             "net_tflops": round(net_gflop / net_ms, 2), "net_gflop_per_frame": round(net_gflop, 1),
             "net_fp8_ms": round(m(t_n8), 4), "frame_fp8_ms": round(raster_ms + m(t_n8), 4),
-            "psnr_fp8_db": round(m(p_net8), 3)}
+            "psnr_fp8_db": round(m(p_net8), 3), "fp8_layers": fp8_layers,
+            "splat_aniso_ms": round(aniso_ms, 3), "splat_aniso_pairs": apairs,
+            "splat_aniso": "Gaussians elongated along the velocity, s = 300, first frame"}
 
 
 def main():
@@ -260,6 +285,8 @@ def main():
     ap.add_argument("--frame-only", action="store_true",
                     help="run only the 1080p frame section (for profiling the network kernels)")
     ap.add_argument("--train-steps", type=int, default=2500, help="Adam steps of the frame section's training")
+    ap.add_argument("--no-layout", action="store_true",
+                    help="skip the frames over the Morton layout (whole-batch culling)")
     ap.add_argument("--no-hinted", action="store_true",
                     help="skip the viewer loop with the previous frame's keys as hint (for profiling the plain stage)")
     args = ap.parse_args()
@@ -376,6 +403,55 @@ def main():
     # (a moving camera only: with one view the hint would be the answer itself)
     hinted = None if args.no_hinted or len(cams) < 2 else viewer_loop_hinted()
 
+    # the same frames rendered over the cloud's Morton layout (built once, not
+    # timed per frame), whose batches are culled whole against the view volume
+    # and the tile bounds; same keys bit for bit (checked on the last frame)
+    def layout_loop():
+        log("Morton layout: build, then the same frames with whole-batch culling")
+        lb0, lb1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        lb0.record(stream)
+        L = narvis.build_layout(pts, n)
+        lb1.record(stream)
+        torch.cuda.synchronize()
+        build_ms = lb0.elapsed_time(lb1)
+
+        def lstep(k, ev=None):
+            vp, nf, ff = narvis.narvis_camera_matrix(cams[k % len(cams)], W, H)
+            narvis.narvis_raster_clear(g.keys, W, H, stream)
+            if ev is not None:
+                ev[0].record(stream)
+            narvis.narvis_raster_render_layout(L, n, vp, nf, ff, W, H, g.keys, bounds=g.bounds, stream=stream)
+            if ev is not None:
+                ev[1].record(stream)
+            narvis.narvis_raster_resolve(pts, sc.attrs, n, vp, W, H, g, stream=stream)
+
+        for k in range(args.warmup):
+            lstep(k)
+        levs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        start.record(stream)
+        for k in range(args.steps):
+            lstep(k, levs[k])
+        stop.record(stream)
+        torch.cuda.synchronize()
+        total = start.elapsed_time(stop)
+        render = float(np.mean([a.elapsed_time(b) for a, b in levs]))
+        last = g.keys.clone()
+        vp, nf, ff = narvis.narvis_camera_matrix(cams[(args.steps - 1) % len(cams)], W, H)
+        narvis.narvis_raster_clear(g.keys, W, H, stream)
+        narvis.narvis_raster_render(pts, n, vp, nf, ff, W, H, g.keys, bounds=g.bounds, stream=stream)
+        same = bool(torch.equal(g.keys, last))
+        del L, last
+        torch.cuda.empty_cache()
+        return {"value": round(n * args.steps / (total / 1e3) / 1e9, 3), "unit": "Gpoints/s",
+                "ms_per_step": round(total / args.steps, 4), "render_stage_ms": round(render, 4),
+                "layout_build_ms": round(build_ms, 2),
+                "layout": "stable sort by 30-bit Morton code, 2048-point batches with boxes; keys carry the "
+                          "original index",
+                "same_keys_as_original_order_last_frame": same}
+
+    morton = None if args.no_layout else layout_loop()
+
     # coverage of the first frame, for context
     step(0)
     torch.cuda.synchronize()
@@ -458,6 +534,8 @@ def main():
     }
     if hinted is not None:
         out["viewer_loop_hinted"] = hinted
+    if morton is not None:
+        out["morton_layout"] = morton
     if sc.name == "terrain" and W * H >= 3840 * 2160 and len(sc.attrs) >= 3:
         # end-to-end 4K frame: the whole-frame raster call resolves the RGB
         # (uint8 colours in the RGB8 mode) and depth planes straight into the

@@ -224,6 +224,15 @@ typedef struct {
     const float *lut;       /* device float[256][3] for NARVIS_COLOR_LUT       */
     float lut_min;
     float lut_inv_range;
+    int32_t aniso;          /* 0: isotropic; 1: elongated along the velocity
+                               (see narvis_splat)                               */
+    int32_t vel_attr;       /* aniso: first of the three velocity attributes   */
+    float stretch;          /* aniso: s of S = diag(s, 1, 1), in [1, 1e6]      */
+    float focal_px;         /* ignored on input: narvis_splat derives it from
+                               the camera (narvis_camera_focal_px)              */
+    uint64_t max_pairs;     /* pair capacity of the workspace; 0 = the
+                               isotropic worst case (required > 0 for aniso;
+                               narvis_splat_count_pairs gives the exact need) */
 } narvis_splat_params;
 
 /* Human-readable name of a status code (static storage). */
@@ -429,10 +438,45 @@ size_t narvis_splat_workspace_size(uint64_t n, int32_t W, int32_t H, const narvi
  * img: float[3][H][W] device, written entirely.  workspace: device memory of
  * at least narvis_splat_workspace_size bytes, owned by the caller, contents
  * scratch.  n < 2^30.  INVALID_ARG on bad arguments, WORKSPACE if ws_bytes
- * is too small. */
+ * is too small.
+ *
+ * Anisotropic splat (p->aniso = 1; the paper's GR for vector fields, Sec. 4.2:
+ * Gaussians elongated along the vector v with covariance R diag(s, 1, 1) R^T,
+ * R orthonormal with first column v / |v|).  Reading of the base size: the
+ * world covariance is rho^2 (I + (s - 1) u u^T), u = v / |v| (0 when |v| is 0
+ * or not finite), rho = sigma_px * w / f (the cross-section projects to about
+ * sigma_px pixels at the point's depth; f = narvis_camera_focal_px).  The
+ * screen covariance is J Sigma J^T, J the Jacobian of (sx, sy).  In fp32,
+ * each operation rounded in the order written (M_rc: the clip matrix; c =
+ * 0, 1, 2):
+ *   ww = w * w;  hx = 0.5 * W;  hy = 0.5 * H
+ *   jx_c = (((M0c * w) - (cx * M3c)) / ww) * hx
+ *   jy_c = -((((M1c * w) - (cy * M3c)) / ww) * hy)
+ *   sxx = (jx_0 jx_0 + jx_1 jx_1) + jx_2 jx_2   (likewise sxy = jx . jy, syy)
+ *   vn = sqrt((vx vx + vy vy) + vz vz);  u = v / vn if 0 < vn <= FLT_MAX
+ *   ax = (jx_0 u_0 + jx_1 u_1) + jx_2 u_2;  ay likewise with jy;  k = s - 1
+ *   rho = (sigma * w) / f;  r2 = rho * rho
+ *   S00 = (sxx + k (ax ax)) r2;  S01 = (sxy + k (ax ay)) r2;  S11 = (syy + k (ay ay)) r2
+ *   det = (S00 S11) - (S01 S01); the point is dropped unless 0 < det <= FLT_MAX
+ *   Q00 = S11 / det;  Q01 = -(S01 / det);  Q11 = S00 / det
+ *   half extents rx = 3 sqrt(S00), ry = 3 sqrt(S11) replace 3 sigma in the
+ *   footprint rectangle;  a pixel is reached iff
+ *   q = ((Q00 dx) dx + ((Q01 dx) dy) 2) + (Q11 dy) dy <= 9, and
+ *   alpha = min(0.99, opacity exp(-q / 2)).
+ * Pairs beyond p->max_pairs are dropped (the image is then incomplete):
+ * size the workspace with narvis_splat_count_pairs. */
 narvis_status narvis_splat(const narvis_points *pts, const narvis_attrs *attrs, uint64_t n,
                            const narvis_camera *cam, int32_t W, int32_t H, float *img,
                            const narvis_splat_params *p, void *workspace, size_t ws_bytes, void *stream);
+
+/* Exact number of (tile, point) pairs narvis_splat will emit for these
+ * arguments (projection only, 64-bit sum; synchronises `stream`).  The
+ * workspace needs narvis_splat_workspace_size(n, W, H, p) bytes for any
+ * p->max_pairs (1 keeps it small).  Same errors as narvis_splat. */
+narvis_status narvis_splat_count_pairs(const narvis_points *pts, const narvis_attrs *attrs, uint64_t n,
+                                       const narvis_camera *cam, int32_t W, int32_t H,
+                                       const narvis_splat_params *p, void *workspace, size_t ws_bytes,
+                                       uint64_t *pairs, void *stream);
 
 /* Number of (tile, key) pairs that the last narvis_splat call on `workspace`
  * emitted and depth-sorted (with the same n, W, H and *p): for every point
@@ -500,16 +544,26 @@ size_t narvis_postprocess_workspace_size(int32_t B, int32_t W, int32_t H);
 narvis_status narvis_postprocess(const narvis_weights *w, const float *feat, int32_t B, int32_t W, int32_t H,
                                  float *img, int32_t precision, void *ws, size_t ws_bytes, void *stream);
 
-/* Prepare FP8 inference (OCP e4m3 on the matrix cores, fp32 accumulation;
- * the ten layers below full resolution run in FP8, the full-resolution
- * layers and the 1x1 head stay in bfloat16): run the bfloat16 forward on the
- * calibration batch feat [B][8][H][W],
- * take each layer's input max-abs as its static activation scale (max/448)
- * and quantise each layer's weights with one scale per output channel
- * (max |W[co]| / 448).  Needs narvis_train_workspace_size(B, W, H) bytes of
- * workspace; synchronises the stream (the scales are read back). */
+/* Prepare FP8 inference (OCP e4m3 on the matrix cores, fp32 accumulation)
+ * from the calibration batch feat [B][8][H][W] (training views, not the
+ * images to be processed): run the bfloat16 forward, take each layer's input
+ * max-abs as its static activation scale (max/448) and quantise each layer's
+ * weights with one scale per output channel (max |W[co]| / 448).  Then choose
+ * the layers that run in FP8 (e4m3 keeps three significand bits, and how far
+ * a layer's rounding moves the image depends on the trained weights after
+ * it): candidates are the ten layers below full resolution (the
+ * full-resolution layers and the 1x1 head always stay in bfloat16); each
+ * candidate alone in FP8 is scored by max |image - bfloat16 image| over the
+ * calibration batch, and candidates are added in ascending order of that
+ * score while the whole set's score stays within 0.025.  Needs
+ * narvis_train_workspace_size(B, W, H) bytes of workspace; synchronises the
+ * stream (the scales and scores are read back). */
 narvis_status narvis_weights_calibrate_fp8(narvis_weights *w, const float *feat, int32_t B, int32_t W, int32_t H,
                                            void *ws, size_t ws_bytes, void *stream);
+
+/* Layers chosen by the last narvis_weights_calibrate_fp8 (bit l set: layer l
+ * in blob order runs in FP8).  UNSUPPORTED before a calibration. */
+narvis_status narvis_weights_fp8_layers(const narvis_weights *w, uint32_t *mask);
 
 /* Device workspace bytes for narvis_train_step / narvis_train_gradients. */
 size_t narvis_train_workspace_size(int32_t B, int32_t W, int32_t H);

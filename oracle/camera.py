@@ -59,3 +59,9 @@ def clip_matrix(cam, W: int, H: int):
     """(M as float32 row-major [16], near as float32, far as float32)."""
     M = clip_matrix64(cam, W, H).astype(np.float32).reshape(16)
     return M, np.float32(cam.znear), np.float32(cam.zfar)
+
+
+def focal_px(cam, H: int) -> np.float32:
+    """Focal length in pixels for an image H pixels high, (H / 2) / tan(fovy / 2),
+    in float64 rounded once to float32 (the scale of the projected splat radius)."""
+    return np.float32(H * 0.5 / math.tan(math.radians(cam.fovy_deg) / 2.0))

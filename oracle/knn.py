@@ -33,6 +33,7 @@ def radius(x, y, z, queries=None, chunk=256):
     out = np.zeros(q.shape[0], np.float32)
     xs, ys, zs = x[ok], y[ok], z[ok]
     idx = np.nonzero(ok)[0]
+    chunk = max(1, min(chunk, (1 << 25) // max(1, xs.shape[0])))  # bounded temporaries
     for c0 in range(0, q.shape[0], chunk):
         qi = q[c0:c0 + chunk]
         with np.errstate(invalid="ignore", over="ignore"):

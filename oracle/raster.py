@@ -33,6 +33,9 @@ def lib():
         L.oracle_render_mt.argtypes = [P, P, P, ctypes.c_uint64, P, ctypes.c_float, ctypes.c_float,
                                        ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int]
         L.oracle_render_mt.restype = ctypes.c_int
+        L.oracle_render_glyph.argtypes = [P, P, P, ctypes.c_uint64, P, ctypes.c_float, ctypes.c_float,
+                                          ctypes.c_int32, ctypes.c_int32, P, P]
+        L.oracle_resolve_radius.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_float, P]
         L.oracle_project_point.argtypes = [P, ctypes.c_float, ctypes.c_float, ctypes.c_int32, ctypes.c_int32,
                                            ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                            ctypes.POINTER(ctypes.c_float)]
@@ -58,6 +61,28 @@ def render(x, y, z, M, near, far, W, H):
     keys = np.empty(W * H, dtype=np.uint64)
     lib().oracle_render(px, py, pz, x.shape[0], pm, float(near), float(far), W, H, keys.ctypes.data)
     return keys
+
+
+def render_glyph(x, y, z, M, near, far, W, H, glyph):
+    """Key buffer of the glyph-priority render (glyph: uint8 [n], nonzero = glyph point)."""
+    x, px = _f32(x)
+    y, py = _f32(y)
+    z, pz = _f32(z)
+    M, pm = _f32(M)
+    g = np.ascontiguousarray(glyph, dtype=np.uint8)
+    keys = np.empty(W * H, dtype=np.uint64)
+    lib().oracle_render_glyph(px, py, pz, x.shape[0], pm, float(near), float(far), W, H, g.ctypes.data,
+                              keys.ctypes.data)
+    return keys
+
+
+def resolve_radius(keys, W, H, r_world, focal_px):
+    """Projected splat radius plane [H*W] of a key buffer."""
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    r = np.ascontiguousarray(r_world, dtype=np.float32)
+    out = np.empty(W * H, np.float32)
+    lib().oracle_resolve_radius(keys.ctypes.data, W, H, r.ctypes.data, float(np.float32(focal_px)), out.ctypes.data)
+    return out
 
 
 def render_mt(x, y, z, M, near, far, W, H, threads):

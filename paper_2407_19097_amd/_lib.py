@@ -60,7 +60,8 @@ class RasterOpts(ctypes.Structure):
 class SplatParams(ctypes.Structure):
     _fields_ = [("sigma_px", ctypes.c_float), ("opacity", ctypes.c_float), ("color_mode", ctypes.c_int32),
                 ("color_attr", ctypes.c_int32), ("lut", ctypes.c_void_p), ("lut_min", ctypes.c_float),
-                ("lut_inv_range", ctypes.c_float)]
+                ("lut_inv_range", ctypes.c_float), ("aniso", ctypes.c_int32), ("vel_attr", ctypes.c_int32),
+                ("stretch", ctypes.c_float), ("focal_px", ctypes.c_float), ("max_pairs", ctypes.c_uint64)]
 
 
 class Layout(ctypes.Structure):
@@ -108,6 +109,10 @@ SIGNATURES = {
     "narvis_splat": (ctypes.c_int, [ctypes.POINTER(Points), ctypes.POINTER(Attrs), ctypes.c_uint64,
                                     ctypes.POINTER(Camera), ctypes.c_int32, ctypes.c_int32, _P,
                                     ctypes.POINTER(SplatParams), _P, ctypes.c_size_t, _P]),
+    "narvis_splat_count_pairs": (ctypes.c_int, [ctypes.POINTER(Points), ctypes.POINTER(Attrs), ctypes.c_uint64,
+                                                ctypes.POINTER(Camera), ctypes.c_int32, ctypes.c_int32,
+                                                ctypes.POINTER(SplatParams), _P, ctypes.c_size_t,
+                                                ctypes.POINTER(ctypes.c_uint64), _P]),
     "narvis_splat_pair_count": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint64, ctypes.c_int32,
                                                 ctypes.c_int32, ctypes.POINTER(SplatParams),
                                                 ctypes.POINTER(ctypes.c_uint64), ctypes.c_void_p]),
@@ -120,6 +125,7 @@ SIGNATURES = {
                                           ctypes.c_int32, _P, ctypes.c_size_t, _P]),
     "narvis_weights_calibrate_fp8": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P,
                                                     ctypes.c_size_t, _P]),
+    "narvis_weights_fp8_layers": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint32)]),
     "narvis_train_workspace_size": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "narvis_train_step": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_float, ctypes.c_float, _P, _P, ctypes.c_size_t, _P]),

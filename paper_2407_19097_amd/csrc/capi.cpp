@@ -424,13 +424,18 @@ bool splat_params_ok(const narvis_splat_params *p, const AttrPack &pack)
     } else {
         return false;
     }
+    if (p->aniso != 0 && p->aniso != 1) return false;
+    if (p->aniso) {
+        if (p->vel_attr < 0 || p->vel_attr + 2 >= pack.count || p->max_pairs == 0) return false;
+        if (!(p->stretch >= 1.0f && p->stretch <= 1e6f)) return false;
+    }
     return true;
 }
 
 bool splat_size_ok(uint64_t n, int32_t W, int32_t H, const narvis_splat_params *p)
 {
     if (!image_ok(W, H) || n >= (uint64_t(1) << 30) || !p || !(p->sigma_px > 0.0f && p->sigma_px <= 32.0f)) return false;
-    const SplatLayout L = splat_layout(n, W, H, p->sigma_px);
+    const SplatLayout L = splat_layout(n, W, H, p->sigma_px, p->aniso != 0, p->max_pairs);
     return L.cap < (uint64_t(1) << 32) && L.nblk < (uint64_t(1) << 31);
 }
 
@@ -439,7 +444,7 @@ bool splat_size_ok(uint64_t n, int32_t W, int32_t H, const narvis_splat_params *
 extern "C" size_t narvis_splat_workspace_size(uint64_t n, int32_t W, int32_t H, const narvis_splat_params *p)
 {
     if (!splat_size_ok(n, W, H, p)) return 0;
-    return (size_t)splat_layout(n, W, H, p->sigma_px).bytes;
+    return (size_t)splat_layout(n, W, H, p->sigma_px, p->aniso != 0, p->max_pairs).bytes;
 }
 
 extern "C" narvis_status narvis_splat(const narvis_points *pts, const narvis_attrs *attrs, uint64_t n,
@@ -456,9 +461,12 @@ extern "C" narvis_status narvis_splat(const narvis_points *pts, const narvis_att
     if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255u) ||
         (reinterpret_cast<uintptr_t>(img) & 3u))
         return NARVIS_ERR_INVALID_ARG;
-    if (ws_bytes < (size_t)splat_layout(n, W, H, p->sigma_px).bytes) return NARVIS_ERR_WORKSPACE;
+    if (ws_bytes < (size_t)splat_layout(n, W, H, p->sigma_px, p->aniso != 0, p->max_pairs).bytes)
+        return NARVIS_ERR_WORKSPACE;
+    narvis_splat_params q = *p;
+    if (narvis_camera_focal_px(cam, H, &q.focal_px) != NARVIS_OK) return NARVIS_ERR_INVALID_ARG;
     const Proj P = make_proj(vp, near_f, far_f, W, H);
-    return from_hip(launch_splat(n ? pts->x : nullptr, n ? pts->y : nullptr, n ? pts->z : nullptr, n, P, pack, *p, img,
+    return from_hip(launch_splat(n ? pts->x : nullptr, n ? pts->y : nullptr, n ? pts->z : nullptr, n, P, pack, q, img,
                                  workspace, static_cast<hipStream_t>(stream)));
 }
 
@@ -468,15 +476,37 @@ extern "C" narvis_status narvis_splat_pair_count(const void *workspace, size_t w
 {
     if (!workspace || !pairs || !splat_size_ok(n, W, H, p) || (reinterpret_cast<uintptr_t>(workspace) & 255u))
         return NARVIS_ERR_INVALID_ARG;
-    const SplatLayout L = splat_layout(n, W, H, p->sigma_px);
+    const SplatLayout L = splat_layout(n, W, H, p->sigma_px, p->aniso != 0, p->max_pairs);
     if (ws_bytes < (size_t)L.bytes) return NARVIS_ERR_WORKSPACE;
-    // the exclusive scan of the per-point tile counts leaves the total at cnt[n]
+    // the exclusive scan of the tile counts in depth order leaves the total at scnt[n]
     uint32_t total = 0;
     const hipStream_t s = static_cast<hipStream_t>(stream);
-    const char *src = static_cast<const char *>(workspace) + L.off_cnt + n * sizeof(uint32_t);
+    const char *src = static_cast<const char *>(workspace) + L.off_scnt + n * sizeof(uint32_t);
     if (hipMemcpyAsync(&total, src, sizeof(total), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return NARVIS_ERR_DEVICE;
     *pairs = total < L.cap ? total : L.cap;
     return NARVIS_OK;
+}
+
+extern "C" narvis_status narvis_splat_count_pairs(const narvis_points *pts, const narvis_attrs *attrs, uint64_t n,
+                                                  const narvis_camera *cam, int32_t W, int32_t H,
+                                                  const narvis_splat_params *p, void *workspace, size_t ws_bytes,
+                                                  uint64_t *pairs, void *stream)
+{
+    float vp[16], near_f = 0.0f, far_f = 0.0f;
+    narvis_status st = narvis_camera_matrix(cam, W, H, vp, &near_f, &far_f);
+    if (st != NARVIS_OK) return st;
+    if (!pairs || !points_ok(pts, n) || !matrix_ok(vp, near_f, far_f) || !splat_size_ok(n, W, H, p))
+        return NARVIS_ERR_INVALID_ARG;
+    AttrPack pack;
+    if (!pack_attrs(attrs, n, pack) || !splat_params_ok(p, pack)) return NARVIS_ERR_INVALID_ARG;
+    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255u)) return NARVIS_ERR_INVALID_ARG;
+    if (ws_bytes < (size_t)splat_layout(n, W, H, p->sigma_px, p->aniso != 0, p->max_pairs).bytes)
+        return NARVIS_ERR_WORKSPACE;
+    narvis_splat_params q = *p;
+    if (narvis_camera_focal_px(cam, H, &q.focal_px) != NARVIS_OK) return NARVIS_ERR_INVALID_ARG;
+    const Proj P = make_proj(vp, near_f, far_f, W, H);
+    return from_hip(launch_splat_count(n ? pts->x : nullptr, n ? pts->y : nullptr, n ? pts->z : nullptr, n, P, pack,
+                                       q, workspace, static_cast<hipStream_t>(stream), pairs));
 }

@@ -81,13 +81,18 @@ hipError_t launch_resolve(const float *x, const float *y, const float *z, uint64
 struct SplatLayout {
     int32_t tiles_x, tiles_y;
     uint64_t cap, nblk, nsums;
-    uint64_t off_ctr, off_col, off_wbits, off_cnt, off_ka, off_va, off_kb, off_vb, off_hist, off_sums, off_range;
+    uint64_t off_ctr, off_col, off_wbits, off_cnt, off_ka, off_va, off_kb, off_vb, off_hist, off_sums, off_range,
+        off_conic, off_ext, off_scnt, off_npts;
     uint64_t bytes;
     int key_bits;
 };
-SplatLayout splat_layout(uint64_t n, int32_t W, int32_t H, float sigma);
+SplatLayout splat_layout(uint64_t n, int32_t W, int32_t H, float sigma, bool aniso, uint64_t max_pairs);
 hipError_t launch_splat(const float *x, const float *y, const float *z, uint64_t n, const Proj &P, const AttrPack &A,
                         const narvis_splat_params &prm, float *img, void *ws, hipStream_t s);
+// projection only, then the exact number of (tile, point) pairs (64-bit sum; synchronises)
+hipError_t launch_splat_count(const float *x, const float *y, const float *z, uint64_t n, const Proj &P,
+                              const AttrPack &A, const narvis_splat_params &prm, void *ws, hipStream_t s,
+                              uint64_t *pairs);
 
 // Workspace carve-up of the layout build (shared by the size query and the
 // launcher).

@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <algorithm>
 #include <cstring>
 #include <vector>
 
@@ -76,6 +77,7 @@ struct narvis_weights {
     unsigned int *amax;      // [kNumLayers] activation max-abs (calibration)
     int64_t step;
     bool fp8_ready;
+    uint32_t fp8_mask;       // layers that run in FP8 (bit l = layer l), set by calibration
 };
 
 namespace {
@@ -272,15 +274,16 @@ SliceArgs slice(const __bf16 *in, int is, int io, __bf16 *out, int os, int oo, i
     } while (0)
 
 // Forward pass; the head writes fp32 planar [B][3][H][W] to `img`.
-// Under FP8 the ten layers below full resolution (the matrix-core bound part)
-// run in FP8; the full-resolution layers (bandwidth bound, and closest to the
-// raw features and to the output image) and the head stay in bfloat16.
-bool fp8_layer(int layer) { return layer >= E2A && layer <= D2B; }
+// Under FP8 the layers of w->fp8_mask run in FP8, the others in bfloat16.
+// Candidates are the ten layers below full resolution (the matrix-core
+// bound part); the full-resolution layers (bandwidth bound, and closest to the
+// raw features and to the output image) and the head always stay in bfloat16.
+bool fp8_candidate(int layer) { return layer >= E2A && layer <= D2B; }
 
 hipError_t run_conv(const narvis_weights *w, int layer, const ConvArgs &a, bool fp8, hipStream_t s)
 {
     const LayerBuf &l = w->L[layer];
-    return (fp8 && fp8_layer(layer)) ? conv_fp8(a, l.ks, l.wq, l.sw, l.sa, s) : conv(a, l.ks, s);
+    return (fp8 && ((w->fp8_mask >> layer) & 1u)) ? conv_fp8(a, l.ks, l.wq, l.sw, l.sa, s) : conv(a, l.ks, s);
 }
 
 hipError_t forward(const narvis_weights *w, const float *feat_planes, char *ws, const Plan &p, float *img, hipStream_t s,
@@ -564,6 +567,7 @@ extern "C" narvis_status narvis_weights_create(const float *host_blob, size_t co
     }
     w->amax = reinterpret_cast<unsigned int *>(base + off_amax);
     w->fp8_ready = false;
+    w->fp8_mask = 0;
     hipError_t e = hipMemset(w->pool, 0, o);
     if (e == hipSuccess) e = hipMemcpy(w->master, host_blob, count * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = refresh(w, nullptr);
@@ -729,6 +733,10 @@ extern "C" narvis_status narvis_train_tensor(int32_t B, int32_t W, int32_t H, co
     return NARVIS_ERR_INVALID_ARG;
 }
 
+// Largest max-abs change of the image that the FP8 layers may make on the
+// calibration batch (images in [0, 1]).
+constexpr float kFp8Budget = 0.025f;
+
 extern "C" narvis_status narvis_weights_calibrate_fp8(narvis_weights *w, const float *feat, int32_t B, int32_t W,
                                                       int32_t H, void *ws, size_t ws_bytes, void *stream)
 {
@@ -766,6 +774,53 @@ extern "C" narvis_status narvis_weights_calibrate_fp8(narvis_weights *w, const f
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return NARVIS_ERR_DEVICE;
+    // Which layers run in FP8: e4m3 keeps three significand bits, and how
+    // much a layer's rounding moves the image depends on the trained weights
+    // downstream of it.  On the calibration batch, with the bfloat16 forward
+    // as reference (in the gradient region g_cat1, unused by a forward), take
+    // each candidate alone in FP8 and measure max |image - reference|; then
+    // add the candidates in ascending order of that error while the error of
+    // the whole set stays within kFp8Budget.
+    const int64_t nimg = (int64_t)B * 3 * H * W;
+    float *ref = reinterpret_cast<float *>(base + p.g_cat1);
+    float *out = reinterpret_cast<float *>(base + p.out);
+    e = forward(w, feat, base, p, ref, s, false, false);
+    auto image_error = [&](uint32_t mask, float *err) {
+        w->fp8_mask = mask;
+        hipError_t r = forward(w, feat, base, p, out, s, true, false);
+        if (r == hipSuccess) r = hipMemsetAsync(w->amax, 0, 4, s);
+        if (r == hipSuccess) r = absdiff_max_f32(out, ref, nimg, w->amax, s);
+        unsigned int bits = 0;
+        if (r == hipSuccess) r = hipMemcpyAsync(&bits, w->amax, 4, hipMemcpyDeviceToHost, s);
+        if (r == hipSuccess) r = hipStreamSynchronize(s);
+        std::memcpy(err, &bits, 4);
+        return r;
+    };
+    std::vector<std::pair<float, int>> solo;
+    for (int i = 0; i < kNumLayers && e == hipSuccess; ++i) {
+        if (!fp8_candidate(i)) continue;
+        float err = 0.0f;
+        e = image_error(1u << i, &err);
+        solo.push_back({err, i});
+    }
+    std::stable_sort(solo.begin(), solo.end(),
+                     [](const std::pair<float, int> &a, const std::pair<float, int> &b) { return a.first < b.first; });
+    uint32_t mask = 0;
+    for (size_t k = 0; k < solo.size() && e == hipSuccess; ++k) {
+        float err = 0.0f;
+        e = image_error(mask | (1u << solo[k].second), &err);
+        if (err <= kFp8Budget) mask |= 1u << solo[k].second;
+    }
+    w->fp8_mask = mask;
+    if (e != hipSuccess) return NARVIS_ERR_DEVICE;
     w->fp8_ready = true;
+    return NARVIS_OK;
+}
+
+extern "C" narvis_status narvis_weights_fp8_layers(const narvis_weights *w, uint32_t *mask)
+{
+    if (!w || !mask) return NARVIS_ERR_INVALID_ARG;
+    if (!w->fp8_ready) return NARVIS_ERR_UNSUPPORTED;
+    *mask = w->fp8_mask;
     return NARVIS_OK;
 }

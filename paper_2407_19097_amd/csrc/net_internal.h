@@ -76,6 +76,7 @@ hipError_t conv_fp8(const ConvArgs &a, int KS, const uint8_t *wq, const float *s
 hipError_t quant_weights(const float *master, int Cout, int Cin, int KS, int rows, int kpad, uint8_t *wq, float *sw,
                          hipStream_t s);
 hipError_t absmax_bf16(const __bf16 *x, int64_t n, unsigned int *out, hipStream_t s);
+hipError_t absdiff_max_f32(const float *a, const float *b, int64_t n, unsigned int *out, hipStream_t s);
 hipError_t features(const float *in, __bf16 *out, int B, int H, int W, hipStream_t s);
 hipError_t upsample2(const SliceArgs &a, hipStream_t s);
 hipError_t upsample2_bwd(const SliceArgs &a, hipStream_t s);

@@ -1474,6 +1474,32 @@ hipError_t quant_weights(const float *master, int Cout, int Cin, int KS, int row
     return hipGetLastError();
 }
 
+// max |a - b| over two fp32 buffers (NaN counts as +inf: a calibration that
+// produced one must not pass)
+__global__ __launch_bounds__(256) void k_absdiff_max(const float *a, const float *b, int64_t n, unsigned int *out)
+{
+    __shared__ float red[256];
+    float m = 0.0f;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const float d = fabsf(a[i] - b[i]);
+        m = fmaxf(m, d == d ? d : __builtin_inff());
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int s2 = 128; s2 > 0; s2 >>= 1) {
+        if (threadIdx.x < s2) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s2]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(out, __float_as_uint(red[0]));
+}
+
+hipError_t absdiff_max_f32(const float *a, const float *b, int64_t n, unsigned int *out, hipStream_t s)
+{
+    const int64_t blocks = std::min<int64_t>(4096, (n + 255) / 256);
+    hipLaunchKernelGGL(k_absdiff_max, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(256), 0, s, a, b, n, out);
+    return hipGetLastError();
+}
+
 hipError_t absmax_bf16(const __bf16 *x, int64_t n, unsigned int *out, hipStream_t s)
 {
     const int64_t blocks = std::min<int64_t>(4096, (n + 255) / 256);

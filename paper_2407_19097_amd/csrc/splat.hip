@@ -7,12 +7,13 @@
 // standard deviation sigma pixels at its projected position.  Pipeline:
 //   project -- same fp32 transform and cull as the rasterizer; the Gaussian's
 //              3-sigma footprint gives a rectangle of screen tiles;
-//   scan    -- exclusive prefix sum of the per-point tile counts;
-//   emit    -- one (tile << 32 | depth bits, point index) pair per covered tile,
-//              written in point order;
-//   sort    -- stable least-significant-digit radix sort on the 64-bit key, so
-//              equal (tile, depth) keep the point order: within a tile the list
-//              is ordered exactly like the rasterizer's (depth, index) key;
+//   order   -- stable radix sort of the points by depth bits (culled points
+//              last): equal depths keep the index order, so this is the order
+//              of the rasterizer's (depth, index) key;
+//   scan    -- exclusive prefix sum of the tile counts in that order;
+//   emit    -- one (tile, point index) pair per covered tile, in that order;
+//   sort    -- stable radix sort of the pairs by tile (two 8-bit passes for up
+//              to 65536 tiles): within a tile the list keeps the depth order;
 //   ranges  -- first and one-past-last pair of every tile;
 //   blend   -- one workgroup per 16x16 tile, one thread per pixel; batches of
 //              the tile's list are staged through LDS and composited front to
@@ -35,7 +36,8 @@ constexpr int kScanItems = 16;     // elements per thread in scans and the sort
 constexpr int kScanTile = kT * kScanItems;
 constexpr int kTile = 16;          // splat screen tile edge in pixels
 
-__device__ __forceinline__ bool project(const Proj &P, float x, float y, float z, float &sx, float &sy, float &w)
+__device__ __forceinline__ bool project(const Proj &P, float x, float y, float z, float &sx, float &sy, float &w,
+                                        float &cx_out, float &cy_out)
 {
     float cx = P.m00 * x;
     cx = cx + P.m01 * y;
@@ -62,6 +64,8 @@ __device__ __forceinline__ bool project(const Proj &P, float x, float y, float z
     sx = a;
     sy = b;
     w = ww;
+    cx_out = cx;
+    cy_out = cy;
     return true;
 }
 
@@ -91,15 +95,100 @@ struct SplatArgs {
     uint32_t *wbits;      // [n] depth bits
     uint32_t *cnt;        // [n + 1] tile counts, scanned in place to offsets
     uint64_t cap;         // capacity of the pair arrays
+    // anisotropic footprint (aniso != 0)
+    int32_t aniso, vel_attr;
+    float sigma, stretch_k, focal;  // sigma_px, s - 1, focal length in pixels
+    float4 *conic;        // [n] Q00, Q01, Q11 of the inverse screen covariance
+    float2 *ext;          // [n] 3-sigma half extents of the footprint in x and y
 };
+
+// Screen-space footprint of a Gaussian elongated along the point's velocity
+// (Sec. 4.2: covariance R diag(s, 1, 1) R^T whose dominant axis is v).  World
+// covariance rho^2 (I + (s - 1) u u^T) with u = v / |v| and rho = sigma w / f,
+// projected by the Jacobian J of the screen position: J Sigma J^T.  Every
+// operation is rounded to fp32 in the order written (the host header spells
+// the same sequence out).  False when the covariance is not positive
+// definite or not finite (the point is then dropped).
+__device__ __forceinline__ bool aniso_footprint(const SplatArgs &S, float cx, float cy, float w, float vx, float vy,
+                                                float vz, float4 &q, float2 &ext)
+{
+    const Proj &P = S.P;
+    const float ww = w * w;
+    const float hx = 0.5f * P.Wf, hy = 0.5f * P.Hf;
+    const float m0[3] = {P.m00, P.m01, P.m02}, m1[3] = {P.m10, P.m11, P.m12}, m3[3] = {P.m30, P.m31, P.m32};
+    float jx[3], jy[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        float a = m0[c] * w;
+        float b = cx * m3[c];
+        float t = a - b;
+        t = t / ww;
+        jx[c] = t * hx;
+        a = m1[c] * w;
+        b = cy * m3[c];
+        t = a - b;
+        t = t / ww;
+        t = t * hy;
+        jy[c] = -t;
+    }
+    float sxx = jx[0] * jx[0];
+    sxx = sxx + jx[1] * jx[1];
+    sxx = sxx + jx[2] * jx[2];
+    float sxy = jx[0] * jy[0];
+    sxy = sxy + jx[1] * jy[1];
+    sxy = sxy + jx[2] * jy[2];
+    float syy = jy[0] * jy[0];
+    syy = syy + jy[1] * jy[1];
+    syy = syy + jy[2] * jy[2];
+    float vn = vx * vx;
+    vn = vn + vy * vy;
+    vn = vn + vz * vz;
+    vn = sqrtf(vn);
+    float ux = 0.0f, uy = 0.0f, uz = 0.0f;
+    if (vn > 0.0f && vn <= 3.40282347e38f) {
+        ux = vx / vn;
+        uy = vy / vn;
+        uz = vz / vn;
+    }
+    float ax = jx[0] * ux;
+    ax = ax + jx[1] * uy;
+    ax = ax + jx[2] * uz;
+    float ay = jy[0] * ux;
+    ay = ay + jy[1] * uy;
+    ay = ay + jy[2] * uz;
+    float rho = S.sigma * w;
+    rho = rho / S.focal;
+    const float r2 = rho * rho;
+    float s00 = ax * ax;
+    s00 = S.stretch_k * s00;
+    s00 = sxx + s00;
+    s00 = s00 * r2;
+    float s01 = ax * ay;
+    s01 = S.stretch_k * s01;
+    s01 = sxy + s01;
+    s01 = s01 * r2;
+    float s11 = ay * ay;
+    s11 = S.stretch_k * s11;
+    s11 = syy + s11;
+    s11 = s11 * r2;
+    float det = s00 * s11;
+    const float e = s01 * s01;
+    det = det - e;
+    if (!(det > 0.0f && det <= 3.40282347e38f)) return false;
+    q = make_float4(s11 / det, -(s01 / det), s00 / det, 0.0f);
+    ext = make_float2(3.0f * sqrtf(s00), 3.0f * sqrtf(s11));
+    return ext.x <= 3.40282347e38f && ext.y <= 3.40282347e38f;
+}
 
 // footprint rectangle in tiles (conservative: every pixel whose centre can be
 // within `reach` of (sx, sy) is inside)
-__device__ __forceinline__ void tile_rect(const SplatArgs &S, float sx, float sy, int &tx0, int &tx1, int &ty0, int &ty1)
+__device__ __forceinline__ void tile_rect(const SplatArgs &S, float sx, float sy, float rx, float ry, int &tx0,
+                                          int &tx1, int &ty0, int &ty1)
 {
     const int W = S.P.W, H = S.P.H;
-    int x0 = (int)floorf(sx - S.reach - 1.0f), x1 = (int)floorf(sx + S.reach + 1.0f);
-    int y0 = (int)floorf(sy - S.reach - 1.0f), y1 = (int)floorf(sy + S.reach + 1.0f);
+    // clamped in float first: an anisotropic extent can exceed the int range
+    int x0 = (int)fmaxf(floorf(sx - rx - 1.0f), -1.0f), x1 = (int)fminf(floorf(sx + rx + 1.0f), (float)W);
+    int y0 = (int)fmaxf(floorf(sy - ry - 1.0f), -1.0f), y1 = (int)fminf(floorf(sy + ry + 1.0f), (float)H);
     x0 = max(x0, 0);
     y0 = max(y0, 0);
     x1 = min(x1, W - 1);
@@ -118,10 +207,25 @@ __global__ __launch_bounds__(kT) void k_splat_project(SplatArgs S)
         S.cnt[i] = 0;
         return;
     }
-    float sx, sy, w;
-    if (!project(S.P, S.X[i], S.Y[i], S.Z[i], sx, sy, w)) {
+    float sx, sy, w, cx, cy;
+    if (!project(S.P, S.X[i], S.Y[i], S.Z[i], sx, sy, w, cx, cy)) {
         S.cnt[i] = 0;
         return;
+    }
+    float rx = S.reach, ry = S.reach;
+    if (S.aniso) {
+        float4 q;
+        float2 ext;
+        const float vx = attr_f32(S.A.a[S.vel_attr], (uint32_t)i), vy = attr_f32(S.A.a[S.vel_attr + 1], (uint32_t)i),
+                    vz = attr_f32(S.A.a[S.vel_attr + 2], (uint32_t)i);
+        if (!aniso_footprint(S, cx, cy, w, vx, vy, vz, q, ext)) {
+            S.cnt[i] = 0;
+            return;
+        }
+        S.conic[i] = q;
+        S.ext[i] = ext;
+        rx = ext.x;
+        ry = ext.y;
     }
     float4 c;
     if (S.color_mode == NARVIS_COLOR_LUT) {
@@ -140,29 +244,52 @@ __global__ __launch_bounds__(kT) void k_splat_project(SplatArgs S)
                         attr_f32(S.A.a[S.color_attr + 2], (uint32_t)i) * s, 0.0f);
     }
     int tx0, tx1, ty0, ty1;
-    tile_rect(S, sx, sy, tx0, tx1, ty0, ty1);
+    tile_rect(S, sx, sy, rx, ry, tx0, tx1, ty0, ty1);
     S.ctr[i] = make_float2(sx, sy);
     S.col[i] = c;
     S.wbits[i] = __float_as_uint(w);
     S.cnt[i] = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
 }
 
-__global__ __launch_bounds__(kT) void k_splat_emit(SplatArgs S, unsigned long long *keys, uint32_t *vals)
+// depth keys of the point order: a culled point (no tile) sorts after every
+// kept one (kept depth bits are below 0x7F800000)
+__global__ __launch_bounds__(kT) void k_depth_keys(SplatArgs S, unsigned long long *keys, uint32_t *vals)
 {
     const uint64_t i = (uint64_t)blockIdx.x * kT + threadIdx.x;
     if (i >= S.n) return;
-    const uint32_t start = S.cnt[i], stop = S.cnt[i + 1];
+    keys[i] = S.cnt[i] ? S.wbits[i] : 0xFFFFFFFFull;
+    vals[i] = (uint32_t)i;
+}
+
+// tile counts in depth order (scnt[n] = 0: the scan's total slot)
+__global__ __launch_bounds__(kT) void k_gather_counts(const uint32_t *cnt, const uint32_t *order, uint64_t n,
+                                                      uint32_t *scnt)
+{
+    const uint64_t j = (uint64_t)blockIdx.x * kT + threadIdx.x;
+    if (j > n) return;
+    scnt[j] = j < n ? cnt[order[j]] : 0u;
+}
+
+// sorted position j: the pairs of point order[j] at [scnt[j], scnt[j + 1])
+__global__ __launch_bounds__(kT) void k_splat_emit(SplatArgs S, const uint32_t *order, const uint32_t *scnt,
+                                                   unsigned long long *keys, uint32_t *vals)
+{
+    const uint64_t j = (uint64_t)blockIdx.x * kT + threadIdx.x;
+    if (j >= S.n) return;
+    const uint32_t start = scnt[j], stop = scnt[j + 1];
     if (start == stop) return;
+    const uint32_t i = order[j];
+    if ((uint64_t)i >= S.n) return;  // a permutation of [0, n); guards the reads regardless
     const float2 c = S.ctr[i];
+    const float2 ext = S.aniso ? S.ext[i] : make_float2(S.reach, S.reach);
     int tx0, tx1, ty0, ty1;
-    tile_rect(S, c.x, c.y, tx0, tx1, ty0, ty1);
-    const unsigned long long d = S.wbits[i];
+    tile_rect(S, c.x, c.y, ext.x, ext.y, tx0, tx1, ty0, ty1);
     uint32_t o = start;
     for (int ty = ty0; ty <= ty1; ++ty)
         for (int tx = tx0; tx <= tx1; ++tx, ++o) {
             if (o >= stop || o >= S.cap) return;  // the count bounds the rectangle; guard anyway
-            keys[o] = ((unsigned long long)(uint32_t)(ty * S.tiles_x + tx) << 32) | d;
-            vals[o] = (uint32_t)i;
+            keys[o] = (unsigned long long)(uint32_t)(ty * S.tiles_x + tx);
+            vals[o] = i;
         }
 }
 
@@ -381,10 +508,10 @@ __global__ __launch_bounds__(kT) void k_tile_ranges(const unsigned long long *ke
     const uint64_t p = (uint64_t)blockIdx.x * kT + threadIdx.x;
     const uint64_t N = min((uint64_t)*count, cap);
     if (p >= N) return;
-    const uint32_t t = (uint32_t)(keys[p] >> 32);
+    const uint32_t t = (uint32_t)keys[p];
     if (t >= ntiles) return;
-    if (p == 0 || (uint32_t)(keys[p - 1] >> 32) != t) range[2 * t] = (uint32_t)p;
-    if (p + 1 == N || (uint32_t)(keys[p + 1] >> 32) != t) range[2 * t + 1] = (uint32_t)(p + 1);
+    if (p == 0 || (uint32_t)keys[p - 1] != t) range[2 * t] = (uint32_t)p;
+    if (p + 1 == N || (uint32_t)keys[p + 1] != t) range[2 * t + 1] = (uint32_t)(p + 1);
 }
 
 struct BlendArgs {
@@ -394,15 +521,22 @@ struct BlendArgs {
     const uint32_t *vals;
     const float2 *ctr;
     const float4 *col;
+    const float4 *conic;  // ANISO: per point Q00, Q01, Q11
     float *img;
     int32_t W, H, tiles_x;
     float cut2, inv2s2, opacity;
 };
 
+// ANISO: a Gaussian reaches a pixel when its quadratic form
+// q = ((Q00 dx) dx + ((Q01 dx) dy) 2) + (Q11 dy) dy is at most 9 (3 sigma),
+// alpha = min(0.99, opacity exp(-q / 2)); otherwise d2 = dx^2 + dy^2 against
+// (3 sigma)^2 and alpha = min(0.99, opacity exp(-d2 / 2 sigma^2)).
+template <bool ANISO>
 __global__ __launch_bounds__(kT) void k_splat_blend(BlendArgs B)
 {
     __shared__ float2 sc[kT];
     __shared__ float4 scol[kT];
+    __shared__ float4 sq[ANISO ? kT : 1];
     const int tile = blockIdx.x;
     const int tx = tile % B.tiles_x, ty = tile / B.tiles_x;
     const int px = tx * kTile + (threadIdx.x % kTile);
@@ -421,6 +555,7 @@ __global__ __launch_bounds__(kT) void k_splat_blend(BlendArgs B)
             const bool ok = i < B.n;  // always true for consistent lists
             sc[threadIdx.x] = ok ? B.ctr[i] : make_float2(-1e30f, -1e30f);
             scol[threadIdx.x] = ok ? B.col[i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (ANISO) sq[threadIdx.x] = ok ? B.conic[i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         }
         __syncthreads();
         const int m = (int)min((uint32_t)kT, stop - s0);
@@ -428,10 +563,26 @@ __global__ __launch_bounds__(kT) void k_splat_blend(BlendArgs B)
             const float2 c = sc[j];
             const float dx = fx - c.x;
             const float dy = fy - c.y;
-            float d2 = dx * dx;
-            d2 = d2 + dy * dy;
-            if (!(d2 <= B.cut2)) continue;
-            float a = B.opacity * expf(-d2 * B.inv2s2);
+            float a;
+            if (ANISO) {
+                const float4 cq = sq[j];
+                float t0 = cq.x * dx;
+                t0 = t0 * dx;
+                float t1 = cq.y * dx;
+                t1 = t1 * dy;
+                t1 = t1 + t1;
+                float t2 = cq.z * dy;
+                t2 = t2 * dy;
+                float qf = t0 + t1;
+                qf = qf + t2;
+                if (!(qf <= 9.0f)) continue;
+                a = B.opacity * expf(-0.5f * qf);
+            } else {
+                float d2 = dx * dx;
+                d2 = d2 + dy * dy;
+                if (!(d2 <= B.cut2)) continue;
+                a = B.opacity * expf(-d2 * B.inv2s2);
+            }
             a = fminf(a, 0.99f);
             if (a < 1.0f / 255.0f) continue;
             const float Tn = T * (1.0f - a);
@@ -461,7 +612,7 @@ uint64_t align256(uint64_t v) { return (v + 255) & ~uint64_t(255); }
 }  // namespace
 
 // Workspace carve-up, shared by the size query and the launcher.
-SplatLayout splat_layout(uint64_t n, int32_t W, int32_t H, float sigma)
+SplatLayout splat_layout(uint64_t n, int32_t W, int32_t H, float sigma, bool aniso, uint64_t max_pairs)
 {
     SplatLayout L{};
     // the footprint rectangle spans x1 - x0 <= 2 reach + 3 pixels in exact
@@ -471,8 +622,10 @@ SplatLayout splat_layout(uint64_t n, int32_t W, int32_t H, float sigma)
     const uint64_t per_axis = (uint64_t)((2.0f * reach + 4.0f) / (float)kTile) + 2;
     L.tiles_x = (W + kTile - 1) / kTile;
     L.tiles_y = (H + kTile - 1) / kTile;
-    L.cap = n * per_axis * per_axis;
-    L.nblk = (L.cap + kScanTile - 1) / kScanTile;
+    L.cap = max_pairs ? max_pairs : n * per_axis * per_axis;
+    // the pair arrays also hold the point order (n elements) before the pairs
+    const uint64_t elems = L.cap > n ? L.cap : n;
+    L.nblk = (elems + kScanTile - 1) / kScanTile;
     if (L.nblk == 0) L.nblk = 1;
     const uint64_t histlen = L.nblk * 256;
     const uint64_t scanlen = histlen > n + 1 ? histlen : n + 1;
@@ -482,17 +635,21 @@ SplatLayout splat_layout(uint64_t n, int32_t W, int32_t H, float sigma)
     L.off_col = o; o = align256(o + n * sizeof(float4));
     L.off_wbits = o; o = align256(o + n * 4);
     L.off_cnt = o; o = align256(o + (n + 1) * 4);
-    L.off_ka = o; o = align256(o + L.cap * 8);
-    L.off_va = o; o = align256(o + L.cap * 4);
-    L.off_kb = o; o = align256(o + L.cap * 8);
-    L.off_vb = o; o = align256(o + L.cap * 4);
+    L.off_ka = o; o = align256(o + elems * 8);
+    L.off_va = o; o = align256(o + elems * 4);
+    L.off_kb = o; o = align256(o + elems * 8);
+    L.off_vb = o; o = align256(o + elems * 4);
+    L.off_scnt = o; o = align256(o + (n + 1) * 4);
+    L.off_npts = o; o = align256(o + 4);
     L.off_hist = o; o = align256(o + histlen * 4);
     L.off_sums = o; o = align256(o + L.nsums * 4);
     L.off_range = o; o = align256(o + (uint64_t)L.tiles_x * L.tiles_y * 8);
+    L.off_conic = o; o = align256(o + (aniso ? n * sizeof(float4) : 0));
+    L.off_ext = o; o = align256(o + (aniso ? n * sizeof(float2) : 0));
     L.bytes = o;
-    int bits = 0;
+    int bits = 1;
     while ((1ull << bits) < (uint64_t)L.tiles_x * L.tiles_y) ++bits;
-    L.key_bits = 32 + bits;
+    L.key_bits = bits;  // of the pair sort (tile ids)
     return L;
 }
 
@@ -504,6 +661,63 @@ static hipError_t scan_excl(const uint32_t *in, uint32_t *out, uint64_t len, uin
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kT), 0, s, sums, (uint32_t)nb);
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kT), 0, s, in, out, len, sums);
     return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kT) void k_sum_u32(const uint32_t *v, uint64_t n, unsigned long long *sum)
+{
+    unsigned long long c = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (uint64_t)gridDim.x * kT) c += v[i];
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) c += __shfl_xor(c, d);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(sum, c);
+}
+
+hipError_t launch_splat_count(const float *x, const float *y, const float *z, uint64_t n, const Proj &P,
+                              const AttrPack &A, const narvis_splat_params &prm, void *ws, hipStream_t s,
+                              uint64_t *pairs)
+{
+    const SplatLayout L = splat_layout(n, P.W, P.H, prm.sigma_px, prm.aniso != 0, prm.max_pairs);
+    char *base = static_cast<char *>(ws);
+    SplatArgs S{};
+    S.X = x;
+    S.Y = y;
+    S.Z = z;
+    S.n = n;
+    S.P = P;
+    S.A = A;
+    S.color_mode = prm.color_mode;
+    S.color_attr = prm.color_attr;
+    S.lut = prm.lut;
+    S.lut_min = prm.lut_min;
+    S.lut_inv = prm.lut_inv_range;
+    S.reach = 3.0f * prm.sigma_px;
+    S.tiles_x = L.tiles_x;
+    S.tiles_y = L.tiles_y;
+    S.ctr = reinterpret_cast<float2 *>(base + L.off_ctr);
+    S.col = reinterpret_cast<float4 *>(base + L.off_col);
+    S.wbits = reinterpret_cast<uint32_t *>(base + L.off_wbits);
+    S.cnt = reinterpret_cast<uint32_t *>(base + L.off_cnt);
+    S.cap = L.cap;
+    S.aniso = prm.aniso;
+    S.vel_attr = prm.vel_attr;
+    S.sigma = prm.sigma_px;
+    S.stretch_k = prm.stretch - 1.0f;
+    S.focal = prm.focal_px;
+    S.conic = reinterpret_cast<float4 *>(base + L.off_conic);
+    S.ext = reinterpret_cast<float2 *>(base + L.off_ext);
+    auto *sum = reinterpret_cast<unsigned long long *>(base + L.off_sums);
+    hipLaunchKernelGGL(k_splat_project, dim3((unsigned)((n + 1 + kT - 1) / kT)), dim3(kT), 0, s, S);
+    hipError_t e = hipMemsetAsync(sum, 0, 8, s);
+    if (e != hipSuccess) return e;
+    const uint64_t blocks = (n + kT - 1) / kT;
+    hipLaunchKernelGGL(k_sum_u32, dim3((unsigned)(blocks < 4096 ? (blocks ? blocks : 1) : 4096)), dim3(kT), 0, s,
+                       S.cnt, n, sum);
+    unsigned long long total = 0;
+    e = hipMemcpyAsync(&total, sum, 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    *pairs = total;
+    return hipSuccess;
 }
 
 hipError_t launch_radix_sort(unsigned long long *ka, uint32_t *va, unsigned long long *kb, uint32_t *vb,
@@ -539,7 +753,7 @@ uint64_t radix_sort_sums_len(uint64_t cap)
 hipError_t launch_splat(const float *x, const float *y, const float *z, uint64_t n, const Proj &P, const AttrPack &A,
                         const narvis_splat_params &prm, float *img, void *ws, hipStream_t s)
 {
-    const SplatLayout L = splat_layout(n, P.W, P.H, prm.sigma_px);
+    const SplatLayout L = splat_layout(n, P.W, P.H, prm.sigma_px, prm.aniso != 0, prm.max_pairs);
     char *base = static_cast<char *>(ws);
     SplatArgs S;
     S.X = x;
@@ -561,6 +775,13 @@ hipError_t launch_splat(const float *x, const float *y, const float *z, uint64_t
     S.wbits = reinterpret_cast<uint32_t *>(base + L.off_wbits);
     S.cnt = reinterpret_cast<uint32_t *>(base + L.off_cnt);
     S.cap = L.cap;
+    S.aniso = prm.aniso;
+    S.vel_attr = prm.vel_attr;
+    S.sigma = prm.sigma_px;
+    S.stretch_k = prm.stretch - 1.0f;
+    S.focal = prm.focal_px;
+    S.conic = reinterpret_cast<float4 *>(base + L.off_conic);
+    S.ext = reinterpret_cast<float2 *>(base + L.off_ext);
     auto *ka = reinterpret_cast<unsigned long long *>(base + L.off_ka);
     auto *kb = reinterpret_cast<unsigned long long *>(base + L.off_kb);
     auto *va = reinterpret_cast<uint32_t *>(base + L.off_va);
@@ -569,25 +790,37 @@ hipError_t launch_splat(const float *x, const float *y, const float *z, uint64_t
     auto *sums = reinterpret_cast<uint32_t *>(base + L.off_sums);
     auto *range = reinterpret_cast<uint32_t *>(base + L.off_range);
     const uint64_t ntiles = (uint64_t)L.tiles_x * L.tiles_y;
-    const uint32_t *total = S.cnt + n;  // after the scan
 
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((2 * ntiles + kT - 1) / kT)), dim3(kT), 0, s, range, 2 * ntiles, 0u);
     hipLaunchKernelGGL(k_splat_project, dim3((unsigned)((n + 1 + kT - 1) / kT)), dim3(kT), 0, s, S);
-    hipError_t e = scan_excl(S.cnt, S.cnt, n + 1, sums, s);
-    if (e != hipSuccess) return e;
-    if (n > 0) hipLaunchKernelGGL(k_splat_emit, dim3((unsigned)((n + kT - 1) / kT)), dim3(kT), 0, s, S, ka, va);
-    const uint32_t nblk = (uint32_t)L.nblk;
-    for (int shift = 0; shift < L.key_bits; shift += 8) {
-        hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kT), 0, s, ka, total, L.cap, shift, hist, nblk);
-        e = scan_excl(hist, hist, (uint64_t)nblk * 256, sums, s);
+    auto *scnt = reinterpret_cast<uint32_t *>(base + L.off_scnt);
+    auto *npts = reinterpret_cast<uint32_t *>(base + L.off_npts);
+    const uint32_t *total = scnt + n;  // after the scan
+    hipError_t e = hipSuccess;
+    if (n > 0) {
+        // point order by depth (4 passes over 32 depth bits; ends in ka/va)
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kT), 0, s, npts, (uint64_t)1, (uint32_t)n);
+        hipLaunchKernelGGL(k_depth_keys, dim3((unsigned)((n + kT - 1) / kT)), dim3(kT), 0, s, S, ka, va);
+        bool in_b = false;
+        e = launch_radix_sort(ka, va, kb, vb, npts, n, 32, hist, sums, s, &in_b);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(kT), 0, s, ka, va, kb, vb, total, L.cap, shift, hist, nblk);
-        unsigned long long *tk = ka;
-        ka = kb;
-        kb = tk;
-        uint32_t *tv = va;
-        va = vb;
-        vb = tv;
+        const uint32_t *order = in_b ? vb : va;
+        unsigned long long *pk = in_b ? ka : kb;  // the free pair of arrays
+        uint32_t *pv = in_b ? va : vb;
+        hipLaunchKernelGGL(k_gather_counts, dim3((unsigned)((n + 1 + kT - 1) / kT)), dim3(kT), 0, s, S.cnt, order, n,
+                           scnt);
+        e = scan_excl(scnt, scnt, n + 1, sums, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_splat_emit, dim3((unsigned)((n + kT - 1) / kT)), dim3(kT), 0, s, S, order, scnt, pk, pv);
+        // pairs by tile, stable (depth order kept within a tile)
+        unsigned long long *qk = in_b ? kb : ka;
+        uint32_t *qv = in_b ? vb : va;
+        e = launch_radix_sort(pk, pv, qk, qv, total, L.cap, L.key_bits, hist, sums, s, &in_b);
+        if (e != hipSuccess) return e;
+        ka = in_b ? qk : pk;
+        va = in_b ? qv : pv;
+    } else {
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kT), 0, s, scnt, (uint64_t)1, 0u);
     }
     hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)((L.cap + kT - 1) / kT > 0 ? (L.cap + kT - 1) / kT : 1)), dim3(kT),
                        0, s, ka, total, L.cap, range, (uint32_t)ntiles);
@@ -599,6 +832,7 @@ hipError_t launch_splat(const float *x, const float *y, const float *z, uint64_t
     B.vals = va;
     B.ctr = S.ctr;
     B.col = S.col;
+    B.conic = S.conic;
     B.img = img;
     B.W = P.W;
     B.H = P.H;
@@ -607,7 +841,10 @@ hipError_t launch_splat(const float *x, const float *y, const float *z, uint64_t
     B.cut2 = reach * reach;
     B.inv2s2 = 1.0f / (2.0f * prm.sigma_px * prm.sigma_px);
     B.opacity = prm.opacity;
-    hipLaunchKernelGGL(k_splat_blend, dim3((unsigned)ntiles), dim3(kT), 0, s, B);
+    if (prm.aniso)
+        hipLaunchKernelGGL(k_splat_blend<true>, dim3((unsigned)ntiles), dim3(kT), 0, s, B);
+    else
+        hipLaunchKernelGGL(k_splat_blend<false>, dim3((unsigned)ntiles), dim3(kT), 0, s, B);
     return hipGetLastError();
 }
 

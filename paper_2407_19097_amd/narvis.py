@@ -294,10 +294,15 @@ class SplatParams:
     lut: object = None            # float32 [256][3] device tensor for COLOR_LUT
     lut_min: float = 0.0
     lut_inv_range: float = 1.0
+    aniso: int = 0                # 1: Gaussians elongated along the velocity (attributes vel_attr..+2)
+    vel_attr: int = -1
+    stretch: float = 1.0          # s of S = diag(s, 1, 1)
+    max_pairs: int = 0            # pair capacity; 0 = isotropic worst case (aniso: narvis_splat_count_pairs)
 
     def struct(self) -> _lib.SplatParams:
         return _lib.SplatParams(float(self.sigma_px), float(self.opacity), int(self.color_mode),
-                                int(self.color_attr), _ptr(self.lut), float(self.lut_min), float(self.lut_inv_range))
+                                int(self.color_attr), _ptr(self.lut), float(self.lut_min), float(self.lut_inv_range),
+                                int(self.aniso), int(self.vel_attr), float(self.stretch), 0.0, int(self.max_pairs))
 
 
 def narvis_splat_workspace_size(n: int, W: int, H: int, params: SplatParams) -> int:
@@ -317,6 +322,21 @@ def narvis_splat(points, attrs, n: int, camera, W: int, H: int, img, params: Spl
     _lib.check(_lib.load().narvis_splat(ctypes.byref(pt), ctypes.byref(a), int(n), ctypes.byref(c), W, H, _ptr(img),
                                         ctypes.byref(p), _ptr(workspace), nbytes, _stream_ptr(stream)),
                "narvis_splat")
+
+
+def narvis_splat_count_pairs(points, attrs, n: int, camera, W: int, H: int, params: SplatParams, workspace,
+                             stream=None) -> int:
+    """Exact number of (tile, point) pairs narvis_splat emits (synchronises)."""
+    pt = points_struct(points)
+    a = attrs_struct(attrs or [])
+    c = camera_struct(camera)
+    p = params.struct()
+    out = ctypes.c_uint64()
+    nbytes = workspace.numel() * workspace.element_size()
+    _lib.check(_lib.load().narvis_splat_count_pairs(ctypes.byref(pt), ctypes.byref(a), int(n), ctypes.byref(c), W, H,
+                                                    ctypes.byref(p), _ptr(workspace), nbytes, ctypes.byref(out),
+                                                    _stream_ptr(stream)), "narvis_splat_count_pairs")
+    return int(out.value)
 
 
 def narvis_splat_pair_count(workspace, n: int, W: int, H: int, params: SplatParams, stream=None) -> int:
@@ -399,6 +419,13 @@ def narvis_weights_calibrate_fp8(weights: NetWeights, feat, B: int, W: int, H: i
     nbytes = workspace.numel() * workspace.element_size()
     _lib.check(_lib.load().narvis_weights_calibrate_fp8(weights.handle, _ptr(feat), B, W, H, _ptr(workspace), nbytes,
                                                         _stream_ptr(stream)), "narvis_weights_calibrate_fp8")
+
+
+def narvis_weights_fp8_layers(weights: NetWeights) -> int:
+    """Bit mask of the layers the last FP8 calibration put in FP8 (blob order)."""
+    m = ctypes.c_uint32()
+    _lib.check(_lib.load().narvis_weights_fp8_layers(weights.handle, ctypes.byref(m)), "narvis_weights_fp8_layers")
+    return int(m.value)
 
 
 def narvis_train_tensor(B: int, W: int, H: int, name: str):

@@ -133,7 +133,7 @@ def test_training_follows_oracle_loss_curve():
 def test_fp8_forward_matches_oracle(B, H, W):
     """FP8 (e4m3, per-output-channel weight scales, static per-layer
     activation scales calibrated on another batch drawn from the same
-    distribution; the layers below full resolution in FP8, the rest in bf16)
+    distribution; the layers the calibration chose in FP8, the rest in bf16)
     within 6e-2 max-abs of the FP64 forward."""
     announce(f"FP8 network forward B={B} {H}x{W}")
     P = random_net(B * 77 + H)
@@ -147,12 +147,14 @@ def test_fp8_forward_matches_oracle(B, H, W):
         narvis.narvis_postprocess(w, feat, B, W, H, img, ws, precision=narvis.PRECISION_FP8)
     cal = torch.from_numpy(random_planes(np.random.default_rng(W + 1005), B, H, W)).cuda()
     narvis.narvis_weights_calibrate_fp8(w, cal, B, W, H, ws)
+    mask = narvis.narvis_weights_fp8_layers(w)
     narvis.narvis_postprocess(w, feat, B, W, H, img, ws, precision=narvis.PRECISION_FP8)
     torch.cuda.synchronize()
     got = img.cpu().numpy().astype(np.float64)
     want, _ = onet.forward(P, onet.features(planes))
     err = np.abs(got - want).max()
-    print(f"  FP8 max |gpu - fp64| = {err:.3g}", flush=True)
+    print(f"  FP8 layers {fp8_names(mask)}; max |gpu - fp64| = {err:.3g}", flush=True)
+    assert mask != 0
     assert np.isfinite(got).all()
     assert err <= 6e-2
     w.close()
@@ -183,12 +185,25 @@ def gpu_trained_forward(w, planes, precision):
     return img.cpu().numpy().astype(np.float64)
 
 
+LAYER_NAMES = [n for n, *_ in onet.LAYERS]
+
+
+def fp8_names(mask):
+    return [n for i, n in enumerate(LAYER_NAMES) if (mask >> i) & 1]
+
+
 def calibrate_on_training_views(c4):
+    """FP8 calibration on 16 training views (never the tested ones); returns
+    the chosen layer mask, which must put at least one layer in FP8."""
     cal = c4["cal"]
     B, _, H, W = cal.shape
     ws = torch.empty(narvis.narvis_train_workspace_size(B, W, H), dtype=torch.uint8, device="cuda")
     narvis.narvis_weights_calibrate_fp8(c4["weights"], cal, B, W, H, ws)
     torch.cuda.synchronize()
+    mask = narvis.narvis_weights_fp8_layers(c4["weights"])
+    print(f"  FP8 layers chosen on the training views: {fp8_names(mask)}", flush=True)
+    assert mask != 0
+    return mask
 
 
 @pytest.mark.timeout(900)

@@ -148,3 +148,64 @@ def test_permutation_invariance_distinct_depths():
     b = osplat.splat(sc.x[perm], sc.y[perm], sc.z[perm], M, near, far, sc.W, sc.H, [t[perm] for t in sc.attrs], **kw)
     np.testing.assert_allclose(a, b, atol=1e-12)
     assert a.max() > 0.3
+
+
+# ---------------------------------------------------------------------------
+# anisotropic splat (Gaussians elongated along the velocity)
+# ---------------------------------------------------------------------------
+
+IDENT90 = scenes.Camera(eye=(0.0, 0.0, 0.0), target=(0.0, 0.0, -1.0), up=(0.0, 1.0, 0.0), fovy_deg=90.0)
+
+
+def aniso_one(v, stretch, W=48, H=48, d=2.0, sigma=1.5):
+    from oracle import splat as osplat
+    M, near, far = ocam.clip_matrix(IDENT90, W, H)
+    x = np.array([0.0], np.float32)
+    y = np.array([0.0], np.float32)
+    z = np.array([-d], np.float32)
+    c = np.ones(1, np.float32)
+    attrs = [np.array([v[0]], np.float32), np.array([v[1]], np.float32), np.array([v[2]], np.float32), c]
+    lut = np.ones((256, 3), np.float32)
+    return osplat.splat_aniso(x, y, z, M, near, far, W, H, attrs, vel_attr=0, stretch=stretch,
+                              focal_px=ocam.focal_px(IDENT90, H), sigma=sigma, lut=lut, lut_attr=3)
+
+
+def test_aniso_closed_form_on_axis():
+    """On the optical axis of an identity view the screen covariance is
+    sigma^2 diag(s, 1) for v along x (exactly, in real arithmetic): every
+    pixel equals min(0.99, exp(-q/2)) with q = dx^2/(s sigma^2) + dy^2/sigma^2
+    where q <= 9, and 0 elsewhere."""
+    W = H = 48
+    s, sig = 16.0, 1.5
+    img = aniso_one((3.0, 0.0, 0.0), s, W, H, sigma=sig)[0].reshape(H, W)
+    py, px = np.mgrid[0:H, 0:W]
+    dx = px + 0.5 - W / 2
+    dy = py + 0.5 - H / 2
+    q = dx * dx / (s * sig * sig) + dy * dy / (sig * sig)
+    want = np.where(q <= 9.0, np.minimum(0.99, np.exp(-q / 2)), 0.0)
+    want = np.where(want >= 1 / 255, want, 0.0)
+    edge = np.abs(q - 9.0) < 1e-3
+    assert np.max(np.abs(img - want)[~edge]) < 1e-5
+    assert (img > 0).sum() > 3 * (np.pi * 9 * sig * sig)   # about sqrt(s) = 4 times the round footprint
+
+
+def test_aniso_reduces_to_round_without_stretch_or_velocity():
+    from oracle import splat as osplat
+    round_img = aniso_one((0.0, 0.0, 0.0), 300.0)          # no velocity: round
+    ident = aniso_one((2.0, 1.0, 0.0), 1.0)                 # s = 1: round
+    along_view = aniso_one((0.0, 0.0, 5.0), 300.0)          # v along the view axis: projects to nothing
+    M, near, far = ocam.clip_matrix(IDENT90, 48, 48)
+    iso = osplat.splat(np.zeros(1, np.float32), np.zeros(1, np.float32), np.array([-2.0], np.float32), M, near,
+                       far, 48, 48, [np.ones(1, np.float32)], sigma=1.5, lut=np.ones((256, 3), np.float32),
+                       lut_attr=0)
+    for img in (round_img, ident, along_view):
+        assert np.max(np.abs(img - iso)) < 1e-5
+
+
+def test_aniso_orientation_follows_projected_velocity():
+    # v along y (screen vertical): the footprint is tall; along x: wide
+    tall = (aniso_one((0.0, 2.0, 0.0), 25.0)[0].reshape(48, 48) > 0)
+    wide = (aniso_one((2.0, 0.0, 0.0), 25.0)[0].reshape(48, 48) > 0)
+    assert tall.any(axis=1).sum() > 2 * tall.any(axis=0).sum()
+    assert wide.any(axis=0).sum() > 2 * wide.any(axis=1).sum()
+    assert np.array_equal(tall, wide.T)

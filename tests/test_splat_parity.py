@@ -177,3 +177,71 @@ def test_splat_pair_count(sigma):
     want = int(((x1 // 16 - x0 // 16 + 1) * (y1 // 16 - y0 // 16 + 1)).sum())
     assert keep.sum() > 100
     assert got == want
+
+
+# ---------------------------------------------------------------------------
+# anisotropic splat: Gaussians elongated along the velocity (Sec. 4.2 GR)
+# ---------------------------------------------------------------------------
+
+def gpu_splat_aniso(X, Y, Z, A, n, cam, W, H, params):
+    """Counts the pairs first, sizes the workspace for exactly that many."""
+    small = narvis.SplatParams(**{**params.__dict__, "max_pairs": 1})
+    ws = torch.empty(max(256, narvis.narvis_splat_workspace_size(n, W, H, small)), dtype=torch.uint8, device="cuda")
+    pairs = narvis.narvis_splat_count_pairs((X, Y, Z), A, n, cam, W, H, small, ws)
+    del ws
+    full = narvis.SplatParams(**{**params.__dict__, "max_pairs": max(1, pairs)})
+    ws = torch.empty(narvis.narvis_splat_workspace_size(n, W, H, full), dtype=torch.uint8, device="cuda")
+    img = torch.full((3, W * H), float("nan"), dtype=torch.float32, device="cuda")
+    narvis.narvis_splat((X, Y, Z), A, n, cam, W, H, img, full, ws)
+    torch.cuda.synchronize()
+    emitted = narvis.narvis_splat_pair_count(ws, n, W, H, full)
+    assert emitted == pairs
+    return img.cpu().numpy().astype(np.float64), pairs
+
+
+@pytest.mark.parametrize("stretch", [1.0, 16.0, 300.0])
+def test_aniso_splat_unit_cube(stretch):
+    n, W, H = 100003, 160, 120
+    announce(f"anisotropic splat, unit cube n={n} with N(0,1) velocities, s={stretch}, {W}x{H}")
+    sc = scenes.unit_cube(n=n, seed=17, W=W, H=H)
+    cam = scenes.Camera(eye=(1.7, 1.5, 1.3), target=(0.5, 0.5, 0.5))
+    lut = scenes.colour_lut()
+    params = lut_params(sc, dev(lut))
+    params.aniso, params.vel_attr, params.stretch = 1, 0, stretch
+    X, Y, Z = dev(sc.x), dev(sc.y), dev(sc.z)
+    got, pairs = gpu_splat_aniso(X, Y, Z, [dev(a) for a in sc.attrs], n, cam, W, H, params)
+    M, near, far = ocam.clip_matrix(cam, W, H)
+    want, frag = osplat.splat_aniso(sc.x, sc.y, sc.z, M, near, far, W, H, sc.attrs, vel_attr=0, stretch=stretch,
+                                    focal_px=ocam.focal_px(cam, H), lut=lut, lut_attr=sc.lut_attr,
+                                    lut_min=sc.lut_min, lut_inv_range=params.lut_inv_range, with_fragile=True)
+    d = compare(got, want, frag)
+    print(f"  {pairs} pairs, max err {d.max():.3g}, fragile pixels {int(frag.sum())}", flush=True)
+
+
+def test_aniso_splat_vector_field_window():
+    """The 50M-point vector field at 1920x1080 with s = 300 (the paper's
+    stretch for its hurricane vector field): the GPU renders the whole frame;
+    the oracle composites a 96x96 window at the vortex core and one at the
+    image corner from all points."""
+    announce("anisotropic splat, vector field 50M points at 1920x1080, s=300, two 96x96 windows")
+    sc = scenes.vector_field(device="cuda")
+    lut = scenes.colour_lut()
+    params = lut_params(sc, dev(lut))
+    params.aniso, params.vel_attr, params.stretch = 1, sc.vel_attr, 300.0
+    W, H = sc.W, sc.H
+    cam = sc.cameras[0]
+    got, pairs = gpu_splat_aniso(sc.x, sc.y, sc.z, sc.attrs, sc.n, cam, W, H, params)
+    print(f"  {pairs} pairs", flush=True)
+    M, near, far = ocam.clip_matrix(cam, W, H)
+    xh, yh, zh = (t.cpu().numpy() for t in (sc.x, sc.y, sc.z))
+    ah = [a.cpu().numpy() for a in sc.attrs]
+    for (x0, y0) in ((912, 492), (0, 0)):
+        win = (x0, y0, x0 + 96, y0 + 96)
+        want, frag = osplat.splat_aniso(xh, yh, zh, M, near, far, W, H, ah, vel_attr=sc.vel_attr, stretch=300.0,
+                                        focal_px=ocam.focal_px(cam, H), lut=lut, lut_attr=sc.lut_attr,
+                                        lut_min=sc.lut_min, lut_inv_range=params.lut_inv_range, window=win,
+                                        with_fragile=True)
+        idx = (np.arange(y0, y0 + 96)[:, None] * W + np.arange(x0, x0 + 96)[None, :]).reshape(-1)
+        d = compare(got[:, idx], want[:, idx], frag[idx])
+        print(f"  window {win}: max err {d.max():.3g}, covered {(want[:, idx].sum(axis=0) > 0).mean():.2f}",
+              flush=True)
