@@ -273,6 +273,47 @@ def frame_section(torch, log_fn, frames=12, train_views=2000, train_steps=2500):
             "splat_aniso": "Gaussians elongated along the velocity, s = 300, first frame"}
 
 
+def splat_section(torch, log_fn, frames):
+    """Isotropic (sigma 1.5 px) and anisotropic (s = 300) splats of `frames`
+    vector-field orbit frames at 1920x1080, each timed with HIP events."""
+    from paper_2407_19097_amd import narvis, scenes
+    sc = scenes.vector_field(device="cuda")
+    W, H = 1920, 1080
+    lut = torch.from_numpy(scenes.colour_lut()).cuda()
+    inv = float(np.float32(1.0 / (sc.lut_max - sc.lut_min)))
+    img = torch.empty((3, W * H), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    cams = [sc.cameras[int(k * len(sc.cameras) / max(1, frames))] for k in range(max(1, frames))]
+    out = {}
+    for name, aniso in (("isotropic", 0), ("anisotropic_s300", 1)):
+        p = narvis.SplatParams(sigma_px=1.5, opacity=1.0, color_mode=narvis.COLOR_LUT, color_attr=sc.lut_attr, lut=lut,
+                               lut_min=sc.lut_min, lut_inv_range=inv, aniso=aniso, vel_attr=sc.vel_attr,
+                               stretch=300.0, max_pairs=1 if aniso else 0)
+        if aniso:
+            ws = torch.empty(narvis.narvis_splat_workspace_size(sc.n, W, H, p), dtype=torch.uint8, device="cuda")
+            p.max_pairs = max(narvis.narvis_splat_count_pairs((sc.x, sc.y, sc.z), sc.attrs, sc.n, c, W, H, p, ws)
+                              for c in cams)
+            del ws
+        ws = torch.empty(narvis.narvis_splat_workspace_size(sc.n, W, H, p), dtype=torch.uint8, device="cuda")
+        run = lambda c: narvis.narvis_splat((sc.x, sc.y, sc.z), sc.attrs, sc.n, c, W, H, img, p, ws, stream=stream)
+        run(cams[0])
+        ev = []
+        for c in cams:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            run(c)
+            e1.record(stream)
+            ev.append((e0, e1))
+        torch.cuda.synchronize()
+        ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+        pairs = narvis.narvis_splat_pair_count(ws, sc.n, W, H, p)
+        log_fn(f"{name}: {ms:.3f} ms per frame, {pairs} pairs in the last frame")
+        out[name] = {"ms": round(ms, 3), "pairs_last_frame": pairs}
+        del ws
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -285,6 +326,9 @@ def main():
     ap.add_argument("--frame-only", action="store_true",
                     help="run only the 1080p frame section (for profiling the network kernels)")
     ap.add_argument("--train-steps", type=int, default=2500, help="Adam steps of the frame section's training")
+    ap.add_argument("--splat-only", action="store_true",
+                    help="only time the Gaussian splat (isotropic and anisotropic) of vector-field frames at 1920x1080 "
+                         "(for profiling the splat kernels)")
     ap.add_argument("--no-layout", action="store_true",
                     help="skip the frames over the Morton layout (whole-batch culling)")
     ap.add_argument("--no-hinted", action="store_true",
@@ -300,6 +344,9 @@ def main():
 
     if args.frame_only:
         print(json.dumps({"frame_1080p": frame_section(torch, log, train_steps=args.train_steps)}), flush=True)
+        return
+    if args.splat_only:
+        print(json.dumps({"splat_1080p": splat_section(torch, log, args.steps)}), flush=True)
         return
 
     dev = "cuda"
