@@ -607,6 +607,55 @@ narvis_status narvis_train_gradients(narvis_weights *w, const float *feat, const
 narvis_status narvis_train_tensor(int32_t B, int32_t W, int32_t H, const char *name, size_t *offset,
                                   int32_t *channels, int32_t *height, int32_t *width, int32_t *dtype);
 
+/* ------------------------------------------------------------------------
+ * The paper's own post-processor (Sec. 3.3, Fig. 4, Eq. 1): a U-Net with
+ * gated convolutions.  Readings where the paper is silent:
+ *   descriptors  d_0 = conv1x1(x_0) (8 -> 8 channels, bias), downscaled by
+ *                2x2 average pooling to five scales d_0..d_4;
+ *   encoder      level l = 0..4 (widths w_l, the paper's 64-128-256-512-1024
+ *                by default): z = conv3x3([x_l | d_l]) (zero padding 1,
+ *                bias) with 2 w_l outputs, y_l = ELU(z[:w_l]) *
+ *                sigmoid(z[w_l:]), x_{l+1} = avgpool2(y_l); x_0 = the
+ *                network input of narvis_postprocess (depth as 1/depth);
+ *   decoder      level l = 3..0: u = transposed 2x2 stride-2 convolution
+ *                (w_{l+1} -> w_l, bias) of the level above (y_4, then the
+ *                decoder outputs): u[2i+a][2j+b][c] = sum_k in[i][j][k] *
+ *                T[a][b][c][k] + bias[c]; z = conv3x3([u | y_l]) with 2 w_l
+ *                outputs, y'_l = gate(z);
+ *   head         conv1x1(w_0 -> 3), linear.
+ * Parameter blob (fp32), per layer: desc (W [8][8], b [8]), enc0..enc4
+ * (W [2 w_l][c_in][3][3], b [2 w_l], c_in = 16 for level 0, w_{l-1} + 8
+ * otherwise), then for l = 3, 2, 1, 0: up_l (T [2][2][w_l][w_{l+1}],
+ * b [w_l]) and dec_l (W [2 w_l][2 w_l][3][3], b [2 w_l]), then head
+ * (W [3][w_0], b [3]).  Every w_l a multiple of 32 in [32, 4096]; H and W
+ * multiples of 16.  Activations bf16 NHWC, fp32 accumulation.  Training:
+ * the loss and Adam of narvis_train_step.
+ * ------------------------------------------------------------------------ */
+typedef struct narvis_unet narvis_unet;
+
+/* Floats in the parameter blob for these widths (0 if invalid). */
+size_t narvis_unet_param_count(const int32_t widths[5]);
+/* Create (allocates device memory, synchronises).  INVALID_ARG on bad
+ * widths, a wrong count or non-finite values; OUT_OF_MEMORY. */
+narvis_status narvis_unet_create(const int32_t widths[5], const float *host_blob, size_t count, narvis_unet **out);
+void narvis_unet_destroy(narvis_unet *u);
+narvis_status narvis_unet_read(const narvis_unet *u, float *host_blob, size_t count);
+/* Workspace bytes for B images of W x H; train != 0 for the training calls. */
+size_t narvis_unet_workspace_size(const narvis_unet *u, int32_t B, int32_t W, int32_t H, int32_t train);
+/* feat [B][8][H][W] fp32 (the network input of narvis_postprocess) ->
+ * img [B][3][H][W] fp32. */
+narvis_status narvis_unet_forward(const narvis_unet *u, const float *feat, int32_t B, int32_t W, int32_t H,
+                                  float *img, void *ws, size_t ws_bytes, void *stream);
+/* One training step (forward, loss, backward, Adam), as narvis_train_step. */
+narvis_status narvis_unet_train_step(narvis_unet *u, const float *feat, const float *target, int32_t B, int32_t W,
+                                     int32_t H, float lr, float lam_tv, float *loss_out, void *ws, size_t ws_bytes,
+                                     void *stream);
+/* Forward, loss and backward without the update: every parameter's gradient
+ * to grad_out (device fp32, blob order), the loss to *loss_out. */
+narvis_status narvis_unet_gradients(narvis_unet *u, const float *feat, const float *target, int32_t B, int32_t W,
+                                    int32_t H, float lam_tv, float *grad_out, float *loss_out, void *ws,
+                                    size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -126,6 +126,19 @@ SIGNATURES = {
     "narvis_weights_calibrate_fp8": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P,
                                                     ctypes.c_size_t, _P]),
     "narvis_weights_fp8_layers": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint32)]),
+    "narvis_unet_param_count": (ctypes.c_size_t, [ctypes.POINTER(ctypes.c_int32)]),
+    "narvis_unet_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int32), _P, ctypes.c_size_t,
+                                          ctypes.POINTER(ctypes.c_void_p)]),
+    "narvis_unet_destroy": (None, [_P]),
+    "narvis_unet_read": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
+    "narvis_unet_workspace_size": (ctypes.c_size_t, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                     ctypes.c_int32]),
+    "narvis_unet_forward": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P,
+                                           ctypes.c_size_t, _P]),
+    "narvis_unet_train_step": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                              ctypes.c_float, ctypes.c_float, _P, _P, ctypes.c_size_t, _P]),
+    "narvis_unet_gradients": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.c_float, _P, _P, _P, ctypes.c_size_t, _P]),
     "narvis_train_workspace_size": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "narvis_train_step": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_float, ctypes.c_float, _P, _P, ctypes.c_size_t, _P]),

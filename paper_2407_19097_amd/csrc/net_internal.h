@@ -91,6 +91,15 @@ hipError_t adam(float *p, const float *g, float *m, float *v, int64_t n, float l
 hipError_t grad_to_blob(const float *dw, int Kpad, int Cout, int Cin, int KS, float *blob, hipStream_t s);
 hipError_t copy_f32(const float *src, float *dst, int64_t n, hipStream_t s);
 hipError_t zero_bf16(__bf16 *p, int64_t n, hipStream_t s);
+// the paper's gated U-Net
+hipError_t gate(const __bf16 *z, __bf16 *y, int y_stride, int y_off, int C, int64_t P, hipStream_t s);
+hipError_t gate_bwd(const __bf16 *z, const __bf16 *dy, int dy_stride, int dy_off, __bf16 *dz, int C, int64_t P,
+                    hipStream_t s);
+hipError_t pool2(const SliceArgs &a, hipStream_t s);
+hipError_t shuffle_up(const SliceArgs &a, hipStream_t s);
+hipError_t shuffle_down(const SliceArgs &a, hipStream_t s);
+hipError_t bias_phases(const float *b, int C, float *rows, hipStream_t s);
+hipError_t bias_grad_phases(const float *rows, int C, float *b, hipStream_t s);
 
 }  // namespace net
 }  // namespace narvis

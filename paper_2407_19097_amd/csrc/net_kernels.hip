@@ -1500,6 +1500,160 @@ hipError_t absdiff_max_f32(const float *a, const float *b, int64_t n, unsigned i
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// kernels of the paper's gated U-Net
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ float elu1(float x) { return x > 0.0f ? x : expm1f(x); }
+__device__ __forceinline__ float sigm(float x) { return 1.0f / (1.0f + expf(-x)); }
+
+// y = ELU(z[:, :C]) * sigmoid(z[:, C:]), z dense [P][2C], y a slice
+__global__ __launch_bounds__(256) void k_gate(const __bf16 *z, __bf16 *y, int y_stride, int y_off, int C, int64_t P)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= P * C) return;
+    const int64_t p = t / C;
+    const int c = (int)(t - p * C);
+    const float f = (float)z[p * 2 * C + c], g = (float)z[p * 2 * C + C + c];
+    y[p * y_stride + y_off + c] = (__bf16)(elu1(f) * sigm(g));
+}
+
+// dz = [dy sigmoid(g) ELU'(f), dy ELU(f) sigmoid(g) (1 - sigmoid(g))]
+__global__ __launch_bounds__(256) void k_gate_bwd(const __bf16 *z, const __bf16 *dy, int dy_stride, int dy_off,
+                                                  __bf16 *dz, int C, int64_t P)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= P * C) return;
+    const int64_t p = t / C;
+    const int c = (int)(t - p * C);
+    const float f = (float)z[p * 2 * C + c], g = (float)z[p * 2 * C + C + c];
+    const float d = (float)dy[p * dy_stride + dy_off + c];
+    const float sg = sigm(g);
+    const float de = f > 0.0f ? 1.0f : expf(f);
+    dz[p * 2 * C + c] = (__bf16)(d * sg * de);
+    dz[p * 2 * C + C + c] = (__bf16)(d * elu1(f) * sg * (1.0f - sg));
+}
+
+// 2x2 average pooling of a slice [B][H][W][C] -> [B][H/2][W/2][C] (C multiple of 8)
+__global__ __launch_bounds__(256) void k_pool2(SliceArgs s)
+{
+    const int groups = s.C / 8;
+    const int H2 = s.H / 2, W2 = s.W / 2;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (int64_t)s.B * H2 * W2 * groups) return;
+    const int c8 = (int)(t % groups);
+    const int64_t q = t / groups;
+    const int64_t b = q / ((int64_t)H2 * W2);
+    const int64_t rem = q - b * H2 * W2;
+    const int y = (int)(rem / W2), x = (int)(rem % W2);
+    const int64_t p00 = (b * s.H + 2 * y) * s.W + 2 * x;
+    const bf16x8 a0 = load8(s.in + p00 * s.in_stride + s.in_off + c8 * 8);
+    const bf16x8 a1 = load8(s.in + (p00 + 1) * s.in_stride + s.in_off + c8 * 8);
+    const bf16x8 a2 = load8(s.in + (p00 + s.W) * s.in_stride + s.in_off + c8 * 8);
+    const bf16x8 a3 = load8(s.in + (p00 + s.W + 1) * s.in_stride + s.in_off + c8 * 8);
+    bf16x8 o;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) o[j] = (__bf16)(0.25f * (((float)a0[j] + (float)a1[j]) + ((float)a2[j] + (float)a3[j])));
+    *reinterpret_cast<bf16x8 *>(s.out + q * s.out_stride + s.out_off + c8 * 8) = o;
+}
+
+// transposed 2x2 stride-2 convolution as a 1x1 convolution with 4C outputs
+// (row (2a + b) C + c) followed by this depth-to-space step:
+// out[2i + a][2j + b][c] = in[i][j][(2a + b) C + c]; s.H, s.W: the low grid
+__global__ __launch_bounds__(256) void k_shuffle_up(SliceArgs s)
+{
+    const int groups = s.C / 8;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (int64_t)s.B * s.H * s.W * 4 * groups) return;
+    const int c8 = (int)(t % groups);
+    const int64_t r = t / groups;
+    const int ph = (int)(r % 4);
+    const int64_t q = r / 4;
+    const int64_t b = q / ((int64_t)s.H * s.W);
+    const int64_t rem = q - b * s.H * s.W;
+    const int i = (int)(rem / s.W), j = (int)(rem % s.W);
+    const int a = ph >> 1, bb = ph & 1;
+    const int64_t o = (b * 2 * s.H + 2 * i + a) * (2 * s.W) + 2 * j + bb;
+    *reinterpret_cast<bf16x8 *>(s.out + o * s.out_stride + s.out_off + c8 * 8) =
+        load8(s.in + q * s.in_stride + s.in_off + ph * s.C + c8 * 8);
+}
+
+// adjoint of k_shuffle_up: in a slice of the high grid, out [B][H][W][4C]
+__global__ __launch_bounds__(256) void k_shuffle_down(SliceArgs s)
+{
+    const int groups = s.C / 8;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (int64_t)s.B * s.H * s.W * 4 * groups) return;
+    const int c8 = (int)(t % groups);
+    const int64_t r = t / groups;
+    const int ph = (int)(r % 4);
+    const int64_t q = r / 4;
+    const int64_t b = q / ((int64_t)s.H * s.W);
+    const int64_t rem = q - b * s.H * s.W;
+    const int i = (int)(rem / s.W), j = (int)(rem % s.W);
+    const int a = ph >> 1, bb = ph & 1;
+    const int64_t o = (b * 2 * s.H + 2 * i + a) * (2 * s.W) + 2 * j + bb;
+    *reinterpret_cast<bf16x8 *>(s.out + q * s.out_stride + s.out_off + ph * s.C + c8 * 8) =
+        load8(s.in + o * s.in_stride + s.in_off + c8 * 8);
+}
+
+// bias of the 4C rows of a transposed convolution from its C biases, and the
+// C bias gradients from the 4C row gradients
+__global__ __launch_bounds__(256) void k_bias_phases(const float *b, int C, float *rows)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < 4 * C) rows[i] = b[i % C];
+}
+
+__global__ __launch_bounds__(256) void k_bias_grad_phases(const float *rows, int C, float *b)
+{
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c < C) b[c] = ((rows[c] + rows[C + c]) + rows[2 * C + c]) + rows[3 * C + c];
+}
+
+hipError_t gate(const __bf16 *z, __bf16 *y, int y_stride, int y_off, int C, int64_t P, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gate, dim3(nblocks(P * C)), dim3(256), 0, s, z, y, y_stride, y_off, C, P);
+    return hipGetLastError();
+}
+
+hipError_t gate_bwd(const __bf16 *z, const __bf16 *dy, int dy_stride, int dy_off, __bf16 *dz, int C, int64_t P,
+                    hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gate_bwd, dim3(nblocks(P * C)), dim3(256), 0, s, z, dy, dy_stride, dy_off, dz, C, P);
+    return hipGetLastError();
+}
+
+hipError_t pool2(const SliceArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pool2, dim3(nblocks((int64_t)a.B * (a.H / 2) * (a.W / 2) * (a.C / 8))), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t shuffle_up(const SliceArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_shuffle_up, dim3(nblocks((int64_t)a.B * a.H * a.W * 4 * (a.C / 8))), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t shuffle_down(const SliceArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_shuffle_down, dim3(nblocks((int64_t)a.B * a.H * a.W * 4 * (a.C / 8))), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t bias_phases(const float *b, int C, float *rows, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_bias_phases, dim3((unsigned)((4 * C + 255) / 256)), dim3(256), 0, s, b, C, rows);
+    return hipGetLastError();
+}
+
+hipError_t bias_grad_phases(const float *rows, int C, float *b, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_bias_grad_phases, dim3((unsigned)((C + 255) / 256)), dim3(256), 0, s, rows, C, b);
+    return hipGetLastError();
+}
+
 hipError_t absmax_bf16(const __bf16 *x, int64_t n, unsigned int *out, hipStream_t s)
 {
     const int64_t blocks = std::min<int64_t>(4096, (n + 255) / 256);

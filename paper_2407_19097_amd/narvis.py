@@ -436,3 +436,73 @@ def narvis_train_tensor(B: int, W: int, H: int, name: str):
                                                ctypes.byref(h), ctypes.byref(w), ctypes.byref(dt)),
                "narvis_train_tensor")
     return int(off.value), int(c.value), int(h.value), int(w.value), int(dt.value)
+
+
+# ---------------------------------------------------------------------------
+# the paper's gated U-Net
+# ---------------------------------------------------------------------------
+
+UNET_WIDTHS = (64, 128, 256, 512, 1024)
+
+
+def _widths(widths):
+    return (ctypes.c_int32 * 5)(*[int(v) for v in widths])
+
+
+def narvis_unet_param_count(widths=UNET_WIDTHS) -> int:
+    return int(_lib.load().narvis_unet_param_count(_widths(widths)))
+
+
+class UNet:
+    """Library-owned parameters of the gated U-Net (create / destroy pair)."""
+
+    def __init__(self, blob, widths=UNET_WIDTHS):
+        blob = np.ascontiguousarray(blob, dtype=np.float32)
+        self.widths = tuple(int(v) for v in widths)
+        h = ctypes.c_void_p()
+        _lib.check(_lib.load().narvis_unet_create(_widths(self.widths), blob.ctypes.data, blob.size, ctypes.byref(h)),
+                   "narvis_unet_create")
+        self.handle = h
+        self.count = blob.size
+
+    def read(self) -> np.ndarray:
+        out = np.empty(self.count, np.float32)
+        _lib.check(_lib.load().narvis_unet_read(self.handle, out.ctypes.data, out.size), "narvis_unet_read")
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.load().narvis_unet_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def narvis_unet_workspace_size(u: UNet, B: int, W: int, H: int, train: bool = False) -> int:
+    return int(_lib.load().narvis_unet_workspace_size(u.handle, B, W, H, int(bool(train))))
+
+
+def narvis_unet_forward(u: UNet, feat, B: int, W: int, H: int, img, workspace, stream=None) -> None:
+    nbytes = workspace.numel() * workspace.element_size()
+    _lib.check(_lib.load().narvis_unet_forward(u.handle, _ptr(feat), B, W, H, _ptr(img), _ptr(workspace), nbytes,
+                                               _stream_ptr(stream)), "narvis_unet_forward")
+
+
+def narvis_unet_train_step(u: UNet, feat, target, B: int, W: int, H: int, lr: float, lam_tv: float, loss_out,
+                           workspace, stream=None) -> None:
+    nbytes = workspace.numel() * workspace.element_size()
+    _lib.check(_lib.load().narvis_unet_train_step(u.handle, _ptr(feat), _ptr(target), B, W, H, float(lr),
+                                                  float(lam_tv), _ptr(loss_out), _ptr(workspace), nbytes,
+                                                  _stream_ptr(stream)), "narvis_unet_train_step")
+
+
+def narvis_unet_gradients(u: UNet, feat, target, B: int, W: int, H: int, lam_tv: float, grad_out, loss_out,
+                          workspace, stream=None) -> None:
+    nbytes = workspace.numel() * workspace.element_size()
+    _lib.check(_lib.load().narvis_unet_gradients(u.handle, _ptr(feat), _ptr(target), B, W, H, float(lam_tv),
+                                                 _ptr(grad_out), _ptr(loss_out), _ptr(workspace), nbytes,
+                                                 _stream_ptr(stream)), "narvis_unet_gradients")
