@@ -314,6 +314,68 @@ def splat_section(torch, log_fn, frames):
     return out
 
 
+def unet_flop_per_px(widths):
+    """Multiply-adds x 2 per pixel of the full-resolution grid, summed over the
+    gated U-Net's convolutions (a level-l layer runs on 4^-l of the pixels)."""
+    w = [int(v) for v in widths]
+    f = 2.0 * 8 * 8                                                   # descriptors
+    for l in range(5):
+        f += 2.0 * 2 * w[l] * ((w[l - 1] if l else 8) + 8) * 9 / 4 ** l  # encoder
+    for l in range(4):
+        f += 2.0 * 4 * w[l] * w[l + 1] / 4 ** (l + 1)                   # transposed conv
+        f += 2.0 * 2 * w[l] * 2 * w[l] * 9 / 4 ** l                     # decoder
+    return f + 2.0 * 3 * w[0]                                         # head
+
+
+def unet_section(torch, log_fn, frames=10):
+    """The paper's gated U-Net (widths 64..1024, He-initialised): forward on
+    one 1920x1080 frame (run on 1920x1088) and one training step of batch 16
+    at 512x512, timed with HIP events."""
+    from paper_2407_19097_amd import narvis, train
+    widths = narvis.UNET_WIDTHS
+    u = narvis.UNet(train.unet_init_blob(0, widths), widths)
+    W, H = 1920, 1080
+    stream = torch.cuda.current_stream()
+    feat = torch.rand((1, 8, H, W), dtype=torch.float32, device="cuda")
+    img = torch.empty((1, 3, H, W), dtype=torch.float32, device="cuda")
+    ws = torch.empty(narvis.narvis_unet_workspace_size(u, 1, W, H), dtype=torch.uint8, device="cuda")
+    fwd = lambda: narvis.narvis_unet_forward(u, feat, 1, W, H, img, ws, stream=stream)
+    fwd()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(frames):
+        fwd()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    fwd_ms = e0.elapsed_time(e1) / frames
+    del ws, feat, img
+    fpp = unet_flop_per_px(widths)
+    gflop = fpp * W * 1088 / 1e9
+    log_fn(f"gated U-Net forward 1920x1080: {fwd_ms:.3f} ms, {gflop:.0f} GFLOP, {gflop / fwd_ms:.1f} TFLOP/s")
+    B, R = 16, 512
+    tws = torch.empty(narvis.narvis_unet_workspace_size(u, B, R, R, train=True), dtype=torch.uint8, device="cuda")
+    fb = torch.rand((B, 8, R, R), dtype=torch.float32, device="cuda")
+    tb = torch.rand((B, 3, R, R), dtype=torch.float32, device="cuda")
+    tl = torch.empty(1, dtype=torch.float32, device="cuda")
+    step = lambda: narvis.narvis_unet_train_step(u, fb, tb, B, R, R, 1e-4, 1e-3, tl, tws, stream=stream)
+    step()
+    e0.record(stream)
+    for _ in range(5):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    step_ms = e0.elapsed_time(e1) / 5
+    tflop = 3 * fpp * B * R * R / 1e12
+    log_fn(f"gated U-Net training step b{B} {R}x{R}: {step_ms:.2f} ms, {tflop / (step_ms / 1e3):.1f} TFLOP/s")
+    u.close()
+    del tws, fb, tb
+    torch.cuda.empty_cache()
+    return {"widths": list(widths), "forward_1080p_ms": round(fwd_ms, 3), "gflop_per_frame": round(gflop, 1),
+            "forward_tflops": round(gflop / fwd_ms, 1), "mflop_per_px": round(fpp / 1e6, 4),
+            "train_step_ms_b16_512": round(step_ms, 2),
+            "train_tflops": round(tflop / (step_ms / 1e3), 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -329,6 +391,8 @@ def main():
     ap.add_argument("--splat-only", action="store_true",
                     help="only time the Gaussian splat (isotropic and anisotropic) of vector-field frames at 1920x1080 "
                          "(for profiling the splat kernels)")
+    ap.add_argument("--unet-only", action="store_true",
+                    help="only time the paper's gated U-Net (forward at 1920x1080, a training step)")
     ap.add_argument("--no-layout", action="store_true",
                     help="skip the frames over the Morton layout (whole-batch culling)")
     ap.add_argument("--no-hinted", action="store_true",
@@ -344,6 +408,9 @@ def main():
 
     if args.frame_only:
         print(json.dumps({"frame_1080p": frame_section(torch, log, train_steps=args.train_steps)}), flush=True)
+        return
+    if args.unet_only:
+        print(json.dumps({"unet": unet_section(torch, log)}), flush=True)
         return
     if args.splat_only:
         print(json.dumps({"splat_1080p": splat_section(torch, log, args.steps)}), flush=True)

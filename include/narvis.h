@@ -627,9 +627,12 @@ narvis_status narvis_train_tensor(int32_t B, int32_t W, int32_t H, const char *n
  * (W [2 w_l][c_in][3][3], b [2 w_l], c_in = 16 for level 0, w_{l-1} + 8
  * otherwise), then for l = 3, 2, 1, 0: up_l (T [2][2][w_l][w_{l+1}],
  * b [w_l]) and dec_l (W [2 w_l][2 w_l][3][3], b [2 w_l]), then head
- * (W [3][w_0], b [3]).  Every w_l a multiple of 32 in [32, 4096]; H and W
- * multiples of 16.  Activations bf16 NHWC, fp32 accumulation.  Training:
- * the loss and Adam of narvis_train_step.
+ * (W [3][w_0], b [3]).  Every w_l a multiple of 32 in [32, 4096].
+ * Inference takes any H x W: the network runs on the grid padded to the next
+ * multiples of 16 (the padded pixels are empty pixels, every input channel
+ * 0) and the top-left H x W of its output is returned.  Training frames are
+ * whole multiples of 16.  Activations bf16 NHWC, fp32 accumulation.
+ * Training: the loss and Adam of narvis_train_step.
  * ------------------------------------------------------------------------ */
 typedef struct narvis_unet narvis_unet;
 

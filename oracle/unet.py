@@ -20,7 +20,8 @@ paper is silent (each also in the design notes):
   decoder level l (l = 3..0): u_l = convT2x2 stride 2 (w_{l+1} -> w_l, bias)
       of the level above (y_4, then the decoder outputs), y'_l = gate(conv(
       concat[u_l, y_l]));
-  head: conv1x1(w_0 -> 3), linear.
+  head: conv1x1(w_0 -> 3), linear;
+  inference on frames that are not multiples of 16: zero-pad, run, crop.
   convT2x2: out[2i+a, 2j+b, co] = sum_ci in[i, j, ci] * T[a][b][co][ci] + bias[co].
 
 Parameter blob (float64 here, fp32 for the library), per layer in this order:
@@ -179,6 +180,18 @@ def forward(P, x):
     cache["last"] = up_in
     out = conv1(up_in, P["head"][0], P["head"][1])
     return out, cache
+
+
+def infer(P, x):
+    """Inference on any H x W (a reading: the paper's frames need not be
+    multiples of 16): the input zero-padded at the bottom and right to the
+    next multiples of 16 (a padded pixel is an empty pixel, every channel 0),
+    the top-left H x W of the output."""
+    N, C, H, W = x.shape
+    Hp, Wp = -(-H // 16) * 16, -(-W // 16) * 16
+    xp = np.zeros((N, C, Hp, Wp))
+    xp[:, :, :H, :W] = x
+    return forward(P, xp)[0][:, :, :H, :W]
 
 
 def backward(P, cache, dy):

@@ -98,6 +98,8 @@ hipError_t gate_bwd(const __bf16 *z, const __bf16 *dy, int dy_stride, int dy_off
 hipError_t pool2(const SliceArgs &a, hipStream_t s);
 hipError_t shuffle_up(const SliceArgs &a, hipStream_t s);
 hipError_t shuffle_down(const SliceArgs &a, hipStream_t s);
+hipError_t features_pad(const float *in, __bf16 *out, int B, int H, int W, int Hp, int Wp, hipStream_t s);
+hipError_t crop_planes(const float *src, float *dst, int BC, int H, int W, int Hp, int Wp, hipStream_t s);
 hipError_t bias_phases(const float *b, int C, float *rows, hipStream_t s);
 hipError_t bias_grad_phases(const float *rows, int C, float *b, hipStream_t s);
 

@@ -1599,6 +1599,40 @@ __global__ __launch_bounds__(256) void k_shuffle_down(SliceArgs s)
 
 // bias of the 4C rows of a transposed convolution from its C biases, and the
 // C bias gradients from the 4C row gradients
+// network input of an H x W frame on the zero-padded Hp x Wp grid (padded
+// pixels are empty pixels: every channel 0); out [B][Hp][Wp][8]
+__global__ __launch_bounds__(256) void k_features_pad(const float *in, __bf16 *out, int B, int H, int W, int Hp, int Wp)
+{
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= (int64_t)B * Hp * Wp) return;
+    const int64_t b = p / ((int64_t)Hp * Wp);
+    const int64_t rem = p - b * Hp * Wp;
+    const int y = (int)(rem / Wp), x = (int)(rem % Wp);
+    bf16x8 v = zero8();
+    if (y < H && x < W) {
+        const int64_t hw = (int64_t)H * W;
+        const float *src = in + b * 8 * hw + (int64_t)y * W + x;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            float f = src[c * hw];
+            if (c == 3) f = f > 0.0f ? 1.0f / f : 0.0f;
+            v[c] = (__bf16)f;
+        }
+    }
+    *reinterpret_cast<bf16x8 *>(out + p * 8) = v;
+}
+
+// planar [B][C][Hp][Wp] fp32 -> its top-left [B][C][H][W]
+__global__ __launch_bounds__(256) void k_crop_planes(const float *src, float *dst, int BC, int H, int W, int Hp, int Wp)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (int64_t)BC * H * W) return;
+    const int64_t bc = t / ((int64_t)H * W);
+    const int64_t rem = t - bc * H * W;
+    const int y = (int)(rem / W), x = (int)(rem % W);
+    dst[t] = src[(bc * Hp + y) * Wp + x];
+}
+
 __global__ __launch_bounds__(256) void k_bias_phases(const float *b, int C, float *rows)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
@@ -1639,6 +1673,18 @@ hipError_t shuffle_up(const SliceArgs &a, hipStream_t s)
 hipError_t shuffle_down(const SliceArgs &a, hipStream_t s)
 {
     hipLaunchKernelGGL(k_shuffle_down, dim3(nblocks((int64_t)a.B * a.H * a.W * 4 * (a.C / 8))), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t features_pad(const float *in, __bf16 *out, int B, int H, int W, int Hp, int Wp, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_features_pad, dim3(nblocks((int64_t)B * Hp * Wp)), dim3(256), 0, s, in, out, B, H, W, Hp, Wp);
+    return hipGetLastError();
+}
+
+hipError_t crop_planes(const float *src, float *dst, int BC, int H, int W, int Hp, int Wp, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_crop_planes, dim3(nblocks((int64_t)BC * H * W)), dim3(256), 0, s, src, dst, BC, H, W, Hp, Wp);
     return hipGetLastError();
 }
 

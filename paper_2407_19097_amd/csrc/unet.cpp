@@ -110,9 +110,10 @@ struct narvis_unet {
 
 namespace {
 
-// Workspace plan for B images of H x W (multiples of 16).
+// Workspace plan for B images of H x W, run on the grid padded to multiples
+// of 16 (Hp x Wp).
 struct UPlan {
-    int B, H, W;
+    int B, H, W, Hp, Wp;
     int64_t P[kLevels];
     uint64_t feat, d[kLevels], x[kLevels], ez[kLevels], ey[kLevels], tz[4], u[4], dz[4], dy[4];
     uint64_t out;
@@ -148,7 +149,9 @@ UPlan make_uplan(const narvis_unet *u, int B, int H, int W, bool train)
     p.B = B;
     p.H = H;
     p.W = W;
-    for (int l = 0; l < kLevels; ++l) p.P[l] = (int64_t)B * (H >> l) * (W >> l);
+    p.Hp = round_up(H, 16);
+    p.Wp = round_up(W, 16);
+    for (int l = 0; l < kLevels; ++l) p.P[l] = (int64_t)B * (p.Hp >> l) * (p.Wp >> l);
     const int32_t *w = u->w;
     uint64_t o = 0;
     auto bf = [&](int64_t px, int ch) {
@@ -264,11 +267,11 @@ hipError_t uforward(const narvis_unet *u, const float *feat_planes, char *ws, co
     const int B = p.B;
     const int32_t *w = u->w;
     const ULayer *L = u->L;
-    auto Hl = [&](int l) { return p.H >> l; };
-    auto Wl = [&](int l) { return p.W >> l; };
-    TRY(features(feat_planes, c.b(p.feat), B, p.H, p.W, s));
+    auto Hl = [&](int l) { return p.Hp >> l; };
+    auto Wl = [&](int l) { return p.Wp >> l; };
+    TRY(features_pad(feat_planes, c.b(p.feat), B, p.H, p.W, p.Hp, p.Wp, s));
     // descriptors at five scales
-    TRY(conv(uconv(L[U_DESC], c.b(p.feat), 8, 0, nullptr, 0, c.b(p.d[0]), B, p.H, p.W), 1, s));
+    TRY(conv(uconv(L[U_DESC], c.b(p.feat), 8, 0, nullptr, 0, c.b(p.d[0]), B, p.Hp, p.Wp), 1, s));
     for (int l = 1; l < kLevels; ++l)
         TRY(pool2(uslice(c.b(p.d[l - 1]), 8, 0, c.b(p.d[l]), 8, 0, 8, B, Hl(l - 1), Wl(l - 1)), s));
     // encoder
@@ -289,9 +292,12 @@ hipError_t uforward(const narvis_unet *u, const float *feat_planes, char *ws, co
         TRY(gate(c.b(p.dz[l]), c.b(p.dy[l]), w[l], 0, w[l], p.P[l], s));
         up_in = c.b(p.dy[l]);
     }
-    ConvArgs h = uconv(L[U_HEAD], c.b(p.dy[0]), w[0], 0, nullptr, 0, nullptr, B, p.H, p.W);
-    h.out_f32 = img;
-    return conv(h, 1, s);
+    ConvArgs h = uconv(L[U_HEAD], c.b(p.dy[0]), w[0], 0, nullptr, 0, nullptr, B, p.Hp, p.Wp);
+    const bool padded = p.Hp != p.H || p.Wp != p.W;
+    h.out_f32 = padded ? reinterpret_cast<float *>(ws + p.out) : img;
+    TRY(conv(h, 1, s));
+    if (padded) TRY(crop_planes(h.out_f32, img, B * 3, p.H, p.W, p.Hp, p.Wp, s));
+    return hipSuccess;
 }
 
 // weight gradient (and, when dx is given, input gradient) of one layer
@@ -347,10 +353,10 @@ hipError_t ubackward(const narvis_unet *u, char *ws, const UPlan &p, hipStream_t
     const int B = p.B;
     const int32_t *w = u->w;
     const ULayer *L = u->L;
-    auto Hl = [&](int l) { return p.H >> l; };
-    auto Wl = [&](int l) { return p.W >> l; };
+    auto Hl = [&](int l) { return p.Hp >> l; };
+    auto Wl = [&](int l) { return p.Wp >> l; };
     // head: loss gradient [P][8] (3 channels used)
-    TRY(ulayer_backward(L[U_HEAD], c.b(p.gy), 8, c.b(p.dy[0]), w[0], nullptr, 0, 0, c.b(p.g_dy[0]), B, p.H, p.W, p, ws,
+    TRY(ulayer_backward(L[U_HEAD], c.b(p.gy), 8, c.b(p.dy[0]), w[0], nullptr, 0, 0, c.b(p.g_dy[0]), B, p.Hp, p.Wp, p, ws,
                         s));
     // decoder, from level 0 back up
     for (int l = 0; l < 4; ++l) {
@@ -397,7 +403,7 @@ hipError_t ubackward(const narvis_unet *u, char *ws, const UPlan &p, hipStream_t
         a.in2_off = cprev;
         TRY(pool2_bwd_add(a, s));
     }
-    TRY(ulayer_backward(L[U_DESC], c.b(p.g_d[0]), 8, c.b(p.feat), 8, nullptr, 0, 0, nullptr, B, p.H, p.W, p, ws, s));
+    TRY(ulayer_backward(L[U_DESC], c.b(p.g_d[0]), 8, c.b(p.feat), 8, nullptr, 0, 0, nullptr, B, p.Hp, p.Wp, p, ws, s));
     // gradient matrices -> blob order
     for (int i = 0; i < kUL; ++i) {
         const ULayer &l = L[i];
@@ -424,10 +430,13 @@ hipError_t urefresh(narvis_unet *u, hipStream_t s)
     return hipSuccess;
 }
 
-bool udims_ok(int B, int W, int H)
+// any frame size for inference (run on the padded grid); training frames
+// are whole multiples of 16
+bool udims_ok(int B, int W, int H, bool train)
 {
-    return B >= 1 && W >= 16 && H >= 16 && W <= 32768 && H <= 32768 && W % 16 == 0 && H % 16 == 0 &&
-           (int64_t)B * W * H < (int64_t(1) << 31);
+    if (B < 1 || W < 1 || H < 1 || W > 32768 || H > 32768) return false;
+    if (train && (W % 16 || H % 16)) return false;
+    return (int64_t)B * round_up(W, 16) * round_up(H, 16) < (int64_t(1) << 31);
 }
 
 narvis_status ust(hipError_t e) { return e == hipSuccess ? NARVIS_OK : NARVIS_ERR_DEVICE; }
@@ -435,7 +444,8 @@ narvis_status ust(hipError_t e) { return e == hipSuccess ? NARVIS_OK : NARVIS_ER
 narvis_status uloss_backward(narvis_unet *u, const float *feat, const float *target, int32_t B, int32_t W, int32_t H,
                              float lam_tv, float *loss_out, void *ws, size_t ws_bytes, hipStream_t s)
 {
-    if (!u || !feat || !target || !loss_out || !ws || !udims_ok(B, W, H) || !std::isfinite(lam_tv) || lam_tv < 0)
+    if (!u || !feat || !target || !loss_out || !ws || !udims_ok(B, W, H, true) || !std::isfinite(lam_tv) ||
+        lam_tv < 0)
         return NARVIS_ERR_INVALID_ARG;
     if (reinterpret_cast<uintptr_t>(ws) & 255u) return NARVIS_ERR_INVALID_ARG;
     const UPlan p = make_uplan(u, B, H, W, true);
@@ -534,14 +544,14 @@ extern "C" narvis_status narvis_unet_read(const narvis_unet *u, float *host_blob
 
 extern "C" size_t narvis_unet_workspace_size(const narvis_unet *u, int32_t B, int32_t W, int32_t H, int32_t train)
 {
-    if (!u || !udims_ok(B, W, H)) return 0;
+    if (!u || !udims_ok(B, W, H, train != 0)) return 0;
     return (size_t)make_uplan(u, B, H, W, train != 0).bytes;
 }
 
 extern "C" narvis_status narvis_unet_forward(const narvis_unet *u, const float *feat, int32_t B, int32_t W, int32_t H,
                                              float *img, void *ws, size_t ws_bytes, void *stream)
 {
-    if (!u || !feat || !img || !ws || !udims_ok(B, W, H)) return NARVIS_ERR_INVALID_ARG;
+    if (!u || !feat || !img || !ws || !udims_ok(B, W, H, false)) return NARVIS_ERR_INVALID_ARG;
     if ((reinterpret_cast<uintptr_t>(ws) & 255u) || (reinterpret_cast<uintptr_t>(feat) & 3u) ||
         (reinterpret_cast<uintptr_t>(img) & 3u))
         return NARVIS_ERR_INVALID_ARG;

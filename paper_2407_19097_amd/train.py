@@ -106,12 +106,39 @@ def init_blob(seed: int) -> np.ndarray:
     return blob
 
 
-def train(weights: narvis.NetWeights, feats, targets, steps: int, batch=16, lr=1e-3, lam_tv=1e-3, seed=0,
+def unet_init_blob(seed: int, widths=narvis.UNET_WIDTHS) -> np.ndarray:
+    """He-normal weights (fan-in) and zero biases of the gated U-Net in the
+    library's blob order: desc, enc0..enc4, (up_l, dec_l) for l = 3..0, head."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    w = [int(v) for v in widths]
+    layers = [(8 * 8, 8, 8)]                                     # (weights, biases, fan-in)
+    for l in range(5):
+        cin = (w[l - 1] if l else 8) + 8
+        layers.append((2 * w[l] * cin * 9, 2 * w[l], cin * 9))
+    for l in (3, 2, 1, 0):
+        layers.append((4 * w[l] * w[l + 1], w[l], w[l + 1]))
+        layers.append((2 * w[l] * 2 * w[l] * 9, 2 * w[l], 2 * w[l] * 9))
+    layers.append((3 * w[0], 3, w[0]))
+    parts = []
+    for nw, nb, fan in layers:
+        parts.append((rng.standard_normal(nw) * math.sqrt(2.0 / fan)).astype(np.float32))
+        parts.append(np.zeros(nb, np.float32))
+    blob = np.concatenate(parts)
+    assert blob.size == narvis.narvis_unet_param_count(widths)
+    return blob
+
+
+def train(weights, feats, targets, steps: int, batch=16, lr=1e-3, lam_tv=1e-3, seed=0,
           log=print, log_every=50, time_budget_s: Optional[float] = None):
-    torch = feats.__class__  # noqa: F841  (torch tensor class; keep the import local)
+    """Adam on random batches of (feats, targets); `weights` is a NetWeights
+    (the small network) or a UNet (the paper's gated U-Net)."""
     import torch
     n, _, H, W = feats.shape
-    ws = torch.empty(narvis.narvis_train_workspace_size(batch, W, H), dtype=torch.uint8, device="cuda")
+    unet = isinstance(weights, narvis.UNet)
+    wsb = (narvis.narvis_unet_workspace_size(weights, batch, W, H, train=True) if unet
+           else narvis.narvis_train_workspace_size(batch, W, H))
+    step_fn = narvis.narvis_unet_train_step if unet else narvis.narvis_train_step
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
     lossv = torch.empty(1, dtype=torch.float32, device="cuda")
     fb = torch.empty((batch, 8, H, W), dtype=torch.float32, device="cuda")
     tb = torch.empty((batch, 3, H, W), dtype=torch.float32, device="cuda")
@@ -129,7 +156,7 @@ def train(weights: narvis.NetWeights, feats, targets, steps: int, batch=16, lr=1
         pos += batch
         torch.index_select(feats, 0, idx, out=fb)
         torch.index_select(targets, 0, idx, out=tb)
-        narvis.narvis_train_step(weights, fb, tb, batch, W, H, lr, lam_tv, lossv, ws)
+        step_fn(weights, fb, tb, batch, W, H, lr, lam_tv, lossv, ws)
         if (s + 1) % log_every == 0 or s + 1 == steps:
             l = float(lossv.item())
             losses.append((s + 1, l))
@@ -173,16 +200,21 @@ def train_c4(sc: scenes.Scene, views: int = 2000, steps: int = 2500, res: int = 
     return w, cal, cams[ntr:], secs, losses
 
 
-def evaluate(weights: narvis.NetWeights, feats, targets, chunk=8):
-    """(psnr of the network output, psnr of the raster's RGB planes alone, ssim net, ssim raster) vs targets."""
+def evaluate(weights, feats, targets, chunk=8):
+    """(psnr of the network output, psnr of the raster's RGB planes alone, ssim net, ssim raster) vs targets;
+    `weights` a NetWeights or a UNet."""
     import torch
     n, _, H, W = feats.shape
-    ws = torch.empty(narvis.narvis_postprocess_workspace_size(chunk, W, H), dtype=torch.uint8, device="cuda")
+    unet = isinstance(weights, narvis.UNet)
+    wsb = (narvis.narvis_unet_workspace_size(weights, chunk, W, H) if unet
+           else narvis.narvis_postprocess_workspace_size(chunk, W, H))
+    run = narvis.narvis_unet_forward if unet else narvis.narvis_postprocess
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
     out = torch.empty((chunk, 3, H, W), dtype=torch.float32, device="cuda")
     p_net, p_ras, s_net, s_ras = [], [], [], []
     for i in range(0, n, chunk):
         b = min(chunk, n - i)
-        narvis.narvis_postprocess(weights, feats[i:i + b].contiguous(), b, W, H, out, ws)
+        run(weights, feats[i:i + b].contiguous(), b, W, H, out, ws)
         y = out[:b]
         t = targets[i:i + b]
         p_net.append(metrics.psnr(y, t))

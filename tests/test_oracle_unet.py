@@ -92,3 +92,18 @@ def test_blob_roundtrip_and_count():
     assert all(np.array_equal(P[k][0], Q[k][0]) and np.array_equal(P[k][1], Q[k][1]) for k in P)
     # the paper's widths: about 27 million parameters
     assert 26_000_000 < ounet.param_count() < 29_000_000
+
+
+def test_padded_inference_matches_torch():
+    """Frames that are not multiples of 16: torch pads with F.pad, runs its own
+    composition and crops; a frame that already is one is the plain forward."""
+    rng = np.random.default_rng(11)
+    P = ounet.init_params(rng, SMALL)
+    P = {k: (w, rng.standard_normal(b.shape) * 0.1) for k, (w, b) in P.items()}
+    x = rng.random((1, 8, 21, 35))
+    got = ounet.infer(P, x)
+    assert got.shape == (1, 3, 21, 35)
+    ty, _ = torch_forward(P, F.pad(torch.tensor(x), (0, 13, 0, 11)).numpy())
+    assert np.max(np.abs(got - ty.detach().numpy()[:, :, :21, :35])) < 1e-11
+    x16 = rng.random((1, 8, 32, 16))
+    assert np.array_equal(ounet.infer(P, x16), ounet.forward(P, x16)[0])

@@ -2,7 +2,7 @@
 
 Forward: bf16 operands and activations, fp32 accumulation, within 2e-2
 max-abs of the FP64 forward on the fp32 parameters (the bf16 bound of the
-network contract).  Gradients: every layer's weight and bias gradient within
+network contract), on frames on and off the 16-pixel grid.  Gradients: every layer's weight and bias gradient within
 a normwise relative bound of the FP64 backward fed the same bf16-rounded
 parameters and input; the GPU stores every activation and gradient tensor in
 bf16 (2^-9 relative each), and the gating's products chain about a dozen such
@@ -45,7 +45,8 @@ def bf16(a):
     return torch.from_numpy(np.asarray(a, np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
 
 
-@pytest.mark.parametrize("widths,B,H,W", [(SMALL, 2, 32, 48), (SMALL, 1, 64, 80), (ounet.WIDTHS, 1, 32, 32)])
+@pytest.mark.parametrize("widths,B,H,W", [(SMALL, 2, 32, 48), (SMALL, 1, 64, 80), (ounet.WIDTHS, 1, 32, 32),
+                                           (SMALL, 1, 36, 50), (SMALL, 2, 17, 40)])
 def test_unet_forward_matches_oracle(widths, B, H, W):
     announce(f"gated U-Net forward, widths {widths}, B={B} {H}x{W}")
     P = random_unet(B * 31 + H, widths)
@@ -56,7 +57,7 @@ def test_unet_forward_matches_oracle(widths, B, H, W):
     narvis.narvis_unet_forward(u, torch.from_numpy(planes).cuda(), B, W, H, img, ws)
     torch.cuda.synchronize()
     got = img.cpu().numpy().astype(np.float64)
-    want, _ = ounet.forward(P, onet.features(planes))
+    want = ounet.infer(P, onet.features(planes))  # frames off the 16 grid: zero-padded, cropped
     err = float(np.abs(got - want).max())
     print(f"  max |gpu - fp64| = {err:.4g}, output range [{want.min():.2f}, {want.max():.2f}]", flush=True)
     assert np.isfinite(got).all()
