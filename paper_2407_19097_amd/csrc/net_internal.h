@@ -41,6 +41,14 @@ struct ConvArgs {
     // slice at H/2 x W/2 (halo kernel, H and W even)
     __bf16 *pool_out;
     int pool_stride, pool_off;         // multiples of 4
+    // gated output (halo kernel, Cout_pad = Cout a multiple of 64): the
+    // weights' rows are in gate order (gate_rows), and the layer writes
+    // y = ELU(z_f) * sigmoid(z_g) with Cout / 2 channels instead of z
+    int gate;
+    // depth-to-space output (1x1 layers, Cout a multiple of 16): row
+    // (2 a + b) C + c of pixel (i, j) of the H x W grid goes to channel c of
+    // pixel (2 i + a, 2 j + b) of the 2H x 2W output (C = Cout / 4)
+    int shuffle;
 };
 
 // Pooling / upsampling / gradient-sum kernels over channel slices (C multiple of 8).
@@ -84,11 +92,13 @@ hipError_t pool2_bwd_add(const SliceArgs &a, hipStream_t s);
 hipError_t wgrad(const WgradArgs &a, float *dw, float *db, hipStream_t s);
 hipError_t loss(const float *y, const float *t, int B, int H, int W, float lam, __bf16 *grad, float *partial,
                 float *out, hipStream_t s);
+// CinD: input channels of the device layouts (>= Cin, the rest zero; 0 = Cin)
 hipError_t prep_weights(const float *master, int Cout, int Cin, int KS, __bf16 *fwd, int fwd_rows, int fwd_kpad,
-                        __bf16 *bwd, int bwd_rows, int bwd_cin, int bwd_kpad, hipStream_t s);
+                        __bf16 *bwd, int bwd_rows, int bwd_cin, int bwd_kpad, hipStream_t s, int CinD = 0);
 hipError_t adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2, float eps,
                 float c1, float c2, hipStream_t s);
-hipError_t grad_to_blob(const float *dw, int Kpad, int Cout, int Cin, int KS, float *blob, hipStream_t s);
+hipError_t grad_to_blob(const float *dw, int Kpad, int Cout, int Cin, int KS, float *blob, hipStream_t s,
+                        int CinD = 0);
 hipError_t copy_f32(const float *src, float *dst, int64_t n, hipStream_t s);
 hipError_t zero_bf16(__bf16 *p, int64_t n, hipStream_t s);
 // the paper's gated U-Net
@@ -96,11 +106,14 @@ hipError_t gate(const __bf16 *z, __bf16 *y, int y_stride, int y_off, int C, int6
 hipError_t gate_bwd(const __bf16 *z, const __bf16 *dy, int dy_stride, int dy_off, __bf16 *dz, int C, int64_t P,
                     hipStream_t s);
 hipError_t pool2(const SliceArgs &a, hipStream_t s);
-hipError_t shuffle_up(const SliceArgs &a, hipStream_t s);
 hipError_t shuffle_down(const SliceArgs &a, hipStream_t s);
-hipError_t features_pad(const float *in, __bf16 *out, int B, int H, int W, int Hp, int Wp, hipStream_t s);
+hipError_t features_pad(const float *in, __bf16 *out, int B, int H, int W, int Hp, int Wp, int oc, hipStream_t s);
 hipError_t crop_planes(const float *src, float *dst, int BC, int H, int W, int Hp, int Wp, hipStream_t s);
 hipError_t bias_phases(const float *b, int C, float *rows, hipStream_t s);
+// rows of a gated layer's forward weights (and biases) in gate order: in each
+// group of 32 device rows, 16 rows of z's first half, then the 16 matching
+// rows of its second half
+hipError_t gate_rows(const __bf16 *w, const float *b, int rows, int kpad, __bf16 *wg, float *bg, hipStream_t s);
 hipError_t bias_grad_phases(const float *rows, int C, float *b, hipStream_t s);
 
 }  // namespace net

@@ -398,7 +398,19 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a, const uint8_t *wq,
                 for (int e = 0; e < 4; ++e)
                     if (cb + e < a.Cout) a.out_f32[(b * a.Cout + cb + e) * hw + pix] = v[e];
             } else if (cb < a.Cout) {
-                __bf16 *o = a.out + p * a.out_stride + a.out_off + cb;
+                int64_t q = p;
+                int c = cb;
+                if (a.shuffle) {
+                    // depth-to-space: phase (2 sy + sx) of the 2x2 block (C = Cout / 4 a multiple of 4,
+                    // so the lane's 4 channels share one phase)
+                    const int C4 = a.Cout >> 2, ph = cb / C4;
+                    c = cb - ph * C4;
+                    const int64_t hw = (int64_t)a.H * a.W;
+                    const int64_t b = p / hw, rem = p - b * hw;
+                    const int64_t i = rem / a.W, j = rem - i * a.W;
+                    q = (b * 2 * a.H + 2 * i + (ph >> 1)) * (2 * (int64_t)a.W) + 2 * j + (ph & 1);
+                }
+                __bf16 *o = a.out + q * a.out_stride + a.out_off + c;
                 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
                 bf16x4 w4;
 #pragma unroll
@@ -453,16 +465,21 @@ __device__ __forceinline__ bf16x8 upsample_piece(const __bf16 *in, int stride, i
 // Within a pixel's 64 bytes the four 16-byte pieces are XOR-swizzled by
 // pixel bits 1-2, so eight lanes reading eight consecutive pixels at the same
 // channel offset hit distinct banks, for every tap shift.
+// the gated convolution's activation: ELU (alpha 1) times the logistic gate
+__device__ __forceinline__ float elu1(float x) { return x > 0.0f ? x : expm1f(x); }
+__device__ __forceinline__ float sigm(float x) { return 1.0f / (1.0f + expf(-x)); }
+
 constexpr int kHaloRows = 4;   // output rows per workgroup of the first-layer kernel
 constexpr int kHaloCols = 64;  // output pixels per row of a tile
 
 __device__ __forceinline__ int halo_at(int p, int part) { return p * 32 + 8 * (part ^ ((p >> 1) & 3)); }
 
-template <int CO, int ROWS, bool MASK, bool HEAD, bool UP, bool FP8>
+template <int CO, int ROWS, bool MASK, bool HEAD, bool UP, bool FP8, bool GATE = false>
 __global__ __launch_bounds__(64 * ROWS * CO / 32, 4) void k_conv_halo(ConvArgs a, const uint8_t *wq, const float *sw,
                                                                       float sa)
 {
     static_assert(!FP8 || (!MASK && !HEAD), "FP8 runs inference layers without the fused head");
+    static_assert(!GATE || (!MASK && !HEAD && !UP && !FP8), "the gated output is an inference epilogue");
     static_assert(ROWS % 2 == 0 && (CO / 32) * (ROWS / 2) * 8 * 64 * 8 <= 9 * CO * 32 * (FP8 ? 1 : 2),
                   "room in the weights' LDS for the pooled rows");
     typedef ConvOps<FP8> Ops;
@@ -682,27 +699,41 @@ __global__ __launch_bounds__(64 * ROWS * CO / 32, 4) void k_conv_halo(ConvArgs a
     bf16x4 *const pl = reinterpret_cast<bf16x4 *>(ws);  // [(wch, row pair, i, f)][lane]
     const int pslot = (wch * (ROWS / 2) + (wrow >> 1)) * 8;
     if (pool) __syncthreads();  // every wave is done with the tiles
-    bf16x4 own[2][4];
+    // GATE: device rows co0 + 32 wch + 4 g + e (acc[0]) and the same + 16
+    // (acc[1]) are the two halves of output channel (co0 + 32 wch) / 2 + 4 g + e
+    constexpr int NI = GATE ? 1 : 2;
+    const int cout_lim = GATE ? a.Cout / 2 : a.Cout;
+    auto out_base = [&](int i) { return GATE ? (co0 + 32 * wch) / 2 + 4 * g : co0 + 32 * wch + 16 * i + 4 * g; };
+    bf16x4 own[NI][4];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const int cb = co0 + 32 * wch + 16 * i + 4 * g;
-        float bias[4], scale[4];
+    for (int i = 0; i < NI; ++i) {
+        const int cb = out_base(i);
+        const int rb = co0 + 32 * wch + 16 * i + 4 * g;
+        float bias[4], scale[4], bias_g[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            bias[e] = a.bias ? a.bias[cb + e] : 0.0f;
-            scale[e] = FP8 ? sw[cb + e] * sa : 1.0f;  // FP8: dequantise (weight scale x activation scale)
+            bias[e] = a.bias ? a.bias[rb + e] : 0.0f;
+            bias_g[e] = GATE && a.bias ? a.bias[rb + 16 + e] : 0.0f;
+            scale[e] = FP8 ? sw[rb + e] * sa : 1.0f;  // FP8: dequantise (weight scale x activation scale)
         }
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
             const int x = x0 + 16 * f + r;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                float t = FP8 ? acc[i][f][e] * scale[e] + bias[e] : acc[i][f][e] + bias[e];
-                if (a.relu) t = fmaxf(t, 0.0f);
-                own[i][f][e] = (__bf16)t;
+                if constexpr (GATE) {
+                    // z rounded to bf16 as the unfused layer stores it
+                    const float zf = (float)(__bf16)(acc[0][f][e] + bias[e]);
+                    const float zg = (float)(__bf16)(acc[1][f][e] + bias_g[e]);
+                    own[i][f][e] = (__bf16)(elu1(zf) * sigm(zg));
+                } else {
+                    float t = FP8 ? acc[i][f][e] * scale[e] + bias[e] : acc[i][f][e] + bias[e];
+                    if (a.relu) t = fmaxf(t, 0.0f);
+                    own[i][f][e] = (__bf16)t;
+                }
             }
             if (pool && (wrow & 1)) pl[(pslot + 4 * i + f) * 64 + lane] = own[i][f];
-            if (y >= a.H || x >= a.W || cb >= a.Cout) continue;
+            if (y >= a.H || x >= a.W || cb >= cout_lim) continue;
             const int64_t p = ((int64_t)b * a.H + y) * a.W + x;
             *reinterpret_cast<bf16x4 *>(a.out + p * a.out_stride + a.out_off + cb) = own[i][f];
         }
@@ -712,8 +743,8 @@ __global__ __launch_bounds__(64 * ROWS * CO / 32, 4) void k_conv_halo(ConvArgs a
     if (wrow & 1) return;
     const int Wo = a.W / 2;
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const int cb = co0 + 32 * wch + 16 * i + 4 * g;
+    for (int i = 0; i < NI; ++i) {
+        const int cb = out_base(i);
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
             // the right neighbour's output (lane r ^ 1), as two 32-bit words
@@ -723,7 +754,7 @@ __global__ __launch_bounds__(64 * ROWS * CO / 32, 4) void k_conv_halo(ConvArgs a
             theirs[1] = __shfl_xor(mine[1], 1);
             const bf16x4 right = __builtin_bit_cast(bf16x4, theirs);
             const int x = x0 + 16 * f + r;
-            if ((r & 1) || y >= a.H || x >= a.W || cb >= a.Cout) continue;
+            if ((r & 1) || y >= a.H || x >= a.W || cb >= cout_lim) continue;
             const bf16x4 below = pl[(pslot + 4 * i + f) * 64 + lane];
             const bf16x4 below_right = pl[(pslot + 4 * i + f) * 64 + lane + 1];
             bf16x4 o;
@@ -1239,9 +1270,10 @@ __global__ __launch_bounds__(256) void k_sum(const float *partial, int64_t n, fl
 // ---------------------------------------------------------------------------
 
 // master W in the blob's [Cout][Cin][k][k] order
-__global__ __launch_bounds__(256) void k_prep_weights(const float *master, int Cout, int Cin, int KS, __bf16 *fwd,
-                                                      int fwd_rows, int fwd_kpad, __bf16 *bwd, int bwd_rows,
-                                                      int bwd_cin, int bwd_kpad)
+// device layouts use CinD >= Cin input channels (the ones past Cin are zero)
+__global__ __launch_bounds__(256) void k_prep_weights(const float *master, int Cout, int Cin, int CinD, int KS,
+                                                      __bf16 *fwd, int fwd_rows, int fwd_kpad, __bf16 *bwd,
+                                                      int bwd_rows, int bwd_cin, int bwd_kpad)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t nf = (int64_t)fwd_rows * fwd_kpad;
@@ -1250,9 +1282,9 @@ __global__ __launch_bounds__(256) void k_prep_weights(const float *master, int C
     if (i < nf) {
         const int co = (int)(i / fwd_kpad), k = (int)(i % fwd_kpad);
         float v = 0.0f;
-        if (co < Cout && k < T * Cin) {
-            const int tap = k / Cin, ci = k % Cin;
-            v = master[((int64_t)co * Cin + ci) * T + tap];
+        if (co < Cout && k < T * CinD) {
+            const int tap = k / CinD, ci = k % CinD;
+            if (ci < Cin) v = master[((int64_t)co * Cin + ci) * T + tap];
         }
         fwd[i] = (__bf16)v;
     }
@@ -1286,7 +1318,8 @@ __global__ __launch_bounds__(256) void k_adam(float *p, const float *g, float *m
 }
 
 // gradient matrix [Cout_pad][Kpad] in (tap, ci) order -> blob order [Cout][Cin][k][k]
-__global__ __launch_bounds__(256) void k_grad_to_blob(const float *dw, int Kpad, int Cout, int Cin, int KS, float *blob)
+__global__ __launch_bounds__(256) void k_grad_to_blob(const float *dw, int Kpad, int Cout, int Cin, int CinD, int KS,
+                                                      float *blob)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int T = KS * KS;
@@ -1294,7 +1327,7 @@ __global__ __launch_bounds__(256) void k_grad_to_blob(const float *dw, int Kpad,
     const int tap = (int)(i % T);
     const int ci = (int)((i / T) % Cin);
     const int co = (int)(i / ((int64_t)T * Cin));
-    blob[i] = dw[(int64_t)co * Kpad + tap * Cin + ci];
+    blob[i] = dw[(int64_t)co * Kpad + tap * CinD + ci];
 }
 
 __global__ __launch_bounds__(256) void k_copy_f32(const float *src, float *dst, int64_t n)
@@ -1397,6 +1430,12 @@ static hipError_t launch_conv(const ConvArgs &a, int KS, const uint8_t *wq, cons
                          (int64_t)a.B * (cop % 64 ? cop / 32 : cop / 64) <= 65535;
     if (a.pool_out && (!halo_ok || a.head_out || a.H % 2 || a.W % 2 || a.pool_stride % 4 || a.pool_off % 4))
         return hipErrorInvalidValue;
+    if (a.gate) {
+        if (FP8 || !halo_ok || cop % 64 || a.Cout != cop || a.in_mask || a.up_in || a.head_out) return hipErrorInvalidValue;
+        const dim3 grid(gx, (unsigned)((a.H + 3) / 4), (unsigned)(a.B * (cop / 64)));
+        hipLaunchKernelGGL((k_conv_halo<64, 4, false, false, false, false, true>), grid, dim3(512), 0, s, a, wq, sw, sa);
+        return hipGetLastError();
+    }
     // first layer (8 input channels, 32 output channels)
     if (!FP8 && KS == 3 && cop == 32 && a.Cin == 8 && a.Kpad == 96 && !a.in_mask && !a.in2 && !a.out_f32) {
         hipLaunchKernelGGL(k_conv_c8, dim3(gx, gy, (unsigned)a.B), dim3(256), 0, s, a);
@@ -1433,6 +1472,15 @@ static hipError_t launch_conv(const ConvArgs &a, int KS, const uint8_t *wq, cons
         return hipGetLastError();
     }
     if (a.up_in) return hipErrorInvalidValue;
+    // 1x1 layers with 64 or more output channels (the U-Net's transposed
+    // convolutions, optionally written depth-to-space): LDS-staged tiles
+    const bool lds1 = !FP8 && KS == 1 && cop % 64 == 0 && !a.out_f32 && !a.in_mask;
+    if (a.shuffle && (!lds1 || a.Cout != cop || a.Cout % 16)) return hipErrorInvalidValue;
+    if (lds1) {
+        dim3 grid(nblocks(P, 128), cop / 64);
+        hipLaunchKernelGGL((k_conv_lds<64, 128, 1, false, false>), grid, dim3(256), 0, s, a, wq, sw, sa);
+        return hipGetLastError();
+    }
     // other 3x3 layers with 64 or more output channels (FP8, or Cin not a
     // multiple of 32): LDS-staged im2col tiles
     if (KS == 3 && cop % 64 == 0) {
@@ -1504,9 +1552,6 @@ hipError_t absdiff_max_f32(const float *a, const float *b, int64_t n, unsigned i
 // kernels of the paper's gated U-Net
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ float elu1(float x) { return x > 0.0f ? x : expm1f(x); }
-__device__ __forceinline__ float sigm(float x) { return 1.0f / (1.0f + expf(-x)); }
-
 // y = ELU(z[:, :C]) * sigmoid(z[:, C:]), z dense [P][2C], y a slice
 __global__ __launch_bounds__(256) void k_gate(const __bf16 *z, __bf16 *y, int y_stride, int y_off, int C, int64_t P)
 {
@@ -1557,28 +1602,10 @@ __global__ __launch_bounds__(256) void k_pool2(SliceArgs s)
     *reinterpret_cast<bf16x8 *>(s.out + q * s.out_stride + s.out_off + c8 * 8) = o;
 }
 
-// transposed 2x2 stride-2 convolution as a 1x1 convolution with 4C outputs
-// (row (2a + b) C + c) followed by this depth-to-space step:
-// out[2i + a][2j + b][c] = in[i][j][(2a + b) C + c]; s.H, s.W: the low grid
-__global__ __launch_bounds__(256) void k_shuffle_up(SliceArgs s)
-{
-    const int groups = s.C / 8;
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t >= (int64_t)s.B * s.H * s.W * 4 * groups) return;
-    const int c8 = (int)(t % groups);
-    const int64_t r = t / groups;
-    const int ph = (int)(r % 4);
-    const int64_t q = r / 4;
-    const int64_t b = q / ((int64_t)s.H * s.W);
-    const int64_t rem = q - b * s.H * s.W;
-    const int i = (int)(rem / s.W), j = (int)(rem % s.W);
-    const int a = ph >> 1, bb = ph & 1;
-    const int64_t o = (b * 2 * s.H + 2 * i + a) * (2 * s.W) + 2 * j + bb;
-    *reinterpret_cast<bf16x8 *>(s.out + o * s.out_stride + s.out_off + c8 * 8) =
-        load8(s.in + q * s.in_stride + s.in_off + ph * s.C + c8 * 8);
-}
-
-// adjoint of k_shuffle_up: in a slice of the high grid, out [B][H][W][4C]
+// adjoint of the depth-to-space step of the transposed convolution (a 1x1
+// convolution with 4C outputs, row (2a + b) C + c, written to
+// out[2i + a][2j + b][c]): in a slice of the high grid, out [B][H][W][4C]
+// with out[i][j][(2a + b) C + c] = in[2i + a][2j + b][c]; s.H, s.W: the low grid
 __global__ __launch_bounds__(256) void k_shuffle_down(SliceArgs s)
 {
     const int groups = s.C / 8;
@@ -1600,8 +1627,10 @@ __global__ __launch_bounds__(256) void k_shuffle_down(SliceArgs s)
 // bias of the 4C rows of a transposed convolution from its C biases, and the
 // C bias gradients from the 4C row gradients
 // network input of an H x W frame on the zero-padded Hp x Wp grid (padded
-// pixels are empty pixels: every channel 0); out [B][Hp][Wp][8]
-__global__ __launch_bounds__(256) void k_features_pad(const float *in, __bf16 *out, int B, int H, int W, int Hp, int Wp)
+// pixels are empty pixels: every channel 0); out [B][Hp][Wp][oc], the 8
+// input channels then oc - 8 zero channels (oc a multiple of 8)
+__global__ __launch_bounds__(256) void k_features_pad(const float *in, __bf16 *out, int B, int H, int W, int Hp, int Wp,
+                                                      int oc)
 {
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= (int64_t)B * Hp * Wp) return;
@@ -1619,7 +1648,8 @@ __global__ __launch_bounds__(256) void k_features_pad(const float *in, __bf16 *o
             v[c] = (__bf16)f;
         }
     }
-    *reinterpret_cast<bf16x8 *>(out + p * 8) = v;
+    *reinterpret_cast<bf16x8 *>(out + p * oc) = v;
+    for (int c = 8; c < oc; c += 8) *reinterpret_cast<bf16x8 *>(out + p * oc + c) = zero8();
 }
 
 // planar [B][C][Hp][Wp] fp32 -> its top-left [B][C][H][W]
@@ -1664,21 +1694,38 @@ hipError_t pool2(const SliceArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t shuffle_up(const SliceArgs &a, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_shuffle_up, dim3(nblocks((int64_t)a.B * a.H * a.W * 4 * (a.C / 8))), dim3(256), 0, s, a);
-    return hipGetLastError();
-}
-
 hipError_t shuffle_down(const SliceArgs &a, hipStream_t s)
 {
     hipLaunchKernelGGL(k_shuffle_down, dim3(nblocks((int64_t)a.B * a.H * a.W * 4 * (a.C / 8))), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t features_pad(const float *in, __bf16 *out, int B, int H, int W, int Hp, int Wp, hipStream_t s)
+// wg row d = w row (first half of z: 16 q + t for t < 16, second half:
+// rows / 2 + 16 q + t - 16), q = d / 32, t = d % 32
+__global__ __launch_bounds__(256) void k_gate_rows(const __bf16 *w, const float *b, int rows, int kpad, __bf16 *wg,
+                                                   float *bg)
 {
-    hipLaunchKernelGGL(k_features_pad, dim3(nblocks((int64_t)B * Hp * Wp)), dim3(256), 0, s, in, out, B, H, W, Hp, Wp);
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (int64_t)rows * kpad) return;
+    const int d = (int)(i / kpad), k = (int)(i - (int64_t)d * kpad);
+    const int q = d >> 5, t = d & 31;
+    const int src = t < 16 ? 16 * q + t : rows / 2 + 16 * q + (t - 16);
+    wg[i] = w[(int64_t)src * kpad + k];
+    if (k == 0) bg[d] = b[src];
+}
+
+hipError_t gate_rows(const __bf16 *w, const float *b, int rows, int kpad, __bf16 *wg, float *bg, hipStream_t s)
+{
+    if (rows % 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gate_rows, dim3(nblocks((int64_t)rows * kpad)), dim3(256), 0, s, w, b, rows, kpad, wg, bg);
+    return hipGetLastError();
+}
+
+hipError_t features_pad(const float *in, __bf16 *out, int B, int H, int W, int Hp, int Wp, int oc, hipStream_t s)
+{
+    if (oc < 8 || oc % 8) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_features_pad, dim3(nblocks((int64_t)B * Hp * Wp)), dim3(256), 0, s, in, out, B, H, W, Hp, Wp,
+                       oc);
     return hipGetLastError();
 }
 
@@ -1775,11 +1822,11 @@ hipError_t loss(const float *y, const float *t, int B, int H, int W, float lam, 
 }
 
 hipError_t prep_weights(const float *master, int Cout, int Cin, int KS, __bf16 *fwd, int fwd_rows, int fwd_kpad,
-                        __bf16 *bwd, int bwd_rows, int bwd_cin, int bwd_kpad, hipStream_t s)
+                        __bf16 *bwd, int bwd_rows, int bwd_cin, int bwd_kpad, hipStream_t s, int CinD)
 {
     const int64_t nf = (int64_t)fwd_rows * fwd_kpad, nb = bwd ? (int64_t)bwd_rows * bwd_kpad : 0;
-    hipLaunchKernelGGL(k_prep_weights, dim3(nblocks(nf > nb ? nf : nb)), dim3(256), 0, s, master, Cout, Cin, KS, fwd,
-                       fwd_rows, fwd_kpad, bwd, bwd_rows, bwd_cin, bwd_kpad);
+    hipLaunchKernelGGL(k_prep_weights, dim3(nblocks(nf > nb ? nf : nb)), dim3(256), 0, s, master, Cout, Cin,
+                       CinD > 0 ? CinD : Cin, KS, fwd, fwd_rows, fwd_kpad, bwd, bwd_rows, bwd_cin, bwd_kpad);
     return hipGetLastError();
 }
 
@@ -1790,10 +1837,11 @@ hipError_t adam(float *p, const float *g, float *m, float *v, int64_t n, float l
     return hipGetLastError();
 }
 
-hipError_t grad_to_blob(const float *dw, int Kpad, int Cout, int Cin, int KS, float *blob, hipStream_t s)
+hipError_t grad_to_blob(const float *dw, int Kpad, int Cout, int Cin, int KS, float *blob, hipStream_t s, int CinD)
 {
     const int64_t n = (int64_t)Cout * Cin * KS * KS;
-    hipLaunchKernelGGL(k_grad_to_blob, dim3(nblocks(n)), dim3(256), 0, s, dw, Kpad, Cout, Cin, KS, blob);
+    hipLaunchKernelGGL(k_grad_to_blob, dim3(nblocks(n)), dim3(256), 0, s, dw, Kpad, Cout, Cin, CinD > 0 ? CinD : Cin,
+                       KS, blob);
     return hipGetLastError();
 }
 

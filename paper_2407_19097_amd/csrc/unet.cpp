@@ -10,7 +10,13 @@
 //
 // Every convolution runs on the small network's matrix-core kernels (bf16
 // operands, fp32 accumulation, NHWC activations); a concatenated input is
-// read from two tensors.  The transposed convolution is a 1x1 convolution
+// read from two tensors.  The encoder's descriptor channels are carried in
+// 32-channel tensors (8 channels and 24 zeros; level 0 holds the 8 input
+// channels, the 8 descriptor channels and 16 zeros) so that every 3x3 layer
+// reads whole 32-channel groups and runs on the direct halo-tile kernel; the
+// device weights have zero columns there.  In inference the gate (and the
+// encoder's pooling) is the convolution's epilogue, on weights whose rows are
+// stored in gate order.  The transposed convolution is a 1x1 convolution
 // with 4 w_l outputs (one block per output phase) followed by a depth-to-
 // space copy.  Training: MSE + TV loss, backward through every layer with
 // the same kernels (input gradients on flipped weights, weight gradients by
@@ -44,11 +50,12 @@ uint64_t align256(uint64_t v) { return (v + 255) & ~uint64_t(255); }
 
 struct ULayer {
     int kind, cin, cout, ks;       // the convolution's view (gate3: 2 w outputs; tconv: 4 w)
+    int cind;                      // input channels of the device layouts (>= cin, the rest zero)
     int rows, kpad, bcin, brows, bkpad;
     int nbias;                     // biases in the blob (tconv: w, not 4 w)
     int64_t blob_w, blob_b;
-    __bf16 *wf, *wb;
-    float *bias, *dw, *db;
+    __bf16 *wf, *wb, *wg;          // wg: gate3 forward weights in gate order (inference)
+    float *bias, *dw, *db, *bg;
 };
 
 bool widths_ok(const int32_t *w)
@@ -59,27 +66,34 @@ bool widths_ok(const int32_t *w)
     return true;
 }
 
+// device input channels of encoder level l: [x_l | d_l] with the 8
+// descriptor channels in a 32-channel group (level 0: one 32-channel group
+// holding the 8 input and the 8 descriptor channels)
+int enc_cind(const int32_t *w, int l) { return l ? w[l - 1] + 32 : 32; }
+
 void describe(const int32_t *w, ULayer *L)
 {
-    auto set = [](ULayer &l, int kind, int cin, int cout, int ks, int nbias) {
+    auto set = [](ULayer &l, int kind, int cin, int cind, int cout, int ks, int nbias) {
         l.kind = kind;
         l.cin = cin;
+        l.cind = cind;
         l.cout = cout;
         l.ks = ks;
         l.nbias = nbias;
         l.rows = round_up(cout, 16);
-        l.kpad = round_up(ks * ks * cin, 32);
+        l.kpad = round_up(ks * ks * cind, 32);
         l.bcin = round_up(cout, 8);
-        l.brows = round_up(cin, 16);
+        l.brows = round_up(cind, 16);
         l.bkpad = round_up(ks * ks * l.bcin, 32);
     };
-    set(L[U_DESC], K_CONV1, 8, 8, 1, 8);
-    for (int l = 0; l < kLevels; ++l) set(L[U_ENC0 + l], K_GATE3, (l ? w[l - 1] : 8) + 8, 2 * w[l], 3, 2 * w[l]);
+    set(L[U_DESC], K_CONV1, 8, 8, 8, 1, 8);
+    for (int l = 0; l < kLevels; ++l)
+        set(L[U_ENC0 + l], K_GATE3, (l ? w[l - 1] : 8) + 8, enc_cind(w, l), 2 * w[l], 3, 2 * w[l]);
     for (int l = 3; l >= 0; --l) {
-        set(L[u_up(l)], K_TCONV, w[l + 1], 4 * w[l], 1, w[l]);
-        set(L[u_dec(l)], K_GATE3, 2 * w[l], 2 * w[l], 3, 2 * w[l]);
+        set(L[u_up(l)], K_TCONV, w[l + 1], w[l + 1], 4 * w[l], 1, w[l]);
+        set(L[u_dec(l)], K_GATE3, 2 * w[l], 2 * w[l], 2 * w[l], 3, 2 * w[l]);
     }
-    set(L[U_HEAD], K_CONV1, w[0], 3, 1, 3);
+    set(L[U_HEAD], K_CONV1, w[0], w[0], 3, 1, 3);
     int64_t o = 0;
     for (int i = 0; i < kUL; ++i) {
         L[i].blob_w = o;
@@ -115,7 +129,7 @@ namespace {
 struct UPlan {
     int B, H, W, Hp, Wp;
     int64_t P[kLevels];
-    uint64_t feat, d[kLevels], x[kLevels], ez[kLevels], ey[kLevels], tz[4], u[4], dz[4], dy[4];
+    uint64_t x0, d[kLevels], dzero, dzero_end, x[kLevels], ez[kLevels], ey[kLevels], u[4], dz[4], dy[4];
     uint64_t out;
     uint64_t gy, g_dy[4], g_ey4, g_dz[4], g_dcat[4], g_tz[4], g_ey[4], g_ez[kLevels], g_ecat[kLevels], g_d[4];
     uint64_t part, bpart, lpart;
@@ -159,15 +173,16 @@ UPlan make_uplan(const narvis_unet *u, int B, int H, int W, bool train)
         o = align256(o + (uint64_t)px * ch * 2);
         return at;
     };
-    p.feat = bf(p.P[0], 8);
-    for (int l = 0; l < kLevels; ++l) p.d[l] = bf(p.P[l], 8);
+    p.x0 = bf(p.P[0], 32);  // [input (8) | d_0 (8) | 0 (16)]
+    p.dzero = o;
+    for (int l = 1; l < kLevels; ++l) p.d[l] = bf(p.P[l], 32);  // [d_l (8) | 0 (24)]
+    p.dzero_end = o;
     for (int l = 1; l < kLevels; ++l) p.x[l] = bf(p.P[l], w[l - 1]);
     for (int l = 0; l < kLevels; ++l) {
         p.ez[l] = bf(p.P[l], 2 * w[l]);
         p.ey[l] = bf(p.P[l], w[l]);
     }
     for (int l = 0; l < 4; ++l) {
-        p.tz[l] = bf(p.P[l + 1], 4 * w[l]);
         p.u[l] = bf(p.P[l], w[l]);
         p.dz[l] = bf(p.P[l], 2 * w[l]);
         p.dy[l] = bf(p.P[l], w[l]);
@@ -187,7 +202,7 @@ UPlan make_uplan(const narvis_unet *u, int B, int H, int W, bool train)
         p.g_ey4 = bf(p.P[4], w[4]);
         for (int l = 0; l < kLevels; ++l) {
             p.g_ez[l] = bf(p.P[l], 2 * w[l]);
-            p.g_ecat[l] = bf(p.P[l], (l ? w[l - 1] : 8) + 8);
+            p.g_ecat[l] = bf(p.P[l], enc_cind(w, l));
         }
         int64_t pf = 0, bfl = 0;
         for (int i = 0; i < kUL; ++i) {
@@ -225,7 +240,7 @@ ConvArgs uconv(const ULayer &l, const __bf16 *in, int in_stride, int cin1, const
     ConvArgs a{};
     a.in = in;
     a.in_stride = in_stride;
-    a.Cin = l.cin;
+    a.Cin = l.cind;
     if (in2) {
         a.in2 = in2;
         a.in2_stride = in2_stride;
@@ -260,7 +275,9 @@ SliceArgs uslice(const __bf16 *in, int is, int io, __bf16 *out, int os, int oo, 
     return s;
 }
 
-hipError_t uforward(const narvis_unet *u, const float *feat_planes, char *ws, const UPlan &p, float *img,
+// fused: inference (gates and encoder pooling in the convolutions'
+// epilogues, z never stored); otherwise every z is kept for the backward pass
+hipError_t uforward(const narvis_unet *u, const float *feat_planes, char *ws, const UPlan &p, float *img, bool fused,
                     hipStream_t s)
 {
     UCtx c{ws};
@@ -269,16 +286,35 @@ hipError_t uforward(const narvis_unet *u, const float *feat_planes, char *ws, co
     const ULayer *L = u->L;
     auto Hl = [&](int l) { return p.Hp >> l; };
     auto Wl = [&](int l) { return p.Wp >> l; };
-    TRY(features_pad(feat_planes, c.b(p.feat), B, p.H, p.W, p.Hp, p.Wp, s));
-    // descriptors at five scales
-    TRY(conv(uconv(L[U_DESC], c.b(p.feat), 8, 0, nullptr, 0, c.b(p.d[0]), B, p.Hp, p.Wp), 1, s));
-    for (int l = 1; l < kLevels; ++l)
-        TRY(pool2(uslice(c.b(p.d[l - 1]), 8, 0, c.b(p.d[l]), 8, 0, 8, B, Hl(l - 1), Wl(l - 1)), s));
+    TRY(features_pad(feat_planes, c.b(p.x0), B, p.H, p.W, p.Hp, p.Wp, 32, s));
+    // descriptors at five scales: d_0 into channels 8..15 of the level-0 input
+    ConvArgs dc = uconv(L[U_DESC], c.b(p.x0), 32, 0, nullptr, 0, c.b(p.x0), B, p.Hp, p.Wp);
+    dc.out_stride = 32;
+    dc.out_off = 8;
+    TRY(conv(dc, 1, s));
+    TRY(zero_bf16(c.b(p.dzero), (int64_t)(p.dzero_end - p.dzero) / 2, s));
+    TRY(pool2(uslice(c.b(p.x0), 32, 8, c.b(p.d[1]), 32, 0, 8, B, Hl(0), Wl(0)), s));
+    for (int l = 2; l < kLevels; ++l)
+        TRY(pool2(uslice(c.b(p.d[l - 1]), 32, 0, c.b(p.d[l]), 32, 0, 8, B, Hl(l - 1), Wl(l - 1)), s));
     // encoder
     for (int l = 0; l < kLevels; ++l) {
-        const int cprev = l ? w[l - 1] : 8;
-        const __bf16 *in = l ? c.b(p.x[l]) : c.b(p.feat);
-        TRY(conv(uconv(L[U_ENC0 + l], in, cprev, cprev, c.b(p.d[l]), 8, c.b(p.ez[l]), B, Hl(l), Wl(l)), 3, s));
+        const ULayer &ly = L[U_ENC0 + l];
+        ConvArgs a = l ? uconv(ly, c.b(p.x[l]), w[l - 1], w[l - 1], c.b(p.d[l]), 32, c.b(p.ez[l]), B, Hl(l), Wl(l))
+                       : uconv(ly, c.b(p.x0), 32, 0, nullptr, 0, c.b(p.ez[l]), B, Hl(l), Wl(l));
+        if (fused) {
+            a.gate = 1;
+            a.wt = ly.wg;
+            a.bias = ly.bg;
+            a.out = c.b(p.ey[l]);
+            a.out_stride = w[l];
+            if (l + 1 < kLevels) {
+                a.pool_out = c.b(p.x[l + 1]);
+                a.pool_stride = w[l];
+            }
+            TRY(conv(a, 3, s));
+            continue;
+        }
+        TRY(conv(a, 3, s));
         TRY(gate(c.b(p.ez[l]), c.b(p.ey[l]), w[l], 0, w[l], p.P[l], s));
         if (l + 1 < kLevels)
             TRY(pool2(uslice(c.b(p.ey[l]), w[l], 0, c.b(p.x[l + 1]), w[l], 0, w[l], B, Hl(l), Wl(l)), s));
@@ -286,10 +322,24 @@ hipError_t uforward(const narvis_unet *u, const float *feat_planes, char *ws, co
     // decoder
     const __bf16 *up_in = c.b(p.ey[4]);
     for (int l = 3; l >= 0; --l) {
-        TRY(conv(uconv(L[u_up(l)], up_in, w[l + 1], 0, nullptr, 0, c.b(p.tz[l]), B, Hl(l + 1), Wl(l + 1)), 1, s));
-        TRY(shuffle_up(uslice(c.b(p.tz[l]), 4 * w[l], 0, c.b(p.u[l]), w[l], 0, w[l], B, Hl(l + 1), Wl(l + 1)), s));
-        TRY(conv(uconv(L[u_dec(l)], c.b(p.u[l]), w[l], w[l], c.b(p.ey[l]), w[l], c.b(p.dz[l]), B, Hl(l), Wl(l)), 3, s));
-        TRY(gate(c.b(p.dz[l]), c.b(p.dy[l]), w[l], 0, w[l], p.P[l], s));
+        const ULayer &ly = L[u_dec(l)];
+        // transposed convolution: 1x1 with 4 w_l outputs written depth-to-space
+        ConvArgs t = uconv(L[u_up(l)], up_in, w[l + 1], 0, nullptr, 0, c.b(p.u[l]), B, Hl(l + 1), Wl(l + 1));
+        t.shuffle = 1;
+        t.out_stride = w[l];
+        TRY(conv(t, 1, s));
+        ConvArgs a = uconv(ly, c.b(p.u[l]), w[l], w[l], c.b(p.ey[l]), w[l], c.b(p.dz[l]), B, Hl(l), Wl(l));
+        if (fused) {
+            a.gate = 1;
+            a.wt = ly.wg;
+            a.bias = ly.bg;
+            a.out = c.b(p.dy[l]);
+            a.out_stride = w[l];
+            TRY(conv(a, 3, s));
+        } else {
+            TRY(conv(a, 3, s));
+            TRY(gate(c.b(p.dz[l]), c.b(p.dy[l]), w[l], 0, w[l], p.P[l], s));
+        }
         up_in = c.b(p.dy[l]);
     }
     ConvArgs h = uconv(L[U_HEAD], c.b(p.dy[0]), w[0], 0, nullptr, 0, nullptr, B, p.Hp, p.Wp);
@@ -313,7 +363,7 @@ hipError_t ulayer_backward(const ULayer &l, const __bf16 *dy, int dy_stride, con
     a.x2 = x2;
     a.x2_stride = x2_stride;
     a.xCin1 = x2 ? xcin1 : 0;
-    a.Cin = l.cin;
+    a.Cin = l.cind;
     a.KS = l.ks;
     a.Cout = l.cout;
     a.Cout_pad = l.rows;
@@ -335,13 +385,13 @@ hipError_t ulayer_backward(const ULayer &l, const __bf16 *dy, int dy_stride, con
         c.Cin = l.bcin;
         c.wt = l.wb;
         c.Kpad = l.bkpad;
-        c.Cout = l.cin;
+        c.Cout = l.cind;
         c.Cout_pad = l.brows;
         c.B = B;
         c.H = H;
         c.W = W;
         c.out = dx;
-        c.out_stride = l.cin;
+        c.out_stride = l.cind;
         TRY(conv(c, l.ks, s));
     }
     return hipSuccess;
@@ -379,7 +429,8 @@ hipError_t ubackward(const narvis_unet *u, char *ws, const UPlan &p, hipStream_t
             gy_l = c.b(p.g_ey4);
         } else {
             // pooled path from the level below + the skip part of the decoder's input gradient
-            SliceArgs a = uslice(c.b(p.g_ecat[l + 1]), w[l] + 8, 0, c.b(p.g_ey[l]), w[l], 0, w[l], B, Hl(l), Wl(l));
+            SliceArgs a = uslice(c.b(p.g_ecat[l + 1]), enc_cind(w, l + 1), 0, c.b(p.g_ey[l]), w[l], 0, w[l], B, Hl(l),
+                                 Wl(l));
             a.in2 = c.b(p.g_dcat[l]);
             a.in2_stride = 2 * w[l];
             a.in2_off = w[l];
@@ -387,27 +438,29 @@ hipError_t ubackward(const narvis_unet *u, char *ws, const UPlan &p, hipStream_t
             gy_l = c.b(p.g_ey[l]);
         }
         TRY(gate_bwd(c.b(p.ez[l]), gy_l, w[l], 0, c.b(p.g_ez[l]), w[l], p.P[l], s));
-        const __bf16 *x = l ? c.b(p.x[l]) : c.b(p.feat);
-        TRY(ulayer_backward(L[U_ENC0 + l], c.b(p.g_ez[l]), 2 * w[l], x, cprev, c.b(p.d[l]), 8, cprev,
-                            c.b(p.g_ecat[l]), B, Hl(l), Wl(l), p, ws, s));
+        if (l)
+            TRY(ulayer_backward(L[U_ENC0 + l], c.b(p.g_ez[l]), 2 * w[l], c.b(p.x[l]), cprev, c.b(p.d[l]), 32, cprev,
+                                c.b(p.g_ecat[l]), B, Hl(l), Wl(l), p, ws, s));
+        else
+            TRY(ulayer_backward(L[U_ENC0], c.b(p.g_ez[0]), 2 * w[0], c.b(p.x0), 32, nullptr, 0, 0, c.b(p.g_ecat[0]), B,
+                                Hl(0), Wl(0), p, ws, s));
     }
     // descriptors: d_l = pool^l(d_0), so the gradient of d_0 sums every scale's
+    // (d_l sits after the cprev_l = w_{l-1} (level 0: 8) channels of x_l)
     for (int l = kLevels - 2; l >= 0; --l) {
-        const int cprev_hi = l + 1 < kLevels ? w[l] : 0;  // channels before d in level l+1's input
-        SliceArgs a = l == kLevels - 2
-                          ? uslice(c.b(p.g_ecat[l + 1]), cprev_hi + 8, cprev_hi, c.b(p.g_d[l]), 8, 0, 8, B, Hl(l), Wl(l))
-                          : uslice(c.b(p.g_d[l + 1]), 8, 0, c.b(p.g_d[l]), 8, 0, 8, B, Hl(l), Wl(l));
-        const int cprev = l ? w[l - 1] : 8;
+        SliceArgs a = l == kLevels - 2 ? uslice(c.b(p.g_ecat[l + 1]), enc_cind(w, l + 1), w[l], c.b(p.g_d[l]), 8, 0, 8,
+                                                B, Hl(l), Wl(l))
+                                       : uslice(c.b(p.g_d[l + 1]), 8, 0, c.b(p.g_d[l]), 8, 0, 8, B, Hl(l), Wl(l));
         a.in2 = c.b(p.g_ecat[l]);
-        a.in2_stride = cprev + 8;
-        a.in2_off = cprev;
+        a.in2_stride = enc_cind(w, l);
+        a.in2_off = l ? w[l - 1] : 8;
         TRY(pool2_bwd_add(a, s));
     }
-    TRY(ulayer_backward(L[U_DESC], c.b(p.g_d[0]), 8, c.b(p.feat), 8, nullptr, 0, 0, nullptr, B, p.Hp, p.Wp, p, ws, s));
+    TRY(ulayer_backward(L[U_DESC], c.b(p.g_d[0]), 8, c.b(p.x0), 32, nullptr, 0, 0, nullptr, B, p.Hp, p.Wp, p, ws, s));
     // gradient matrices -> blob order
     for (int i = 0; i < kUL; ++i) {
         const ULayer &l = L[i];
-        TRY(grad_to_blob(l.dw, l.kpad, l.cout, l.cin, l.ks, u->grad + l.blob_w, s));
+        TRY(grad_to_blob(l.dw, l.kpad, l.cout, l.cin, l.ks, u->grad + l.blob_w, s, l.cind));
         if (l.kind == K_TCONV)
             TRY(bias_grad_phases(l.db, l.nbias, u->grad + l.blob_b, s));
         else
@@ -421,11 +474,12 @@ hipError_t urefresh(narvis_unet *u, hipStream_t s)
     for (int i = 0; i < kUL; ++i) {
         ULayer &l = u->L[i];
         TRY(prep_weights(u->master + l.blob_w, l.cout, l.cin, l.ks, l.wf, l.rows, l.kpad, l.wb, l.brows, l.bcin,
-                         l.bkpad, s));
+                         l.bkpad, s, l.cind));
         if (l.kind == K_TCONV)
             TRY(bias_phases(u->master + l.blob_b, l.nbias, l.bias, s));
         else
             TRY(copy_f32(u->master + l.blob_b, l.bias, l.nbias, s));
+        if (l.kind == K_GATE3) TRY(gate_rows(l.wf, l.bias, l.rows, l.kpad, l.wg, l.bg, s));
     }
     return hipSuccess;
 }
@@ -452,7 +506,7 @@ narvis_status uloss_backward(narvis_unet *u, const float *feat, const float *tar
     if (ws_bytes < p.bytes) return NARVIS_ERR_WORKSPACE;
     char *base = static_cast<char *>(ws);
     float *y = reinterpret_cast<float *>(base + p.out);
-    hipError_t e = uforward(u, feat, base, p, y, s);
+    hipError_t e = uforward(u, feat, base, p, y, false, s);
     if (e == hipSuccess)
         e = loss(y, target, B, H, W, lam_tv, reinterpret_cast<__bf16 *>(base + p.gy),
                  reinterpret_cast<float *>(base + p.lpart), loss_out, s);
@@ -484,14 +538,17 @@ extern "C" narvis_status narvis_unet_create(const int32_t widths[5], const float
     u->nparams = count_params(widths);
     const uint64_t blob_bytes = align256((uint64_t)u->nparams * 4);
     uint64_t o = 4 * blob_bytes;
-    std::vector<uint64_t> offs(kUL * 5);
+    std::vector<uint64_t> offs(kUL * 7);
     for (int i = 0; i < kUL; ++i) {
         const ULayer &l = u->L[i];
-        offs[i * 5 + 0] = o; o = align256(o + (uint64_t)l.rows * l.kpad * 2);
-        offs[i * 5 + 1] = o; o = align256(o + (uint64_t)l.brows * l.bkpad * 2);
-        offs[i * 5 + 2] = o; o = align256(o + (uint64_t)l.rows * 4);
-        offs[i * 5 + 3] = o; o = align256(o + (uint64_t)l.rows * l.kpad * 4);
-        offs[i * 5 + 4] = o; o = align256(o + (uint64_t)l.rows * 4);
+        const bool g = l.kind == K_GATE3;
+        offs[i * 7 + 0] = o; o = align256(o + (uint64_t)l.rows * l.kpad * 2);
+        offs[i * 7 + 1] = o; o = align256(o + (uint64_t)l.brows * l.bkpad * 2);
+        offs[i * 7 + 2] = o; o = align256(o + (uint64_t)l.rows * 4);
+        offs[i * 7 + 3] = o; o = align256(o + (uint64_t)l.rows * l.kpad * 4);
+        offs[i * 7 + 4] = o; o = align256(o + (uint64_t)l.rows * 4);
+        offs[i * 7 + 5] = o; o = align256(o + (g ? (uint64_t)l.rows * l.kpad * 2 : 0));
+        offs[i * 7 + 6] = o; o = align256(o + (g ? (uint64_t)l.rows * 4 : 0));
     }
     if (hipMalloc(&u->pool, o) != hipSuccess) {
         delete u;
@@ -504,11 +561,13 @@ extern "C" narvis_status narvis_unet_create(const int32_t widths[5], const float
     u->v = reinterpret_cast<float *>(base + 3 * blob_bytes);
     for (int i = 0; i < kUL; ++i) {
         ULayer &l = u->L[i];
-        l.wf = reinterpret_cast<__bf16 *>(base + offs[i * 5 + 0]);
-        l.wb = reinterpret_cast<__bf16 *>(base + offs[i * 5 + 1]);
-        l.bias = reinterpret_cast<float *>(base + offs[i * 5 + 2]);
-        l.dw = reinterpret_cast<float *>(base + offs[i * 5 + 3]);
-        l.db = reinterpret_cast<float *>(base + offs[i * 5 + 4]);
+        l.wf = reinterpret_cast<__bf16 *>(base + offs[i * 7 + 0]);
+        l.wb = reinterpret_cast<__bf16 *>(base + offs[i * 7 + 1]);
+        l.bias = reinterpret_cast<float *>(base + offs[i * 7 + 2]);
+        l.dw = reinterpret_cast<float *>(base + offs[i * 7 + 3]);
+        l.db = reinterpret_cast<float *>(base + offs[i * 7 + 4]);
+        l.wg = l.kind == K_GATE3 ? reinterpret_cast<__bf16 *>(base + offs[i * 7 + 5]) : nullptr;
+        l.bg = l.kind == K_GATE3 ? reinterpret_cast<float *>(base + offs[i * 7 + 6]) : nullptr;
     }
     hipError_t e = hipMemset(u->pool, 0, o);
     if (e == hipSuccess) e = hipMemcpy(u->master, host_blob, count * 4, hipMemcpyHostToDevice);
@@ -557,7 +616,7 @@ extern "C" narvis_status narvis_unet_forward(const narvis_unet *u, const float *
         return NARVIS_ERR_INVALID_ARG;
     const UPlan p = make_uplan(u, B, H, W, false);
     if (ws_bytes < p.bytes) return NARVIS_ERR_WORKSPACE;
-    return ust(uforward(u, feat, static_cast<char *>(ws), p, img, static_cast<hipStream_t>(stream)));
+    return ust(uforward(u, feat, static_cast<char *>(ws), p, img, true, static_cast<hipStream_t>(stream)));
 }
 
 extern "C" narvis_status narvis_unet_gradients(narvis_unet *u, const float *feat, const float *target, int32_t B,
