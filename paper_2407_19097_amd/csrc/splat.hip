@@ -253,11 +253,11 @@ __global__ __launch_bounds__(kT) void k_splat_project(SplatArgs S)
 
 // depth keys of the point order: a culled point (no tile) sorts after every
 // kept one (kept depth bits are below 0x7F800000)
-__global__ __launch_bounds__(kT) void k_depth_keys(SplatArgs S, unsigned long long *keys, uint32_t *vals)
+__global__ __launch_bounds__(kT) void k_depth_keys(SplatArgs S, uint32_t *keys, uint32_t *vals)
 {
     const uint64_t i = (uint64_t)blockIdx.x * kT + threadIdx.x;
     if (i >= S.n) return;
-    keys[i] = S.cnt[i] ? S.wbits[i] : 0xFFFFFFFFull;
+    keys[i] = S.cnt[i] ? S.wbits[i] : 0xFFFFFFFFu;
     vals[i] = (uint32_t)i;
 }
 
@@ -272,7 +272,7 @@ __global__ __launch_bounds__(kT) void k_gather_counts(const uint32_t *cnt, const
 
 // sorted position j: the pairs of point order[j] at [scnt[j], scnt[j + 1])
 __global__ __launch_bounds__(kT) void k_splat_emit(SplatArgs S, const uint32_t *order, const uint32_t *scnt,
-                                                   unsigned long long *keys, uint32_t *vals)
+                                                   uint32_t *keys, uint32_t *vals)
 {
     const uint64_t j = (uint64_t)blockIdx.x * kT + threadIdx.x;
     if (j >= S.n) return;
@@ -288,7 +288,7 @@ __global__ __launch_bounds__(kT) void k_splat_emit(SplatArgs S, const uint32_t *
     for (int ty = ty0; ty <= ty1; ++ty)
         for (int tx = tx0; tx <= tx1; ++tx, ++o) {
             if (o >= stop || o >= S.cap) return;  // the count bounds the rectangle; guard anyway
-            keys[o] = (unsigned long long)(uint32_t)(ty * S.tiles_x + tx);
+            keys[o] = (uint32_t)(ty * S.tiles_x + tx);
             vals[o] = i;
         }
 }
@@ -383,8 +383,9 @@ __global__ __launch_bounds__(kT) void k_scan_apply(const uint32_t *in, uint32_t 
 // stable LSD radix sort, 8-bit digits, 4096 elements per workgroup
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kT) void k_radix_hist(const unsigned long long *keys, const uint32_t *count, uint64_t cap,
-                                                   int shift, uint32_t *hist, uint32_t nblk)
+template <typename K>
+__global__ __launch_bounds__(kT) void k_radix_hist(const K *keys, const uint32_t *count, uint64_t cap, int shift,
+                                                   uint32_t *hist, uint32_t nblk)
 {
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
@@ -410,13 +411,14 @@ __global__ __launch_bounds__(kT) void k_radix_hist(const unsigned long long *key
 // (ballot match on the 8 digit bits).  The per-wave counts are then combined
 // into block offsets, the block is reordered in LDS, and written out with
 // consecutive threads on consecutive destinations.
-__global__ __launch_bounds__(kT) void k_radix_scatter(const unsigned long long *kin, const uint32_t *vin,
-                                                      unsigned long long *kout, uint32_t *vout, const uint32_t *count,
-                                                      uint64_t cap, int shift, const uint32_t *offs, uint32_t nblk)
+template <typename K>
+__global__ __launch_bounds__(kT) void k_radix_scatter(const K *kin, const uint32_t *vin, K *kout, uint32_t *vout,
+                                                      const uint32_t *count, uint64_t cap, int shift,
+                                                      const uint32_t *offs, uint32_t nblk)
 {
     constexpr int NW = kT / 64;
     constexpr int PER_WAVE = kScanTile / NW;
-    __shared__ unsigned long long skey[kScanTile];
+    __shared__ K skey[kScanTile];
     __shared__ uint32_t sval[kScanTile];
     __shared__ uint32_t wcnt[NW][256];  // running digit counts of each wave, then each wave's offset
     __shared__ uint32_t bstart[256];
@@ -427,13 +429,13 @@ __global__ __launch_bounds__(kT) void k_radix_scatter(const unsigned long long *
     if (base >= N) return;  // uniform for the workgroup
 #pragma unroll
     for (int w = 0; w < NW; ++w) wcnt[w][threadIdx.x] = 0u;
-    unsigned long long k[kScanItems];
+    K k[kScanItems];
     uint32_t v[kScanItems], rank[kScanItems], dig[kScanItems];
 #pragma unroll
     for (int r = 0; r < kScanItems; ++r) {
         const uint64_t e = base + (uint64_t)wid * PER_WAVE + (uint64_t)r * 64 + lane;
         const bool ok = e < N;
-        k[r] = ok ? kin[e] : 0ull;
+        k[r] = ok ? kin[e] : (K)0;
         v[r] = ok ? vin[e] : 0u;
         dig[r] = ok ? ((uint32_t)(k[r] >> shift) & 255u) : 256u;
     }
@@ -482,7 +484,7 @@ __global__ __launch_bounds__(kT) void k_radix_scatter(const unsigned long long *
     __syncthreads();
     const uint32_t inblock = (uint32_t)min((uint64_t)kScanTile, N - base);
     for (uint32_t i = threadIdx.x; i < inblock; i += kT) {
-        const unsigned long long key = skey[i];
+        const K key = skey[i];
         const uint32_t d = (uint32_t)(key >> shift) & 255u;
         const uint64_t dst = (uint64_t)offs[(uint64_t)d * nblk + blockIdx.x] + (i - bstart[d]);
         if (dst < N) {  // always true for a consistent histogram; guards the buffer regardless
@@ -502,16 +504,16 @@ __global__ __launch_bounds__(kT) void k_fill_u32(uint32_t *p, uint64_t cnt, uint
     if (i < cnt) p[i] = v;
 }
 
-__global__ __launch_bounds__(kT) void k_tile_ranges(const unsigned long long *keys, const uint32_t *count, uint64_t cap,
+__global__ __launch_bounds__(kT) void k_tile_ranges(const uint32_t *keys, const uint32_t *count, uint64_t cap,
                                                     uint32_t *range, uint32_t ntiles)
 {
     const uint64_t p = (uint64_t)blockIdx.x * kT + threadIdx.x;
     const uint64_t N = min((uint64_t)*count, cap);
     if (p >= N) return;
-    const uint32_t t = (uint32_t)keys[p];
+    const uint32_t t = keys[p];
     if (t >= ntiles) return;
-    if (p == 0 || (uint32_t)keys[p - 1] != t) range[2 * t] = (uint32_t)p;
-    if (p + 1 == N || (uint32_t)keys[p + 1] != t) range[2 * t + 1] = (uint32_t)(p + 1);
+    if (p == 0 || keys[p - 1] != t) range[2 * t] = (uint32_t)p;
+    if (p + 1 == N || keys[p + 1] != t) range[2 * t + 1] = (uint32_t)(p + 1);
 }
 
 struct BlendArgs {
@@ -635,9 +637,9 @@ SplatLayout splat_layout(uint64_t n, int32_t W, int32_t H, float sigma, bool ani
     L.off_col = o; o = align256(o + n * sizeof(float4));
     L.off_wbits = o; o = align256(o + n * 4);
     L.off_cnt = o; o = align256(o + (n + 1) * 4);
-    L.off_ka = o; o = align256(o + elems * 8);
+    L.off_ka = o; o = align256(o + elems * 4);
     L.off_va = o; o = align256(o + elems * 4);
-    L.off_kb = o; o = align256(o + elems * 8);
+    L.off_kb = o; o = align256(o + elems * 4);
     L.off_vb = o; o = align256(o + elems * 4);
     L.off_scnt = o; o = align256(o + (n + 1) * 4);
     L.off_npts = o; o = align256(o + 4);
@@ -720,23 +722,30 @@ hipError_t launch_splat_count(const float *x, const float *y, const float *z, ui
     return hipSuccess;
 }
 
-hipError_t launch_radix_sort(unsigned long long *ka, uint32_t *va, unsigned long long *kb, uint32_t *vb,
-                             const uint32_t *count, uint64_t cap, int key_bits, uint32_t *hist, uint32_t *sums,
-                             hipStream_t s, bool *in_b)
+template <typename K>
+static hipError_t radix_sort(K *ka, uint32_t *va, K *kb, uint32_t *vb, const uint32_t *count, uint64_t cap,
+                             int key_bits, uint32_t *hist, uint32_t *sums, hipStream_t s, bool *in_b)
 {
     const uint64_t nblk64 = (cap + kScanTile - 1) / kScanTile;
     const uint32_t nblk = (uint32_t)(nblk64 ? nblk64 : 1);
     bool b = false;
     for (int shift = 0; shift < key_bits; shift += 8) {
-        hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kT), 0, s, b ? kb : ka, count, cap, shift, hist, nblk);
+        hipLaunchKernelGGL(k_radix_hist<K>, dim3(nblk), dim3(kT), 0, s, b ? kb : ka, count, cap, shift, hist, nblk);
         const hipError_t e = scan_excl(hist, hist, (uint64_t)nblk * 256, sums, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(kT), 0, s, b ? kb : ka, b ? vb : va, b ? ka : kb,
+        hipLaunchKernelGGL(k_radix_scatter<K>, dim3(nblk), dim3(kT), 0, s, b ? kb : ka, b ? vb : va, b ? ka : kb,
                            b ? va : vb, count, cap, shift, hist, nblk);
         b = !b;
     }
     *in_b = b;
     return hipGetLastError();
+}
+
+hipError_t launch_radix_sort(unsigned long long *ka, uint32_t *va, unsigned long long *kb, uint32_t *vb,
+                             const uint32_t *count, uint64_t cap, int key_bits, uint32_t *hist, uint32_t *sums,
+                             hipStream_t s, bool *in_b)
+{
+    return radix_sort(ka, va, kb, vb, count, cap, key_bits, hist, sums, s, in_b);
 }
 
 uint64_t radix_sort_hist_len(uint64_t cap)
@@ -782,8 +791,8 @@ hipError_t launch_splat(const float *x, const float *y, const float *z, uint64_t
     S.focal = prm.focal_px;
     S.conic = reinterpret_cast<float4 *>(base + L.off_conic);
     S.ext = reinterpret_cast<float2 *>(base + L.off_ext);
-    auto *ka = reinterpret_cast<unsigned long long *>(base + L.off_ka);
-    auto *kb = reinterpret_cast<unsigned long long *>(base + L.off_kb);
+    auto *ka = reinterpret_cast<uint32_t *>(base + L.off_ka);
+    auto *kb = reinterpret_cast<uint32_t *>(base + L.off_kb);
     auto *va = reinterpret_cast<uint32_t *>(base + L.off_va);
     auto *vb = reinterpret_cast<uint32_t *>(base + L.off_vb);
     auto *hist = reinterpret_cast<uint32_t *>(base + L.off_hist);
@@ -802,10 +811,10 @@ hipError_t launch_splat(const float *x, const float *y, const float *z, uint64_t
         hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kT), 0, s, npts, (uint64_t)1, (uint32_t)n);
         hipLaunchKernelGGL(k_depth_keys, dim3((unsigned)((n + kT - 1) / kT)), dim3(kT), 0, s, S, ka, va);
         bool in_b = false;
-        e = launch_radix_sort(ka, va, kb, vb, npts, n, 32, hist, sums, s, &in_b);
+        e = radix_sort(ka, va, kb, vb, npts, n, 32, hist, sums, s, &in_b);
         if (e != hipSuccess) return e;
         const uint32_t *order = in_b ? vb : va;
-        unsigned long long *pk = in_b ? ka : kb;  // the free pair of arrays
+        uint32_t *pk = in_b ? ka : kb;  // the free pair of arrays
         uint32_t *pv = in_b ? va : vb;
         hipLaunchKernelGGL(k_gather_counts, dim3((unsigned)((n + 1 + kT - 1) / kT)), dim3(kT), 0, s, S.cnt, order, n,
                            scnt);
@@ -813,9 +822,9 @@ hipError_t launch_splat(const float *x, const float *y, const float *z, uint64_t
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_splat_emit, dim3((unsigned)((n + kT - 1) / kT)), dim3(kT), 0, s, S, order, scnt, pk, pv);
         // pairs by tile, stable (depth order kept within a tile)
-        unsigned long long *qk = in_b ? kb : ka;
+        uint32_t *qk = in_b ? kb : ka;
         uint32_t *qv = in_b ? vb : va;
-        e = launch_radix_sort(pk, pv, qk, qv, total, L.cap, L.key_bits, hist, sums, s, &in_b);
+        e = radix_sort(pk, pv, qk, qv, total, L.cap, L.key_bits, hist, sums, s, &in_b);
         if (e != hipSuccess) return e;
         ka = in_b ? qk : pk;
         va = in_b ? qv : pv;
