@@ -143,14 +143,16 @@ def cpu_baseline(sc, cams, budget_s=10.0):
                       f"(depth, attributes), {dtm:.1f} s; single thread: first {S} points of frame 0, {dt1:.1f} s"}
 
 
-def frame_section(torch, log_fn, frames=12, train_views=2000, train_steps=2500):
+def frame_section(torch, log_fn, frames=12, train_views=2000, train_steps=2500, unet_steps=1500):
     """1080p frame of the vector-field orbit: raster G-buffer + BF16 network
-    vs the Gaussian splat.  The network is first trained by the library's own
-    kernels on the 9:1 training split of 2000 hemisphere views at 512 x 512
-    (not timed)."""
+    vs the Gaussian splat.  The network and the paper's gated U-Net are first
+    trained by the library's own kernels on the 9:1 training split of 2000
+    hemisphere views at 512 x 512 (not timed)."""
     from paper_2407_19097_amd import metrics, narvis, scenes, train
     sc = scenes.vector_field(device="cuda")
-    w, cal, heldout, train_s, losses = train.train_c4(sc, views=train_views, steps=train_steps, log=log_fn)
+    c4 = train.train_c4(sc, views=train_views, steps=train_steps, log=log_fn, unet_steps=unet_steps)
+    u = c4.unet
+    w, cal, heldout, train_s, losses = c4.weights, c4.cal, c4.heldout, c4.secs, c4.losses
     ntr = train_views - len(heldout)
     # training step throughput: 10 timed steps on a fixed batch of 16 views
     # (a separate, freshly initialised parameter set, so the trained one is
@@ -200,9 +202,13 @@ def frame_section(torch, log_fn, frames=12, train_views=2000, train_steps=2500):
     bf16 = lambda out: narvis.narvis_postprocess(w, feat, 1, W, H, out, ws, stream=stream)
     fp8 = lambda out: narvis.narvis_postprocess(w, feat, 1, W, H, out, ws, precision=narvis.PRECISION_FP8,
                                                 stream=stream)
+    uws = torch.empty(narvis.narvis_unet_workspace_size(u, 1, W, H), dtype=torch.uint8, device="cuda")
+    uimg = torch.empty_like(img)
+    unet = lambda out: narvis.narvis_unet_forward(u, feat, 1, W, H, out, uws, stream=stream)
+    t_u, p_u, s_u = [], [], []
     # the frame loop as a viewer runs it (G-buffer, network, next frame), once
     # with the BF16 and once with the FP8 network; the first frame warms up
-    for net, t_net in ((bf16, t_n), (fp8, t_n8)):
+    for net, t_net in ((bf16, t_n), (fp8, t_n8), (unet, t_u)):
         evs = []
         for k in [picks[0]] + picks:
             evs.append((timed(lambda: r.gbuffer(sc.cameras[k], feat[0], hint=True)), timed(lambda: net(img))))
@@ -217,6 +223,7 @@ def frame_section(torch, log_fn, frames=12, train_views=2000, train_steps=2500):
         r.gbuffer(cam, feat[0])
         bf16(img)
         fp8(img8)
+        unet(uimg)
         sp = timed(lambda: r.splat(cam, tgt))
         torch.cuda.synchronize()
         if rep == 0:
@@ -225,6 +232,8 @@ def frame_section(torch, log_fn, frames=12, train_views=2000, train_steps=2500):
         t3 = tgt.view(1, 3, H, W)
         y = img
         p_net8.append(metrics.psnr(img8, t3).item())
+        p_u.append(metrics.psnr(uimg, t3).item())
+        s_u.append(metrics.ssim(uimg, t3).item())
         p_net.append(metrics.psnr(y, t3).item())
         p_ras.append(metrics.psnr(feat[:, 0:3].view(1, 3, H, W), t3).item())
         s_net.append(metrics.ssim(y, t3).item())
@@ -250,8 +259,9 @@ def frame_section(torch, log_fn, frames=12, train_views=2000, train_steps=2500):
     ta = [timed(aimg) for _ in range(3)]
     torch.cuda.synchronize()
     aniso_ms = float(np.mean([a.elapsed_time(b) for a, b in ta]))
-    del aws
+    del aws, uws
     w.close()
+    u.close()
     m = lambda xs: float(np.mean(xs))
     raster_ms, net_ms, splat_ms = m(t_r), m(t_n), m(t_s)
     net_gflop = 327360.0 * W * H / 1e9
@@ -270,7 +280,14 @@ def frame_section(torch, log_fn, frames=12, train_views=2000, train_steps=2500):
             "net_fp8_ms": round(m(t_n8), 4), "frame_fp8_ms": round(raster_ms + m(t_n8), 4),
             "psnr_fp8_db": round(m(p_net8), 3), "fp8_layers": fp8_layers,
             "splat_aniso_ms": round(aniso_ms, 3), "splat_aniso_pairs": apairs,
-            "splat_aniso": "Gaussians elongated along the velocity, s = 300, first frame"}
+            "splat_aniso": "Gaussians elongated along the velocity, s = 300, first frame",
+            "unet": {"network": "the paper's gated U-Net, widths 64-128-256-512-1024, descriptors at 5 scales",
+                     "train": f"{unet_steps} Adam steps of batch 16 on the same views ({c4.unet_secs:.0f} s, loss "
+                              f"{c4.unet_losses[0][1]:.5f} -> {c4.unet_losses[-1][1]:.5f})",
+                     "net_ms": round(m(t_u), 4), "frame_ms": round(raster_ms + m(t_u), 4),
+                     "frame_fraction_of_splat": round((raster_ms + m(t_u)) / splat_ms, 4),
+                     "tflops": round(unet_flop_per_px(narvis.UNET_WIDTHS) * W * 1088 / 1e12 / (m(t_u) / 1e3), 1),
+                     "psnr_db": round(m(p_u), 3), "ssim": round(m(s_u), 4)}}
 
 
 def splat_section(torch, log_fn, frames):
@@ -388,6 +405,7 @@ def main():
     ap.add_argument("--frame-only", action="store_true",
                     help="run only the 1080p frame section (for profiling the network kernels)")
     ap.add_argument("--train-steps", type=int, default=2500, help="Adam steps of the frame section's training")
+    ap.add_argument("--unet-steps", type=int, default=1500, help="Adam steps of the frame section's U-Net training")
     ap.add_argument("--splat-only", action="store_true",
                     help="only time the Gaussian splat (isotropic and anisotropic) of vector-field frames at 1920x1080 "
                          "(for profiling the splat kernels)")
@@ -407,7 +425,8 @@ def main():
     from paper_2407_19097_amd import narvis, scenes
 
     if args.frame_only:
-        print(json.dumps({"frame_1080p": frame_section(torch, log, train_steps=args.train_steps)}), flush=True)
+        print(json.dumps({"frame_1080p": frame_section(torch, log, train_steps=args.train_steps,
+                                                       unet_steps=args.unet_steps)}), flush=True)
         return
     if args.unet_only:
         print(json.dumps({"unet": unet_section(torch, log)}), flush=True)
@@ -691,7 +710,7 @@ def main():
                                    "net_tflops": round(327360.0 * W * H / (net_ms / 1e3) / 1e12, 1)}
     if not args.no_frame:
         log("1080p frame section: training the network, then raster + network vs splat")
-        out["frame_1080p"] = frame_section(torch, log, train_steps=args.train_steps)
+        out["frame_1080p"] = frame_section(torch, log, train_steps=args.train_steps, unet_steps=args.unet_steps)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline(sc, cams)

@@ -181,11 +181,22 @@ def c4_views(n: int = 2000, seed: int = 4) -> List[scenes.Camera]:
     return hemisphere_views(n, C2_CENTRE, 0.75 * C2_DIAG, seed=seed)
 
 
-def train_c4(sc: scenes.Scene, views: int = 2000, steps: int = 2500, res: int = 512, seed: int = 0, log=print):
+class C4:
+    """What train_c4 returns: the trained small network (`weights`), 16
+    training views' inputs for FP8 calibration (`cal`), the held-out cameras,
+    training seconds and loss log, and, when asked for, the trained gated
+    U-Net with its own seconds and loss log."""
+
+    def __init__(self, **kw):
+        self.__dict__.update(kw)
+
+
+def train_c4(sc: scenes.Scene, views: int = 2000, steps: int = 2500, res: int = 512, seed: int = 0, log=print,
+             unet_steps: int = 0, unet_lr: float = 1e-3) -> C4:
     """Train the post-process on the 9:1 training split of `views` hemisphere
     views of `sc` at res x res (G-buffer input, splat target), Adam lr 1e-3,
-    batch 16, lam_tv 1e-3.  Returns (weights, 16 training views' inputs for
-    FP8 calibration, the held-out cameras, training seconds, loss log)."""
+    batch 16, lam_tv 1e-3; with unet_steps > 0 the paper's gated U-Net is
+    trained on the same views too (Adam lr unet_lr, batch 16)."""
     import torch
     cams = c4_views(views)
     ntr = int(0.9 * views)
@@ -194,10 +205,16 @@ def train_c4(sc: scenes.Scene, views: int = 2000, steps: int = 2500, res: int = 
     w = narvis.NetWeights(init_blob(seed))
     losses, secs = train(w, feats, targets, steps, batch=16, lr=1e-3, lam_tv=1e-3, seed=seed, log=log,
                          log_every=500)
-    cal = feats[:16].clone()
+    out = C4(weights=w, heldout=cams[ntr:], secs=secs, losses=losses, unet=None, unet_secs=0.0, unet_losses=[])
+    if unet_steps > 0:
+        u = narvis.UNet(unet_init_blob(seed))
+        out.unet = u
+        out.unet_losses, out.unet_secs = train(u, feats, targets, unet_steps, batch=16, lr=unet_lr, lam_tv=1e-3,
+                                               seed=seed, log=log, log_every=250)
+    out.cal = feats[:16].clone()
     del feats, targets, r
     torch.cuda.empty_cache()
-    return w, cal, cams[ntr:], secs, losses
+    return out
 
 
 def evaluate(weights, feats, targets, chunk=8):

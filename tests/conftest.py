@@ -18,18 +18,22 @@ def c4_net():
     """The post-process trained on the GPU by the library's own kernels: 1800
     hemisphere views of the 50M-point vector field at 512 x 512 (the 9:1
     training split of 2000), splat targets with sigma 1.5 px, 2500 Adam steps
-    of batch 16.  Yields the scene, the weights, 16 training views' inputs
-    (FP8 calibration) and the 200 held-out cameras."""
+    of batch 16; the paper's gated U-Net on the same views, 1500 steps.
+    Yields the scene, both networks, 16 training views' inputs (FP8
+    calibration) and the 200 held-out cameras."""
     import time
     torch = pytest.importorskip("torch")
     from paper_2407_19097_amd import scenes, train
     log = lambda m: print(f"  [c4] {m}", flush=True)
-    print("\n[fixture] training the post-process: 1800 views of the vector field at 512x512, 2500 steps", flush=True)
+    print("\n[fixture] training the post-process (2500 steps) and the gated U-Net (1500 steps): 1800 views of the "
+          "vector field at 512x512", flush=True)
     t0 = time.time()
     sc = scenes.vector_field(device="cuda")
-    w, cal, heldout, secs, losses = train.train_c4(sc, log=log)
-    log(f"done in {time.time() - t0:.0f} s (training {secs:.0f} s)")
-    yield {"scene": sc, "weights": w, "cal": cal, "heldout": heldout, "losses": losses}
-    w.close()
-    del sc, cal
+    c4 = train.train_c4(sc, log=log, unet_steps=1500)
+    log(f"done in {time.time() - t0:.0f} s (training {c4.secs:.0f} s + {c4.unet_secs:.0f} s)")
+    yield {"scene": sc, "weights": c4.weights, "cal": c4.cal, "heldout": c4.heldout, "losses": c4.losses,
+           "unet": c4.unet, "unet_losses": c4.unet_losses}
+    c4.weights.close()
+    c4.unet.close()
+    del sc, c4
     torch.cuda.empty_cache()

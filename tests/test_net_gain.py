@@ -6,7 +6,9 @@ backward kernels on the 9:1 training split of 2000 hemisphere views of the
 1e-3, batch 16; the shared `c4_net` fixture) and evaluated at 1920 x 1080 on
 the 200 held-out views.  The baseline is the rasterizer's RGB G-buffer alone
 (points as pixels), the analogue of the paper's CR row.  Pass: the network
-is at least 3 dB better and reaches 30 dB PSNR against the splat."""
+is at least 3 dB better and reaches 30 dB PSNR against the splat.  The
+paper's own gated U-Net, trained on the same views (1500 steps), must pass
+the same bar."""
 import numpy as np
 import pytest
 
@@ -27,23 +29,33 @@ def test_trained_network_beats_raster_rgb_1080p(c4_net):
     img = torch.empty((1, 3, H, W), dtype=torch.float32, device="cuda")
     tgt = torch.empty((3, H * W), dtype=torch.float32, device="cuda")
     ws = torch.empty(narvis.narvis_postprocess_workspace_size(1, W, H), dtype=torch.uint8, device="cuda")
-    p_net, p_ras, s_net, s_ras = [], [], [], []
+    u = c4_net["unet"]
+    uws = torch.empty(narvis.narvis_unet_workspace_size(u, 1, W, H), dtype=torch.uint8, device="cuda")
+    uimg = torch.empty_like(img)
+    p_net, p_ras, s_net, s_ras, p_u, s_u = [], [], [], [], [], []
     for i, cam in enumerate(c4_net["heldout"]):
         r.gbuffer(cam, feat)
         narvis.narvis_postprocess(w, feat.view(1, 8, H * W), 1, W, H, img, ws)
+        narvis.narvis_unet_forward(u, feat.view(1, 8, H * W), 1, W, H, uimg, uws)
         r.splat(cam, tgt)
         t3 = tgt.view(1, 3, H, W)
         ras = feat[0:3].view(1, 3, H, W)
         p_net.append(metrics.psnr(img, t3).item())
         p_ras.append(metrics.psnr(ras, t3).item())
+        p_u.append(metrics.psnr(uimg, t3).item())
         s_net.append(metrics.ssim(img, t3).item())
         s_ras.append(metrics.ssim(ras, t3).item())
+        s_u.append(metrics.ssim(uimg, t3).item())
         if (i + 1) % 50 == 0:
-            print(f"  {i + 1} views: PSNR net {np.mean(p_net):.2f} raster {np.mean(p_ras):.2f}", flush=True)
-    pn, pr, sn, sr = (float(np.mean(v)) for v in (p_net, p_ras, s_net, s_ras))
-    print(f"  PSNR net {pn:.2f} dB vs raster RGB {pr:.2f} dB; SSIM {sn:.4f} vs {sr:.4f} "
-          f"(worst view: net {min(p_net):.2f} dB)", flush=True)
+            print(f"  {i + 1} views: PSNR net {np.mean(p_net):.2f} U-Net {np.mean(p_u):.2f} raster {np.mean(p_ras):.2f}",
+                  flush=True)
+    pn, pr, sn, sr, pu, su = (float(np.mean(v)) for v in (p_net, p_ras, s_net, s_ras, p_u, s_u))
+    print(f"  PSNR net {pn:.2f} dB, gated U-Net {pu:.2f} dB vs raster RGB {pr:.2f} dB; SSIM {sn:.4f}, {su:.4f} vs "
+          f"{sr:.4f} (worst view: net {min(p_net):.2f} dB, U-Net {min(p_u):.2f} dB)", flush=True)
     assert len(p_net) == 200
     assert c4_net["losses"][-1][1] < c4_net["losses"][0][1]
+    assert c4_net["unet_losses"][-1][1] < c4_net["unet_losses"][0][1]
     assert pn >= pr + 3.0
     assert pn >= 30.0
+    assert pu >= pr + 3.0
+    assert pu >= 30.0
