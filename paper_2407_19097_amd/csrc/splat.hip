@@ -509,11 +509,16 @@ __global__ __launch_bounds__(kT) void k_tile_ranges(const uint32_t *keys, const 
 {
     const uint64_t p = (uint64_t)blockIdx.x * kT + threadIdx.x;
     const uint64_t N = min((uint64_t)*count, cap);
-    if (p >= N) return;
-    const uint32_t t = keys[p];
-    if (t >= ntiles) return;
-    if (p == 0 || keys[p - 1] != t) range[2 * t] = (uint32_t)p;
-    if (p + 1 == N || keys[p + 1] != t) range[2 * t + 1] = (uint32_t)(p + 1);
+    if ((uint64_t)blockIdx.x * kT >= N) return;  // uniform for the workgroup
+    // neighbours from the adjacent lanes; the wave's end lanes read their own
+    const int lane = threadIdx.x & 63;
+    const uint32_t t = p < N ? keys[p] : 0xFFFFFFFFu;
+    uint32_t prev = __shfl_up(t, 1), next = __shfl_down(t, 1);
+    if (lane == 0) prev = p > 0 && p - 1 < N ? keys[p - 1] : 0xFFFFFFFFu;
+    if (lane == 63) next = p + 1 < N ? keys[p + 1] : 0xFFFFFFFFu;
+    if (p >= N || t >= ntiles) return;
+    if (p == 0 || prev != t) range[2 * t] = (uint32_t)p;
+    if (p + 1 == N || next != t) range[2 * t + 1] = (uint32_t)(p + 1);
 }
 
 struct BlendArgs {
