@@ -514,7 +514,9 @@ narvis_status narvis_splat_pair_count(const void *workspace, size_t ws_bytes, ui
 typedef enum { NARVIS_PRECISION_BF16 = 0, NARVIS_PRECISION_FP8 = 1 } narvis_precision;
 
 /* Opaque, library-owned network parameters on the device that was current
- * at creation (fp32 master copy, bf16 working copies, Adam moments). */
+ * at creation (fp32 master copy, bf16 working copies, Adam moments).  Every
+ * call that runs the network must be made with that device current
+ * (INVALID_ARG otherwise). */
 typedef struct narvis_weights narvis_weights;
 
 /* Number of floats in the parameter blob. */
@@ -633,6 +635,9 @@ narvis_status narvis_train_tensor(int32_t B, int32_t W, int32_t H, const char *n
  * 0) and the top-left H x W of its output is returned.  Training frames are
  * whole multiples of 16.  Activations bf16 NHWC, fp32 accumulation.
  * Training: the loss and Adam of narvis_train_step.
+ * Parameters live on the device current at narvis_unet_create; the forward
+ * and training calls must be made with that device current (INVALID_ARG
+ * otherwise).
  * ------------------------------------------------------------------------ */
 typedef struct narvis_unet narvis_unet;
 

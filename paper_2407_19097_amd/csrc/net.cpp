@@ -498,6 +498,13 @@ bool dims_ok(int B, int W, int H)
 
 narvis_status st(hipError_t e) { return e == hipSuccess ? NARVIS_OK : NARVIS_ERR_DEVICE; }
 
+// the handle's device must be the current one (its buffers live there)
+bool on_device(int dev)
+{
+    int cur = -1;
+    return hipGetDevice(&cur) == hipSuccess && cur == dev;
+}
+
 }  // namespace
 
 extern "C" size_t narvis_net_param_count(void) { return (size_t)param_count(); }
@@ -610,7 +617,7 @@ extern "C" size_t narvis_postprocess_workspace_size(int32_t B, int32_t W, int32_
 extern "C" narvis_status narvis_postprocess(const narvis_weights *w, const float *feat, int32_t B, int32_t W, int32_t H,
                                             float *img, int32_t precision, void *ws, size_t ws_bytes, void *stream)
 {
-    if (!w || !feat || !img || !ws || !dims_ok(B, W, H)) return NARVIS_ERR_INVALID_ARG;
+    if (!w || !feat || !img || !ws || !dims_ok(B, W, H) || !on_device(w->device)) return NARVIS_ERR_INVALID_ARG;
     if (precision != NARVIS_PRECISION_BF16 && precision != NARVIS_PRECISION_FP8) return NARVIS_ERR_INVALID_ARG;
     if (precision == NARVIS_PRECISION_FP8 && !w->fp8_ready) return NARVIS_ERR_UNSUPPORTED;
     if ((reinterpret_cast<uintptr_t>(ws) & 255u) || (reinterpret_cast<uintptr_t>(feat) & 3u) ||
@@ -635,7 +642,7 @@ narvis_status train_common(narvis_weights *w, const float *feat, const float *ta
 {
     if (!w || !feat || !target || !loss_out || !ws || !dims_ok(B, W, H) || !std::isfinite(lam_tv) || lam_tv < 0)
         return NARVIS_ERR_INVALID_ARG;
-    if (reinterpret_cast<uintptr_t>(ws) & 255u) return NARVIS_ERR_INVALID_ARG;
+    if ((reinterpret_cast<uintptr_t>(ws) & 255u) || !on_device(w->device)) return NARVIS_ERR_INVALID_ARG;
     p = make_plan(B, H, W, true);
     if (ws_bytes < p.bytes) return NARVIS_ERR_WORKSPACE;
     char *base = static_cast<char *>(ws);
@@ -740,7 +747,7 @@ constexpr float kFp8Budget = 0.025f;
 extern "C" narvis_status narvis_weights_calibrate_fp8(narvis_weights *w, const float *feat, int32_t B, int32_t W,
                                                       int32_t H, void *ws, size_t ws_bytes, void *stream)
 {
-    if (!w || !feat || !ws || !dims_ok(B, W, H) || (reinterpret_cast<uintptr_t>(ws) & 255u))
+    if (!w || !feat || !ws || !dims_ok(B, W, H) || (reinterpret_cast<uintptr_t>(ws) & 255u) || !on_device(w->device))
         return NARVIS_ERR_INVALID_ARG;
     const Plan p = make_plan(B, H, W, true);
     if (ws_bytes < p.bytes) return NARVIS_ERR_WORKSPACE;

@@ -495,13 +495,20 @@ bool udims_ok(int B, int W, int H, bool train)
 
 narvis_status ust(hipError_t e) { return e == hipSuccess ? NARVIS_OK : NARVIS_ERR_DEVICE; }
 
+// the handle's device must be the current one (its buffers live there)
+bool u_on_device(const narvis_unet *u)
+{
+    int cur = -1;
+    return hipGetDevice(&cur) == hipSuccess && cur == u->device;
+}
+
 narvis_status uloss_backward(narvis_unet *u, const float *feat, const float *target, int32_t B, int32_t W, int32_t H,
                              float lam_tv, float *loss_out, void *ws, size_t ws_bytes, hipStream_t s)
 {
     if (!u || !feat || !target || !loss_out || !ws || !udims_ok(B, W, H, true) || !std::isfinite(lam_tv) ||
         lam_tv < 0)
         return NARVIS_ERR_INVALID_ARG;
-    if (reinterpret_cast<uintptr_t>(ws) & 255u) return NARVIS_ERR_INVALID_ARG;
+    if ((reinterpret_cast<uintptr_t>(ws) & 255u) || !u_on_device(u)) return NARVIS_ERR_INVALID_ARG;
     const UPlan p = make_uplan(u, B, H, W, true);
     if (ws_bytes < p.bytes) return NARVIS_ERR_WORKSPACE;
     char *base = static_cast<char *>(ws);
@@ -610,7 +617,7 @@ extern "C" size_t narvis_unet_workspace_size(const narvis_unet *u, int32_t B, in
 extern "C" narvis_status narvis_unet_forward(const narvis_unet *u, const float *feat, int32_t B, int32_t W, int32_t H,
                                              float *img, void *ws, size_t ws_bytes, void *stream)
 {
-    if (!u || !feat || !img || !ws || !udims_ok(B, W, H, false)) return NARVIS_ERR_INVALID_ARG;
+    if (!u || !feat || !img || !ws || !udims_ok(B, W, H, false) || !u_on_device(u)) return NARVIS_ERR_INVALID_ARG;
     if ((reinterpret_cast<uintptr_t>(ws) & 255u) || (reinterpret_cast<uintptr_t>(feat) & 3u) ||
         (reinterpret_cast<uintptr_t>(img) & 3u))
         return NARVIS_ERR_INVALID_ARG;

@@ -118,3 +118,46 @@ def test_unet_training_lowers_the_loss():
     assert all(np.isfinite(losses))
     assert losses[-1] < 0.5 * losses[0]
     u.close()
+
+
+@pytest.mark.timeout(600)
+def test_unet_trained_forward_1080p(c4_net):
+    """The gated U-Net trained by the shared fixture, on a held-out view at
+    1920 x 1080: the GPU runs the whole frame; the FP64 oracle runs the three
+    256 x 256 crops (origins on a 64-pixel grid, so on the 16-pixel pooling
+    grid) whose centres hold the most covered pixels, and the centre 64 x 64
+    of each is compared.  A changed input pixel moves outputs up to 47 pixels
+    away (measured on the oracle for a pixel at the start of a 16-pixel
+    block; at most 15 more elsewhere in the block), less than the 96-pixel
+    margin, so those outputs see no crop border."""
+    from paper_2407_19097_amd import train
+    announce("trained gated U-Net, held-out view at 1920x1080 vs the FP64 oracle on the three most covered "
+             "256x256 crops")
+    sc, u = c4_net["scene"], c4_net["unet"]
+    W, H = 1920, 1080
+    r = train.Renderer(sc, W, H)
+    feat = torch.empty((8, H * W), dtype=torch.float32, device="cuda")
+    r.gbuffer(c4_net["heldout"][0], feat)
+    img = torch.empty((1, 3, H, W), dtype=torch.float32, device="cuda")
+    ws = torch.empty(narvis.narvis_unet_workspace_size(u, 1, W, H), dtype=torch.uint8, device="cuda")
+    narvis.narvis_unet_forward(u, feat.view(1, 8, H * W), 1, W, H, img, ws)
+    torch.cuda.synchronize()
+    planes = feat.view(1, 8, H, W).cpu().numpy()
+    got = img.cpu().numpy().astype(np.float64)
+    P = ounet.from_blob(u.read().astype(np.float64), ounet.WIDTHS)
+    # the three crops (origins on a 64-pixel grid) whose compared centres hold
+    # the most covered pixels
+    cov = planes[0, 3] > 0
+    cands = [(int(cov[y + 96:y + 160, x + 96:x + 160].sum()), y, x)
+             for y in range(0, H - 256 + 1, 64) for x in range(0, W - 256 + 1, 64)]
+    crops = [(y, x) for _, y, x in sorted(cands, reverse=True)[:3]]
+    print(f"  crops {crops}, covered centre pixels {[c for c, *_ in sorted(cands, reverse=True)[:3]]}", flush=True)
+    worst = 0.0
+    for y0, x0 in crops:
+        x = onet.features(planes[:, :, y0:y0 + 256, x0:x0 + 256])
+        want = ounet.forward(P, x)[0][:, :, 96:160, 96:160]
+        err = float(np.abs(got[:, :, y0 + 96:y0 + 160, x0 + 96:x0 + 160] - want).max())
+        print(f"  crop ({y0}, {x0}): max |gpu - fp64| = {err:.4g}, output range [{want.min():.2f}, {want.max():.2f}]",
+              flush=True)
+        worst = max(worst, err)
+    assert worst <= 2e-2
