@@ -248,3 +248,29 @@ def test_train_tensor_layout(B, H, W):
         narvis.narvis_train_tensor(B, W, H, "nope")
     with pytest.raises(narvis.NarvisError):
         narvis.narvis_train_tensor(B, W + 1, H, "feat")
+
+
+def test_unet_host_logic():
+    """The gated U-Net's host-side checks: parameter count against the oracle's
+    layer list, widths outside [32, 4096] or not multiples of 32, wrong counts
+    and non-finite values, and null handles are rejected before any device
+    call."""
+    from oracle import unet as ounet
+    L = _lib.load()
+    W = lambda w: (ctypes.c_int32 * 5)(*w)
+    for widths in (ounet.WIDTHS, (32, 32, 64, 64, 64), (32, 64, 96, 128, 4096)):
+        assert int(L.narvis_unet_param_count(W(widths))) == ounet.param_count(widths)
+    for bad in ((16, 32, 64, 64, 64), (32, 48, 64, 64, 64), (32, 32, 64, 64, 8192), (0, 32, 32, 32, 32)):
+        assert L.narvis_unet_param_count(W(bad)) == 0
+    h = ctypes.c_void_p()
+    n = ounet.param_count((32, 32, 64, 64, 64))
+    blob = np.zeros(n, np.float32)
+    assert L.narvis_unet_create(W((32, 32, 64, 64, 64)), blob.ctypes.data, n - 1, ctypes.byref(h)) == -1
+    assert L.narvis_unet_create(W((16, 32, 64, 64, 64)), blob.ctypes.data, n, ctypes.byref(h)) == -1
+    blob[7] = np.inf
+    assert L.narvis_unet_create(W((32, 32, 64, 64, 64)), blob.ctypes.data, n, ctypes.byref(h)) == -1
+    assert L.narvis_unet_workspace_size(None, 1, 64, 64, 0) == 0
+    assert L.narvis_unet_forward(None, None, 1, 64, 64, None, None, 0, None) == -1
+    assert L.narvis_unet_train_step(None, None, None, 1, 64, 64, 1e-3, 1e-3, None, None, 0, None) == -1
+    assert L.narvis_unet_gradients(None, None, None, 1, 64, 64, 1e-3, None, None, None, 0, None) == -1
+    assert L.narvis_unet_read(None, None, 0) == -1
