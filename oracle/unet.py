@@ -97,7 +97,8 @@ def elu(x):
 
 
 def sigmoid(x):
-    return 1.0 / (1.0 + np.exp(-x))
+    with np.errstate(over="ignore"):  # exp(-x) = inf for x far below 0: the value is 0, as it should be
+        return 1.0 / (1.0 + np.exp(-x))
 
 
 def conv1(x, Wm, b):
