@@ -310,7 +310,17 @@ narvis_status narvis_rasterize(const narvis_points *pts, const narvis_attrs *att
  *                           box of its points with finite coordinates:
  *                           xmin, ymin, zmin, 0, xmax, ymax, zmax, 0
  *                           (+inf ... -inf when it has none),
- *                           nb = narvis_layout_batches(n).
+ *                           nb = narvis_layout_batches(n);
+ * and, optionally (all five or none), the render's depth sample: every 8th
+ * point of the layout order (positions 0, 8, 16, ...), ns =
+ * narvis_layout_samples(n) points, which the bounded render draws first so
+ * that its depth bounds cover the whole cloud evenly:
+ *   sx, sy, sz float[ns], sindex uint32[ns]  as x, y, z, index at 8 j,
+ *   sboxes   float[nsb][8]  boxes of the sample's batches of 2048,
+ *                           nsb = narvis_layout_batches(ns).
+ * Without the sample the render draws every 8th batch first instead; in
+ * layout order a batch is a compact piece of space, so those leave whole
+ * screen regions without bounds on views that see the whole cloud.
  * Order (narvis_layout_build): the stable sort by the 30-bit Morton code of
  * each point's cell in a 1024^3 grid over the box [lo, hi] of all points
  * with finite coordinates: per axis t = (a - lo) * (1024 / (hi - lo)) in fp32
@@ -324,10 +334,18 @@ typedef struct {
     float *z;
     uint32_t *index;
     float *boxes;
+    float *sx;
+    float *sy;
+    float *sz;
+    uint32_t *sindex;
+    float *sboxes;
 } narvis_layout;
 
 /* Number of batches (boxes) of a layout of n points: ceil(n / 2048). */
 uint64_t narvis_layout_batches(uint64_t n);
+
+/* Points of a layout's depth sample: ceil(n / 8). */
+uint64_t narvis_layout_samples(uint64_t n);
 
 /* Device workspace bytes of narvis_layout_build for n points (24 n bytes
  * and a little more); 0 for n >= 2^32. */
@@ -345,8 +363,10 @@ narvis_status narvis_layout_build(const narvis_points *pts, uint64_t n, const na
  * index), with whole batches skipped when their box cannot hold a kept
  * point.  opts: variant AUTO or LDS only, bounds as for narvis_raster_render
  * (then batches are also skipped when their box's nearest depth exceeds
- * every tile bound under its screen rectangle); hint_keys must be NULL.
- * n < 2^32.  INVALID_ARG otherwise. */
+ * every tile bound under its screen rectangle; with the layout's depth
+ * sample the sample is drawn first and then every batch, without it every
+ * 8th batch and then the others); hint_keys must be NULL.  n < 2^32.
+ * INVALID_ARG otherwise. */
 narvis_status narvis_raster_render_layout(const narvis_layout *L, uint64_t n, const float vp_rowmajor[16],
                                           float near_f, float far_f, int32_t W, int32_t H, uint64_t *keys,
                                           const narvis_raster_opts *opts, void *stream);

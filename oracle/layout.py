@@ -20,6 +20,7 @@ The layout is the stable sort of the points by code (equal codes keep the
 original index order), i.e. perm[j] = original index of the j-th point, and
 for each batch of B consecutive points of the sorted order the box
 [min, max] per axis over its finite points (+inf / -inf when it has none).
+The render's depth sample is every 8th point of that order (depth_sample).
 Plain numpy, one step at a time; a stable argsort is the only library
 primitive.
 """
@@ -89,3 +90,24 @@ def layout(x, y, z, batch=2048):
             boxes[b, 0, a] = v[ok].min() if ok.any() else np.float32(np.inf)
             boxes[b, 1, a] = v[ok].max() if ok.any() else np.float32(-np.inf)
     return perm, boxes
+
+
+def depth_sample(x, y, z, perm, batch=2048):
+    """The render's depth sample of a layout (a reading of how to spread the
+    first-drawn points evenly over the cloud): every 8th point of the layout
+    order, positions 0, 8, 16, ...  Returns (original indices uint32
+    [ceil(n / 8)], boxes of its consecutive batches of `batch` sample points,
+    as layout() gives them)."""
+    x, y, z = (np.asarray(a, np.float32) for a in (x, y, z))
+    sidx = np.asarray(perm, np.uint32)[0::8]
+    ns = sidx.shape[0]
+    nb = (ns + batch - 1) // batch
+    boxes = np.empty((nb, 2, 3), np.float32)
+    for b in range(nb):
+        idx = sidx[b * batch:(b + 1) * batch]
+        px, py, pz = x[idx], y[idx], z[idx]
+        ok = np.isfinite(px) & np.isfinite(py) & np.isfinite(pz)
+        for a, v in enumerate((px, py, pz)):
+            boxes[b, 0, a] = v[ok].min() if ok.any() else np.float32(np.inf)
+            boxes[b, 1, a] = v[ok].max() if ok.any() else np.float32(-np.inf)
+    return sidx, boxes

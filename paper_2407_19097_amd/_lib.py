@@ -66,7 +66,8 @@ class SplatParams(ctypes.Structure):
 
 class Layout(ctypes.Structure):
     _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p), ("index", ctypes.c_void_p),
-                ("boxes", ctypes.c_void_p)]
+                ("boxes", ctypes.c_void_p), ("sx", ctypes.c_void_p), ("sy", ctypes.c_void_p), ("sz", ctypes.c_void_p),
+                ("sindex", ctypes.c_void_p), ("sboxes", ctypes.c_void_p)]
 
 
 _P = ctypes.c_void_p
@@ -95,6 +96,7 @@ SIGNATURES = {
                                                ctypes.POINTER(Camera), ctypes.c_int32, ctypes.c_int32,
                                                ctypes.POINTER(GBuffer), _P]),
     "narvis_layout_batches": (ctypes.c_uint64, [ctypes.c_uint64]),
+    "narvis_layout_samples": (ctypes.c_uint64, [ctypes.c_uint64]),
     "narvis_layout_workspace_size": (ctypes.c_size_t, [ctypes.c_uint64]),
     "narvis_layout_build": (ctypes.c_int, [ctypes.POINTER(Points), ctypes.c_uint64, ctypes.POINTER(Layout), _P,
                                            ctypes.c_size_t, _P]),

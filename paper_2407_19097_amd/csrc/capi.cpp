@@ -275,6 +275,8 @@ extern "C" narvis_status narvis_rasterize_static(const narvis_points *pts, const
 
 extern "C" uint64_t narvis_layout_batches(uint64_t n) { return (n + NARVIS_LAYOUT_BATCH - 1) / NARVIS_LAYOUT_BATCH; }
 
+extern "C" uint64_t narvis_layout_samples(uint64_t n) { return (n + 7) / 8; }
+
 extern "C" size_t narvis_layout_workspace_size(uint64_t n)
 {
     if (n >= (uint64_t(1) << 32)) return 0;
@@ -285,11 +287,17 @@ namespace {
 
 bool aligned16(const void *p) { return !(reinterpret_cast<uintptr_t>(p) & 15u); }
 
-// a layout of n points: every array given and 16-byte aligned
+// a layout of n points: every array given and 16-byte aligned; the depth
+// sample's five arrays all given (and aligned) or all null
 bool layout_ok(const narvis_layout *L, uint64_t n)
 {
     if (!L || n >= (uint64_t(1) << 32)) return false;
+    const int given = !!L->sx + !!L->sy + !!L->sz + !!L->sindex + !!L->sboxes;
+    if (given != 0 && given != 5) return false;
     if (n == 0) return true;
+    if (given && !(aligned16(L->sx) && aligned16(L->sy) && aligned16(L->sz) && aligned16(L->sindex) &&
+                   aligned16(L->sboxes)))
+        return false;
     return L->x && L->y && L->z && L->index && L->boxes && aligned16(L->x) && aligned16(L->y) && aligned16(L->z) &&
            aligned16(L->index) && aligned16(L->boxes);
 }
@@ -313,8 +321,18 @@ extern "C" narvis_status narvis_layout_build(const narvis_points *pts, uint64_t 
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b)
             if (o[a] < in[b] + 4 * n && in[b] < o[a] + 4 * n) return NARVIS_ERR_INVALID_ARG;
-    return from_hip(launch_layout(pts->x, pts->y, pts->z, n, out->x, out->y, out->z, out->index, out->boxes, ws,
-                                  static_cast<hipStream_t>(stream)));
+    // the sample is gathered from the layout's own arrays: no overlap with them
+    if (out->sx) {
+        const uint64_t ns = narvis_layout_samples(n);
+        const uintptr_t so[4] = {reinterpret_cast<uintptr_t>(out->sx), reinterpret_cast<uintptr_t>(out->sy),
+                                 reinterpret_cast<uintptr_t>(out->sz), reinterpret_cast<uintptr_t>(out->sindex)};
+        const uintptr_t lo[4] = {o[0], o[1], o[2], reinterpret_cast<uintptr_t>(out->index)};
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b)
+                if (so[a] < lo[b] + 4 * n && lo[b] < so[a] + 4 * ns) return NARVIS_ERR_INVALID_ARG;
+    }
+    return from_hip(launch_layout(pts->x, pts->y, pts->z, n, out->x, out->y, out->z, out->index, out->boxes, out->sx,
+                                  out->sy, out->sz, out->sindex, out->sboxes, ws, static_cast<hipStream_t>(stream)));
 }
 
 extern "C" size_t narvis_knn_radius_workspace_size(uint64_t n)
@@ -345,7 +363,16 @@ namespace {
 
 LayoutArgs layout_args(const narvis_layout *L, uint64_t n)
 {
-    return LayoutArgs{n ? L->index : nullptr, n ? reinterpret_cast<const float4 *>(L->boxes) : nullptr, nullptr};
+    LayoutArgs a{n ? L->index : nullptr, n ? reinterpret_cast<const float4 *>(L->boxes) : nullptr, nullptr};
+    if (n && L->sx) {
+        a.sx = L->sx;
+        a.sy = L->sy;
+        a.sz = L->sz;
+        a.six = L->sindex;
+        a.sbox = reinterpret_cast<const float4 *>(L->sboxes);
+        a.ns = narvis_layout_samples(n);
+    }
+    return a;
 }
 
 }  // namespace

@@ -66,6 +66,11 @@ struct LayoutArgs {
     const uint32_t *ix;
     const float4 *box;
     const uint8_t *glyph;
+    // the layout's depth sample (every 8th point), or null
+    const float *sx, *sy, *sz;
+    const uint32_t *six;
+    const float4 *sbox;
+    uint64_t ns;
 };
 
 hipError_t launch_clear(uint64_t *keys, int64_t npx, hipStream_t s);
@@ -102,7 +107,8 @@ struct LayoutWorkspace {
 };
 LayoutWorkspace layout_workspace(uint64_t n);
 hipError_t launch_layout(const float *x, const float *y, const float *z, uint64_t n, float *xs, float *ys, float *zs,
-                         uint32_t *ix, float *box, void *ws, hipStream_t s);
+                         uint32_t *ix, float *box, float *sx, float *sy, float *sz, uint32_t *six, float *sbox,
+                         void *ws, hipStream_t s);
 
 // Stable LSD radix sort (8-bit digits) of the first min(*count, cap) (key,
 // value) pairs by the low key_bits bits of the keys, ping-ponging between

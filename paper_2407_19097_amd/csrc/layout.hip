@@ -146,6 +146,20 @@ __global__ __launch_bounds__(kT) void k_layout_gather(const uint32_t *__restrict
     ix[j] = i;
 }
 
+// the depth sample: every 8th point of the layout order
+__global__ __launch_bounds__(kT) void k_layout_sample(const float *__restrict__ xs, const float *__restrict__ ys,
+                                                     const float *__restrict__ zs, const uint32_t *__restrict__ ix,
+                                                     uint64_t ns, float *__restrict__ sx, float *__restrict__ sy,
+                                                     float *__restrict__ sz, uint32_t *__restrict__ six)
+{
+    const uint64_t j = (uint64_t)blockIdx.x * kT + threadIdx.x;
+    if (j >= ns) return;
+    sx[j] = xs[8 * j];
+    sy[j] = ys[8 * j];
+    sz[j] = zs[8 * j];
+    six[j] = ix[8 * j];
+}
+
 // one workgroup per batch: box of its finite points
 __global__ __launch_bounds__(kT) void k_layout_boxes(const float *__restrict__ xs, const float *__restrict__ ys,
                                                     const float *__restrict__ zs, uint64_t n,
@@ -490,7 +504,8 @@ LayoutWorkspace layout_workspace(uint64_t n)
 }
 
 hipError_t launch_layout(const float *x, const float *y, const float *z, uint64_t n, float *xs, float *ys, float *zs,
-                         uint32_t *ix, float *box, void *ws, hipStream_t s)
+                         uint32_t *ix, float *box, float *sx, float *sy, float *sz, uint32_t *six, float *sbox,
+                         void *ws, hipStream_t s)
 {
     const LayoutWorkspace L = layout_workspace(n);
     char *base = static_cast<char *>(ws);
@@ -516,6 +531,14 @@ hipError_t launch_layout(const float *x, const float *y, const float *z, uint64_
     const uint64_t nb = (n + NARVIS_LAYOUT_BATCH - 1) / NARVIS_LAYOUT_BATCH;
     hipLaunchKernelGGL(k_layout_boxes, dim3((unsigned)nb), dim3(kT), 0, s, xs, ys, zs, n,
                        reinterpret_cast<float4 *>(box));
+    if (sx) {
+        const uint64_t ns = (n + 7) / 8;
+        hipLaunchKernelGGL(k_layout_sample, dim3((unsigned)((ns + kT - 1) / kT)), dim3(kT), 0, s, xs, ys, zs, ix, ns,
+                           sx, sy, sz, six);
+        const uint64_t nsb = (ns + NARVIS_LAYOUT_BATCH - 1) / NARVIS_LAYOUT_BATCH;
+        hipLaunchKernelGGL(k_layout_boxes, dim3((unsigned)nsb), dim3(kT), 0, s, sx, sy, sz, ns,
+                           reinterpret_cast<float4 *>(sbox));
+    }
     return hipGetLastError();
 }
 

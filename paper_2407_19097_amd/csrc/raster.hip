@@ -999,13 +999,15 @@ hipError_t launch_render(const float *x, const float *y, const float *z, uint64_
         const uint64_t nchunks = ((n >> 2) + kChunkQuads - 1) / kChunkQuads;
         const bool ix = lay.ix != nullptr;
         const int mode = ix ? 1 : (lay.glyph ? 2 : 0);
-        auto lds = [&](const ChunkSel &sel, uint64_t nblocks) {
+        auto lds_on = [&](const float *px, const float *py, const float *pz, uint64_t pn, const ChunkSel &sel,
+                          uint64_t nblocks, const LayoutArgs &la) {
             const ChunkOrder o = order_of(nblocks);
             auto kern = rcp ? (mode == 1 ? k_render_lds<true, 1> : mode == 2 ? k_render_lds<true, 2> : k_render_lds<true, 0>)
                             : (mode == 1 ? k_render_lds<false, 1>
                                          : mode == 2 ? k_render_lds<false, 2> : k_render_lds<false, 0>);
-            hipLaunchKernelGGL(kern, dim3((unsigned)nblocks), dim3(kBlock), 0, s, x, y, z, n, P, k, o, sel, lay);
+            hipLaunchKernelGGL(kern, dim3((unsigned)nblocks), dim3(kBlock), 0, s, px, py, pz, pn, P, k, o, sel, la);
         };
+        auto lds = [&](const ChunkSel &sel, uint64_t nblocks) { lds_on(x, y, z, n, sel, nblocks, lay); };
         // bounded render for at least two chunks (24-bit pixel arithmetic)
         if (bounds && n >= 4096 && P.W < (1 << 24) && P.H < (1 << 24)) {
             uint32_t *pixb = reinterpret_cast<uint32_t *>(bounds + kMaxTiles);
@@ -1023,34 +1025,54 @@ hipError_t launch_render(const float *x, const float *y, const float *z, uint64_
                                    reinterpret_cast<const unsigned long long *>(hint), npx, x, y, z, n, P, k,
                                    lay.glyph);
             }
-            for (int lv = 0; lv < kNumLevels; ++lv) {
-                ChunkSel sel;
-                sel.mul = kLevels[lv];
-                sel.excl = lv ? kLevels[lv - 1] / kLevels[lv] : 0u;
-                sel.nv = ceil_div(nchunks, sel.mul) - (lv ? ceil_div(nchunks, kLevels[lv - 1]) : 0u);
-                sel.tail = lv == 0;
-                if (lv == 0) {
-                    lds(sel, grid_of(sel.nv));
-                } else {
-                    hipLaunchKernelGGL(k_tile_bounds, dim3(tg.ntiles), dim3(kBlock), 0, s, k, P.W, P.H, tg.shift,
-                                       tg.tiles_x, bounds, pixb);
-                    if (sel.nv == 0) continue;
-                    // a resident grid: each workgroup loads the bounds once
-                    const uint64_t resident = (uint64_t)dev.cus * (2048 / kCullBlock);
-                    const uint64_t nb = grid_of(grid_blocks > 0 ? (uint64_t)grid_blocks
-                                                                : (sel.nv < resident ? sel.nv : resident));
-                    const ChunkOrder o = order_of(nb);
-                    const bool off32 = (uint64_t)P.W * (uint64_t)P.H < (1ull << 29);
-                    auto pick = [&](auto m) {
-                        constexpr int M = decltype(m)::value;
-                        return rcp ? (off32 ? k_render_cull<true, true, M> : k_render_cull<true, false, M>)
-                                   : (off32 ? k_render_cull<false, true, M> : k_render_cull<false, false, M>);
-                    };
-                    auto kern = mode == 1 ? pick(std::integral_constant<int, 1>{})
-                                          : mode == 2 ? pick(std::integral_constant<int, 2>{})
-                                                      : pick(std::integral_constant<int, 0>{});
-                    hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(kCullBlock), 0, s, x, y, z, n, P, k, o, sel, tg,
-                                       lay);
+            auto bounds_of_keys = [&]() {
+                hipLaunchKernelGGL(k_tile_bounds, dim3(tg.ntiles), dim3(kBlock), 0, s, k, P.W, P.H, tg.shift,
+                                   tg.tiles_x, bounds, pixb);
+            };
+            auto cull = [&](const ChunkSel &sel) {
+                // a resident grid: each workgroup loads the bounds once
+                const uint64_t resident = (uint64_t)dev.cus * (2048 / kCullBlock);
+                const uint64_t nb = grid_of(grid_blocks > 0 ? (uint64_t)grid_blocks
+                                                            : (sel.nv < resident ? sel.nv : resident));
+                const ChunkOrder o = order_of(nb);
+                const bool off32 = (uint64_t)P.W * (uint64_t)P.H < (1ull << 29);
+                auto pick = [&](auto m) {
+                    constexpr int M = decltype(m)::value;
+                    return rcp ? (off32 ? k_render_cull<true, true, M> : k_render_cull<true, false, M>)
+                               : (off32 ? k_render_cull<false, true, M> : k_render_cull<false, false, M>);
+                };
+                auto kern = mode == 1 ? pick(std::integral_constant<int, 1>{})
+                                      : mode == 2 ? pick(std::integral_constant<int, 2>{})
+                                                  : pick(std::integral_constant<int, 0>{});
+                hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(kCullBlock), 0, s, x, y, z, n, P, k, o, sel, tg,
+                                   lay);
+            };
+            if (ix && lay.sx) {
+                // the layout's depth sample (every 8th point, spread over the
+                // whole cloud) first, then every batch against its bounds (the
+                // sampled points merge again, which changes nothing)
+                const uint64_t ns_chunks = ((lay.ns >> 2) + kChunkQuads - 1) / kChunkQuads;
+                LayoutArgs ls = lay;
+                ls.ix = lay.six;
+                ls.box = lay.sbox;
+                const ChunkSel s0{1u, 0u, ns_chunks, 1u};
+                lds_on(lay.sx, lay.sy, lay.sz, lay.ns, s0, grid_of(ns_chunks), ls);
+                bounds_of_keys();
+                cull(ChunkSel{1u, 0u, nchunks, 1u});
+            } else {
+                for (int lv = 0; lv < kNumLevels; ++lv) {
+                    ChunkSel sel;
+                    sel.mul = kLevels[lv];
+                    sel.excl = lv ? kLevels[lv - 1] / kLevels[lv] : 0u;
+                    sel.nv = ceil_div(nchunks, sel.mul) - (lv ? ceil_div(nchunks, kLevels[lv - 1]) : 0u);
+                    sel.tail = lv == 0;
+                    if (lv == 0) {
+                        lds(sel, grid_of(sel.nv));
+                    } else {
+                        bounds_of_keys();
+                        if (sel.nv == 0) continue;
+                        cull(sel);
+                    }
                 }
             }
         } else {

@@ -203,19 +203,31 @@ LAYOUT_BATCH = 2048
 class Layout:
     """Morton layout of a point cloud in caller-owned device tensors: x, y, z
     float32 [n] in layout order, index uint32 (as int32) [n] original index,
-    boxes float32 [nbatch][8]."""
+    boxes float32 [nbatch][8]; with sample=True also the render's depth
+    sample (every 8th point: sx, sy, sz, sindex [ceil(n / 8)], sboxes)."""
 
-    def __init__(self, n: int, device="cuda"):
+    def __init__(self, n: int, device="cuda", sample: bool = True):
         import torch
+        L = _lib.load()
         self.n = int(n)
-        nb = int(_lib.load().narvis_layout_batches(self.n))
+        nb = int(L.narvis_layout_batches(self.n))
         e = lambda m: torch.empty(max(m, 4), dtype=torch.float32, device=device)
         self.x, self.y, self.z = e(self.n), e(self.n), e(self.n)
         self.index = torch.empty(max(self.n, 4), dtype=torch.int32, device=device)
         self.boxes = torch.empty((max(nb, 1), 8), dtype=torch.float32, device=device)
+        self.sample = bool(sample)
+        if self.sample:
+            ns = int(L.narvis_layout_samples(self.n))
+            nsb = int(L.narvis_layout_batches(ns))
+            self.sx, self.sy, self.sz = e(ns), e(ns), e(ns)
+            self.sindex = torch.empty(max(ns, 4), dtype=torch.int32, device=device)
+            self.sboxes = torch.empty((max(nsb, 1), 8), dtype=torch.float32, device=device)
 
     def struct(self) -> _lib.Layout:
-        return _lib.Layout(_ptr(self.x), _ptr(self.y), _ptr(self.z), _ptr(self.index), _ptr(self.boxes))
+        if not self.sample:
+            return _lib.Layout(_ptr(self.x), _ptr(self.y), _ptr(self.z), _ptr(self.index), _ptr(self.boxes))
+        return _lib.Layout(_ptr(self.x), _ptr(self.y), _ptr(self.z), _ptr(self.index), _ptr(self.boxes),
+                           _ptr(self.sx), _ptr(self.sy), _ptr(self.sz), _ptr(self.sindex), _ptr(self.sboxes))
 
 
 def narvis_knn_radius_workspace_size(n: int) -> int:
@@ -249,10 +261,10 @@ def narvis_layout_build(points, n: int, layout: Layout, workspace, stream=None) 
                                                _stream_ptr(stream)), "narvis_layout_build")
 
 
-def build_layout(points, n: int, device="cuda") -> Layout:
+def build_layout(points, n: int, device="cuda", sample: bool = True) -> Layout:
     """Allocate a Layout and build it (the workspace is freed afterwards)."""
     import torch
-    L = Layout(n, device)
+    L = Layout(n, device, sample=sample)
     ws = torch.empty(max(1, narvis_layout_workspace_size(n)), dtype=torch.uint8, device=device)
     narvis_layout_build(points, n, L, ws)
     del ws

@@ -28,10 +28,10 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def gpu_layout(x, y, z):
+def gpu_layout(x, y, z, sample=True):
     n = int(x.shape[0])
     X, Y, Z = dev(x), dev(y), dev(z)
-    L = narvis.build_layout((X, Y, Z), n)
+    L = narvis.build_layout((X, Y, Z), n, sample=sample)
     torch.cuda.synchronize()
     return (X, Y, Z), L
 
@@ -45,6 +45,14 @@ def check_layout(x, y, z, L):
         assert np.array_equal(t[:n].cpu().numpy().view(np.uint32), a[perm].view(np.uint32))
     gb = L.boxes[:boxes.shape[0]].cpu().numpy()
     assert np.array_equal(gb[:, 0:3], boxes[:, 0]) and np.array_equal(gb[:, 4:7], boxes[:, 1])
+    if L.sample:
+        sidx, sboxes = olay.depth_sample(x, y, z, perm, batch=narvis.LAYOUT_BATCH)
+        ns = sidx.shape[0]
+        assert np.array_equal(L.sindex[:ns].cpu().numpy().view(np.uint32), sidx)
+        for a, t in zip((x, y, z), (L.sx, L.sy, L.sz)):
+            assert np.array_equal(t[:ns].cpu().numpy().view(np.uint32), a[sidx].view(np.uint32))
+        gs = L.sboxes[:sboxes.shape[0]].cpu().numpy()
+        assert np.array_equal(gs[:, 0:3], sboxes[:, 0]) and np.array_equal(gs[:, 4:7], sboxes[:, 1])
 
 
 def render_layout(L, n, cam, W, H, bounded):
@@ -91,14 +99,15 @@ def test_layout_build_degenerate_extent():
     check_layout(x, y, z, L)
 
 
-@pytest.mark.parametrize("bounded", [False, True])
+@pytest.mark.parametrize("bounded,sample", [(False, True), (True, True), (True, False)])
 @pytest.mark.parametrize("n", [4097, 300001, 1_000_003])
-def test_layout_render_matches_oracle(n, bounded):
-    announce(f"layout render vs oracle (original order), unit cube n={n}, bounded={bounded}, 4 cameras")
+def test_layout_render_matches_oracle(n, bounded, sample):
+    announce(f"layout render vs oracle (original order), unit cube n={n}, bounded={bounded}, depth sample={sample}, "
+             "4 cameras")
     rng = np.random.default_rng(7 + n)
     x, y, z = rng.random((3, n), dtype=np.float32)
     x[rng.integers(0, n, 30)] = np.nan
-    _, L = gpu_layout(x, y, z)
+    _, L = gpu_layout(x, y, z, sample=sample)
     for cam in CAMS:
         for W, H in ((320, 240), (97, 131)):
             got = render_layout(L, n, cam, W, H, bounded)

@@ -88,3 +88,26 @@ def test_batches_are_compact():
     perm, boxes = olay.layout(x, y, z, batch=512)
     ext = boxes[:, 1] - boxes[:, 0]
     assert np.median(ext.prod(axis=1)) < 4.0 / 128  # generation order: ~1
+
+
+def test_depth_sample_is_every_8th_point_with_tight_boxes():
+    rng = np.random.default_rng(9)
+    for n in (1, 7, 8, 9, 5000, 40001):
+        x, y, z = rng.random((3, n), dtype=np.float32)
+        if n > 100:
+            y[::97] = np.nan
+        perm, _ = olay.layout(x, y, z, batch=64)
+        sidx, boxes = olay.depth_sample(x, y, z, perm, batch=64)
+        assert sidx.shape[0] == (n + 7) // 8
+        assert all(int(sidx[j]) == int(perm[8 * j]) for j in range(sidx.shape[0]))
+        assert boxes.shape[0] == (sidx.shape[0] + 63) // 64
+        for b in range(boxes.shape[0]):
+            idx = sidx[64 * b:64 * (b + 1)]
+            ok = np.isfinite(x[idx]) & np.isfinite(y[idx]) & np.isfinite(z[idx])
+            for a, v in enumerate((x, y, z)):
+                vv = v[idx][ok]
+                if vv.size:
+                    assert boxes[b, 0, a] == vv.min() and boxes[b, 1, a] == vv.max()
+                    assert np.all(vv >= boxes[b, 0, a]) and np.all(vv <= boxes[b, 1, a])
+                else:
+                    assert boxes[b, 0, a] == np.inf and boxes[b, 1, a] == -np.inf
