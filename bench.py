@@ -576,10 +576,16 @@ def main():
         same = bool(torch.equal(g.keys, last))
         del L, last
         torch.cuda.empty_cache()
+        saved = render_avg - render
         return {"value": round(n * args.steps / (total / 1e3) / 1e9, 3), "unit": "Gpoints/s",
                 "ms_per_step": round(total / args.steps, 4), "render_stage_ms": round(render, 4),
                 "layout_build_ms": round(build_ms, 2),
-                "layout": "stable sort by 30-bit Morton code, 2048-point batches with boxes; keys carry the "
+                "frames_to_repay_build": round(build_ms / saved, 1) if saved > 0 else None,
+                "effective_frac": round(alg_bytes / (render / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),
+                "effective_frac_note": "algorithmic bytes of the whole cloud / render stage time / 8 TB/s; whole "
+                                       "batches culled by their boxes are not read, so this is not HBM traffic",
+                "layout": "stable sort by 30-bit Morton code, 2048-point batches with boxes; the depth sample "
+                          "(every 8th point of that order) drawn first, then every batch; keys carry the "
                           "original index",
                 "same_keys_as_original_order_last_frame": same}
 
