@@ -347,7 +347,7 @@ uint64_t narvis_layout_batches(uint64_t n);
 /* Points of a layout's depth sample: ceil(n / 8). */
 uint64_t narvis_layout_samples(uint64_t n);
 
-/* Device workspace bytes of narvis_layout_build for n points (24 n bytes
+/* Device workspace bytes of narvis_layout_build for n points (16 n bytes
  * and a little more); 0 for n >= 2^32. */
 size_t narvis_layout_workspace_size(uint64_t n);
 

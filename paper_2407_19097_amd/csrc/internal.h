@@ -117,6 +117,9 @@ hipError_t launch_layout(const float *x, const float *y, const float *z, uint64_
 hipError_t launch_radix_sort(unsigned long long *ka, uint32_t *va, unsigned long long *kb, uint32_t *vb,
                              const uint32_t *count, uint64_t cap, int key_bits, uint32_t *hist, uint32_t *sums,
                              hipStream_t s, bool *in_b);
+// the same with 32-bit keys
+hipError_t launch_radix_sort32(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, const uint32_t *count,
+                               uint64_t cap, int key_bits, uint32_t *hist, uint32_t *sums, hipStream_t s, bool *in_b);
 uint64_t radix_sort_hist_len(uint64_t cap);
 uint64_t radix_sort_sums_len(uint64_t cap);
 

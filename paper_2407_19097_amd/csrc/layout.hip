@@ -109,8 +109,8 @@ __device__ __forceinline__ uint32_t cell(float a, float lo, float scale)
 
 __global__ __launch_bounds__(kT) void k_layout_codes(const float *__restrict__ X, const float *__restrict__ Y,
                                                     const float *__restrict__ Z, uint64_t n,
-                                                    const uint32_t *__restrict__ bb,
-                                                    unsigned long long *__restrict__ keys, uint32_t *__restrict__ vals)
+                                                    const uint32_t *__restrict__ bb, uint32_t *__restrict__ keys,
+                                                    uint32_t *__restrict__ vals)
 {
     const uint64_t i = (uint64_t)blockIdx.x * kT + threadIdx.x;
     if (i >= n) return;
@@ -493,8 +493,8 @@ LayoutWorkspace layout_workspace(uint64_t n)
     uint64_t o = 0;
     L.off_bb = o; o = align256(o + 8 * 4);
     L.off_count = o; o = align256(o + 4);
-    L.off_ka = o; o = align256(o + n * 8);
-    L.off_kb = o; o = align256(o + n * 8);
+    L.off_ka = o; o = align256(o + n * 4);
+    L.off_kb = o; o = align256(o + n * 4);
     L.off_va = o; o = align256(o + n * 4);
     L.off_vb = o; o = align256(o + n * 4);
     L.off_hist = o; o = align256(o + radix_sort_hist_len(n) * 4);
@@ -511,8 +511,8 @@ hipError_t launch_layout(const float *x, const float *y, const float *z, uint64_
     char *base = static_cast<char *>(ws);
     auto *bb = reinterpret_cast<uint32_t *>(base + L.off_bb);
     auto *count = reinterpret_cast<uint32_t *>(base + L.off_count);
-    auto *ka = reinterpret_cast<unsigned long long *>(base + L.off_ka);
-    auto *kb = reinterpret_cast<unsigned long long *>(base + L.off_kb);
+    auto *ka = reinterpret_cast<uint32_t *>(base + L.off_ka);
+    auto *kb = reinterpret_cast<uint32_t *>(base + L.off_kb);
     auto *va = reinterpret_cast<uint32_t *>(base + L.off_va);
     auto *vb = reinterpret_cast<uint32_t *>(base + L.off_vb);
     auto *hist = reinterpret_cast<uint32_t *>(base + L.off_hist);
@@ -524,7 +524,7 @@ hipError_t launch_layout(const float *x, const float *y, const float *z, uint64_
     hipLaunchKernelGGL(k_layout_bbox, dim3((unsigned)red_blocks), dim3(kT), 0, s, x, y, z, n, bb);
     hipLaunchKernelGGL(k_layout_codes, dim3((unsigned)blocks), dim3(kT), 0, s, x, y, z, n, bb, ka, va);
     bool in_b = false;
-    hipError_t e = launch_radix_sort(ka, va, kb, vb, count, n, 31, hist, sums, s, &in_b);
+    hipError_t e = launch_radix_sort32(ka, va, kb, vb, count, n, 31, hist, sums, s, &in_b);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_layout_gather, dim3((unsigned)blocks), dim3(kT), 0, s, in_b ? vb : va, x, y, z, n, xs, ys,
                        zs, ix);

@@ -753,6 +753,12 @@ hipError_t launch_radix_sort(unsigned long long *ka, uint32_t *va, unsigned long
     return radix_sort(ka, va, kb, vb, count, cap, key_bits, hist, sums, s, in_b);
 }
 
+hipError_t launch_radix_sort32(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, const uint32_t *count,
+                               uint64_t cap, int key_bits, uint32_t *hist, uint32_t *sums, hipStream_t s, bool *in_b)
+{
+    return radix_sort(ka, va, kb, vb, count, cap, key_bits, hist, sums, s, in_b);
+}
+
 uint64_t radix_sort_hist_len(uint64_t cap)
 {
     const uint64_t nblk = (cap + kScanTile - 1) / kScanTile;
