@@ -580,6 +580,7 @@ def main():
         return {"value": round(n * args.steps / (total / 1e3) / 1e9, 3), "unit": "Gpoints/s",
                 "ms_per_step": round(total / args.steps, 4), "render_stage_ms": round(render, 4),
                 "layout_build_ms": round(build_ms, 2),
+                "value_including_build": round(n * args.steps / ((total + build_ms) / 1e3) / 1e9, 3),
                 "frames_to_repay_build": round(build_ms / saved, 1) if saved > 0 else None,
                 "effective_frac": round(alg_bytes / (render / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),
                 "effective_frac_note": "algorithmic bytes of the whole cloud / render stage time / 8 TB/s; whole "
