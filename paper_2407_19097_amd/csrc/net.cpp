@@ -580,7 +580,7 @@ extern "C" narvis_status narvis_weights_create(const float *host_blob, size_t co
     if (e == hipSuccess) e = refresh(w, nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
-        hipFree(w->pool);
+        (void)hipFree(w->pool);
         delete w;
         return NARVIS_ERR_DEVICE;
     }
@@ -592,12 +592,13 @@ extern "C" narvis_status narvis_weights_create(const float *host_blob, size_t co
 extern "C" void narvis_weights_destroy(narvis_weights *w)
 {
     if (!w) return;
+    // best effort: a destroy has no error to report
     int cur = 0;
-    hipGetDevice(&cur);
-    hipSetDevice(w->device);
-    hipDeviceSynchronize();
-    hipFree(w->pool);
-    hipSetDevice(cur);
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(w->device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(w->pool);
+    (void)hipSetDevice(cur);
     delete w;
 }
 

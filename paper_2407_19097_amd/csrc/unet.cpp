@@ -581,7 +581,7 @@ extern "C" narvis_status narvis_unet_create(const int32_t widths[5], const float
     if (e == hipSuccess) e = urefresh(u, nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
-        hipFree(u->pool);
+        (void)hipFree(u->pool);
         delete u;
         return NARVIS_ERR_DEVICE;
     }
@@ -592,12 +592,13 @@ extern "C" narvis_status narvis_unet_create(const int32_t widths[5], const float
 extern "C" void narvis_unet_destroy(narvis_unet *u)
 {
     if (!u) return;
+    // best effort: a destroy has no error to report
     int prev = 0;
-    hipGetDevice(&prev);
-    hipSetDevice(u->device);
-    hipDeviceSynchronize();
-    hipFree(u->pool);
-    hipSetDevice(prev);
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(u->device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(u->pool);
+    (void)hipSetDevice(prev);
     delete u;
 }
 
