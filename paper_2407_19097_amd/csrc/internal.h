@@ -87,7 +87,7 @@ struct SplatLayout {
     int32_t tiles_x, tiles_y;
     uint64_t cap, nblk, nsums;
     uint64_t off_ctr, off_col, off_wbits, off_cnt, off_ka, off_va, off_kb, off_vb, off_hist, off_sums, off_range,
-        off_conic, off_ext, off_scnt, off_npts;
+        off_conic, off_ext, off_scnt, off_npts, off_brange, off_part, off_plan;
     uint64_t bytes;
     int key_bits;
 };

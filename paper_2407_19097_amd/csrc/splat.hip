@@ -9,7 +9,9 @@
 //              3-sigma footprint gives a rectangle of screen tiles;
 //   order   -- stable radix sort of the points by depth bits (culled points
 //              last): equal depths keep the index order, so this is the order
-//              of the rasterizer's (depth, index) key;
+//              of the rasterizer's (depth, index) key.  Three 8-bit passes
+//              when the kept depths span under 2^24 - 1 ulps (bits taken
+//              relative to the nearest), else four; chosen on the device;
 //   scan    -- exclusive prefix sum of the tile counts in that order;
 //   emit    -- one (tile, point index) pair per covered tile, in that order;
 //   sort    -- stable radix sort of the pairs by tile (two 8-bit passes for up
@@ -35,6 +37,7 @@ constexpr int kT = 256;            // threads per workgroup everywhere here
 constexpr int kScanItems = 16;     // elements per thread in scans and the sort
 constexpr int kScanTile = kT * kScanItems;
 constexpr int kTile = 16;          // splat screen tile edge in pixels
+constexpr int kRangeParts = 256;   // workgroups folding the projection's depth ranges
 
 __device__ __forceinline__ bool project(const Proj &P, float x, float y, float z, float &sx, float &sy, float &w,
                                         float &cx_out, float &cy_out)
@@ -94,6 +97,7 @@ struct SplatArgs {
     float4 *col;          // [n] colour
     uint32_t *wbits;      // [n] depth bits
     uint32_t *cnt;        // [n + 1] tile counts, scanned in place to offsets
+    uint2 *brange;        // [project workgroups] least and greatest kept depth bits
     uint64_t cap;         // capacity of the pair arrays
     // anisotropic footprint (aniso != 0)
     int32_t aniso, vel_attr;
@@ -180,37 +184,63 @@ __device__ __forceinline__ bool aniso_footprint(const SplatArgs &S, float cx, fl
     return ext.x <= 3.40282347e38f && ext.y <= 3.40282347e38f;
 }
 
-// footprint rectangle in tiles (conservative: every pixel whose centre can be
-// within `reach` of (sx, sy) is inside)
-__device__ __forceinline__ void tile_rect(const SplatArgs &S, float sx, float sy, float rx, float ry, int &tx0,
-                                          int &tx1, int &ty0, int &ty1)
+// footprint rectangle in pixels, clipped to the image (conservative: every
+// pixel whose centre can be within `reach` of (sx, sy) is inside)
+__device__ __forceinline__ void pixel_rect(int W, int H, float sx, float sy, float rx, float ry, int &x0, int &x1,
+                                           int &y0, int &y1)
 {
-    const int W = S.P.W, H = S.P.H;
     // clamped in float first: an anisotropic extent can exceed the int range
-    int x0 = (int)fmaxf(floorf(sx - rx - 1.0f), -1.0f), x1 = (int)fminf(floorf(sx + rx + 1.0f), (float)W);
-    int y0 = (int)fmaxf(floorf(sy - ry - 1.0f), -1.0f), y1 = (int)fminf(floorf(sy + ry + 1.0f), (float)H);
+    x0 = (int)fmaxf(floorf(sx - rx - 1.0f), -1.0f);
+    x1 = (int)fminf(floorf(sx + rx + 1.0f), (float)W);
+    y0 = (int)fmaxf(floorf(sy - ry - 1.0f), -1.0f);
+    y1 = (int)fminf(floorf(sy + ry + 1.0f), (float)H);
     x0 = max(x0, 0);
     y0 = max(y0, 0);
     x1 = min(x1, W - 1);
     y1 = min(y1, H - 1);
+}
+
+// the same rectangle in tiles
+__device__ __forceinline__ void tile_rect(const SplatArgs &S, float sx, float sy, float rx, float ry, int &tx0,
+                                          int &tx1, int &ty0, int &ty1)
+{
+    int x0, x1, y0, y1;
+    pixel_rect(S.P.W, S.P.H, sx, sy, rx, ry, x0, x1, y0, y1);
     tx0 = x0 / kTile;
     tx1 = x1 / kTile;
     ty0 = y0 / kTile;
     ty1 = y1 / kTile;
 }
 
-__global__ __launch_bounds__(kT) void k_splat_project(SplatArgs S)
+// least and greatest over the workgroup (every thread gets both)
+__device__ __forceinline__ void block_range(uint32_t &lo, uint32_t &hi, uint32_t *lo4, uint32_t *hi4)
 {
-    const uint64_t i = (uint64_t)blockIdx.x * kT + threadIdx.x;
-    if (i > S.n) return;
-    if (i == S.n) {  // the scan's extra slot, so that cnt[n] becomes the total
-        S.cnt[i] = 0;
-        return;
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        lo = min(lo, (uint32_t)__shfl_xor(lo, d));
+        hi = max(hi, (uint32_t)__shfl_xor(hi, d));
     }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+        lo4[wid] = lo;
+        hi4[wid] = hi;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kT / 64; ++k) {
+        lo = min(lo, lo4[k]);
+        hi = max(hi, hi4[k]);
+    }
+}
+
+// one point: footprint, colour, depth bits and tile count; false when culled
+// (its count is then 0)
+__device__ __forceinline__ bool project_point(const SplatArgs &S, uint64_t i, uint32_t &wb)
+{
     float sx, sy, w, cx, cy;
     if (!project(S.P, S.X[i], S.Y[i], S.Z[i], sx, sy, w, cx, cy)) {
         S.cnt[i] = 0;
-        return;
+        return false;
     }
     float rx = S.reach, ry = S.reach;
     if (S.aniso) {
@@ -220,7 +250,7 @@ __global__ __launch_bounds__(kT) void k_splat_project(SplatArgs S)
                     vz = attr_f32(S.A.a[S.vel_attr + 2], (uint32_t)i);
         if (!aniso_footprint(S, cx, cy, w, vx, vy, vz, q, ext)) {
             S.cnt[i] = 0;
-            return;
+            return false;
         }
         S.conic[i] = q;
         S.ext[i] = ext;
@@ -247,27 +277,83 @@ __global__ __launch_bounds__(kT) void k_splat_project(SplatArgs S)
     tile_rect(S, sx, sy, rx, ry, tx0, tx1, ty0, ty1);
     S.ctr[i] = make_float2(sx, sy);
     S.col[i] = c;
-    S.wbits[i] = __float_as_uint(w);
+    wb = __float_as_uint(w);
+    S.wbits[i] = wb;
     S.cnt[i] = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+    return true;
 }
 
-// depth keys of the point order: a culled point (no tile) sorts after every
-// kept one (kept depth bits are below 0x7F800000)
-__global__ __launch_bounds__(kT) void k_depth_keys(SplatArgs S, uint32_t *keys, uint32_t *vals)
+// Projection of every point, plus the least and greatest depth bits of the
+// workgroup's kept points (all ones and zero when it keeps none), from which
+// the point sort picks its pass count.
+__global__ __launch_bounds__(kT) void k_splat_project(SplatArgs S)
 {
+    __shared__ uint32_t lo4[kT / 64], hi4[kT / 64];
     const uint64_t i = (uint64_t)blockIdx.x * kT + threadIdx.x;
-    if (i >= S.n) return;
-    keys[i] = S.cnt[i] ? S.wbits[i] : 0xFFFFFFFFu;
-    vals[i] = (uint32_t)i;
+    uint32_t wb = 0;
+    bool kept = false;
+    if (i < S.n) kept = project_point(S, i, wb);
+    else if (i == S.n) S.cnt[i] = 0;  // the scan's extra slot, so that cnt[n] becomes the total
+    uint32_t lo = kept ? wb : 0xFFFFFFFFu, hi = kept ? wb : 0u;
+    block_range(lo, hi, lo4, hi4);
+    if (threadIdx.x == 0) S.brange[blockIdx.x] = make_uint2(lo, hi);
 }
 
-// tile counts in depth order (scnt[n] = 0: the scan's total slot)
-__global__ __launch_bounds__(kT) void k_gather_counts(const uint32_t *cnt, const uint32_t *order, uint64_t n,
+// The point sort's pass count, chosen on the device.  k_range_partial folds
+// the projection's per-workgroup depth ranges into one per workgroup of its
+// own, k_depth_plan folds those and writes plan[0] = least kept depth bits and
+// plan[1] = 1 when the kept depths span at most 2^24 - 2 ulps: three 8-bit
+// passes over the bits relative to plan[0] then order the kept points, and
+// all ones in the low 24 bits (a culled point) still sorts after every one of
+// them.
+__global__ __launch_bounds__(kT) void k_range_partial(const uint2 *br, uint64_t nb, uint2 *part)
+{
+    __shared__ uint32_t lo4[kT / 64], hi4[kT / 64];
+    uint32_t lo = 0xFFFFFFFFu, hi = 0u;
+    for (uint64_t k = (uint64_t)blockIdx.x * kT + threadIdx.x; k < nb; k += (uint64_t)gridDim.x * kT) {
+        const uint2 r = br[k];
+        lo = min(lo, r.x);
+        hi = max(hi, r.y);
+    }
+    block_range(lo, hi, lo4, hi4);
+    if (threadIdx.x == 0) part[blockIdx.x] = make_uint2(lo, hi);
+}
+
+__global__ __launch_bounds__(kT) void k_depth_plan(const uint2 *part, uint32_t np, uint32_t *plan)
+{
+    __shared__ uint32_t lo4[kT / 64], hi4[kT / 64];
+    uint32_t lo = 0xFFFFFFFFu, hi = 0u;
+    for (uint32_t k = threadIdx.x; k < np; k += kT) {
+        const uint2 r = part[k];
+        lo = min(lo, r.x);
+        hi = max(hi, r.y);
+    }
+    block_range(lo, hi, lo4, hi4);
+    if (threadIdx.x == 0) {
+        const bool none = lo > hi;  // nothing kept
+        plan[0] = none ? 0u : lo;
+        plan[1] = (none || hi - lo <= 0xFFFFFEu) ? 1u : 0u;
+    }
+}
+
+// tile counts in depth order (scnt[n] = 0: the scan's total slot).  With three
+// passes the count sits in the sorted key's top byte; 255 there means "255 or
+// more, or culled", read from cnt.
+__global__ __launch_bounds__(kT) void k_gather_counts(const uint32_t *cnt, const uint32_t *order,
+                                                      const uint32_t *keys, const uint32_t *plan, uint64_t n,
                                                       uint32_t *scnt)
 {
     const uint64_t j = (uint64_t)blockIdx.x * kT + threadIdx.x;
     if (j > n) return;
-    scnt[j] = j < n ? cnt[order[j]] : 0u;
+    uint32_t c = 0u;
+    if (j < n) {
+        c = plan[1] ? keys[j] >> 24 : 255u;
+        if (c == 255u) {
+            const uint32_t i = order[j];
+            c = (uint64_t)i < n ? cnt[i] : 0u;  // a permutation of [0, n); guards the read regardless
+        }
+    }
+    scnt[j] = c;
 }
 
 // sorted position j: the pairs of point order[j] at [scnt[j], scnt[j + 1])
@@ -383,11 +469,62 @@ __global__ __launch_bounds__(kT) void k_scan_apply(const uint32_t *in, uint32_t 
 // stable LSD radix sort, 8-bit digits, 4096 elements per workgroup
 // ---------------------------------------------------------------------------
 
+// Where a pass takes its elements from.  ArraySrc: the caller's or the
+// previous pass's arrays, digit position fixed on the host.
 template <typename K>
-__global__ __launch_bounds__(kT) void k_radix_hist(const K *keys, const uint32_t *count, uint64_t cap, int shift,
-                                                   uint32_t *hist, uint32_t nblk)
+struct ArraySrc {
+    const K *k;
+    const uint32_t *v;
+    int sh;
+    __device__ void init() {}
+    __device__ int shift() const { return sh; }
+    __device__ K key(uint64_t e) const { return k[e]; }
+    __device__ uint32_t val(uint64_t e) const { return v[e]; }
+};
+
+// The point sort by depth, four slots of which the plan (k_depth_plan) runs
+// four, over the fp32 depth bits, or the last three, over the bits relative
+// to plan[0] with the tile count (saturated at 255) in the key's top byte,
+// where the count gather after the sort finds it in order.  The first slot
+// that runs builds its keys from the projection (all ones for a culled point,
+// which sorts it last) and numbers the values; the later ones read the
+// previous slot's output.  Slots 1 to 3 write the same buffers in both cases,
+// so the sorted order always ends in slot 3's output.
+struct DepthSrc {
+    const uint32_t *k, *v;        // previous slot's output (slots 1 to 3)
+    const uint32_t *wbits, *cnt;  // projection: depth bits and tile counts
+    const uint32_t *plan;
+    int slot;
+    uint32_t base;
+    bool three, first;
+    __device__ void init()
+    {
+        three = plan[1] != 0u;
+        base = plan[0];
+        first = slot == (three ? 1 : 0);
+    }
+    __device__ int shift() const { return three ? (slot ? 8 * (slot - 1) : -1) : 8 * slot; }
+    __device__ uint32_t key(uint64_t e) const
+    {
+        if (!first) return k[e];
+        const uint32_t c = cnt[e];
+        if (!c) return 0xFFFFFFFFu;
+        const uint32_t w = wbits[e];
+        return three ? ((w - base) | (min(c, 255u) << 24)) : w;
+    }
+    __device__ uint32_t val(uint64_t e) const { return first ? (uint32_t)e : v[e]; }
+};
+
+// per-workgroup digit counts of a pass (skipped, like its scatter, when the
+// source's shift is negative)
+template <typename K, typename Src>
+__global__ __launch_bounds__(kT) void k_radix_hist(Src src, const uint32_t *count, uint64_t cap, uint32_t *hist,
+                                                   uint32_t nblk)
 {
     __shared__ uint32_t h[256];
+    src.init();
+    const int shift = src.shift();
+    if (shift < 0) return;  // uniform for the grid
     h[threadIdx.x] = 0;
     __syncthreads();
     const uint64_t N = min((uint64_t)*count, cap);
@@ -395,7 +532,7 @@ __global__ __launch_bounds__(kT) void k_radix_hist(const K *keys, const uint32_t
 #pragma unroll
     for (int r = 0; r < kScanItems; ++r) {
         const uint64_t e = base + (uint64_t)r * kT;
-        if (e < N) atomicAdd(&h[(uint32_t)(keys[e] >> shift) & 255u], 1u);
+        if (e < N) atomicAdd(&h[(uint32_t)(src.key(e) >> shift) & 255u], 1u);
     }
     __syncthreads();
     hist[(uint64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
@@ -411,10 +548,9 @@ __global__ __launch_bounds__(kT) void k_radix_hist(const K *keys, const uint32_t
 // (ballot match on the 8 digit bits).  The per-wave counts are then combined
 // into block offsets, the block is reordered in LDS, and written out with
 // consecutive threads on consecutive destinations.
-template <typename K>
-__global__ __launch_bounds__(kT) void k_radix_scatter(const K *kin, const uint32_t *vin, K *kout, uint32_t *vout,
-                                                      const uint32_t *count, uint64_t cap, int shift,
-                                                      const uint32_t *offs, uint32_t nblk)
+template <typename K, typename Src>
+__global__ __launch_bounds__(kT) void k_radix_scatter(Src src, K *kout, uint32_t *vout, const uint32_t *count,
+                                                      uint64_t cap, const uint32_t *offs, uint32_t nblk)
 {
     constexpr int NW = kT / 64;
     constexpr int PER_WAVE = kScanTile / NW;
@@ -424,6 +560,9 @@ __global__ __launch_bounds__(kT) void k_radix_scatter(const K *kin, const uint32
     __shared__ uint32_t bstart[256];
     __shared__ uint32_t lds4[NW];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    src.init();
+    const int shift = src.shift();
+    if (shift < 0) return;  // uniform for the grid
     const uint64_t N = min((uint64_t)*count, cap);
     const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
     if (base >= N) return;  // uniform for the workgroup
@@ -435,8 +574,8 @@ __global__ __launch_bounds__(kT) void k_radix_scatter(const K *kin, const uint32
     for (int r = 0; r < kScanItems; ++r) {
         const uint64_t e = base + (uint64_t)wid * PER_WAVE + (uint64_t)r * 64 + lane;
         const bool ok = e < N;
-        k[r] = ok ? kin[e] : (K)0;
-        v[r] = ok ? vin[e] : 0u;
+        k[r] = ok ? src.key(e) : (K)0;
+        v[r] = ok ? src.val(e) : 0u;
         dig[r] = ok ? ((uint32_t)(k[r] >> shift) & 255u) : 256u;
     }
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -529,44 +668,84 @@ struct BlendArgs {
     const float2 *ctr;
     const float4 *col;
     const float4 *conic;  // ANISO: per point Q00, Q01, Q11
+    const float2 *ext;    // ANISO: per point footprint half extents
     float *img;
     int32_t W, H, tiles_x;
-    float cut2, inv2s2, opacity;
+    float reach, cut2, inv2s2, opacity;
 };
 
 // ANISO: a Gaussian reaches a pixel when its quadratic form
 // q = ((Q00 dx) dx + ((Q01 dx) dy) 2) + (Q11 dy) dy is at most 9 (3 sigma),
 // alpha = min(0.99, opacity exp(-q / 2)); otherwise d2 = dx^2 + dy^2 against
 // (3 sigma)^2 and alpha = min(0.99, opacity exp(-d2 / 2 sigma^2)).
+//
+// One workgroup per 16x16 tile, each wave an 8x8 quarter of it.  The tile's
+// list is staged through LDS kT entries at a time; while staging, every
+// entry is tested against the four quarters with the footprint rectangle the
+// tile binning uses (a pixel outside it is never reached), and each wave
+// then walks only its own entries, in list order.
 template <bool ANISO>
 __global__ __launch_bounds__(kT) void k_splat_blend(BlendArgs B)
 {
+    constexpr int NW = kT / 64;
     __shared__ float2 sc[kT];
     __shared__ float4 scol[kT];
     __shared__ float4 sq[ANISO ? kT : 1];
+    __shared__ uint8_t sreach[kT];     // bit w: the entry's rectangle meets quarter w
+    __shared__ uint8_t wlist[NW][kT];  // each wave's entries of the batch
     const int tile = blockIdx.x;
     const int tx = tile % B.tiles_x, ty = tile / B.tiles_x;
-    const int px = tx * kTile + (threadIdx.x % kTile);
-    const int py = ty * kTile + (threadIdx.x / kTile);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int px = tx * kTile + (wid & 1) * 8 + (lane & 7);
+    const int py = ty * kTile + (wid >> 1) * 8 + (lane >> 3);
     const bool inside = px < B.W && py < B.H;
     const uint32_t N = (uint32_t)min((uint64_t)*B.count, B.cap);
     const uint32_t start = B.range[2 * tile], stop = min(B.range[2 * tile + 1], N);
     const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     float T = 1.0f, r = 0.0f, g = 0.0f, b = 0.0f;
     bool done = !inside;
     for (uint32_t s0 = start; s0 < stop; s0 += kT) {
         if (__syncthreads_count(!done) == 0) break;
         const uint32_t e = s0 + threadIdx.x;
+        uint32_t bits = 0u;
         if (e < stop) {
             const uint32_t i = B.vals[e];
             const bool ok = i < B.n;  // always true for consistent lists
-            sc[threadIdx.x] = ok ? B.ctr[i] : make_float2(-1e30f, -1e30f);
+            const float2 c = ok ? B.ctr[i] : make_float2(-1e30f, -1e30f);
+            sc[threadIdx.x] = c;
             scol[threadIdx.x] = ok ? B.col[i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            if (ANISO) sq[threadIdx.x] = ok ? B.conic[i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            float rx = B.reach, ry = B.reach;
+            if (ANISO) {
+                sq[threadIdx.x] = ok ? B.conic[i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                const float2 ex = ok ? B.ext[i] : make_float2(0.0f, 0.0f);
+                rx = ex.x;
+                ry = ex.y;
+            }
+            if (ok) {
+                int x0, x1, y0, y1;
+                pixel_rect(B.W, B.H, c.x, c.y, rx, ry, x0, x1, y0, y1);
+#pragma unroll
+                for (int w = 0; w < NW; ++w) {
+                    const int qx = tx * kTile + (w & 1) * 8, qy = ty * kTile + (w >> 1) * 8;
+                    if (x0 <= qx + 7 && x1 >= qx && y0 <= qy + 7 && y1 >= qy) bits |= 1u << w;
+                }
+            }
         }
+        sreach[threadIdx.x] = (uint8_t)bits;
         __syncthreads();
-        const int m = (int)min((uint32_t)kT, stop - s0);
-        for (int j = 0; j < m && !done; ++j) {
+        // this wave's entries, in list order (a wave's LDS operations complete in order)
+        int mine = 0;
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            const bool f = (sreach[k * 64 + lane] >> wid) & 1u;
+            const unsigned long long m = __ballot(f);
+            if (f) wlist[wid][mine + __popcll(m & below)] = (uint8_t)(k * 64 + lane);
+            mine += __popcll(m);
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (int k = 0; k < mine && !done; ++k) {
+            const int j = wlist[wid][k];
             const float2 c = sc[j];
             const float dx = fx - c.x;
             const float dy = fy - c.y;
@@ -653,6 +832,9 @@ SplatLayout splat_layout(uint64_t n, int32_t W, int32_t H, float sigma, bool ani
     L.off_range = o; o = align256(o + (uint64_t)L.tiles_x * L.tiles_y * 8);
     L.off_conic = o; o = align256(o + (aniso ? n * sizeof(float4) : 0));
     L.off_ext = o; o = align256(o + (aniso ? n * sizeof(float2) : 0));
+    L.off_brange = o; o = align256(o + (n + 1 + kT - 1) / kT * sizeof(uint2));
+    L.off_part = o; o = align256(o + kRangeParts * sizeof(uint2));
+    L.off_plan = o; o = align256(o + 2 * 4);
     L.bytes = o;
     int bits = 1;
     while ((1ull << bits) < (uint64_t)L.tiles_x * L.tiles_y) ++bits;
@@ -704,6 +886,7 @@ hipError_t launch_splat_count(const float *x, const float *y, const float *z, ui
     S.col = reinterpret_cast<float4 *>(base + L.off_col);
     S.wbits = reinterpret_cast<uint32_t *>(base + L.off_wbits);
     S.cnt = reinterpret_cast<uint32_t *>(base + L.off_cnt);
+    S.brange = reinterpret_cast<uint2 *>(base + L.off_brange);
     S.cap = L.cap;
     S.aniso = prm.aniso;
     S.vel_attr = prm.vel_attr;
@@ -735,11 +918,12 @@ static hipError_t radix_sort(K *ka, uint32_t *va, K *kb, uint32_t *vb, const uin
     const uint32_t nblk = (uint32_t)(nblk64 ? nblk64 : 1);
     bool b = false;
     for (int shift = 0; shift < key_bits; shift += 8) {
-        hipLaunchKernelGGL(k_radix_hist<K>, dim3(nblk), dim3(kT), 0, s, b ? kb : ka, count, cap, shift, hist, nblk);
+        const ArraySrc<K> src{b ? kb : ka, b ? vb : va, shift};
+        hipLaunchKernelGGL((k_radix_hist<K, ArraySrc<K>>), dim3(nblk), dim3(kT), 0, s, src, count, cap, hist, nblk);
         const hipError_t e = scan_excl(hist, hist, (uint64_t)nblk * 256, sums, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_radix_scatter<K>, dim3(nblk), dim3(kT), 0, s, b ? kb : ka, b ? vb : va, b ? ka : kb,
-                           b ? va : vb, count, cap, shift, hist, nblk);
+        hipLaunchKernelGGL((k_radix_scatter<K, ArraySrc<K>>), dim3(nblk), dim3(kT), 0, s, src, b ? ka : kb,
+                           b ? va : vb, count, cap, hist, nblk);
         b = !b;
     }
     *in_b = b;
@@ -794,6 +978,7 @@ hipError_t launch_splat(const float *x, const float *y, const float *z, uint64_t
     S.col = reinterpret_cast<float4 *>(base + L.off_col);
     S.wbits = reinterpret_cast<uint32_t *>(base + L.off_wbits);
     S.cnt = reinterpret_cast<uint32_t *>(base + L.off_cnt);
+    S.brange = reinterpret_cast<uint2 *>(base + L.off_brange);
     S.cap = L.cap;
     S.aniso = prm.aniso;
     S.vel_attr = prm.vel_attr;
@@ -818,27 +1003,44 @@ hipError_t launch_splat(const float *x, const float *y, const float *z, uint64_t
     const uint32_t *total = scnt + n;  // after the scan
     hipError_t e = hipSuccess;
     if (n > 0) {
-        // point order by depth (4 passes over 32 depth bits; ends in ka/va)
+        // point order by depth (three or four passes, chosen on the device;
+        // ends in ka/va)
+        const uint64_t nbp = (n + 1 + kT - 1) / kT;  // projection workgroups
+        const uint32_t nparts = (uint32_t)(nbp < (uint64_t)kRangeParts ? nbp : (uint64_t)kRangeParts);
+        auto *part = reinterpret_cast<uint2 *>(base + L.off_part);
+        auto *plan = reinterpret_cast<uint32_t *>(base + L.off_plan);
+        hipLaunchKernelGGL(k_range_partial, dim3(nparts), dim3(kT), 0, s, S.brange, nbp, part);
+        hipLaunchKernelGGL(k_depth_plan, dim3(1), dim3(kT), 0, s, part, nparts, plan);
         hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kT), 0, s, npts, (uint64_t)1, (uint32_t)n);
-        hipLaunchKernelGGL(k_depth_keys, dim3((unsigned)((n + kT - 1) / kT)), dim3(kT), 0, s, S, ka, va);
-        bool in_b = false;
-        e = radix_sort(ka, va, kb, vb, npts, n, 32, hist, sums, s, &in_b);
-        if (e != hipSuccess) return e;
-        const uint32_t *order = in_b ? vb : va;
-        uint32_t *pk = in_b ? ka : kb;  // the free pair of arrays
-        uint32_t *pv = in_b ? va : vb;
-        hipLaunchKernelGGL(k_gather_counts, dim3((unsigned)((n + 1 + kT - 1) / kT)), dim3(kT), 0, s, S.cnt, order, n,
-                           scnt);
+        const uint32_t nblk = (uint32_t)((n + kScanTile - 1) / kScanTile);
+        for (int slot = 0; slot < 4; ++slot) {
+            // slot 0 writes (kb, vb); then (kb, vb) -> (ka, va) -> (kb, vb) -> (ka, va)
+            const bool from_a = slot == 2;
+            const DepthSrc src{from_a ? ka : kb, from_a ? va : vb, S.wbits, S.cnt, plan, slot, 0u, false, false};
+            uint32_t *ko = (slot & 1) ? ka : kb;
+            uint32_t *vo = (slot & 1) ? va : vb;
+            hipLaunchKernelGGL((k_radix_hist<uint32_t, DepthSrc>), dim3(nblk), dim3(kT), 0, s, src, npts, n, hist,
+                               nblk);
+            e = scan_excl(hist, hist, (uint64_t)nblk * 256, sums, s);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL((k_radix_scatter<uint32_t, DepthSrc>), dim3(nblk), dim3(kT), 0, s, src, ko, vo, npts, n,
+                               hist, nblk);
+        }
+        const uint32_t *order = va;
+        uint32_t *pk = kb, *pv = vb;  // the free pair of arrays
+        hipLaunchKernelGGL(k_gather_counts, dim3((unsigned)((n + 1 + kT - 1) / kT)), dim3(kT), 0, s, S.cnt, order, ka,
+                           plan, n, scnt);
         e = scan_excl(scnt, scnt, n + 1, sums, s);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_splat_emit, dim3((unsigned)((n + kT - 1) / kT)), dim3(kT), 0, s, S, order, scnt, pk, pv);
         // pairs by tile, stable (depth order kept within a tile)
-        uint32_t *qk = in_b ? kb : ka;
-        uint32_t *qv = in_b ? vb : va;
-        e = radix_sort(pk, pv, qk, qv, total, L.cap, L.key_bits, hist, sums, s, &in_b);
+        bool in_b = false;
+        e = radix_sort(pk, pv, ka, va, total, L.cap, L.key_bits, hist, sums, s, &in_b);
         if (e != hipSuccess) return e;
-        ka = in_b ? qk : pk;
-        va = in_b ? qv : pv;
+        if (!in_b) {
+            ka = pk;
+            va = pv;
+        }
     } else {
         hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kT), 0, s, scnt, (uint64_t)1, 0u);
     }
@@ -853,11 +1055,13 @@ hipError_t launch_splat(const float *x, const float *y, const float *z, uint64_t
     B.ctr = S.ctr;
     B.col = S.col;
     B.conic = S.conic;
+    B.ext = S.ext;
     B.img = img;
     B.W = P.W;
     B.H = P.H;
     B.tiles_x = L.tiles_x;
     const float reach = 3.0f * prm.sigma_px;
+    B.reach = reach;
     B.cut2 = reach * reach;
     B.inv2s2 = 1.0f / (2.0f * prm.sigma_px * prm.sigma_px);
     B.opacity = prm.opacity;

@@ -104,6 +104,55 @@ def test_rgb8_dense_overlap_and_termination():
     compare(got, want, frag)
 
 
+@pytest.mark.parametrize("far_point", [False, True])
+@pytest.mark.parametrize("aniso", [False, True])
+def test_depth_sort_pass_counts(far_point, aniso):
+    """The point sort runs three radix passes when the kept depths span under
+    2^24 - 1 fp32 ulps and four otherwise, and with three it carries the tile
+    count in the key (255 and up are read back from the counts): depths in
+    [1, 1.5] with exact ties, alone and with one point at depth 8; the
+    anisotropic case (sigma 8 px, s = 300) has footprints of hundreds of
+    tiles."""
+    announce(f"depth sort pass count: far point {far_point}, anisotropic {aniso}")
+    rng = np.random.default_rng(31)
+    n, W, H = 3000, 480, 400
+    d = (1.0 + rng.random(n) * 0.5).astype(np.float32)
+    d[::5] = d[0]  # exact depth ties
+    x = ((rng.random(n) * 1.2 - 0.6) * d).astype(np.float32)
+    y = ((rng.random(n) * 1.0 - 0.5) * d).astype(np.float32)
+    z = -d
+    if far_point:
+        x[n // 2], y[n // 2], z[n // 2] = 0.0, 0.0, -8.0
+    v = rng.standard_normal((3, n)).astype(np.float32)
+    speed = rng.random(n).astype(np.float32)
+    attrs = [v[0], v[1], v[2], speed]
+    cam = scenes.Camera(eye=(0, 0, 0), target=(0, 0, -1), up=(0, 1, 0))
+    M, near, far = ocam.clip_matrix(cam, W, H)
+    Mf = np.asarray(M, np.float32).reshape(4, 4)
+    w = ((Mf[3, 0] * x + Mf[3, 1] * y) + Mf[3, 2] * z) + Mf[3, 3]
+    bits = w.view(np.uint32).astype(np.int64)
+    span = int(bits.max() - bits.min())
+    assert (span > 0xFFFFFE) == far_point, span  # the case exercises the pass count it names
+    lut = scenes.colour_lut()
+    sigma = 8.0 if aniso else 1.5
+    params = narvis.SplatParams(sigma_px=sigma, opacity=0.6, color_mode=narvis.COLOR_LUT, color_attr=3,
+                                lut=dev(lut), lut_min=0.0, lut_inv_range=1.0)
+    if aniso:
+        params.aniso, params.vel_attr, params.stretch = 1, 0, 300.0
+        got, pairs = gpu_splat_aniso(dev(x), dev(y), dev(z), [dev(a) for a in attrs], n, cam, W, H, params)
+        assert pairs > 255 * n  # so some footprint covers more than 255 tiles
+        want, frag = osplat.splat_aniso(x, y, z, M, near, far, W, H, attrs, vel_attr=0, stretch=300.0, sigma=sigma,
+                                        opacity=0.6, focal_px=ocam.focal_px(cam, H), lut=lut, lut_attr=3,
+                                        lut_min=0.0, lut_inv_range=1.0, with_fragile=True)
+    else:
+        got = gpu_splat(x, y, z, attrs, cam, W, H, params)
+        want, frag = osplat.splat(x, y, z, M, near, far, W, H, attrs, sigma=sigma, opacity=0.6,
+                                  color_mode=osplat.COLOR_LUT, lut=lut, lut_attr=3, lut_min=0.0, lut_inv_range=1.0,
+                                  with_fragile=True)
+    dd = compare(got, want, frag)
+    print(f"  depth span {span} ulps, max err {dd.max():.3g}", flush=True)
+
+
 @pytest.mark.parametrize("sigma", [0.7, 3.0])
 def test_sigma_and_opacity(sigma):
     announce(f"sigma={sigma} opacity=0.3")
