@@ -547,7 +547,8 @@ __global__ __launch_bounds__(kT) void k_radix_hist(Src src, const uint32_t *coun
 // so no barrier is needed) plus the equal digits at lower lanes of its round
 // (ballot match on the 8 digit bits).  The per-wave counts are then combined
 // into block offsets, the block is reordered in LDS, and written out with
-// consecutive threads on consecutive destinations.
+// consecutive threads on consecutive destinations.  The block's 256 output
+// offsets are read once, early, so that their latency overlaps the ranking.
 template <typename K, typename Src>
 __global__ __launch_bounds__(kT) void k_radix_scatter(Src src, K *kout, uint32_t *vout, const uint32_t *count,
                                                       uint64_t cap, const uint32_t *offs, uint32_t nblk)
@@ -558,6 +559,7 @@ __global__ __launch_bounds__(kT) void k_radix_scatter(Src src, K *kout, uint32_t
     __shared__ uint32_t sval[kScanTile];
     __shared__ uint32_t wcnt[NW][256];  // running digit counts of each wave, then each wave's offset
     __shared__ uint32_t bstart[256];
+    __shared__ uint32_t sdst[256];
     __shared__ uint32_t lds4[NW];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     src.init();
@@ -568,6 +570,7 @@ __global__ __launch_bounds__(kT) void k_radix_scatter(Src src, K *kout, uint32_t
     if (base >= N) return;  // uniform for the workgroup
 #pragma unroll
     for (int w = 0; w < NW; ++w) wcnt[w][threadIdx.x] = 0u;
+    const uint32_t myoff = offs[(uint64_t)threadIdx.x * nblk + blockIdx.x];  // digit threadIdx.x
     K k[kScanItems];
     uint32_t v[kScanItems], rank[kScanItems], dig[kScanItems];
 #pragma unroll
@@ -608,7 +611,9 @@ __global__ __launch_bounds__(kT) void k_radix_scatter(Src src, K *kout, uint32_t
         tot += c;
     }
     uint32_t total;
-    bstart[threadIdx.x] = block_excl_scan(tot, lds4, &total);
+    const uint32_t bs = block_excl_scan(tot, lds4, &total);
+    bstart[threadIdx.x] = bs;
+    sdst[threadIdx.x] = myoff - bs;  // output index = sdst[digit] + position in the reordered block
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kScanItems; ++r) {
@@ -625,7 +630,7 @@ __global__ __launch_bounds__(kT) void k_radix_scatter(Src src, K *kout, uint32_t
     for (uint32_t i = threadIdx.x; i < inblock; i += kT) {
         const K key = skey[i];
         const uint32_t d = (uint32_t)(key >> shift) & 255u;
-        const uint64_t dst = (uint64_t)offs[(uint64_t)d * nblk + blockIdx.x] + (i - bstart[d]);
+        const uint64_t dst = (uint64_t)(sdst[d] + i);
         if (dst < N) {  // always true for a consistent histogram; guards the buffer regardless
             kout[dst] = key;
             vout[dst] = sval[i];
@@ -643,21 +648,47 @@ __global__ __launch_bounds__(kT) void k_fill_u32(uint32_t *p, uint64_t cnt, uint
     if (i < cnt) p[i] = v;
 }
 
+// First and one-past-last position of every tile in the sorted pair keys.
+// Each thread reads kRangeItems consecutive keys; the neighbours across
+// threads come from the adjacent lanes, and the wave's end lanes read theirs.
+constexpr int kRangeItems = 16;
+
 __global__ __launch_bounds__(kT) void k_tile_ranges(const uint32_t *keys, const uint32_t *count, uint64_t cap,
                                                     uint32_t *range, uint32_t ntiles)
 {
-    const uint64_t p = (uint64_t)blockIdx.x * kT + threadIdx.x;
     const uint64_t N = min((uint64_t)*count, cap);
-    if ((uint64_t)blockIdx.x * kT >= N) return;  // uniform for the workgroup
-    // neighbours from the adjacent lanes; the wave's end lanes read their own
+    if ((uint64_t)blockIdx.x * kT * kRangeItems >= N) return;  // uniform for the workgroup
+    const uint64_t p0 = ((uint64_t)blockIdx.x * kT + threadIdx.x) * kRangeItems;
+    uint32_t t[kRangeItems];
+    if (p0 + kRangeItems <= N) {
+        // 64-byte aligned: the key array is 256-byte aligned and p0 a multiple of 16
+        const uint4 *q = reinterpret_cast<const uint4 *>(keys + p0);
+#pragma unroll
+        for (int k = 0; k < kRangeItems / 4; ++k) {
+            const uint4 v = q[k];
+            t[4 * k] = v.x;
+            t[4 * k + 1] = v.y;
+            t[4 * k + 2] = v.z;
+            t[4 * k + 3] = v.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kRangeItems; ++k) t[k] = p0 + k < N ? keys[p0 + k] : 0xFFFFFFFFu;
+    }
     const int lane = threadIdx.x & 63;
-    const uint32_t t = p < N ? keys[p] : 0xFFFFFFFFu;
-    uint32_t prev = __shfl_up(t, 1), next = __shfl_down(t, 1);
-    if (lane == 0) prev = p > 0 && p - 1 < N ? keys[p - 1] : 0xFFFFFFFFu;
-    if (lane == 63) next = p + 1 < N ? keys[p + 1] : 0xFFFFFFFFu;
-    if (p >= N || t >= ntiles) return;
-    if (p == 0 || prev != t) range[2 * t] = (uint32_t)p;
-    if (p + 1 == N || next != t) range[2 * t + 1] = (uint32_t)(p + 1);
+    uint32_t prev = __shfl_up(t[kRangeItems - 1], 1), next = __shfl_down(t[0], 1);
+    if (lane == 0) prev = p0 > 0 && p0 - 1 < N ? keys[p0 - 1] : 0xFFFFFFFFu;
+    if (lane == 63) next = p0 + kRangeItems < N ? keys[p0 + kRangeItems] : 0xFFFFFFFFu;
+#pragma unroll
+    for (int k = 0; k < kRangeItems; ++k) {
+        const uint64_t p = p0 + k;
+        const uint32_t cur = t[k];
+        if (p >= N || cur >= ntiles) continue;
+        const uint32_t before = k ? t[k - 1] : prev;
+        const uint32_t after = k + 1 < kRangeItems ? t[k + 1] : next;
+        if (p == 0 || before != cur) range[2 * cur] = (uint32_t)p;
+        if (p + 1 == N || after != cur) range[2 * cur + 1] = (uint32_t)(p + 1);
+    }
 }
 
 struct BlendArgs {
@@ -681,9 +712,10 @@ struct BlendArgs {
 //
 // One workgroup per 16x16 tile, each wave an 8x8 quarter of it.  The tile's
 // list is staged through LDS kT entries at a time; while staging, every
-// entry is tested against the four quarters with the footprint rectangle the
-// tile binning uses (a pixel outside it is never reached), and each wave
-// then walks only its own entries, in list order.
+// entry is tested against the four quarters (isotropic: the disc against the
+// quarter's nearest pixel centre; anisotropic: the footprint rectangle the
+// tile binning uses), and each wave then walks only its own entries, in list
+// order.  Neither test drops an entry that reaches a pixel of the quarter.
 template <bool ANISO>
 __global__ __launch_bounds__(kT) void k_splat_blend(BlendArgs B)
 {
@@ -722,7 +754,22 @@ __global__ __launch_bounds__(kT) void k_splat_blend(BlendArgs B)
                 rx = ex.x;
                 ry = ex.y;
             }
-            if (ok) {
+            if (ok && !ANISO) {
+                // the quarter's pixel centres nearest to the centre, in the
+                // pixel test's own arithmetic: no pixel of the quarter gets a
+                // smaller d2 (rounding is monotonic)
+#pragma unroll
+                for (int w = 0; w < NW; ++w) {
+                    const float ax = (float)(tx * kTile + (w & 1) * 8) + 0.5f;
+                    const float ay = (float)(ty * kTile + (w >> 1) * 8) + 0.5f;
+                    const float bx = ax + 7.0f, by = ay + 7.0f;
+                    const float dx = c.x < ax ? ax - c.x : (c.x > bx ? c.x - bx : 0.0f);
+                    const float dy = c.y < ay ? ay - c.y : (c.y > by ? c.y - by : 0.0f);
+                    float d2 = dx * dx;
+                    d2 = d2 + dy * dy;
+                    if (d2 <= B.cut2) bits |= 1u << w;
+                }
+            } else if (ok) {
                 int x0, x1, y0, y1;
                 pixel_rect(B.W, B.H, c.x, c.y, rx, ry, x0, x1, y0, y1);
 #pragma unroll
@@ -1044,7 +1091,8 @@ hipError_t launch_splat(const float *x, const float *y, const float *z, uint64_t
     } else {
         hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kT), 0, s, scnt, (uint64_t)1, 0u);
     }
-    hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)((L.cap + kT - 1) / kT > 0 ? (L.cap + kT - 1) / kT : 1)), dim3(kT),
+    const uint64_t rblocks = (L.cap + (uint64_t)kT * kRangeItems - 1) / ((uint64_t)kT * kRangeItems);
+    hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)(rblocks ? rblocks : 1)), dim3(kT),
                        0, s, ka, total, L.cap, range, (uint32_t)ntiles);
     BlendArgs B;
     B.n = n;
