@@ -351,10 +351,12 @@ uint64_t narvis_layout_samples(uint64_t n);
  * and a little more); 0 for n >= 2^32. */
 size_t narvis_layout_workspace_size(uint64_t n);
 
-/* Build the layout of the n points `pts` (original order, device, any
- * alignment) into `out` (see narvis_layout; every array 16-byte aligned and
- * disjoint from the input).  n < 2^32.  INVALID_ARG on bad arguments,
- * WORKSPACE if ws_bytes is too small.  Asynchronous on `stream`. */
+/* Build the layout of the n points `pts` (original order, device, 4-byte
+ * aligned) into `out` (see narvis_layout; every array 16-byte aligned and
+ * disjoint from the input), using the device workspace `ws` (256-byte
+ * aligned, caller-owned, contents overwritten).  n < 2^32.  INVALID_ARG on
+ * bad arguments, WORKSPACE if ws_bytes is too small.  Asynchronous on
+ * `stream`. */
 narvis_status narvis_layout_build(const narvis_points *pts, uint64_t n, const narvis_layout *out, void *ws,
                                   size_t ws_bytes, void *stream);
 

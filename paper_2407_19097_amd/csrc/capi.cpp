@@ -312,6 +312,7 @@ extern "C" narvis_status narvis_layout_build(const narvis_points *pts, uint64_t 
                    reinterpret_cast<uintptr_t>(pts->z)) & 3u))
         return NARVIS_ERR_INVALID_ARG;
     if (!ws || ws_bytes < narvis_layout_workspace_size(n)) return NARVIS_ERR_WORKSPACE;
+    if (reinterpret_cast<uintptr_t>(ws) & 255u) return NARVIS_ERR_INVALID_ARG;
     if (n == 0) return NARVIS_OK;
     // the outputs must not overlap the inputs (the gather reads them)
     const uintptr_t in[3] = {reinterpret_cast<uintptr_t>(pts->x), reinterpret_cast<uintptr_t>(pts->y),

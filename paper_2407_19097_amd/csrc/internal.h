@@ -110,7 +110,8 @@ hipError_t launch_layout(const float *x, const float *y, const float *z, uint64_
                          uint32_t *ix, float *box, float *sx, float *sy, float *sz, uint32_t *six, float *sbox,
                          void *ws, hipStream_t s);
 
-// Stable LSD radix sort (8-bit digits) of the first min(*count, cap) (key,
+// Stable LSD radix sort (ceil(key_bits / 8) passes of equal digit width, at
+// most 8 bits) of the first min(*count, cap) (key,
 // value) pairs by the low key_bits bits of the keys, ping-ponging between
 // (ka, va) and (kb, vb); *in_b tells where the result ends.  hist and sums
 // hold radix_sort_hist_len(cap) and radix_sort_sums_len(cap) uint32.

@@ -380,7 +380,9 @@ __global__ __launch_bounds__(kT) void k_splat_emit(SplatArgs S, const uint32_t *
 }
 
 // ---------------------------------------------------------------------------
-// exclusive prefix sum of uint32 (three passes: tile sums, scan of sums, apply)
+// exclusive prefix sum of uint32 (three passes: tile sums, scan of sums,
+// apply); each thread takes kScanItems consecutive elements as 16-byte loads
+// and stores (every array scanned here is 256-byte aligned)
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
@@ -418,9 +420,18 @@ __global__ __launch_bounds__(kT) void k_scan_sums(const uint32_t *in, uint64_t l
     __shared__ uint32_t lds4[kT / 64];
     const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
     uint32_t s = 0;
+    if (base + kScanItems <= len) {
+        const uint4 *q = reinterpret_cast<const uint4 *>(in + base);
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k)
-        if (base + k < len) s += in[base + k];
+        for (int k = 0; k < kScanItems / 4; ++k) {
+            const uint4 v = q[k];
+            s += (v.x + v.y) + (v.z + v.w);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k)
+            if (base + k < len) s += in[base + k];
+    }
     uint32_t total;
     block_excl_scan(s, lds4, &total);
     if (threadIdx.x == 0) sums[blockIdx.x] = total;
@@ -451,17 +462,39 @@ __global__ __launch_bounds__(kT) void k_scan_apply(const uint32_t *in, uint32_t 
     const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
     uint32_t v[kScanItems];
     uint32_t s = 0;
+    const bool full = base + kScanItems <= len;
+    if (full) {
+        const uint4 *q = reinterpret_cast<const uint4 *>(in + base);
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        v[k] = base + k < len ? in[base + k] : 0u;
-        s += v[k];
+        for (int k = 0; k < kScanItems / 4; ++k) {
+            const uint4 x = q[k];
+            v[4 * k] = x.x;
+            v[4 * k + 1] = x.y;
+            v[4 * k + 2] = x.z;
+            v[4 * k + 3] = x.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) v[k] = base + k < len ? in[base + k] : 0u;
     }
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) s += v[k];
     uint32_t total;
     uint32_t run = block_excl_scan(s, lds4, &total) + sums[blockIdx.x];
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        if (base + k < len) out[base + k] = run;
-        run += v[k];
+        const uint32_t x = v[k];
+        v[k] = run;
+        run += x;
+    }
+    if (full) {
+        uint4 *q = reinterpret_cast<uint4 *>(out + base);
+#pragma unroll
+        for (int k = 0; k < kScanItems / 4; ++k) q[k] = make_uint4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k)
+            if (base + k < len) out[base + k] = v[k];
     }
 }
 
@@ -476,8 +509,10 @@ struct ArraySrc {
     const K *k;
     const uint32_t *v;
     int sh;
+    uint32_t msk;  // digit mask: 2^(digit bits) - 1, at most 255
     __device__ void init() {}
     __device__ int shift() const { return sh; }
+    __device__ uint32_t mask() const { return msk; }
     __device__ K key(uint64_t e) const { return k[e]; }
     __device__ uint32_t val(uint64_t e) const { return v[e]; }
 };
@@ -504,6 +539,7 @@ struct DepthSrc {
         first = slot == (three ? 1 : 0);
     }
     __device__ int shift() const { return three ? (slot ? 8 * (slot - 1) : -1) : 8 * slot; }
+    __device__ uint32_t mask() const { return 255u; }
     __device__ uint32_t key(uint64_t e) const
     {
         if (!first) return k[e];
@@ -515,7 +551,8 @@ struct DepthSrc {
     __device__ uint32_t val(uint64_t e) const { return first ? (uint32_t)e : v[e]; }
 };
 
-// per-workgroup digit counts of a pass (skipped, like its scatter, when the
+// per-workgroup digit counts of a pass, hist[digit * nblk + workgroup] for
+// the digits under the source's mask (skipped, like its scatter, when the
 // source's shift is negative)
 template <typename K, typename Src>
 __global__ __launch_bounds__(kT) void k_radix_hist(Src src, const uint32_t *count, uint64_t cap, uint32_t *hist,
@@ -525,6 +562,7 @@ __global__ __launch_bounds__(kT) void k_radix_hist(Src src, const uint32_t *coun
     src.init();
     const int shift = src.shift();
     if (shift < 0) return;  // uniform for the grid
+    const uint32_t mask = src.mask();
     h[threadIdx.x] = 0;
     __syncthreads();
     const uint64_t N = min((uint64_t)*count, cap);
@@ -532,10 +570,10 @@ __global__ __launch_bounds__(kT) void k_radix_hist(Src src, const uint32_t *coun
 #pragma unroll
     for (int r = 0; r < kScanItems; ++r) {
         const uint64_t e = base + (uint64_t)r * kT;
-        if (e < N) atomicAdd(&h[(uint32_t)(src.key(e) >> shift) & 255u], 1u);
+        if (e < N) atomicAdd(&h[(uint32_t)(src.key(e) >> shift) & mask], 1u);
     }
     __syncthreads();
-    hist[(uint64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+    if (threadIdx.x <= mask) hist[(uint64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
 }
 
 // One LSD pass: each workgroup moves its kScanTile elements to the offsets
@@ -565,6 +603,7 @@ __global__ __launch_bounds__(kT) void k_radix_scatter(Src src, K *kout, uint32_t
     src.init();
     const int shift = src.shift();
     if (shift < 0) return;  // uniform for the grid
+    const uint32_t mask = src.mask();
     const uint64_t N = min((uint64_t)*count, cap);
     const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
     if (base >= N) return;  // uniform for the workgroup
@@ -579,7 +618,7 @@ __global__ __launch_bounds__(kT) void k_radix_scatter(Src src, K *kout, uint32_t
         const bool ok = e < N;
         k[r] = ok ? src.key(e) : (K)0;
         v[r] = ok ? src.val(e) : 0u;
-        dig[r] = ok ? ((uint32_t)(k[r] >> shift) & 255u) : 256u;
+        dig[r] = ok ? ((uint32_t)(k[r] >> shift) & mask) : 256u;
     }
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     __syncthreads();
@@ -590,6 +629,7 @@ __global__ __launch_bounds__(kT) void k_radix_scatter(Src src, K *kout, uint32_t
         unsigned long long m = __ballot(d < 256u);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
+            if (!((mask >> b) & 1u)) break;  // uniform: the digit has no more bits
             const unsigned long long bb = __ballot((d >> b) & 1u);
             m &= ((d >> b) & 1u) ? bb : ~bb;
         }
@@ -629,7 +669,7 @@ __global__ __launch_bounds__(kT) void k_radix_scatter(Src src, K *kout, uint32_t
     const uint32_t inblock = (uint32_t)min((uint64_t)kScanTile, N - base);
     for (uint32_t i = threadIdx.x; i < inblock; i += kT) {
         const K key = skey[i];
-        const uint32_t d = (uint32_t)(key >> shift) & 255u;
+        const uint32_t d = (uint32_t)(key >> shift) & mask;
         const uint64_t dst = (uint64_t)(sdst[d] + i);
         if (dst < N) {  // always true for a consistent histogram; guards the buffer regardless
             kout[dst] = key;
@@ -957,17 +997,24 @@ hipError_t launch_splat_count(const float *x, const float *y, const float *z, ui
     return hipSuccess;
 }
 
+// ceil(key_bits / 8) passes of equal width (the last one takes what is left):
+// 13-bit tile ids sort in passes of 7 and 6 bits, whose 128 and 64 digits
+// give longer runs per digit in the scatter than 8 and 5 would
 template <typename K>
 static hipError_t radix_sort(K *ka, uint32_t *va, K *kb, uint32_t *vb, const uint32_t *count, uint64_t cap,
                              int key_bits, uint32_t *hist, uint32_t *sums, hipStream_t s, bool *in_b)
 {
     const uint64_t nblk64 = (cap + kScanTile - 1) / kScanTile;
     const uint32_t nblk = (uint32_t)(nblk64 ? nblk64 : 1);
+    const int passes = (key_bits + 7) / 8;
+    const int width = passes ? (key_bits + passes - 1) / passes : 8;
     bool b = false;
-    for (int shift = 0; shift < key_bits; shift += 8) {
-        const ArraySrc<K> src{b ? kb : ka, b ? vb : va, shift};
+    for (int shift = 0; shift < key_bits; shift += width) {
+        const int bits = key_bits - shift < width ? key_bits - shift : width;
+        const uint32_t mask = (1u << bits) - 1u;
+        const ArraySrc<K> src{b ? kb : ka, b ? vb : va, shift, mask};
         hipLaunchKernelGGL((k_radix_hist<K, ArraySrc<K>>), dim3(nblk), dim3(kT), 0, s, src, count, cap, hist, nblk);
-        const hipError_t e = scan_excl(hist, hist, (uint64_t)nblk * 256, sums, s);
+        const hipError_t e = scan_excl(hist, hist, (uint64_t)nblk * (mask + 1u), sums, s);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_radix_scatter<K, ArraySrc<K>>), dim3(nblk), dim3(kT), 0, s, src, b ? ka : kb,
                            b ? va : vb, count, cap, hist, nblk);

@@ -143,6 +143,12 @@ def test_invalid_arguments_rejected_before_any_launch():
     cam = narvis.camera_struct(scenes.Camera(eye=(1, 1, 1), target=(1, 1, 1)))
     assert L.narvis_rasterize(ctypes.byref(pts), ctypes.byref(a), 10, ctypes.byref(cam), 8, 8, ctypes.byref(g),
                               None) == -1
+    # layout build: the workspace must be 256-byte aligned
+    n = 1000
+    lay = _lib.Layout(0x100000, 0x200000, 0x300000, 0x400000, 0x500000)
+    wsz = L.narvis_layout_workspace_size(n)
+    assert L.narvis_layout_build(ctypes.byref(pts), n, ctypes.byref(lay), 0x1000000 + 16, wsz, None) == -1
+    assert L.narvis_layout_build(ctypes.byref(pts), n, ctypes.byref(lay), 0x1000000, wsz - 1, None) == -5
     # whole frame with a hint: without a scratch, misaligned, or over the keys
     good_cam = narvis.camera_struct(scenes.Camera(eye=(2, 2, 2), target=(0, 0, 0)))
     nb = L.narvis_raster_bounds_bytes(8, 8)
