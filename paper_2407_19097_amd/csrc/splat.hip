@@ -751,20 +751,21 @@ struct BlendArgs {
 // (3 sigma)^2 and alpha = min(0.99, opacity exp(-d2 / 2 sigma^2)).
 //
 // One workgroup per 16x16 tile, each wave an 8x8 quarter of it.  The tile's
-// list is staged through LDS kT entries at a time; while staging, every
-// entry is tested against the four quarters (isotropic: the disc against the
+// list is taken kT entries at a time, one per thread, fetched a batch ahead
+// so that the loads overlap the compositing of the batch before.  Each entry
+// is tested against the four quarters (isotropic: the disc against the
 // quarter's nearest pixel centre; anisotropic: the footprint rectangle the
-// tile binning uses), and each wave then walks only its own entries, in list
-// order.  Neither test drops an entry that reaches a pixel of the quarter.
+// tile binning uses; neither drops an entry that reaches a pixel of the
+// quarter) and copied into the LDS list of every quarter it can reach, in
+// list order; each wave then composites its own list.
 template <bool ANISO>
 __global__ __launch_bounds__(kT) void k_splat_blend(BlendArgs B)
 {
     constexpr int NW = kT / 64;
-    __shared__ float2 sc[kT];
-    __shared__ float4 scol[kT];
-    __shared__ float4 sq[ANISO ? kT : 1];
-    __shared__ uint8_t sreach[kT];     // bit w: the entry's rectangle meets quarter w
-    __shared__ uint8_t wlist[NW][kT];  // each wave's entries of the batch
+    __shared__ float2 lc[NW][kT];    // per quarter: centres of the batch entries that can reach it
+    __shared__ float4 lcol[NW][kT];  // their colours
+    __shared__ float4 lq[ANISO ? NW : 1][ANISO ? kT : 1];  // their conics
+    __shared__ uint32_t qcnt[NW][NW];  // [wave][quarter]: the wave's entries that can reach the quarter
     const int tile = blockIdx.x;
     const int tx = tile % B.tiles_x, ty = tile / B.tiles_x;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -777,24 +778,32 @@ __global__ __launch_bounds__(kT) void k_splat_blend(BlendArgs B)
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     float T = 1.0f, r = 0.0f, g = 0.0f, b = 0.0f;
     bool done = !inside;
-    for (uint32_t s0 = start; s0 < stop; s0 += kT) {
-        if (__syncthreads_count(!done) == 0) break;
+    // this thread's entry of the coming batch
+    float2 c = make_float2(0.0f, 0.0f), ex = make_float2(0.0f, 0.0f);
+    float4 col = make_float4(0.0f, 0.0f, 0.0f, 0.0f), cq = col;
+    bool have = false;
+    auto fetch = [&](uint32_t s0) {
         const uint32_t e = s0 + threadIdx.x;
-        uint32_t bits = 0u;
+        have = false;
         if (e < stop) {
             const uint32_t i = B.vals[e];
-            const bool ok = i < B.n;  // always true for consistent lists
-            const float2 c = ok ? B.ctr[i] : make_float2(-1e30f, -1e30f);
-            sc[threadIdx.x] = c;
-            scol[threadIdx.x] = ok ? B.col[i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            float rx = B.reach, ry = B.reach;
-            if (ANISO) {
-                sq[threadIdx.x] = ok ? B.conic[i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                const float2 ex = ok ? B.ext[i] : make_float2(0.0f, 0.0f);
-                rx = ex.x;
-                ry = ex.y;
+            if (i < B.n) {  // always true for consistent lists
+                have = true;
+                c = B.ctr[i];
+                col = B.col[i];
+                if (ANISO) {
+                    cq = B.conic[i];
+                    ex = B.ext[i];
+                }
             }
-            if (ok && !ANISO) {
+        }
+    };
+    if (start < stop) fetch(start);
+    for (uint32_t s0 = start; s0 < stop; s0 += kT) {
+        if (__syncthreads_count(!done) == 0) break;
+        uint32_t bits = 0u;
+        if (have) {
+            if (!ANISO) {
                 // the quarter's pixel centres nearest to the centre, in the
                 // pixel test's own arithmetic: no pixel of the quarter gets a
                 // smaller d2 (rounding is monotonic)
@@ -809,9 +818,9 @@ __global__ __launch_bounds__(kT) void k_splat_blend(BlendArgs B)
                     d2 = d2 + dy * dy;
                     if (d2 <= B.cut2) bits |= 1u << w;
                 }
-            } else if (ok) {
+            } else {
                 int x0, x1, y0, y1;
-                pixel_rect(B.W, B.H, c.x, c.y, rx, ry, x0, x1, y0, y1);
+                pixel_rect(B.W, B.H, c.x, c.y, ex.x, ex.y, x0, x1, y0, y1);
 #pragma unroll
                 for (int w = 0; w < NW; ++w) {
                     const int qx = tx * kTile + (w & 1) * 8, qy = ty * kTile + (w >> 1) * 8;
@@ -819,32 +828,46 @@ __global__ __launch_bounds__(kT) void k_splat_blend(BlendArgs B)
                 }
             }
         }
-        sreach[threadIdx.x] = (uint8_t)bits;
-        __syncthreads();
-        // this wave's entries, in list order (a wave's LDS operations complete in order)
-        int mine = 0;
+        unsigned long long bal[NW];
 #pragma unroll
-        for (int k = 0; k < NW; ++k) {
-            const bool f = (sreach[k * 64 + lane] >> wid) & 1u;
-            const unsigned long long m = __ballot(f);
-            if (f) wlist[wid][mine + __popcll(m & below)] = (uint8_t)(k * 64 + lane);
-            mine += __popcll(m);
+        for (int w = 0; w < NW; ++w) bal[w] = __ballot((bits >> w) & 1u);
+        if (lane == 0) {
+#pragma unroll
+            for (int w = 0; w < NW; ++w) qcnt[wid][w] = (uint32_t)__popcll(bal[w]);
         }
-        __builtin_amdgcn_wave_barrier();
-        for (int k = 0; k < mine && !done; ++k) {
-            const int j = wlist[wid][k];
-            const float2 c = sc[j];
-            const float dx = fx - c.x;
-            const float dy = fy - c.y;
+        const float2 c0 = c;
+        const float4 col0 = col, cq0 = cq;
+        if (s0 + kT < stop) fetch(s0 + kT);
+        __syncthreads();
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            if ((bits >> w) & 1u) {
+                uint32_t off = (uint32_t)__popcll(bal[w] & below);
+#pragma unroll
+                for (int v = 0; v < NW; ++v)
+                    if (v < wid) off += qcnt[v][w];
+                lc[w][off] = c0;
+                lcol[w][off] = col0;
+                if (ANISO) lq[w][off] = cq0;
+            }
+        }
+        uint32_t mine = 0;
+#pragma unroll
+        for (int v = 0; v < NW; ++v) mine += qcnt[v][wid];
+        __syncthreads();
+        for (uint32_t k = 0; k < mine && !done; ++k) {
+            const float2 cc = lc[wid][k];
+            const float dx = fx - cc.x;
+            const float dy = fy - cc.y;
             float a;
             if (ANISO) {
-                const float4 cq = sq[j];
-                float t0 = cq.x * dx;
+                const float4 q = lq[wid][k];
+                float t0 = q.x * dx;
                 t0 = t0 * dx;
-                float t1 = cq.y * dx;
+                float t1 = q.y * dx;
                 t1 = t1 * dy;
                 t1 = t1 + t1;
-                float t2 = cq.z * dy;
+                float t2 = q.z * dy;
                 t2 = t2 * dy;
                 float qf = t0 + t1;
                 qf = qf + t2;
@@ -863,11 +886,11 @@ __global__ __launch_bounds__(kT) void k_splat_blend(BlendArgs B)
                 done = true;
                 break;
             }
-            const float4 cc = scol[j];
+            const float4 cc4 = lcol[wid][k];
             const float at = a * T;
-            r = r + cc.x * at;
-            g = g + cc.y * at;
-            b = b + cc.z * at;
+            r = r + cc4.x * at;
+            g = g + cc4.y * at;
+            b = b + cc4.z * at;
             T = Tn;
         }
     }
