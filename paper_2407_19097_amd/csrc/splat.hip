@@ -855,43 +855,60 @@ __global__ __launch_bounds__(kT) void k_splat_blend(BlendArgs B)
 #pragma unroll
         for (int v = 0; v < NW; ++v) mine += qcnt[v][wid];
         __syncthreads();
-        for (uint32_t k = 0; k < mine && !done; ++k) {
-            const float2 cc = lc[wid][k];
-            const float dx = fx - cc.x;
-            const float dy = fy - cc.y;
-            float a;
-            if (ANISO) {
-                const float4 q = lq[wid][k];
-                float t0 = q.x * dx;
-                t0 = t0 * dx;
-                float t1 = q.y * dx;
-                t1 = t1 * dy;
-                t1 = t1 + t1;
-                float t2 = q.z * dy;
-                t2 = t2 * dy;
-                float qf = t0 + t1;
-                qf = qf + t2;
-                if (!(qf <= 9.0f)) continue;
-                a = B.opacity * expf(-0.5f * qf);
-            } else {
-                float d2 = dx * dx;
-                d2 = d2 + dy * dy;
-                if (!(d2 <= B.cut2)) continue;
-                a = B.opacity * expf(-d2 * B.inv2s2);
+        for (uint32_t k0 = 0; k0 < mine && !done; k0 += 2) {
+            // the alphas of two entries (independent of T) first, then both composited in order
+            float av[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const uint32_t k = k0 + u;
+                float a = 0.0f;
+                if (k < mine) {
+                    const float2 cc = lc[wid][k];
+                    const float dx = fx - cc.x;
+                    const float dy = fy - cc.y;
+                    bool reach;
+                    float e;
+                    if (ANISO) {
+                        const float4 q = lq[wid][k];
+                        float t0 = q.x * dx;
+                        t0 = t0 * dx;
+                        float t1 = q.y * dx;
+                        t1 = t1 * dy;
+                        t1 = t1 + t1;
+                        float t2 = q.z * dy;
+                        t2 = t2 * dy;
+                        float qf = t0 + t1;
+                        qf = qf + t2;
+                        reach = qf <= 9.0f;
+                        e = -0.5f * qf;
+                    } else {
+                        float d2 = dx * dx;
+                        d2 = d2 + dy * dy;
+                        reach = d2 <= B.cut2;
+                        e = -d2 * B.inv2s2;
+                    }
+                    a = B.opacity * expf(e);
+                    a = fminf(a, 0.99f);
+                    if (!reach) a = 0.0f;
+                }
+                av[u] = a;
             }
-            a = fminf(a, 0.99f);
-            if (a < 1.0f / 255.0f) continue;
-            const float Tn = T * (1.0f - a);
-            if (Tn < 1e-4f) {
-                done = true;
-                break;
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const float a = av[u];
+                if (done || a < 1.0f / 255.0f) continue;
+                const float Tn = T * (1.0f - a);
+                if (Tn < 1e-4f) {
+                    done = true;
+                    continue;
+                }
+                const float4 cc4 = lcol[wid][k0 + u];
+                const float at = a * T;
+                r = r + cc4.x * at;
+                g = g + cc4.y * at;
+                b = b + cc4.z * at;
+                T = Tn;
             }
-            const float4 cc4 = lcol[wid][k];
-            const float at = a * T;
-            r = r + cc4.x * at;
-            g = g + cc4.y * at;
-            b = b + cc4.z * at;
-            T = Tn;
         }
     }
     if (inside) {
