@@ -34,8 +34,10 @@ namespace narvis {
 namespace {
 
 constexpr int kT = 256;            // threads per workgroup everywhere here
-constexpr int kScanItems = 16;     // elements per thread in scans and the sort
+constexpr int kScanItems = 16;     // elements per thread in the scans
 constexpr int kScanTile = kT * kScanItems;
+constexpr int kSortItems = 16;     // elements per thread in the radix sort passes
+constexpr int kSortTile = kT * kSortItems;
 constexpr int kTile = 16;          // splat screen tile edge in pixels
 constexpr int kRangeParts = 256;   // workgroups folding the projection's depth ranges
 
@@ -566,9 +568,9 @@ __global__ __launch_bounds__(kT) void k_radix_hist(Src src, const uint32_t *coun
     h[threadIdx.x] = 0;
     __syncthreads();
     const uint64_t N = min((uint64_t)*count, cap);
-    const uint64_t base = (uint64_t)blockIdx.x * kScanTile + threadIdx.x;
+    const uint64_t base = (uint64_t)blockIdx.x * kSortTile + threadIdx.x;
 #pragma unroll
-    for (int r = 0; r < kScanItems; ++r) {
+    for (int r = 0; r < kSortItems; ++r) {
         const uint64_t e = base + (uint64_t)r * kT;
         if (e < N) atomicAdd(&h[(uint32_t)(src.key(e) >> shift) & mask], 1u);
     }
@@ -576,9 +578,9 @@ __global__ __launch_bounds__(kT) void k_radix_hist(Src src, const uint32_t *coun
     if (threadIdx.x <= mask) hist[(uint64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
 }
 
-// One LSD pass: each workgroup moves its kScanTile elements to the offsets
+// One LSD pass: each workgroup moves its kSortTile elements to the offsets
 // the histogram scan gave its digits, in element order (a stable sort).  Wave
-// w ranks the contiguous sub-range [w, w + 1) * kScanTile / 4 of the block,
+// w ranks the contiguous sub-range [w, w + 1) * kSortTile / 4 of the block,
 // 64 elements per round: an element's rank is the number of equal digits in
 // the wave's earlier rounds (a running per-wave count in LDS, updated by the
 // first lane of each digit group: a wave's LDS operations complete in order,
@@ -592,9 +594,9 @@ __global__ __launch_bounds__(kT) void k_radix_scatter(Src src, K *kout, uint32_t
                                                       uint64_t cap, const uint32_t *offs, uint32_t nblk)
 {
     constexpr int NW = kT / 64;
-    constexpr int PER_WAVE = kScanTile / NW;
-    __shared__ K skey[kScanTile];
-    __shared__ uint32_t sval[kScanTile];
+    constexpr int PER_WAVE = kSortTile / NW;
+    __shared__ K skey[kSortTile];
+    __shared__ uint32_t sval[kSortTile];
     __shared__ uint32_t wcnt[NW][256];  // running digit counts of each wave, then each wave's offset
     __shared__ uint32_t bstart[256];
     __shared__ uint32_t sdst[256];
@@ -605,15 +607,15 @@ __global__ __launch_bounds__(kT) void k_radix_scatter(Src src, K *kout, uint32_t
     if (shift < 0) return;  // uniform for the grid
     const uint32_t mask = src.mask();
     const uint64_t N = min((uint64_t)*count, cap);
-    const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+    const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
     if (base >= N) return;  // uniform for the workgroup
 #pragma unroll
     for (int w = 0; w < NW; ++w) wcnt[w][threadIdx.x] = 0u;
     const uint32_t myoff = offs[(uint64_t)threadIdx.x * nblk + blockIdx.x];  // digit threadIdx.x
-    K k[kScanItems];
-    uint32_t v[kScanItems], rank[kScanItems], dig[kScanItems];
+    K k[kSortItems];
+    uint32_t v[kSortItems], rank[kSortItems], dig[kSortItems];
 #pragma unroll
-    for (int r = 0; r < kScanItems; ++r) {
+    for (int r = 0; r < kSortItems; ++r) {
         const uint64_t e = base + (uint64_t)wid * PER_WAVE + (uint64_t)r * 64 + lane;
         const bool ok = e < N;
         k[r] = ok ? src.key(e) : (K)0;
@@ -624,7 +626,7 @@ __global__ __launch_bounds__(kT) void k_radix_scatter(Src src, K *kout, uint32_t
     __syncthreads();
     uint32_t *cnt = wcnt[wid];
 #pragma unroll
-    for (int r = 0; r < kScanItems; ++r) {
+    for (int r = 0; r < kSortItems; ++r) {
         const uint32_t d = dig[r];
         unsigned long long m = __ballot(d < 256u);
 #pragma unroll
@@ -656,17 +658,17 @@ __global__ __launch_bounds__(kT) void k_radix_scatter(Src src, K *kout, uint32_t
     sdst[threadIdx.x] = myoff - bs;  // output index = sdst[digit] + position in the reordered block
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kScanItems; ++r) {
+    for (int r = 0; r < kSortItems; ++r) {
         if (dig[r] < 256u) {
             const uint32_t pos = bstart[dig[r]] + cnt[dig[r]] + rank[r];
-            if (pos < (uint32_t)kScanTile) {
+            if (pos < (uint32_t)kSortTile) {
                 skey[pos] = k[r];
                 sval[pos] = v[r];
             }
         }
     }
     __syncthreads();
-    const uint32_t inblock = (uint32_t)min((uint64_t)kScanTile, N - base);
+    const uint32_t inblock = (uint32_t)min((uint64_t)kSortTile, N - base);
     for (uint32_t i = threadIdx.x; i < inblock; i += kT) {
         const K key = skey[i];
         const uint32_t d = (uint32_t)(key >> shift) & mask;
@@ -938,7 +940,7 @@ SplatLayout splat_layout(uint64_t n, int32_t W, int32_t H, float sigma, bool ani
     L.cap = max_pairs ? max_pairs : n * per_axis * per_axis;
     // the pair arrays also hold the point order (n elements) before the pairs
     const uint64_t elems = L.cap > n ? L.cap : n;
-    L.nblk = (elems + kScanTile - 1) / kScanTile;
+    L.nblk = (elems + kSortTile - 1) / kSortTile;
     if (L.nblk == 0) L.nblk = 1;
     const uint64_t histlen = L.nblk * 256;
     const uint64_t scanlen = histlen > n + 1 ? histlen : n + 1;
@@ -1044,7 +1046,7 @@ template <typename K>
 static hipError_t radix_sort(K *ka, uint32_t *va, K *kb, uint32_t *vb, const uint32_t *count, uint64_t cap,
                              int key_bits, uint32_t *hist, uint32_t *sums, hipStream_t s, bool *in_b)
 {
-    const uint64_t nblk64 = (cap + kScanTile - 1) / kScanTile;
+    const uint64_t nblk64 = (cap + kSortTile - 1) / kSortTile;
     const uint32_t nblk = (uint32_t)(nblk64 ? nblk64 : 1);
     const int passes = (key_bits + 7) / 8;
     const int width = passes ? (key_bits + passes - 1) / passes : 8;
@@ -1079,7 +1081,7 @@ hipError_t launch_radix_sort32(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_
 
 uint64_t radix_sort_hist_len(uint64_t cap)
 {
-    const uint64_t nblk = (cap + kScanTile - 1) / kScanTile;
+    const uint64_t nblk = (cap + kSortTile - 1) / kSortTile;
     return (nblk ? nblk : 1) * 256;
 }
 
@@ -1146,7 +1148,7 @@ hipError_t launch_splat(const float *x, const float *y, const float *z, uint64_t
         hipLaunchKernelGGL(k_range_partial, dim3(nparts), dim3(kT), 0, s, S.brange, nbp, part);
         hipLaunchKernelGGL(k_depth_plan, dim3(1), dim3(kT), 0, s, part, nparts, plan);
         hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kT), 0, s, npts, (uint64_t)1, (uint32_t)n);
-        const uint32_t nblk = (uint32_t)((n + kScanTile - 1) / kScanTile);
+        const uint32_t nblk = (uint32_t)((n + kSortTile - 1) / kSortTile);
         for (int slot = 0; slot < 4; ++slot) {
             // slot 0 writes (kb, vb); then (kb, vb) -> (ka, va) -> (kb, vb) -> (ka, va)
             const bool from_a = slot == 2;
