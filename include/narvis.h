@@ -505,7 +505,12 @@ narvis_status narvis_splat_count_pairs(const narvis_points *pts, const narvis_at
  * that survives the cull, one pair per 16 x 16 pixel tile touched by the
  * pixel rectangle [floor(sx - 3 sigma - 1), floor(sx + 3 sigma + 1)] x
  * [floor(sy - 3 sigma - 1), floor(sy + 3 sigma + 1)] clipped to the image
- * (fp32; the extra pixel covers the rounding of the footprint's ends).  For
+ * (fp32; the extra pixel covers the rounding of the footprint's ends).
+ * Anisotropic: the rectangle uses rx, ry, and only its tiles whose pixel
+ * centres the ellipse can reach count: the least q over the tile's centres
+ * (exact arithmetic, evaluated in fp32) is at most 9 + 4e-6 M + 1e-3, M the
+ * terms' magnitude bound (Q00 U^2 + 2 |Q01| U V + Q11 V^2, U and V the
+ * largest offsets); no tile holding a reached pixel is dropped.  For
  * measurement (the sort's keys per second).  Copies one counter from the workspace to *pairs and synchronises
  * `stream`.  INVALID_ARG on bad arguments, WORKSPACE if ws_bytes is too small,
  * DEVICE if the copy fails. */

@@ -6,7 +6,9 @@
 // alpha-blended front to back.  Here every point is a screen-space Gaussian of
 // standard deviation sigma pixels at its projected position.  Pipeline:
 //   project -- same fp32 transform and cull as the rasterizer; the Gaussian's
-//              3-sigma footprint gives a rectangle of screen tiles;
+//              3-sigma footprint gives a rectangle of screen tiles (an
+//              elongated one keeps only the rectangle's tiles its ellipse
+//              can reach);
 //   order   -- stable radix sort of the points by depth bits (culled points
 //              last): equal depths keep the index order, so this is the order
 //              of the rasterizer's (depth, index) key.  Three 8-bit passes
@@ -214,6 +216,58 @@ __device__ __forceinline__ void tile_rect(const SplatArgs &S, float sx, float sy
     ty1 = y1 / kTile;
 }
 
+// Whether a Gaussian of conic (A, B, C) = (Q00, Q01, Q11) can reach a pixel
+// whose centre lies at an offset (dx, dy) in [u0, u1] x [v0, v1] from the
+// Gaussian's centre: the least q over the box (zero when the box holds the
+// centre, else on an edge, at the edge's clamped stationary point) against 9
+// plus a margin that covers the fp32 rounding of the pixel test (under 8
+// ulps of the terms' magnitudes at any offset of the box) and of this
+// evaluation, doubled.  Never false for a box holding a pixel that the
+// pixel test takes; true when anything overflows.
+__device__ __forceinline__ bool conic_meets_box(float A, float B, float C, float u0, float u1, float v0, float v1)
+{
+    if (u0 <= 0.0f && u1 >= 0.0f && v0 <= 0.0f && v1 >= 0.0f) return true;
+    auto qf = [&](float u, float v) {
+        float t0 = A * u;
+        t0 = t0 * u;
+        float t1 = B * u;
+        t1 = t1 * v;
+        t1 = t1 + t1;
+        float t2 = C * v;
+        t2 = t2 * v;
+        float q = t0 + t1;
+        return q + t2;
+    };
+    float best = INFINITY;
+    const float us[2] = {u0, u1}, vs[2] = {v0, v1};
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const float v = fminf(fmaxf(-(B * us[k]) / C, v0), v1);
+        best = fminf(best, qf(us[k], v));
+        const float u = fminf(fmaxf(-(B * vs[k]) / A, u0), u1);
+        best = fminf(best, qf(u, vs[k]));
+    }
+    const float U = fmaxf(fabsf(u0), fabsf(u1)), V = fmaxf(fabsf(v0), fabsf(v1));
+    float M = A * U;
+    M = M * U;
+    float Mb = fabsf(B) * U;
+    Mb = Mb * V;
+    M = M + (Mb + Mb);
+    float Mc = C * V;
+    Mc = Mc * V;
+    M = M + Mc;
+    if (!(best < INFINITY) || !(M < INFINITY)) return true;
+    return best <= 9.0f + 4e-6f * M + 1e-3f;
+}
+
+// screen tile (tx, ty) against the conic centred at (sx, sy)
+__device__ __forceinline__ bool conic_meets_tile(const float4 &q, float sx, float sy, int tx, int ty)
+{
+    const float ax = (float)(tx * kTile) + 0.5f, ay = (float)(ty * kTile) + 0.5f;
+    return conic_meets_box(q.x, q.y, q.z, ax - sx, (ax + (float)(kTile - 1)) - sx, ay - sy,
+                           (ay + (float)(kTile - 1)) - sy);
+}
+
 // least and greatest over the workgroup (every thread gets both)
 __device__ __forceinline__ void block_range(uint32_t &lo, uint32_t &hi, uint32_t *lo4, uint32_t *hi4)
 {
@@ -245,8 +299,8 @@ __device__ __forceinline__ bool project_point(const SplatArgs &S, uint64_t i, ui
         return false;
     }
     float rx = S.reach, ry = S.reach;
+    float4 q = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     if (S.aniso) {
-        float4 q;
         float2 ext;
         const float vx = attr_f32(S.A.a[S.vel_attr], (uint32_t)i), vy = attr_f32(S.A.a[S.vel_attr + 1], (uint32_t)i),
                     vz = attr_f32(S.A.a[S.vel_attr + 2], (uint32_t)i);
@@ -277,12 +331,18 @@ __device__ __forceinline__ bool project_point(const SplatArgs &S, uint64_t i, ui
     }
     int tx0, tx1, ty0, ty1;
     tile_rect(S, sx, sy, rx, ry, tx0, tx1, ty0, ty1);
+    uint32_t tiles = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+    if (S.aniso) {  // only the rectangle's tiles that the ellipse can reach
+        tiles = 0;
+        for (int ty = ty0; ty <= ty1; ++ty)
+            for (int tx = tx0; tx <= tx1; ++tx) tiles += conic_meets_tile(q, sx, sy, tx, ty) ? 1u : 0u;
+    }
     S.ctr[i] = make_float2(sx, sy);
     S.col[i] = c;
     wb = __float_as_uint(w);
     S.wbits[i] = wb;
-    S.cnt[i] = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
-    return true;
+    S.cnt[i] = tiles;
+    return tiles > 0;
 }
 
 // Projection of every point, plus the least and greatest depth bits of the
@@ -373,6 +433,18 @@ __global__ __launch_bounds__(kT) void k_splat_emit(SplatArgs S, const uint32_t *
     int tx0, tx1, ty0, ty1;
     tile_rect(S, c.x, c.y, ext.x, ext.y, tx0, tx1, ty0, ty1);
     uint32_t o = start;
+    if (S.aniso) {  // the tiles the projection counted, in the same order
+        const float4 q = S.conic[i];
+        for (int ty = ty0; ty <= ty1; ++ty)
+            for (int tx = tx0; tx <= tx1; ++tx) {
+                if (!conic_meets_tile(q, c.x, c.y, tx, ty)) continue;
+                if (o >= stop || o >= S.cap) return;  // the count bounds the tiles; guard anyway
+                keys[o] = (uint32_t)(ty * S.tiles_x + tx);
+                vals[o] = i;
+                ++o;
+            }
+        return;
+    }
     for (int ty = ty0; ty <= ty1; ++ty)
         for (int tx = tx0; tx <= tx1; ++tx, ++o) {
             if (o >= stop || o >= S.cap) return;  // the count bounds the rectangle; guard anyway
@@ -756,9 +828,9 @@ struct BlendArgs {
 // list is taken kT entries at a time, one per thread, fetched a batch ahead
 // so that the loads overlap the compositing of the batch before.  Each entry
 // is tested against the four quarters (isotropic: the disc against the
-// quarter's nearest pixel centre; anisotropic: the footprint rectangle the
-// tile binning uses; neither drops an entry that reaches a pixel of the
-// quarter) and copied into the LDS list of every quarter it can reach, in
+// quarter's nearest pixel centre; anisotropic: the footprint rectangle and
+// the conic's least q over the quarter; neither drops an entry that reaches
+// a pixel of the quarter) and copied into the LDS list of every quarter it can reach, in
 // list order; each wave then composites its own list.
 template <bool ANISO>
 __global__ __launch_bounds__(kT) void k_splat_blend(BlendArgs B)
@@ -821,12 +893,16 @@ __global__ __launch_bounds__(kT) void k_splat_blend(BlendArgs B)
                     if (d2 <= B.cut2) bits |= 1u << w;
                 }
             } else {
+                // the footprint rectangle, then the conic's least q over the quarter
                 int x0, x1, y0, y1;
                 pixel_rect(B.W, B.H, c.x, c.y, ex.x, ex.y, x0, x1, y0, y1);
 #pragma unroll
                 for (int w = 0; w < NW; ++w) {
                     const int qx = tx * kTile + (w & 1) * 8, qy = ty * kTile + (w >> 1) * 8;
-                    if (x0 <= qx + 7 && x1 >= qx && y0 <= qy + 7 && y1 >= qy) bits |= 1u << w;
+                    const float ax = (float)qx + 0.5f, ay = (float)qy + 0.5f;
+                    if (x0 <= qx + 7 && x1 >= qx && y0 <= qy + 7 && y1 >= qy &&
+                        conic_meets_box(cq.x, cq.y, cq.z, ax - c.x, (ax + 7.0f) - c.x, ay - c.y, (ay + 7.0f) - c.y))
+                        bits |= 1u << w;
                 }
             }
         }

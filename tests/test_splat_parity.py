@@ -111,7 +111,7 @@ def test_depth_sort_pass_counts(far_point, aniso):
     2^24 - 1 fp32 ulps and four otherwise, and with three it carries the tile
     count in the key (255 and up are read back from the counts): depths in
     [1, 1.5] with exact ties, alone and with one point at depth 8; the
-    anisotropic case (sigma 8 px, s = 300) has footprints of hundreds of
+    anisotropic case (sigma 32 px, s = 300) has footprints of hundreds of
     tiles."""
     announce(f"depth sort pass count: far point {far_point}, anisotropic {aniso}")
     rng = np.random.default_rng(31)
@@ -134,7 +134,7 @@ def test_depth_sort_pass_counts(far_point, aniso):
     span = int(bits.max() - bits.min())
     assert (span > 0xFFFFFE) == far_point, span  # the case exercises the pass count it names
     lut = scenes.colour_lut()
-    sigma = 8.0 if aniso else 1.5
+    sigma = 32.0 if aniso else 1.5
     params = narvis.SplatParams(sigma_px=sigma, opacity=0.6, color_mode=narvis.COLOR_LUT, color_attr=3,
                                 lut=dev(lut), lut_min=0.0, lut_inv_range=1.0)
     if aniso:
