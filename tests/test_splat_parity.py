@@ -267,6 +267,27 @@ def test_aniso_splat_unit_cube(stretch):
     print(f"  {pairs} pairs, max err {d.max():.3g}, fragile pixels {int(frag.sum())}", flush=True)
 
 
+@pytest.mark.parametrize("stretch", [1e4, 1e6])
+def test_aniso_splat_extreme_stretch(stretch):
+    """Very thin ellipses (condition numbers up to the stretch): the binning's
+    least-q test keeps every tile the fp32 pixel test can reach."""
+    n, W, H = 5000, 160, 120
+    announce(f"anisotropic splat, unit cube n={n}, s={stretch:g}, {W}x{H}")
+    sc = scenes.unit_cube(n=n, seed=23, W=W, H=H)
+    cam = scenes.Camera(eye=(1.7, 1.5, 1.3), target=(0.5, 0.5, 0.5))
+    lut = scenes.colour_lut()
+    params = lut_params(sc, dev(lut))
+    params.aniso, params.vel_attr, params.stretch, params.opacity = 1, 0, stretch, 0.5
+    X, Y, Z = dev(sc.x), dev(sc.y), dev(sc.z)
+    got, pairs = gpu_splat_aniso(X, Y, Z, [dev(a) for a in sc.attrs], n, cam, W, H, params)
+    M, near, far = ocam.clip_matrix(cam, W, H)
+    want, frag = osplat.splat_aniso(sc.x, sc.y, sc.z, M, near, far, W, H, sc.attrs, vel_attr=0, stretch=stretch,
+                                    focal_px=ocam.focal_px(cam, H), opacity=0.5, lut=lut, lut_attr=sc.lut_attr,
+                                    lut_min=sc.lut_min, lut_inv_range=params.lut_inv_range, with_fragile=True)
+    d = compare(got, want, frag)
+    print(f"  {pairs} pairs, max err {d.max():.3g}, fragile pixels {int(frag.sum())}", flush=True)
+
+
 def test_aniso_splat_vector_field_window():
     """The 50M-point vector field at 1920x1080 with s = 300 (the paper's
     stretch for its hurricane vector field): the GPU renders the whole frame;
