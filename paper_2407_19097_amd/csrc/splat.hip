@@ -824,115 +824,97 @@ struct BlendArgs {
 // alpha = min(0.99, opacity exp(-q / 2)); otherwise d2 = dx^2 + dy^2 against
 // (3 sigma)^2 and alpha = min(0.99, opacity exp(-d2 / 2 sigma^2)).
 //
-// One workgroup per 16x16 tile, each wave an 8x8 quarter of it.  The tile's
-// list is taken kT entries at a time, one per thread, fetched a batch ahead
-// so that the loads overlap the compositing of the batch before.  Each entry
-// is tested against the four quarters (isotropic: the disc against the
+// One workgroup per 16x16 tile, each wave an 8x8 quarter of it, and the
+// waves independent of each other: each walks the tile's list 64 entries at
+// a time, one per lane (the list entry read two batches ahead, the point
+// gathered one ahead, so that the loads overlap the compositing), keeps the
+// entries that can reach its quarter (isotropic: the disc against the
 // quarter's nearest pixel centre; anisotropic: the footprint rectangle and
 // the conic's least q over the quarter; neither drops an entry that reaches
-// a pixel of the quarter) and copied into the LDS list of every quarter it can reach, in
-// list order; each wave then composites its own list.
+// a pixel of the quarter), copies them into its LDS list in list order and
+// composites them, until every pixel of its quarter is done.  No barrier
+// ties a wave to the others, so a wave whose pixels terminate early leaves.
 template <bool ANISO>
 __global__ __launch_bounds__(kT) void k_splat_blend(BlendArgs B)
 {
     constexpr int NW = kT / 64;
-    __shared__ float2 lc[NW][kT];    // per quarter: centres of the batch entries that can reach it
-    __shared__ float4 lcol[NW][kT];  // their colours
-    __shared__ float4 lq[ANISO ? NW : 1][ANISO ? kT : 1];  // their conics
-    __shared__ uint32_t qcnt[NW][NW];  // [wave][quarter]: the wave's entries that can reach the quarter
+    __shared__ float2 lc[NW][64];    // per wave: centres of the batch entries that can reach its quarter
+    __shared__ float4 lcol[NW][64];  // their colours
+    __shared__ float4 lq[ANISO ? NW : 1][ANISO ? 64 : 1];  // their conics
     const int tile = blockIdx.x;
     const int tx = tile % B.tiles_x, ty = tile / B.tiles_x;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int px = tx * kTile + (wid & 1) * 8 + (lane & 7);
-    const int py = ty * kTile + (wid >> 1) * 8 + (lane >> 3);
+    const int qx = tx * kTile + (wid & 1) * 8, qy = ty * kTile + (wid >> 1) * 8;  // the wave's quarter
+    const int px = qx + (lane & 7), py = qy + (lane >> 3);
     const bool inside = px < B.W && py < B.H;
     const uint32_t N = (uint32_t)min((uint64_t)*B.count, B.cap);
     const uint32_t start = B.range[2 * tile], stop = min(B.range[2 * tile + 1], N);
     const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+    const float ax = (float)qx + 0.5f, ay = (float)qy + 0.5f;  // the quarter's first pixel centre
+    const float bx = ax + 7.0f, by = ay + 7.0f;                // and its last
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     float T = 1.0f, r = 0.0f, g = 0.0f, b = 0.0f;
     bool done = !inside;
-    // this thread's entry of the coming batch
     float2 c = make_float2(0.0f, 0.0f), ex = make_float2(0.0f, 0.0f);
     float4 col = make_float4(0.0f, 0.0f, 0.0f, 0.0f), cq = col;
-    bool have = false;
-    auto fetch = [&](uint32_t s0) {
-        const uint32_t e = s0 + threadIdx.x;
-        have = false;
-        if (e < stop) {
-            const uint32_t i = B.vals[e];
-            if (i < B.n) {  // always true for consistent lists
-                have = true;
-                c = B.ctr[i];
-                col = B.col[i];
-                if (ANISO) {
-                    cq = B.conic[i];
-                    ex = B.ext[i];
-                }
+    bool have = false, nhave = false;
+    uint32_t nidx = 0u;
+    auto read_index = [&](uint32_t s0) {
+        const uint32_t e = s0 + (uint32_t)lane;
+        nhave = e < stop;
+        nidx = nhave ? B.vals[e] : 0u;
+    };
+    auto gather = [&]() {
+        have = nhave && nidx < B.n;  // the index test is always true for consistent lists
+        if (have) {
+            c = B.ctr[nidx];
+            col = B.col[nidx];
+            if (ANISO) {
+                cq = B.conic[nidx];
+                ex = B.ext[nidx];
             }
         }
     };
-    if (start < stop) fetch(start);
-    for (uint32_t s0 = start; s0 < stop; s0 += kT) {
-        if (__syncthreads_count(!done) == 0) break;
-        uint32_t bits = 0u;
+    if (start < stop) {
+        read_index(start);
+        gather();
+        if (start + 64 < stop) read_index(start + 64);
+    }
+    for (uint32_t s0 = start; s0 < stop; s0 += 64) {
+        if (!__any(!done)) break;  // every pixel of the quarter is done
+        bool reach = false;
         if (have) {
             if (!ANISO) {
-                // the quarter's pixel centres nearest to the centre, in the
+                // the quarter's pixel centre nearest to the centre, in the
                 // pixel test's own arithmetic: no pixel of the quarter gets a
                 // smaller d2 (rounding is monotonic)
-#pragma unroll
-                for (int w = 0; w < NW; ++w) {
-                    const float ax = (float)(tx * kTile + (w & 1) * 8) + 0.5f;
-                    const float ay = (float)(ty * kTile + (w >> 1) * 8) + 0.5f;
-                    const float bx = ax + 7.0f, by = ay + 7.0f;
-                    const float dx = c.x < ax ? ax - c.x : (c.x > bx ? c.x - bx : 0.0f);
-                    const float dy = c.y < ay ? ay - c.y : (c.y > by ? c.y - by : 0.0f);
-                    float d2 = dx * dx;
-                    d2 = d2 + dy * dy;
-                    if (d2 <= B.cut2) bits |= 1u << w;
-                }
+                const float dx = c.x < ax ? ax - c.x : (c.x > bx ? c.x - bx : 0.0f);
+                const float dy = c.y < ay ? ay - c.y : (c.y > by ? c.y - by : 0.0f);
+                float d2 = dx * dx;
+                d2 = d2 + dy * dy;
+                reach = d2 <= B.cut2;
             } else {
-                // the footprint rectangle, then the conic's least q over the quarter
                 int x0, x1, y0, y1;
                 pixel_rect(B.W, B.H, c.x, c.y, ex.x, ex.y, x0, x1, y0, y1);
-#pragma unroll
-                for (int w = 0; w < NW; ++w) {
-                    const int qx = tx * kTile + (w & 1) * 8, qy = ty * kTile + (w >> 1) * 8;
-                    const float ax = (float)qx + 0.5f, ay = (float)qy + 0.5f;
-                    if (x0 <= qx + 7 && x1 >= qx && y0 <= qy + 7 && y1 >= qy &&
-                        conic_meets_box(cq.x, cq.y, cq.z, ax - c.x, (ax + 7.0f) - c.x, ay - c.y, (ay + 7.0f) - c.y))
-                        bits |= 1u << w;
-                }
+                reach = x0 <= qx + 7 && x1 >= qx && y0 <= qy + 7 && y1 >= qy &&
+                        conic_meets_box(cq.x, cq.y, cq.z, ax - c.x, bx - c.x, ay - c.y, by - c.y);
             }
         }
-        unsigned long long bal[NW];
-#pragma unroll
-        for (int w = 0; w < NW; ++w) bal[w] = __ballot((bits >> w) & 1u);
-        if (lane == 0) {
-#pragma unroll
-            for (int w = 0; w < NW; ++w) qcnt[wid][w] = (uint32_t)__popcll(bal[w]);
+        const unsigned long long m = __ballot(reach);
+        if (reach) {
+            const uint32_t off = (uint32_t)__popcll(m & below);
+            lc[wid][off] = c;
+            lcol[wid][off] = col;
+            if (ANISO) lq[wid][off] = cq;
         }
-        const float2 c0 = c;
-        const float4 col0 = col, cq0 = cq;
-        if (s0 + kT < stop) fetch(s0 + kT);
-        __syncthreads();
-#pragma unroll
-        for (int w = 0; w < NW; ++w) {
-            if ((bits >> w) & 1u) {
-                uint32_t off = (uint32_t)__popcll(bal[w] & below);
-#pragma unroll
-                for (int v = 0; v < NW; ++v)
-                    if (v < wid) off += qcnt[v][w];
-                lc[w][off] = c0;
-                lcol[w][off] = col0;
-                if (ANISO) lq[w][off] = cq0;
-            }
+        if (s0 + 64 < stop) {
+            gather();
+            if (s0 + 128 < stop) read_index(s0 + 128);
         }
-        uint32_t mine = 0;
-#pragma unroll
-        for (int v = 0; v < NW; ++v) mine += qcnt[v][wid];
-        __syncthreads();
+        // a wave's LDS operations complete in order: the list is written
+        // before it is read, and read before the next batch overwrites it
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t mine = (uint32_t)__popcll(m);
         for (uint32_t k0 = 0; k0 < mine && !done; k0 += 2) {
             // the alphas of two entries (independent of T) first, then both composited in order
             float av[2];
@@ -988,6 +970,7 @@ __global__ __launch_bounds__(kT) void k_splat_blend(BlendArgs B)
                 T = Tn;
             }
         }
+        __builtin_amdgcn_wave_barrier();
     }
     if (inside) {
         const int64_t npx = (int64_t)B.W * B.H;
