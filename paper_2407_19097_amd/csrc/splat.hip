@@ -828,11 +828,12 @@ struct BlendArgs {
 // waves independent of each other: each walks the tile's list 64 entries at
 // a time, one per lane (the list entry read two batches ahead, the point
 // gathered one ahead, so that the loads overlap the compositing), keeps the
-// entries that can reach its quarter (isotropic: the disc against the
-// quarter's nearest pixel centre; anisotropic: the footprint rectangle and
-// the conic's least q over the quarter; neither drops an entry that reaches
-// a pixel of the quarter), copies them into its LDS list in list order and
-// composites them, until every pixel of its quarter is done.  No barrier
+// entries that can reach a pixel of its quarter not yet done (tested against
+// the bounding box of those pixels -- isotropic: the disc against the box's
+// nearest pixel centre; anisotropic: the footprint rectangle and the conic's
+// least q over the box; neither drops an entry that reaches a pixel of the
+// box), copies them into its LDS list in list order and composites them,
+// until every pixel of its quarter is done.  No barrier
 // ties a wave to the others, so a wave whose pixels terminate early leaves.
 template <bool ANISO>
 __global__ __launch_bounds__(kT) void k_splat_blend(BlendArgs B)
@@ -882,22 +883,34 @@ __global__ __launch_bounds__(kT) void k_splat_blend(BlendArgs B)
     }
     for (uint32_t s0 = start; s0 < stop; s0 += 64) {
         if (!__any(!done)) break;  // every pixel of the quarter is done
+        // the bounding box of the quarter's pixels still open
+        int lx = done ? 0x7FFF : px & 7, hx = done ? -1 : px & 7;
+        int ly = done ? 0x7FFF : py & 7, hy = done ? -1 : py & 7;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            lx = min(lx, __shfl_xor(lx, d));
+            hx = max(hx, __shfl_xor(hx, d));
+            ly = min(ly, __shfl_xor(ly, d));
+            hy = max(hy, __shfl_xor(hy, d));
+        }
+        const float oax = ax + (float)lx, obx = ax + (float)hx;  // its first and last pixel centres
+        const float oay = ay + (float)ly, oby = ay + (float)hy;
         bool reach = false;
         if (have) {
             if (!ANISO) {
-                // the quarter's pixel centre nearest to the centre, in the
-                // pixel test's own arithmetic: no pixel of the quarter gets a
-                // smaller d2 (rounding is monotonic)
-                const float dx = c.x < ax ? ax - c.x : (c.x > bx ? c.x - bx : 0.0f);
-                const float dy = c.y < ay ? ay - c.y : (c.y > by ? c.y - by : 0.0f);
+                // the open box's pixel centre nearest to the centre, in the
+                // pixel test's own arithmetic: no open pixel gets a smaller
+                // d2 (rounding is monotonic)
+                const float dx = c.x < oax ? oax - c.x : (c.x > obx ? c.x - obx : 0.0f);
+                const float dy = c.y < oay ? oay - c.y : (c.y > oby ? c.y - oby : 0.0f);
                 float d2 = dx * dx;
                 d2 = d2 + dy * dy;
                 reach = d2 <= B.cut2;
             } else {
                 int x0, x1, y0, y1;
                 pixel_rect(B.W, B.H, c.x, c.y, ex.x, ex.y, x0, x1, y0, y1);
-                reach = x0 <= qx + 7 && x1 >= qx && y0 <= qy + 7 && y1 >= qy &&
-                        conic_meets_box(cq.x, cq.y, cq.z, ax - c.x, bx - c.x, ay - c.y, by - c.y);
+                reach = x0 <= qx + hx && x1 >= qx + lx && y0 <= qy + hy && y1 >= qy + ly &&
+                        conic_meets_box(cq.x, cq.y, cq.z, oax - c.x, obx - c.x, oay - c.y, oby - c.y);
             }
         }
         const unsigned long long m = __ballot(reach);
