@@ -131,6 +131,36 @@ __global__ __launch_bounds__(kT) void k_layout_codes(const float *__restrict__ X
     vals[i] = (uint32_t)i;
 }
 
+// x, y, z of point i side by side at xyz[3 i], so that the gather below takes
+// one cache line per point instead of three
+__global__ __launch_bounds__(kT) void k_layout_interleave(const float *__restrict__ X, const float *__restrict__ Y,
+                                                         const float *__restrict__ Z, uint64_t n,
+                                                         float *__restrict__ xyz)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * kT + threadIdx.x;
+    if (i >= n) return;
+    xyz[3 * i] = X[i];
+    xyz[3 * i + 1] = Y[i];
+    xyz[3 * i + 2] = Z[i];
+}
+
+__global__ __launch_bounds__(kT) void k_layout_gather_xyz(const uint32_t *__restrict__ order,
+                                                         const float *__restrict__ xyz, uint64_t n,
+                                                         float *__restrict__ xs, float *__restrict__ ys,
+                                                         float *__restrict__ zs, uint32_t *__restrict__ ix)
+{
+    const uint64_t j = (uint64_t)blockIdx.x * kT + threadIdx.x;
+    if (j >= n) return;
+    const uint32_t i = order[j];
+    const bool ok = (uint64_t)i < n;  // always true for a permutation
+    const float *p = xyz + 3 * (uint64_t)(ok ? i : 0u);
+    const float x = p[0], y = p[1], z = p[2];
+    xs[j] = ok ? x : __builtin_nanf("");
+    ys[j] = ok ? y : __builtin_nanf("");
+    zs[j] = ok ? z : __builtin_nanf("");
+    ix[j] = i;
+}
+
 __global__ __launch_bounds__(kT) void k_layout_gather(const uint32_t *__restrict__ order, const float *__restrict__ X,
                                                      const float *__restrict__ Y, const float *__restrict__ Z,
                                                      uint64_t n, float *__restrict__ xs, float *__restrict__ ys,
@@ -493,9 +523,12 @@ LayoutWorkspace layout_workspace(uint64_t n)
     uint64_t o = 0;
     L.off_bb = o; o = align256(o + 8 * 4);
     L.off_count = o; o = align256(o + 4);
+    // va first: after the sort's four passes it holds the order, and ka, kb,
+    // vb behind it form one free region of at least 12 n bytes for the
+    // interleaved coordinates
+    L.off_va = o; o = align256(o + n * 4);
     L.off_ka = o; o = align256(o + n * 4);
     L.off_kb = o; o = align256(o + n * 4);
-    L.off_va = o; o = align256(o + n * 4);
     L.off_vb = o; o = align256(o + n * 4);
     L.off_hist = o; o = align256(o + radix_sort_hist_len(n) * 4);
     L.off_sums = o; o = align256(o + radix_sort_sums_len(n) * 4);
@@ -526,8 +559,14 @@ hipError_t launch_layout(const float *x, const float *y, const float *z, uint64_
     bool in_b = false;
     hipError_t e = launch_radix_sort32(ka, va, kb, vb, count, n, 31, hist, sums, s, &in_b);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_layout_gather, dim3((unsigned)blocks), dim3(kT), 0, s, in_b ? vb : va, x, y, z, n, xs, ys,
-                       zs, ix);
+    if (!in_b) {
+        // the order is in va; ka, kb and vb are free
+        auto *xyz = reinterpret_cast<float *>(ka);
+        hipLaunchKernelGGL(k_layout_interleave, dim3((unsigned)blocks), dim3(kT), 0, s, x, y, z, n, xyz);
+        hipLaunchKernelGGL(k_layout_gather_xyz, dim3((unsigned)blocks), dim3(kT), 0, s, va, xyz, n, xs, ys, zs, ix);
+    } else {
+        hipLaunchKernelGGL(k_layout_gather, dim3((unsigned)blocks), dim3(kT), 0, s, vb, x, y, z, n, xs, ys, zs, ix);
+    }
     const uint64_t nb = (n + NARVIS_LAYOUT_BATCH - 1) / NARVIS_LAYOUT_BATCH;
     hipLaunchKernelGGL(k_layout_boxes, dim3((unsigned)nb), dim3(kT), 0, s, xs, ys, zs, n,
                        reinterpret_cast<float4 *>(box));
