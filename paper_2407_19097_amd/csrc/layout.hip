@@ -144,21 +144,32 @@ __global__ __launch_bounds__(kT) void k_layout_interleave(const float *__restric
     xyz[3 * i + 2] = Z[i];
 }
 
+// ... and, when sx is given, the depth sample (every 8th point of the
+// layout order) written on the way
 __global__ __launch_bounds__(kT) void k_layout_gather_xyz(const uint32_t *__restrict__ order,
                                                          const float *__restrict__ xyz, uint64_t n,
                                                          float *__restrict__ xs, float *__restrict__ ys,
-                                                         float *__restrict__ zs, uint32_t *__restrict__ ix)
+                                                         float *__restrict__ zs, uint32_t *__restrict__ ix,
+                                                         float *__restrict__ sx, float *__restrict__ sy,
+                                                         float *__restrict__ sz, uint32_t *__restrict__ six)
 {
     const uint64_t j = (uint64_t)blockIdx.x * kT + threadIdx.x;
     if (j >= n) return;
     const uint32_t i = order[j];
     const bool ok = (uint64_t)i < n;  // always true for a permutation
     const float *p = xyz + 3 * (uint64_t)(ok ? i : 0u);
-    const float x = p[0], y = p[1], z = p[2];
-    xs[j] = ok ? x : __builtin_nanf("");
-    ys[j] = ok ? y : __builtin_nanf("");
-    zs[j] = ok ? z : __builtin_nanf("");
+    const float x = ok ? p[0] : __builtin_nanf(""), y = ok ? p[1] : __builtin_nanf(""),
+                z = ok ? p[2] : __builtin_nanf("");
+    xs[j] = x;
+    ys[j] = y;
+    zs[j] = z;
     ix[j] = i;
+    if (sx && (j & 7) == 0) {
+        sx[j >> 3] = x;
+        sy[j >> 3] = y;
+        sz[j >> 3] = z;
+        six[j >> 3] = i;
+    }
 }
 
 __global__ __launch_bounds__(kT) void k_layout_gather(const uint32_t *__restrict__ order, const float *__restrict__ X,
@@ -563,7 +574,8 @@ hipError_t launch_layout(const float *x, const float *y, const float *z, uint64_
         // the order is in va; ka, kb and vb are free
         auto *xyz = reinterpret_cast<float *>(ka);
         hipLaunchKernelGGL(k_layout_interleave, dim3((unsigned)blocks), dim3(kT), 0, s, x, y, z, n, xyz);
-        hipLaunchKernelGGL(k_layout_gather_xyz, dim3((unsigned)blocks), dim3(kT), 0, s, va, xyz, n, xs, ys, zs, ix);
+        hipLaunchKernelGGL(k_layout_gather_xyz, dim3((unsigned)blocks), dim3(kT), 0, s, va, xyz, n, xs, ys, zs, ix,
+                           sx, sy, sz, six);
     } else {
         hipLaunchKernelGGL(k_layout_gather, dim3((unsigned)blocks), dim3(kT), 0, s, vb, x, y, z, n, xs, ys, zs, ix);
     }
@@ -572,8 +584,9 @@ hipError_t launch_layout(const float *x, const float *y, const float *z, uint64_
                        reinterpret_cast<float4 *>(box));
     if (sx) {
         const uint64_t ns = (n + 7) / 8;
-        hipLaunchKernelGGL(k_layout_sample, dim3((unsigned)((ns + kT - 1) / kT)), dim3(kT), 0, s, xs, ys, zs, ix, ns,
-                           sx, sy, sz, six);
+        if (in_b)  // else written by the gather
+            hipLaunchKernelGGL(k_layout_sample, dim3((unsigned)((ns + kT - 1) / kT)), dim3(kT), 0, s, xs, ys, zs, ix,
+                               ns, sx, sy, sz, six);
         const uint64_t nsb = (ns + NARVIS_LAYOUT_BATCH - 1) / NARVIS_LAYOUT_BATCH;
         hipLaunchKernelGGL(k_layout_boxes, dim3((unsigned)nsb), dim3(kT), 0, s, sx, sy, sz, ns,
                            reinterpret_cast<float4 *>(sbox));
