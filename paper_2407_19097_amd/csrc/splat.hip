@@ -625,6 +625,19 @@ struct DepthSrc {
     __device__ uint32_t val(uint64_t e) const { return first ? (uint32_t)e : v[e]; }
 };
 
+// Sort block of this workgroup, a permutation of the grid.  Workgroups go to
+// the eight XCDs in turn (workgroup w on XCD w % 8).  Of the blocks that hold
+// elements (their count rounded up to a multiple of 8, which the grid, also
+// a multiple of 8, covers), XCD x takes the x-th eighth in order, so that
+// neighbouring histogram columns and offsets are written and read through one
+// L2 and every XCD has work; the empty blocks beyond keep their own number.
+__device__ __forceinline__ uint32_t sort_block(uint64_t N)
+{
+    const uint32_t act = (uint32_t)(((N + kSortTile - 1) / kSortTile + 7) & ~uint64_t(7));
+    const uint32_t b = blockIdx.x;
+    return b >= act ? b : (b & 7u) * (act >> 3) + (b >> 3);
+}
+
 // per-workgroup digit counts of a pass, hist[digit * nblk + workgroup] for
 // the digits under the source's mask (skipped, like its scatter, when the
 // source's shift is negative)
@@ -640,14 +653,15 @@ __global__ __launch_bounds__(kT) void k_radix_hist(Src src, const uint32_t *coun
     h[threadIdx.x] = 0;
     __syncthreads();
     const uint64_t N = min((uint64_t)*count, cap);
-    const uint64_t base = (uint64_t)blockIdx.x * kSortTile + threadIdx.x;
+    const uint32_t blk = sort_block(N);
+    const uint64_t base = (uint64_t)blk * kSortTile + threadIdx.x;
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
         const uint64_t e = base + (uint64_t)r * kT;
         if (e < N) atomicAdd(&h[(uint32_t)(src.key(e) >> shift) & mask], 1u);
     }
     __syncthreads();
-    if (threadIdx.x <= mask) hist[(uint64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+    if (threadIdx.x <= mask) hist[(uint64_t)threadIdx.x * nblk + blk] = h[threadIdx.x];
 }
 
 // One LSD pass: each workgroup moves its kSortTile elements to the offsets
@@ -679,11 +693,12 @@ __global__ __launch_bounds__(kT) void k_radix_scatter(Src src, K *kout, uint32_t
     if (shift < 0) return;  // uniform for the grid
     const uint32_t mask = src.mask();
     const uint64_t N = min((uint64_t)*count, cap);
-    const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+    const uint32_t blk = sort_block(N);
+    const uint64_t base = (uint64_t)blk * kSortTile;
     if (base >= N) return;  // uniform for the workgroup
 #pragma unroll
     for (int w = 0; w < NW; ++w) wcnt[w][threadIdx.x] = 0u;
-    const uint32_t myoff = offs[(uint64_t)threadIdx.x * nblk + blockIdx.x];  // digit threadIdx.x
+    const uint32_t myoff = offs[(uint64_t)threadIdx.x * nblk + blk];  // digit threadIdx.x
     K k[kSortItems];
     uint32_t v[kSortItems], rank[kSortItems], dig[kSortItems];
 #pragma unroll
@@ -1013,7 +1028,8 @@ SplatLayout splat_layout(uint64_t n, int32_t W, int32_t H, float sigma, bool ani
     // the pair arrays also hold the point order (n elements) before the pairs
     const uint64_t elems = L.cap > n ? L.cap : n;
     L.nblk = (elems + kSortTile - 1) / kSortTile;
-    if (L.nblk == 0) L.nblk = 1;
+    L.nblk = (L.nblk + 7) & ~uint64_t(7);
+    if (L.nblk == 0) L.nblk = 8;
     const uint64_t histlen = L.nblk * 256;
     const uint64_t scanlen = histlen > n + 1 ? histlen : n + 1;
     L.nsums = (scanlen + kScanTile - 1) / kScanTile;
@@ -1118,8 +1134,8 @@ template <typename K>
 static hipError_t radix_sort(K *ka, uint32_t *va, K *kb, uint32_t *vb, const uint32_t *count, uint64_t cap,
                              int key_bits, uint32_t *hist, uint32_t *sums, hipStream_t s, bool *in_b)
 {
-    const uint64_t nblk64 = (cap + kSortTile - 1) / kSortTile;
-    const uint32_t nblk = (uint32_t)(nblk64 ? nblk64 : 1);
+    const uint64_t nblk64 = ((cap + kSortTile - 1) / kSortTile + 7) & ~uint64_t(7);
+    const uint32_t nblk = (uint32_t)(nblk64 ? nblk64 : 8);
     const int passes = (key_bits + 7) / 8;
     const int width = passes ? (key_bits + passes - 1) / passes : 8;
     bool b = false;
@@ -1153,8 +1169,8 @@ hipError_t launch_radix_sort32(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_
 
 uint64_t radix_sort_hist_len(uint64_t cap)
 {
-    const uint64_t nblk = (cap + kSortTile - 1) / kSortTile;
-    return (nblk ? nblk : 1) * 256;
+    const uint64_t nblk = ((cap + kSortTile - 1) / kSortTile + 7) & ~uint64_t(7);
+    return (nblk ? nblk : 8) * 256;
 }
 
 uint64_t radix_sort_sums_len(uint64_t cap)
@@ -1220,7 +1236,7 @@ hipError_t launch_splat(const float *x, const float *y, const float *z, uint64_t
         hipLaunchKernelGGL(k_range_partial, dim3(nparts), dim3(kT), 0, s, S.brange, nbp, part);
         hipLaunchKernelGGL(k_depth_plan, dim3(1), dim3(kT), 0, s, part, nparts, plan);
         hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kT), 0, s, npts, (uint64_t)1, (uint32_t)n);
-        const uint32_t nblk = (uint32_t)((n + kSortTile - 1) / kSortTile);
+        const uint32_t nblk = (uint32_t)((((n + kSortTile - 1) / kSortTile) + 7) & ~uint64_t(7));
         for (int slot = 0; slot < 4; ++slot) {
             // slot 0 writes (kb, vb); then (kb, vb) -> (ka, va) -> (kb, vb) -> (ka, va)
             const bool from_a = slot == 2;
