@@ -638,9 +638,9 @@ __device__ __forceinline__ uint32_t sort_block(uint64_t N)
     return b >= act ? b : (b & 7u) * (act >> 3) + (b >> 3);
 }
 
-// per-workgroup digit counts of a pass, hist[digit * nblk + workgroup] for
-// the digits under the source's mask (skipped, like its scatter, when the
-// source's shift is negative)
+// digit counts of one sort block per workgroup, hist[digit * nblk + block]
+// for the digits under the source's mask (skipped, like its scatter, when
+// the source's shift is negative)
 template <typename K, typename Src>
 __global__ __launch_bounds__(kT) void k_radix_hist(Src src, const uint32_t *count, uint64_t cap, uint32_t *hist,
                                                    uint32_t nblk)
