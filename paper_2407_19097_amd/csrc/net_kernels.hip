@@ -371,7 +371,60 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a, const uint8_t *wq,
         if (more) lstore(buf ^ 1);
         __syncthreads();
     }
-    // epilogue: lane holds channels co0 + wco + 16 i + 4 g + e of pixel p0 + wpx + 16 f + r
+    // epilogue: lane holds channels co0 + wco + 16 i + 4 g + e of pixel p0 + wpx + 16 f + r.
+    // A bf16 output on 8-channel boundaries is staged through LDS (the input
+    // tiles are no longer read) and written as 16-byte pieces, a pixel's TCO
+    // channels contiguous, instead of 8 bytes per lane at pixel stride.
+    constexpr int kOutPitch = TCO + 8;  // elements per staged pixel row (16-byte aligned rows)
+    static_assert(sizeof(lb) >= (size_t)TPX * kOutPitch * 2, "the output tile fits in the input tile's LDS");
+    const bool staged = !a.out_f32 && !(a.out_stride & 7) && !(a.out_off & 7) && !(a.Cout & 7) &&
+                        (!a.shuffle || !((a.Cout >> 2) & 7));
+    if (staged) {
+        __bf16 *so = reinterpret_cast<__bf16 *>(&lb[0][0]);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int cl = wco + 16 * i + 4 * g, cb = co0 + cl;
+            float bias[4], scale[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                bias[e] = a.bias && cb + e < a.Cout_pad ? a.bias[cb + e] : 0.0f;
+                scale[e] = FP8 ? sw[cb + e] * sa : 1.0f;
+            }
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+                bf16x4 w4;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    float v = FP8 ? acc[i][f][e] * scale[e] + bias[e] : acc[i][f][e] + bias[e];
+                    if (a.relu) v = fmaxf(v, 0.0f);
+                    w4[e] = (__bf16)v;
+                }
+                *reinterpret_cast<bf16x4 *>(&so[(wpx + 16 * f + r) * kOutPitch + cl]) = w4;
+            }
+        }
+        __syncthreads();
+        constexpr int PIECES = TCO / 8;
+        for (int idx = threadIdx.x; idx < TPX * PIECES; idx += 256) {
+            const int pr = idx / PIECES, pc = idx - pr * PIECES;
+            const int64_t p = p0 + pr;
+            const int cb = co0 + 8 * pc;
+            if (p >= P || cb >= a.Cout) continue;
+            int64_t q = p;
+            int c = cb;
+            if (a.shuffle) {  // depth-to-space, as below; the 8 channels share one phase
+                const int C4 = a.Cout >> 2, ph = cb / C4;
+                c = cb - ph * C4;
+                const int64_t hw = (int64_t)a.H * a.W;
+                const int64_t b = p / hw, rem = p - b * hw;
+                const int64_t yi = rem / a.W, xj = rem - yi * a.W;
+                q = (b * 2 * a.H + 2 * yi + (ph >> 1)) * (2 * (int64_t)a.W) + 2 * xj + (ph & 1);
+            }
+            *reinterpret_cast<uint4 *>(a.out + q * a.out_stride + a.out_off + c) =
+                *reinterpret_cast<const uint4 *>(&so[pr * kOutPitch + 8 * pc]);
+        }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
         const int cb = co0 + wco + 16 * i + 4 * g;
