@@ -418,38 +418,68 @@ __global__ __launch_bounds__(kT) void k_gather_counts(const uint32_t *cnt, const
     scnt[j] = c;
 }
 
-// sorted position j: the pairs of point order[j] at [scnt[j], scnt[j + 1])
+// sorted position j: the pairs of point order[j] at [scnt[j], scnt[j + 1]).
+// The workgroup's points own one contiguous range of pairs; an isotropic
+// range of up to kEmitStage pairs is assembled in LDS and written out with
+// consecutive threads on consecutive pairs.
+constexpr int kEmitStage = 2048;
+
 __global__ __launch_bounds__(kT) void k_splat_emit(SplatArgs S, const uint32_t *order, const uint32_t *scnt,
                                                    uint32_t *keys, uint32_t *vals)
 {
-    const uint64_t j = (uint64_t)blockIdx.x * kT + threadIdx.x;
-    if (j >= S.n) return;
-    const uint32_t start = scnt[j], stop = scnt[j + 1];
-    if (start == stop) return;
-    const uint32_t i = order[j];
-    if ((uint64_t)i >= S.n) return;  // a permutation of [0, n); guards the reads regardless
-    const float2 c = S.ctr[i];
-    const float2 ext = S.aniso ? S.ext[i] : make_float2(S.reach, S.reach);
-    int tx0, tx1, ty0, ty1;
-    tile_rect(S, c.x, c.y, ext.x, ext.y, tx0, tx1, ty0, ty1);
-    uint32_t o = start;
-    if (S.aniso) {  // the tiles the projection counted, in the same order
-        const float4 q = S.conic[i];
-        for (int ty = ty0; ty <= ty1; ++ty)
-            for (int tx = tx0; tx <= tx1; ++tx) {
-                if (!conic_meets_tile(q, c.x, c.y, tx, ty)) continue;
-                if (o >= stop || o >= S.cap) return;  // the count bounds the tiles; guard anyway
-                keys[o] = (uint32_t)(ty * S.tiles_x + tx);
-                vals[o] = i;
-                ++o;
-            }
-        return;
+    __shared__ uint32_t sk[kEmitStage], sv[kEmitStage];
+    const uint64_t j0 = (uint64_t)blockIdx.x * kT;
+    const uint64_t j1 = j0 + kT < S.n ? j0 + kT : S.n;
+    const uint32_t wbeg = scnt[j0], wend = scnt[j1];  // uniform
+    const bool stage = !S.aniso && wend >= wbeg && wend - wbeg <= (uint32_t)kEmitStage;
+    const uint64_t j = j0 + threadIdx.x;
+    uint32_t start = 0, stop = 0, i = 0;
+    if (j < S.n) {
+        start = scnt[j];
+        stop = scnt[j + 1];
+        if (start != stop) {
+            i = order[j];
+            if ((uint64_t)i >= S.n) stop = start;  // a permutation of [0, n); guards the reads regardless
+        }
     }
-    for (int ty = ty0; ty <= ty1; ++ty)
-        for (int tx = tx0; tx <= tx1; ++tx, ++o) {
-            if (o >= stop || o >= S.cap) return;  // the count bounds the rectangle; guard anyway
-            keys[o] = (uint32_t)(ty * S.tiles_x + tx);
-            vals[o] = i;
+    if (start != stop) {
+        const float2 c = S.ctr[i];
+        const float2 ext = S.aniso ? S.ext[i] : make_float2(S.reach, S.reach);
+        int tx0, tx1, ty0, ty1;
+        tile_rect(S, c.x, c.y, ext.x, ext.y, tx0, tx1, ty0, ty1);
+        uint32_t o = start;
+        if (S.aniso) {  // the tiles the projection counted, in the same order
+            const float4 q = S.conic[i];
+            for (int ty = ty0; ty <= ty1; ++ty)
+                for (int tx = tx0; tx <= tx1; ++tx) {
+                    if (!conic_meets_tile(q, c.x, c.y, tx, ty)) continue;
+                    if (o < stop && o < S.cap) {  // the count bounds the tiles; guard anyway
+                        keys[o] = (uint32_t)(ty * S.tiles_x + tx);
+                        vals[o] = i;
+                    }
+                    ++o;
+                }
+        } else {
+            for (int ty = ty0; ty <= ty1; ++ty)
+                for (int tx = tx0; tx <= tx1; ++tx, ++o) {
+                    if (o >= stop) continue;  // the count bounds the rectangle; guard anyway
+                    const uint32_t key = (uint32_t)(ty * S.tiles_x + tx);
+                    if (stage) {
+                        sk[o - wbeg] = key;
+                        sv[o - wbeg] = i;
+                    } else if (o < S.cap) {
+                        keys[o] = key;
+                        vals[o] = i;
+                    }
+                }
+        }
+    }
+    if (!stage) return;  // uniform
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < wend - wbeg; k += kT)
+        if (wbeg + k < S.cap) {
+            keys[wbeg + k] = sk[k];
+            vals[wbeg + k] = sv[k];
         }
 }
 
