@@ -223,8 +223,11 @@ __device__ __forceinline__ void tile_rect(const SplatArgs &S, float sx, float sy
 // plus a margin that covers the fp32 rounding of the pixel test (under 8
 // ulps of the terms' magnitudes at any offset of the box) and of this
 // evaluation, doubled.  Never false for a box holding a pixel that the
-// pixel test takes; true when anything overflows.
-__device__ __forceinline__ bool conic_meets_box(float A, float B, float C, float u0, float u1, float v0, float v1)
+// pixel test takes; true when anything overflows.  kA = -(B / A) and
+// kC = -(B / C) (per Gaussian) place the edges' stationary points; their
+// rounding moves the edge minima by far less than the margin.
+__device__ __forceinline__ bool conic_meets_box(float A, float B, float C, float kA, float kC, float u0, float u1,
+                                                float v0, float v1)
 {
     if (u0 <= 0.0f && u1 >= 0.0f && v0 <= 0.0f && v1 >= 0.0f) return true;
     auto qf = [&](float u, float v) {
@@ -242,9 +245,9 @@ __device__ __forceinline__ bool conic_meets_box(float A, float B, float C, float
     const float us[2] = {u0, u1}, vs[2] = {v0, v1};
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-        const float v = fminf(fmaxf(-(B * us[k]) / C, v0), v1);
+        const float v = fminf(fmaxf(kC * us[k], v0), v1);
         best = fminf(best, qf(us[k], v));
-        const float u = fminf(fmaxf(-(B * vs[k]) / A, u0), u1);
+        const float u = fminf(fmaxf(kA * vs[k], u0), u1);
         best = fminf(best, qf(u, vs[k]));
     }
     const float U = fmaxf(fabsf(u0), fabsf(u1)), V = fmaxf(fabsf(v0), fabsf(v1));
@@ -261,10 +264,11 @@ __device__ __forceinline__ bool conic_meets_box(float A, float B, float C, float
 }
 
 // screen tile (tx, ty) against the conic centred at (sx, sy)
-__device__ __forceinline__ bool conic_meets_tile(const float4 &q, float sx, float sy, int tx, int ty)
+__device__ __forceinline__ bool conic_meets_tile(const float4 &q, float kA, float kC, float sx, float sy, int tx,
+                                                 int ty)
 {
     const float ax = (float)(tx * kTile) + 0.5f, ay = (float)(ty * kTile) + 0.5f;
-    return conic_meets_box(q.x, q.y, q.z, ax - sx, (ax + (float)(kTile - 1)) - sx, ay - sy,
+    return conic_meets_box(q.x, q.y, q.z, kA, kC, ax - sx, (ax + (float)(kTile - 1)) - sx, ay - sy,
                            (ay + (float)(kTile - 1)) - sy);
 }
 
@@ -334,8 +338,9 @@ __device__ __forceinline__ bool project_point(const SplatArgs &S, uint64_t i, ui
     uint32_t tiles = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
     if (S.aniso) {  // only the rectangle's tiles that the ellipse can reach
         tiles = 0;
+        const float kA = -(q.y / q.x), kC = -(q.y / q.z);
         for (int ty = ty0; ty <= ty1; ++ty)
-            for (int tx = tx0; tx <= tx1; ++tx) tiles += conic_meets_tile(q, sx, sy, tx, ty) ? 1u : 0u;
+            for (int tx = tx0; tx <= tx1; ++tx) tiles += conic_meets_tile(q, kA, kC, sx, sy, tx, ty) ? 1u : 0u;
     }
     S.ctr[i] = make_float2(sx, sy);
     S.col[i] = c;
@@ -450,9 +455,10 @@ __global__ __launch_bounds__(kT) void k_splat_emit(SplatArgs S, const uint32_t *
         uint32_t o = start;
         if (S.aniso) {  // the tiles the projection counted, in the same order
             const float4 q = S.conic[i];
+            const float kA = -(q.y / q.x), kC = -(q.y / q.z);
             for (int ty = ty0; ty <= ty1; ++ty)
                 for (int tx = tx0; tx <= tx1; ++tx) {
-                    if (!conic_meets_tile(q, c.x, c.y, tx, ty)) continue;
+                    if (!conic_meets_tile(q, kA, kC, c.x, c.y, tx, ty)) continue;
                     if (o < stop && o < S.cap) {  // the count bounds the tiles; guard anyway
                         keys[o] = (uint32_t)(ty * S.tiles_x + tx);
                         vals[o] = i;
@@ -955,7 +961,8 @@ __global__ __launch_bounds__(kT) void k_splat_blend(BlendArgs B)
                 int x0, x1, y0, y1;
                 pixel_rect(B.W, B.H, c.x, c.y, ex.x, ex.y, x0, x1, y0, y1);
                 reach = x0 <= qx + hx && x1 >= qx + lx && y0 <= qy + hy && y1 >= qy + ly &&
-                        conic_meets_box(cq.x, cq.y, cq.z, oax - c.x, obx - c.x, oay - c.y, oby - c.y);
+                        conic_meets_box(cq.x, cq.y, cq.z, -(cq.y / cq.x), -(cq.y / cq.z), oax - c.x, obx - c.x,
+                                        oay - c.y, oby - c.y);
             }
         }
         const unsigned long long m = __ballot(reach);
