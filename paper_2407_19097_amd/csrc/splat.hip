@@ -1,10 +1,11 @@
-// Isotropic screen-space Gaussian splat renderer for gfx950.
+// Screen-space Gaussian splat renderer for gfx950.
 //
 // The paper's target renderer is the forward pass of 3D Gaussian splatting
 // applied to the points (Sec. 4.2, "Gaussian Renderer"): each point becomes a
 // Gaussian, the Gaussians reaching a pixel are taken nearest first and
 // alpha-blended front to back.  Here every point is a screen-space Gaussian of
-// standard deviation sigma pixels at its projected position.  Pipeline:
+// standard deviation sigma pixels at its projected position (isotropic), or
+// one elongated along the point's velocity (anisotropic).  Pipeline:
 //   project -- same fp32 transform and cull as the rasterizer; the Gaussian's
 //              3-sigma footprint gives a rectangle of screen tiles (an
 //              elongated one keeps only the rectangle's tiles its ellipse
@@ -16,13 +17,16 @@
 //              relative to the nearest), else four; chosen on the device;
 //   scan    -- exclusive prefix sum of the tile counts in that order;
 //   emit    -- one (tile, point index) pair per covered tile, in that order;
-//   sort    -- stable radix sort of the pairs by tile (two 8-bit passes for up
-//              to 65536 tiles): within a tile the list keeps the depth order;
+//   sort    -- stable radix sort of the pairs by tile (two passes of up to 8
+//              bits for up to 65536 tiles): within a tile the list keeps the
+//              depth order;
 //   ranges  -- first and one-past-last pair of every tile;
-//   blend   -- one workgroup per 16x16 tile, one thread per pixel; batches of
-//              the tile's list are staged through LDS and composited front to
-//              back (alpha = min(0.99, o exp(-d^2 / 2 sigma^2)), skipped below
-//              1/255, stop once transmittance would fall under 1e-4).
+//   blend   -- one workgroup per 16x16 tile, one thread per pixel, each wave
+//              an 8x8 quarter walking the tile's list on its own: entries that
+//              can reach its open pixels are staged through LDS and composited
+//              front to back (alpha = min(0.99, o exp(-d^2 / 2 sigma^2)),
+//              skipped below 1/255, stop once transmittance would fall under
+//              1e-4).
 // No step needs the host: counts stay on the device and kernels whose size
 // depends on them are launched for the worst case and read the count.
 #include <hip/hip_runtime.h>
