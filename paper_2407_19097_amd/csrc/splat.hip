@@ -907,7 +907,6 @@ __global__ __launch_bounds__(kT) void k_splat_blend(BlendArgs B)
     const uint32_t start = B.range[2 * tile], stop = min(B.range[2 * tile + 1], N);
     const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
     const float ax = (float)qx + 0.5f, ay = (float)qy + 0.5f;  // the quarter's first pixel centre
-    const float bx = ax + 7.0f, by = ay + 7.0f;                // and its last
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     float T = 1.0f, r = 0.0f, g = 0.0f, b = 0.0f;
     bool done = !inside;
